@@ -1,0 +1,274 @@
+"""The IOBM scattering system and its direct solution.
+
+ORACLE / TEST INFRASTRUCTURE ONLY: see oracle/__init__.py.
+
+What is computed (Sec. II of the paper):
+  * H_T, the truncated real-space FD Kohn-Sham Hamiltonian on planes
+    0 .. nz-1 (Eqs. (1)-(4); laterally periodic with kappa = 0, couplings
+    beyond the first and last plane dropped), plus the local potential V(r)
+    and, optionally, a separable nonlocal term sum_a B_a D_a h^3 B_a^T;
+  * the IOBM matrix A(E) = E - H_T - Htilde (Eq. (6), Eq. (8)) with
+    Htilde = diag(Sigma_L, 0, ..., 0, Sigma_R) acting on the first and last
+    N_f planes (self-energies of lead.py, in real space);
+  * the right-hand side of Eq. (6): b = C_L Phi_in(lead planes)
+    - Sigma_L Phi_in(boundary planes), C_L being the couplings of H_T to the
+    left-lead planes that truncation dropped (B_z^dagger for N_f = 1), with
+    the incident wave Phi_in a right-moving lateral plane wave x^k;
+  * psi = A^-1 b by sparse direct LU (scipy SuperLU), one factorisation per
+    energy shared by every incident channel;
+  * transmission and reflection from the probability current, as ratios of
+    the current leaving through each lead to the incident current (the
+    Landauer-Buttiker transmission quoted in Sec. III): the current into a
+    lead is psi_B^H Gamma psi_B with Gamma = i (Sigma - Sigma^H), and the
+    incident current is the bond current of Phi_in across a plane cut.
+
+The nonlocal term is carried by the bordered (augmented) matrix
+[[A_loc, B], [B^T, (h^3 D)^-1]] whose Schur complement is A_loc - B h^3 D B^T,
+so the sparse LU keeps its sparsity.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fd import fd_coefficients
+from .lead import LeadMode, mode_numbers, sigma_realspace, z_hopping
+
+
+def _second_difference_1d(n, nf, periodic):
+    """Matrix of sum_{m=-nf}^{nf} chat_|m| f(k+m) on n points (h = 1)."""
+    c = fd_coefficients(nf)
+    D = sp.lil_matrix((n, n))
+    for k in range(n):
+        for m in range(-nf, nf + 1):
+            q = k + m
+            if periodic:
+                D[k, q % n] += c[abs(m)]
+            elif 0 <= q < n:
+                D[k, q] += c[abs(m)]
+    return D.tocsr()
+
+
+def kinetic(g):
+    """-1/2 Laplacian (Eq. (1)) on the truncated grid, flat index
+    (k*ny + j)*nx + i: periodic in x and y, z couplings outside 0..nz-1
+    dropped (Eq. (4))."""
+    Dx = _second_difference_1d(g.nx, g.nf, True) / g.h ** 2
+    Dy = _second_difference_1d(g.ny, g.nf, True) / g.h ** 2
+    Dz = _second_difference_1d(g.nz, g.nf, False) / g.h ** 2
+    Ix, Iy, Iz = (sp.identity(n, format="csr") for n in (g.nx, g.ny, g.nz))
+    lap = sp.kron(Iz, sp.kron(Iy, Dx)) + sp.kron(Iz, sp.kron(Dy, Ix)) + sp.kron(Dz, sp.kron(Iy, Ix))
+    return (-0.5 * lap).tocsr()
+
+
+def lead_coupling(g, side):
+    """Couplings of H between the N_f boundary planes and the N_f adjacent
+    lead planes, dropped by truncation: dense (nf*Nxy, nf*Nxy), rows =
+    boundary planes (0..nf-1 or nz-nf..nz-1), columns = lead planes
+    (-nf..-1 or nz..nz+nf-1), plane index slow."""
+    nf, nxy = g.nf, g.nx * g.ny
+    a = z_hopping(g)
+    Cz = np.zeros((nf, nf))
+    for i in range(nf):
+        for m in range(nf):
+            if side == "L":
+                dist = i - (m - nf)       # boundary plane i, lead plane m - nf
+            else:
+                dist = (g.nz + m) - (g.nz - nf + i)
+            if 1 <= dist <= nf:
+                Cz[i, m] = a[dist]
+    return np.kron(Cz, np.eye(nxy))
+
+
+def kb_matrix(g, nl):
+    """Sparse B (N_pts x nproj) and the per-projector coupling block
+    diag_a(h^3 D_a) (nproj x nproj)."""
+    if nl is None:
+        return None, None
+    rows, cols, vals = [], [], []
+    col = 0
+    blocks = []
+    for idx, beta, D in zip(nl.support, nl.beta, nl.D):
+        r = beta.shape[0]
+        for p in range(r):
+            rows.append(idx)
+            cols.append(np.full(idx.size, col + p))
+            vals.append(beta[p])
+        blocks.append(g.h ** 3 * np.asarray(D, dtype=float))
+        col += r
+    B = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(g.npts, col))
+    from scipy.linalg import block_diag
+    return B, block_diag(*blocks)
+
+
+class Problem:
+    """One transition region: grid, local potential, optional nonlocal term."""
+
+    def __init__(self, g, V, nl=None):
+        self.g = g
+        self.V = np.asarray(V, dtype=float).reshape(g.shape)
+        self.nl = nl
+        self.H_loc = kinetic(g) + sp.diags(self.V.ravel())
+        self.B, self.hD = kb_matrix(g, nl)
+        self._sig = {}
+
+    # --- boundary blocks -------------------------------------------------
+    def sigma(self, E, side):
+        key = (float(E), side)
+        if key not in self._sig:
+            self._sig[key] = sigma_realspace(self.g, E, side)
+        return self._sig[key]
+
+    def boundary_slice(self, side):
+        nf, nxy = self.g.nf, self.g.nx * self.g.ny
+        if side == "L":
+            return slice(0, nf * nxy)
+        return slice(self.g.npts - nf * nxy, self.g.npts)
+
+    # --- operator ----------------------------------------------------------
+    def apply(self, E, x):
+        """y = A(E) x for x of shape (..., N_pts) or (N_pts,), by the plain
+        definition: E x - H_T x - V_NL x - Sigma_L x_B - Sigma_R x_B."""
+        x = np.asarray(x)
+        X = x.reshape(-1, self.g.npts).T  # (N_pts, nrhs)
+        Y = E * X - self.H_loc @ X
+        if self.B is not None:
+            Y = Y - self.B @ (self.hD @ (self.B.T @ X))
+        for side in ("L", "R"):
+            s = self.boundary_slice(side)
+            Y[s] -= self.sigma(E, side) @ X[s]
+        return Y.T.reshape(x.shape)
+
+    def matrix(self, E):
+        """Sparse A(E) (bordered by the nonlocal projectors when present)."""
+        g = self.g
+        A = (E * sp.identity(g.npts, format="csr") - self.H_loc).astype(complex).tolil()
+        for side in ("L", "R"):
+            s = self.boundary_slice(side)
+            A[s, s] = A[s, s] - self.sigma(E, side)
+        A = A.tocsc()
+        if self.B is not None:
+            C = sp.csc_matrix(np.linalg.inv(self.hD))
+            A = sp.bmat([[A, self.B], [self.B.T, C]], format="csc")
+        return A
+
+    # --- incident wave and right-hand side (Eq. (6)) ------------------------
+    def incident(self, E, mode, side="L"):
+        """Phi_in on planes -nf .. nz-1+nf, shape (nz + 2nf, ny, nx): lateral
+        plane wave exp(i G.r) times the propagating Bloch state moving away
+        from the source lead, unit amplitude on the first transition plane
+        it enters (plane 0 from the left, plane nz-1 from the right)."""
+        g = self.g
+        lm = LeadMode(g, E, mode)
+        if not lm.open:
+            raise ValueError(f"mode {mode} is closed at E={E}")
+        x = lm.x_in if side == "L" else lm.x_back
+        k = np.arange(-g.nf, g.nz + g.nf)
+        kref = 0 if side == "L" else g.nz - 1
+        zpart = x ** (k - kref)
+        nux = mode_numbers(g.nx)[mode % g.nx]
+        nuy = mode_numbers(g.ny)[mode // g.nx]
+        jj, ii = np.meshgrid(np.arange(g.ny), np.arange(g.nx), indexing="ij")
+        lat = np.exp(2j * np.pi * (nux * ii / g.nx + nuy * jj / g.ny))
+        return zpart[:, None, None] * lat[None, :, :]
+
+    def rhs(self, E, mode, side="L"):
+        g = self.g
+        nf, nxy = g.nf, g.nx * g.ny
+        Phi = self.incident(E, mode, side)
+        b = np.zeros(g.npts, dtype=complex)
+        if side == "L":
+            lead = Phi[:nf].ravel()                  # planes -nf..-1
+            bnd = Phi[nf:2 * nf].ravel()             # planes 0..nf-1
+        else:
+            lead = Phi[nf + g.nz: 2 * nf + g.nz].ravel()  # planes nz..nz+nf-1
+            bnd = Phi[g.nz: g.nz + nf].ravel()            # planes nz-nf..nz-1
+        s = self.boundary_slice(side)
+        b[s] = lead_coupling(g, side) @ lead - self.sigma(E, side) @ bnd
+        return b
+
+    def incident_current(self, E, mode, side="L"):
+        """Bond current of Phi_in across the cut between lead planes -1 and 0
+        (left) or nz-1 and nz (right), summed over the lateral points:
+        J = -2 sum a_{q-p} Im(conj(Phi_p) Phi_q) over bonds p < cut <= q.
+        Positive in the direction of incidence."""
+        g = self.g
+        a = z_hopping(g)
+        Phi = self.incident(E, mode, side)
+        off = g.nf  # array plane index of transition plane 0
+        cut = 0 if side == "L" else g.nz  # first plane to the right of the cut
+        J = 0.0
+        for n in range(1, g.nf + 1):
+            for p in range(cut - n, cut):
+                q = p + n
+                J += -2.0 * a[n] * np.sum(np.imag(np.conj(Phi[p + off]) * Phi[q + off]))
+        return J if side == "L" else -J
+
+    # --- solve and read out -------------------------------------------------
+    def factor(self, E):
+        return spla.splu(self.matrix(E), permc_spec="COLAMD")
+
+    def solve(self, E, modes, side="L", lu=None, check=True):
+        """psi for every incident mode in `modes`: array (len(modes), nz, ny, nx)."""
+        g = self.g
+        lu = lu or self.factor(E)
+        nb = 0 if self.B is None else self.B.shape[1]
+        Bm = np.zeros((g.npts + nb, len(modes)), dtype=complex)
+        for c, m in enumerate(modes):
+            Bm[:g.npts, c] = self.rhs(E, m, side)
+        X = lu.solve(Bm)
+        psi = X[:g.npts].T.reshape((len(modes),) + g.shape)
+        if check:
+            res = self.apply(E, psi.reshape(len(modes), -1)) - Bm[:g.npts].T
+            rel = np.linalg.norm(res, axis=1) / np.linalg.norm(Bm[:g.npts], axis=0)
+            if rel.max() > 1e-10:
+                raise RuntimeError(f"direct solve residual {rel.max():.3e}")
+        return psi
+
+    def gamma(self, E, side):
+        S = self.sigma(E, side)
+        return 1j * (S - S.conj().T)
+
+    def currents(self, E, mode, psi, side="L"):
+        """(T, R): current leaving through the far / near lead divided by the
+        incident current."""
+        far, near = ("R", "L") if side == "L" else ("L", "R")
+        psi = psi.ravel()
+        Phi = self.incident(E, mode, side)[self.g.nf:self.g.nf + self.g.nz].ravel()
+        J = self.incident_current(E, mode, side)
+        sf, sn = self.boundary_slice(far), self.boundary_slice(near)
+        Jt = np.real(np.vdot(psi[sf], self.gamma(E, far) @ psi[sf]))
+        d = psi[sn] - Phi[sn]
+        Jr = np.real(np.vdot(d, self.gamma(E, near) @ d))
+        return Jt / J, Jr / J
+
+    def transmission_matrix_eigs(self, E, modes, psis, side="L"):
+        """Eigenvalues of t^dagger t for the incident channels `modes` at E:
+        the flux-normalised matrix M[m, m'] = psi_m^H Gamma_far psi_m' /
+        sqrt(J_m J_m') (eigenchannel transmissions, Sec. IV)."""
+        far = "R" if side == "L" else "L"
+        sf = self.boundary_slice(far)
+        G = self.gamma(E, far)
+        P = np.stack([p.ravel()[sf] for p in psis], axis=1)
+        J = np.array([self.incident_current(E, m, side) for m in modes])
+        M = (P.conj().T @ G @ P) / np.sqrt(np.outer(J, J))
+        return np.linalg.eigvalsh(0.5 * (M + M.conj().T))
+
+
+def solve_workload(prob, energies, side="L", channels=None):
+    """Solve every (energy, open channel) pair; returns a list of dicts per
+    energy with keys E, modes, psi, T, R."""
+    from .lead import open_channels
+    out = []
+    for E in energies:
+        modes = open_channels(prob.g, E)
+        if channels == "lowest":
+            modes = modes[:1]
+        lu = prob.factor(E)
+        psi = prob.solve(E, modes, side, lu=lu)
+        TR = [prob.currents(E, m, p, side) for m, p in zip(modes, psi)]
+        out.append({"E": E, "modes": modes, "psi": psi, "lu": lu,
+                    "T": np.array([t for t, _ in TR]), "R": np.array([r for _, r in TR])})
+    return out

@@ -1,0 +1,364 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle:
+values printed in the paper, closed forms, an independent published
+algorithm (Lopez Sancho-Rubio decimation), the Caroli/Fisher-Lee trace
+formula, exact invariants of the discrete system, and finite differences.
+
+Each test names what a plausible mistake would break.
+"""
+from fractions import Fraction
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import Grid, make, random_field
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- Eq. (1)
+def _golden_fd():
+    out = {}
+    for line in open(os.path.join(GOLDEN, "fd_coefficients.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        out[int(f[0])] = [Fraction(v) for v in f[1:]]
+    return out
+
+
+@pytest.mark.parametrize("nf", [1, 2, 3])
+def test_fd_coefficients_match_printed_and_textbook_values(nf):
+    assert O.fd_coefficients_exact(nf) == _golden_fd()[nf]
+
+
+@pytest.mark.parametrize("nf", [1, 2, 3])
+def test_fd_order_of_accuracy(nf):
+    # the 2nf-order stencil on sin(x): error ~ h^(2 nf)
+    c = O.fd_coefficients(nf)
+    errs = []
+    for h in (0.2, 0.1):
+        x0 = 0.3
+        d2 = sum(c[abs(n)] * math.sin(x0 + n * h) for n in range(-nf, nf + 1)) / h ** 2
+        errs.append(abs(d2 + math.sin(x0)))
+    order = math.log(errs[0] / errs[1], 2)
+    assert abs(order - 2 * nf) < 0.3
+
+
+# ------------------------------------------------- Eqs. (11)-(15), (A8)
+def _chi(g, E, mode):
+    """Eq. (13) with kappa = 0 (N_f = 1)."""
+    nux = O.mode_numbers(g.nx)[mode % g.nx]
+    nuy = O.mode_numbers(g.ny)[mode // g.nx]
+    h = g.h
+    return (h * h * E - (1 - math.cos(2 * math.pi * nux / g.nx))
+            - (1 - math.cos(2 * math.pi * nuy / g.ny)) - 1.0)
+
+
+def _sigma_closed_form(g, E, mode):
+    """Eq. (15): Sigma_nu = -exp(i k_z h) / (2 h^2), with k_z from Eq. (12)
+    and the branch rule stated after Eq. (13); for chi > 1 (above the
+    discrete band top) the decaying root of x^2 + 2 chi x + 1 = 0 (Eq. (A8),
+    omega_1 omega_2 = 1) is taken."""
+    chi = _chi(g, E, mode)
+    h = g.h
+    if abs(chi) < 1:
+        x = complex(math.cos(math.acos(-chi)), math.sin(math.acos(-chi)))
+    elif chi < -1:
+        x = math.exp(-math.acosh(-chi))
+    else:
+        x = -chi + math.sqrt(chi * chi - 1)
+    return -x / (2 * h * h)
+
+
+@pytest.mark.parametrize("E", [0.05, 0.4, 2.0, 30.0])
+def test_sigma_nf1_equals_closed_form(E):
+    g = Grid(8, 6, 10, 0.4, 1)
+    for m in range(g.nx * g.ny):
+        lm = O.LeadMode(g, E, m)
+        s = lm.sigma_right()
+        assert s.shape == (1, 1)
+        assert abs(s[0, 0] - _sigma_closed_form(g, E, m)) < 1e-12 * 2 / g.h ** 2
+        assert lm.open == (abs(_chi(g, E, m)) < 1)
+
+
+def _sancho_rubio(g, E, mode, eta=1e-9, itmax=200):
+    """Lopez Sancho, Lopez Sancho & Rubio, J. Phys. F 15, 851 (1985):
+    decimation for the surface Green function of a semi-infinite chain of
+    principal layers (here N_f planes of one lateral mode); returns the
+    right-lead self-energy H01 g_s H10."""
+    nf = g.nf
+    c = O.fd_coefficients(nf)
+    a = [-c[n] / (2 * g.h ** 2) for n in range(nf + 1)]
+    eps = O.lateral_energy(g, mode)
+    H00 = np.zeros((nf, nf))
+    H01 = np.zeros((nf, nf))
+    for i in range(nf):
+        for j in range(nf):
+            d = abs(i - j)
+            H00[i, j] = a[d] + (eps if d == 0 else 0.0)
+            dd = nf + j - i
+            if dd <= nf:
+                H01[i, j] = a[dd]
+    w = (E + 1j * eta) * np.eye(nf)
+    es, e, al, be = H00.astype(complex), H00.astype(complex), H01.astype(complex), H01.T.astype(complex)
+    for _ in range(itmax):
+        gg = np.linalg.inv(w - e)
+        agb, bga = al @ gg @ be, be @ gg @ al
+        es = es + agb
+        e = e + agb + bga
+        al, be = al @ gg @ al, be @ gg @ be
+        if np.abs(al).max() + np.abs(be).max() < 1e-15:
+            break
+    gs = np.linalg.inv(w - es)
+    return H01 @ gs @ H01.T
+
+
+@pytest.mark.parametrize("nf", [2, 3])
+@pytest.mark.parametrize("E", [0.1, 0.9, 3.0])
+def test_sigma_matches_sancho_rubio(nf, E):
+    g = Grid(6, 4, 10, 0.4, nf)
+    for m in range(g.nx * g.ny):
+        s = O.LeadMode(g, E, m).sigma_right()
+        ref = _sancho_rubio(g, E, m)
+        assert np.abs(s - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("nf", [1, 2, 3])
+def test_sigma_symmetric_and_mirror_and_root_pairing(nf):
+    g = Grid(6, 6, 10, 0.35, nf)
+    for E in (0.2, 1.1):
+        for m in range(g.nx * g.ny):
+            lm = O.LeadMode(g, E, m)
+            S, SL = lm.sigma_right(), lm.sigma_left()
+            assert np.abs(S - S.T).max() < 1e-12 * np.abs(S).max()
+            # jellium leads: left = right with the plane order reversed
+            assert np.abs(SL - S[::-1, ::-1]).max() < 1e-12 * np.abs(S).max()
+            # palindromic recurrence: roots pair as x <-> 1/x (omega_1 omega_2 = 1)
+            for x in lm.right:
+                assert np.min(np.abs(lm.left - 1 / x)) < 1e-9 * max(1, abs(1 / x))
+            # retarded: Im Sigma <= 0 (negative semidefinite broadening)
+            G = 1j * (S - S.conj().T)
+            assert np.linalg.eigvalsh(G).min() > -1e-12 * np.abs(S).max()
+
+
+def _golden_counts():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "paper_channel_counts.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, L, N, rs, nin = line.split()
+        rows.append((name, float(L), int(N), float(rs), int(nin)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_counts(), ids=lambda r: r[0])
+def test_channel_count_of_ir_and_au_wires(row):
+    name, L, N, rs, nin = row
+    EF = (9 * math.pi / 4) ** (2 / 3) / (2 * rs * rs)
+    g = Grid(N, N, 4, L / N, 1)
+    assert len(O.open_channels(g, EF)) == nin
+
+
+# ------------------------------------------------------------ whole solve
+@pytest.mark.parametrize("nf", [1, 2, 3])
+def test_flat_wire_transmits_every_open_channel(nf):
+    # h = 0.9 on a 6x6 cell: several lateral channels open at E = 1.0
+    g = Grid(6, 6, 12, 0.9, nf)
+    P = O.Problem(g, np.zeros(g.shape))
+    E = 1.0
+    modes = O.open_channels(g, E)
+    assert len(modes) >= 5
+    psi = P.solve(E, modes)
+    Ts = []
+    for m, p in zip(modes, psi):
+        Phi = P.incident(E, m)[nf:nf + g.nz]
+        assert np.abs(p - Phi).max() < 1e-11
+        T, R = P.currents(E, m, p)
+        Ts.append(T)
+        assert abs(T - 1) < 1e-11 and abs(R) < 1e-11
+    assert abs(sum(Ts) - len(modes)) < 1e-10
+
+
+def _barrier_closed_form(E, V0, n, h):
+    """Transmission of a tight-binding chain (N_f = 1, t = 1/(2h^2)) through n
+    consecutive sites raised by V0: T = [1 + (V0 h^2)^2 |sin(n phi)/sin(phi)|^2
+    / sin^2(theta)]^-1 with cos(theta) = 1 - E h^2, cos(phi) = 1 - (E - V0) h^2."""
+    th = np.arccos(1 - E * h * h)
+    cphi = 1 - (E - V0) * h * h
+    phi = np.arccos(complex(cphi))
+    ratio = n if abs(np.sin(phi)) < 1e-14 else np.sin(n * phi) / np.sin(phi)
+    return 1.0 / (1.0 + (V0 * h * h) ** 2 * abs(ratio) ** 2 / np.sin(th) ** 2)
+
+
+@pytest.mark.parametrize("E,V0,n", [(0.3, 0.5, 7), (0.6, 0.2, 11), (0.25, -0.3, 5)])
+def test_lattice_square_barrier_closed_form(E, V0, n):
+    g = Grid(4, 4, 24, 0.5, 1)
+    V = np.zeros(g.shape)
+    V[8:8 + n] = V0
+    P = O.Problem(g, V)
+    psi = P.solve(E, [0])
+    T, R = P.currents(E, 0, psi[0])
+    assert abs(T - _barrier_closed_form(E, V0, n, g.h)) < 1e-12
+    assert abs(T + R - 1) < 1e-12
+
+
+def test_continuum_barrier_limit_is_second_order():
+    # the continuum formula is approached as O(h^2) (the sharp step limits
+    # the order for every N_f); checks that the discretisation is the
+    # Schrodinger operator with the right units (hbar = m = 1)
+    V0, a, E = 0.5, 2.0, 0.3
+    kap = math.sqrt(2 * (V0 - E))
+    Tc = 1 / (1 + V0 ** 2 * math.sinh(kap * a) ** 2 / (4 * E * (V0 - E)))
+    errs = []
+    for h in (0.2, 0.1):
+        n = int(round(a / h))
+        nz = n + 16
+        g = Grid(2, 2, nz, h, 2)
+        V = np.zeros(g.shape)
+        V[8:8 + n] = V0
+        P = O.Problem(g, V)
+        psi = P.solve(E, [0])
+        errs.append(abs(P.currents(E, 0, psi[0])[0] - Tc))
+    assert errs[1] < errs[0] / 2.5
+
+
+def _random_problem(nf, seed, kb=False, shape=(6, 6, 14), h=0.9):
+    g = Grid(shape[0], shape[1], shape[2], h, nf)
+    rng = np.random.default_rng(seed)
+    V = 0.3 * rng.standard_normal(g.shape)
+    nl = None
+    if kb:
+        from workloads.synth import _kb_projectors
+        centres = [np.array([1.5, 1.8, 4.0]), np.array([2.0, 1.0, 5.5])]
+        nl = _kb_projectors(g, centres, 0.8, 3, rng)
+    return O.Problem(g, V, nl)
+
+
+@pytest.mark.parametrize("nf,kb", [(1, False), (2, False), (3, False), (2, True)])
+def test_flux_conservation_and_reciprocity(nf, kb):
+    P = _random_problem(nf, 7 + nf, kb)
+    E = 1.6
+    modes = O.open_channels(P.g, E)
+    assert len(modes) >= 5
+    psiL = P.solve(E, modes, "L")
+    TL = 0.0
+    for m, p in zip(modes, psiL):
+        T, R = P.currents(E, m, p, "L")
+        assert abs(T + R - 1) < 1e-10
+        assert -1e-12 < T < 1 + 1e-12
+        TL += T
+    psiR = P.solve(E, modes, "R")
+    TR = sum(P.currents(E, m, p, "R")[0] for m, p in zip(modes, psiR))
+    assert abs(TL - TR) < 1e-10
+    eig = P.transmission_matrix_eigs(E, modes, psiL)
+    assert abs(eig.sum() - TL) < 1e-10
+    assert eig.min() > -1e-10 and eig.max() < 1 + 1e-10
+
+
+@pytest.mark.parametrize("nf", [1, 2, 3])
+def test_matrix_is_complex_symmetric(nf):
+    P = _random_problem(nf, 3, kb=(nf == 2))
+    A = P.matrix(0.9)
+    assert abs(A - A.T).max() < 1e-12
+
+
+def test_dense_solve_and_caroli_trace():
+    """Total transmission equals the Caroli / Fisher-Lee trace
+    Tr[Gamma_L G Gamma_R G^H] with G = A^-1 (dense): pins b, the incident
+    current normalisation and the readout together."""
+    P = _random_problem(2, 11)
+    g = P.g
+    E = 1.3
+    A = P.matrix(E).toarray()
+    G = np.linalg.inv(A)
+    sL, sR = P.boundary_slice("L"), P.boundary_slice("R")
+    caroli = np.real(np.trace(P.gamma(E, "L") @ G[sL, sR] @ P.gamma(E, "R") @ G[sL, sR].conj().T))
+    modes = O.open_channels(g, E)
+    psi = P.solve(E, modes)
+    T = sum(P.currents(E, m, p)[0] for m, p in zip(modes, psi))
+    assert abs(T - caroli) < 1e-10 * max(1, caroli)
+    b = P.rhs(E, modes[0])
+    assert np.abs(np.linalg.solve(A, b) - psi[0].ravel()).max() < 1e-10
+
+
+def test_bordered_nonlocal_equals_dense_schur_complement():
+    P = _random_problem(2, 5, kb=True)
+    E = 0.8
+    x = random_field(P.g.npts, 4)
+    y = P.apply(E, x)
+    A_loc = (E * np.eye(P.g.npts) - P.H_loc.toarray()).astype(complex)
+    for side in ("L", "R"):
+        s = P.boundary_slice(side)
+        A_loc[s, s] -= P.sigma(E, side)
+    Bd = P.B.toarray()
+    A_dense = A_loc - Bd @ P.hD @ Bd.T
+    assert np.abs(y - A_dense @ x).max() < 1e-11 * np.abs(y).max()
+    modes = O.open_channels(P.g, E)
+    psi = P.solve(E, modes[:2])
+    for m, p in zip(modes[:2], psi):
+        assert np.abs(A_dense @ p.ravel() - P.rhs(E, m)).max() < 1e-10
+
+
+def test_interior_bond_current_equals_transmitted_current():
+    """Current conservation across every plane cut inside the transition
+    region (real V): the Gamma-based transmitted current must equal the bond
+    current through each interior cut."""
+    P = _random_problem(3, 21)
+    g = P.g
+    E = 1.1
+    modes = O.open_channels(g, E)
+    psi = P.solve(E, modes[:3])
+    a = O.lead.z_hopping(g)
+    for m, p in zip(modes[:3], psi):
+        T, _ = P.currents(E, m, p)
+        J = P.incident_current(E, m)
+        for cut in range(g.nf, g.nz - g.nf + 1):
+            Jc = 0.0
+            for n in range(1, g.nf + 1):
+                for q0 in range(cut - n, cut):
+                    Jc += -2 * a[n] * np.sum(np.imag(np.conj(p[q0]) * p[q0 + n]))
+            assert abs(Jc / J - T) < 1e-10
+
+
+def test_gradient_matches_central_differences():
+    P = _random_problem(2, 31, shape=(4, 4, 10), h=0.7)
+    g = P.g
+    Es = [0.9, 1.4]
+    T0, grad = O.total_transmission_and_gradient(P, Es)
+    assert abs(T0 - O.total_transmission(P, Es)) < 1e-11
+    rng = np.random.default_rng(0)
+    vox = rng.choice(g.npts, 12, replace=False)
+    d = 1e-5
+    for v in vox:
+        Vp, Vm = P.V.copy(), P.V.copy()
+        Vp.flat[v] += d
+        Vm.flat[v] -= d
+        fd = (O.total_transmission(O.Problem(g, Vp), Es) - O.total_transmission(O.Problem(g, Vm), Es)) / (2 * d)
+        assert abs(fd - grad.flat[v]) < 1e-6 * max(1e-3, np.abs(grad).max())
+
+
+def test_threshold_is_rejected():
+    g = Grid(4, 4, 8, 0.5, 2)
+    # the (1,0) lateral threshold is exactly eps of that mode
+    eps = O.lateral_energy(g, 1)
+    with pytest.raises(O.AtThreshold):
+        O.LeadMode(g, eps, 1)
+
+
+def test_workload_channel_counts():
+    """Open-channel counts of the five workloads (Eq. (13) generalised to the
+    workloads' FD orders): flat 1 at E=0.1; barrier 1 per energy; adjoint
+    1/5/9/13; wide 45..57 per energy."""
+    w1 = make(1)
+    assert len(O.open_channels(w1.grid, 0.1)) >= 1
+    w2 = make(2)
+    assert [len(O.open_channels(w2.grid, E)) for E in w2.energies] == [1] * 8
+    w5 = make(5)
+    assert [len(O.open_channels(w5.grid, E)) for E in w5.energies] == [1, 5, 9, 13]
+    from workloads import Grid as G_
+    g4 = G_(48, 48, 4, 0.4, 2)
+    n4 = [len(O.open_channels(g4, E)) for E in make(4, G_(48, 48, 4, 0.4, 2)).energies]
+    assert min(n4) >= 40 and max(n4) <= 60 and sum(n4) == 768
