@@ -1,0 +1,209 @@
+/*
+ * iobm.h -- C ABI of libiobm, the MI355X (gfx950) scattering-state solver of
+ * the improved overbridging-boundary-matching (IOBM) method with FFT-applied
+ * jellium self-energies and preconditioned conjugate gradients
+ * (Egami, Hirose, Ono, "Novel time-saving first-principles calculation
+ * method for electron-transport properties", arXiv:1009.5300).
+ *
+ * Problem (Sec. II, Eqs. (1)-(8)): on an nx x ny x nz real-space grid that
+ * is periodic in x and y (lateral Bloch vector kappa = 0) and truncated
+ * along z (the transport axis), solve for every requested energy E and
+ * incident lateral channel mu
+ *
+ *     [E - H_T - Sigma_L(E) - Sigma_R(E)] psi = b_mu(E)                (Eq. 6)
+ *
+ * where H_T = -1/2 Laplacian (central FD of order 2*nf, Eq. (1)) + V(r)
+ * [+ separable nonlocal term], Sigma_L/R are the retarded self-energies of
+ * two semi-infinite jellium electrodes (V = 0, same stencil), acting on the
+ * first/last nf planes and diagonal in the lateral plane waves (Eqs. (14)-
+ * (15); N_f x N_f per mode for nf > 1), and b_mu carries the unit-amplitude
+ * incident Bloch wave of channel mu.  Transmission and reflection are read
+ * off psi at the boundary planes (scattering condition, Eq. (7)).
+ *
+ * Conventions
+ *  - Hartree atomic units (hbar = m = 1); energies measured from the lead
+ *    band bottom (the jellium potential is 0).
+ *  - Flat voxel index (k*ny + j)*nx + i; x fastest; k = plane 0..nz-1.
+ *    Plane 0 faces the left electrode, plane nz-1 the right one.
+ *  - Complex arrays are interleaved (re, im).  complex128 = 2 doubles,
+ *    complex64 = 2 floats.
+ *  - Lateral channel id m = iy*nx + ix, ix/iy in FFT order
+ *    (nu_x = ix for ix < nx/2, else ix - nx); lateral plane wave
+ *    exp(2 pi i (nu_x i / nx + nu_y j / ny)).
+ *  - Lateral Fourier transform normalised as in Eq. (16): psi~_nu =
+ *    (1/Nxy) sum_l exp(-i G_nu . r_l) psi(r_l).
+ *  - An incident wave has unit amplitude on its lateral plane wave at plane 0.
+ *    t[nu][mu] is the amplitude of outgoing channel nu at plane nz-nf,
+ *    r[nu][mu] the reflected amplitude at plane 0; T_mu = sum_nu
+ *    (v_nu/v_mu) |t_nu,mu|^2 over open nu, R_mu likewise (Landauer-Buttiker,
+ *    Sec. III).
+ *
+ * Ownership and streams
+ *  - The caller owns every buffer it passes.  Pointers documented "device"
+ *    must be device memory on the context's device (e.g. torch tensors);
+ *    "host" pointers are ordinary host memory.
+ *  - The context owns its copies of V, the nonlocal data, per-energy mode
+ *    tables and all solver workspaces; iobm_destroy frees them.
+ *  - All device work is enqueued on the stream given to iobm_create (NULL =
+ *    the null stream).  Calls that return host results synchronise that
+ *    stream before returning; iobm_apply and iobm_precondition do not.
+ *  - A context is not thread-safe; separate contexts are independent.
+ *
+ * Errors
+ *  - Every call returns an iobm_status; no C++ exception crosses the ABI.
+ *    Arguments are validated before any launch.  iobm_last_error(ctx) holds
+ *    a message for the last failure on that context.
+ */
+#ifndef IOBM_H
+#define IOBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct iobm_ctx_s* iobm_ctx;
+
+typedef enum {
+  IOBM_OK = 0,
+  IOBM_E_INVALID_ARG = 1,   /* bad size, pointer, option, channel id, or non-finite input */
+  IOBM_E_BAD_STATE = 2,     /* e.g. solve before iobm_set_potential */
+  IOBM_E_OOM = 3,           /* device allocation failed */
+  IOBM_E_DEVICE = 4,        /* HIP runtime error (message in iobm_last_error) */
+  IOBM_E_NOT_CONVERGED = 5, /* some right-hand side missed the tolerance; results of
+                               converged ones are valid, per-RHS status in the stats */
+  IOBM_E_BREAKDOWN = 6,     /* Krylov breakdown that restarts could not cure */
+  IOBM_E_AT_THRESHOLD = 7,  /* energy within 1e-9 (relative) of a lateral channel threshold */
+  IOBM_E_UNSUPPORTED = 8    /* valid request this build does not implement */
+} iobm_status;
+
+/* Grid: nx, ny >= 2 (lateral, periodic), nz >= 2*nf (planes of the transition
+ * region, both boundary plane groups included), spacings > 0 in bohr,
+ * nf in {1, 2, 3} = half width of the central FD stencil (Eq. (1)). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double hx, hy, hz;
+  int32_t nf;
+} iobm_grid;
+
+enum { IOBM_C128 = 0,          /* complex128 throughout */
+       IOBM_C64_REFINED = 1 }; /* complex64 inner COCG, FP64 residual + refinement */
+
+enum { IOBM_PC_NONE = 0,
+       IOBM_PC_TRUNCATED_LAPLACIAN = 1, /* Eq. (17): C0 g + C1 sum over the 6 face
+                                           neighbours, C0 = 1, C1 = exp(-alpha) */
+       IOBM_PC_LATERAL_FFT = 2 };       /* exact inverse of the V = 0 operator: lateral
+                                           FFT + per-mode z Green's function */
+
+typedef struct {
+  int32_t precision;   /* IOBM_C128 or IOBM_C64_REFINED */
+  int32_t precond;     /* IOBM_PC_* */
+  double alpha;        /* Eq. (17) parameter, C1 = exp(-alpha); default 1.8 */
+  double tol;          /* stop when ||b - A psi||_2 <= tol ||b||_2 (FP64); default 1e-10 */
+  double inner_tol;    /* complex64 inner solve relative tolerance; default 1e-5 */
+  int32_t max_iter;    /* total inner iterations per RHS; default 50000 */
+  int32_t side;        /* 0: incidence from the left electrode, 1: from the right */
+  int32_t check_every; /* iterations between convergence checks; default 8 */
+} iobm_solve_opts;
+
+/* Per right-hand side statistics (the paper's Table 2 counts iterations). */
+typedef struct {
+  int32_t iters;        /* preconditioned COCG iterations (all refinement steps) */
+  int32_t refinements;  /* FP64 residual evaluations after the first */
+  int32_t status;       /* IOBM_OK or IOBM_E_NOT_CONVERGED / IOBM_E_BREAKDOWN */
+  int32_t pad_;
+  double rel_residual;  /* final ||b - A psi|| / ||b|| in FP64 */
+  double flux_error;    /* T + R - 1 */
+} iobm_solve_stat;
+
+/* Fill opts with the defaults listed above. */
+void iobm_default_opts(iobm_solve_opts* opts);
+
+/* Create a context on the current HIP device.  hip_stream: hipStream_t or NULL.
+ * The grid is copied.  Errors: INVALID_ARG (sizes, nf), DEVICE, OOM. */
+iobm_status iobm_create(const iobm_grid* grid, void* hip_stream, iobm_ctx* out);
+
+/* Set the local potential V(r) (Ha), float64 [nz][ny][nx], copied into the
+ * context (Eq. (2): the diagonal of H(z_k)).  on_device: 0 = host pointer,
+ * 1 = device pointer.  Errors: INVALID_ARG (NULL, non-finite value). */
+iobm_status iobm_set_potential(iobm_ctx ctx, const double* V, int32_t on_device);
+
+/* Set a separable (Kleinman-Bylander form) nonlocal term
+ *     V_NL = sum_a B_a D_a h^3 B_a^T,  h^3 = hx*hy*hz,
+ * added to H_T (the pseudopotential part of the Kohn-Sham Hamiltonian of
+ * Sec. III/IV; synthetic here).  ncenters >= 0 (0 removes the term), rank in
+ * 1..8; nsupport[a] = voxels of centre a; support_idx = concatenated flat
+ * voxel ids (host, int64); beta = concatenated per-centre [rank][nsupport[a]]
+ * float64 values (host); D = [ncenters][rank][rank] float64 (host), must be
+ * symmetric so that A stays complex symmetric.  Data are copied.
+ * Errors: INVALID_ARG (index out of range, non-symmetric D, non-finite). */
+iobm_status iobm_set_nonlocal(iobm_ctx ctx, int32_t ncenters, int32_t rank,
+                              const int32_t* nsupport, const int64_t* support_idx,
+                              const double* beta, const double* D);
+
+/* Open lateral channels at energy E (Eqs. (12)-(13), generalised to order
+ * 2*nf): nopen = number of propagating modes.  Optional host outputs (may be
+ * NULL, else sized by the caller to nx*ny): ids (ascending channel ids),
+ * kz (propagating z wave number, 1/bohr, in (0, pi/hz)), v (group velocity,
+ * bohr/a.u. time).  Errors: AT_THRESHOLD, INVALID_ARG. */
+iobm_status iobm_channels(iobm_ctx ctx, double E, int32_t* nopen, int32_t* ids,
+                          double* kz, double* v);
+
+/* Self-energy of the right electrode in lateral-mode space (Eq. (15); an
+ * nf x nf block per mode, plane index i <-> plane nz-nf+i), complex128
+ * interleaved, host array [nx*ny][nf][nf].  The left electrode's block is
+ * the same with the plane order reversed. */
+iobm_status iobm_self_energy(iobm_ctx ctx, double E, double* sigma);
+
+/* y = A(E) x for nrhs vectors: the FD stencil + (E - V) diagonal + nonlocal
+ * term + FFT-applied electrode self-energies (Eqs. (6), (8), (14)-(16)).
+ * x, y: device arrays [nrhs][nz][ny][nx] of complex128 (precision
+ * IOBM_C128) or complex64 (IOBM_C64_REFINED); x and y must not overlap.
+ * Asynchronous on the context stream. */
+iobm_status iobm_apply(iobm_ctx ctx, double E, int32_t nrhs, const void* x, void* y,
+                       int32_t precision);
+
+/* z = P r for nrhs vectors with the preconditioner `precond` (IOBM_PC_*) at
+ * energy E (only IOBM_PC_LATERAL_FFT depends on E), same layout rules as
+ * iobm_apply.  Asynchronous. */
+iobm_status iobm_precondition(iobm_ctx ctx, int32_t precond, double alpha, double E,
+                              int32_t nrhs, const void* r, void* z, int32_t precision);
+
+/* Right-hand side of Eq. (6) for incident channels: b[c] for energy E and
+ * channel ids[c] (must be open), device complex128 [n][nz][ny][nx], zero
+ * outside the first (side 0) or last (side 1) nf planes. */
+iobm_status iobm_rhs(iobm_ctx ctx, double E, int32_t n, const int32_t* ids, int32_t side,
+                     void* b);
+
+/* Solve Eq. (6) for every (energy, incident channel) pair and read out the
+ * scattering amplitudes.
+ *  nE energies E[e] (host); ninc[e] channel ids for energy e, concatenated in
+ *  inc (host; ninc[e] = -1 means "every open channel at E[e]" and consumes no
+ *  entries of inc).  nrhs = total number of pairs, in this order.
+ *  psi: device [nrhs][nz][ny][nx] complex128, or NULL.
+ *  t:   host, per energy [nopen(E)][ninc_e] complex128 (outgoing amplitudes of
+ *       every open channel, concatenated over energies), or NULL.
+ *  T, R: host [nrhs] float64, or NULL.  st: host [nrhs], or NULL.
+ * Synchronises the stream.  Returns NOT_CONVERGED if any pair missed tol. */
+iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, const double* E,
+                       const int32_t* ninc, const int32_t* inc, void* psi, double* t,
+                       double* T, double* R, iobm_solve_stat* st);
+
+/* Total transmission T_tot = sum over energies and every open incident
+ * channel of T_mu, and its gradient with respect to the local potential,
+ * dT_tot/dV(r), by one adjoint solve per channel with the same (complex
+ * symmetric) operator.  T_total: host scalar; dT_dV: device float64
+ * [nz][ny][nx] (overwritten).  Synchronises the stream. */
+iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE,
+                                   const double* E, double* T_total, void* dT_dV);
+
+/* Number of open channels needed to size outputs (same as iobm_channels). */
+iobm_status iobm_destroy(iobm_ctx ctx);
+const char* iobm_status_str(iobm_status s);
+const char* iobm_last_error(iobm_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IOBM_H */

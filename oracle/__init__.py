@@ -16,6 +16,8 @@ Method (Egami, Hirose, Ono, Sec. II and appendix):
              right-hand side of Eq. (6), sparse direct LU, current-based
              transmission / reflection and eigenchannel transmissions
   adjoint.py dT/dV by the transposed solve on the same LU factors
+  precond.py the two preconditioners by their definitions (Eq. (17); the
+             flat-wire inverse by a direct solve)
 
 Every floating-point step is FP64 / complex128.
 """
@@ -24,3 +26,4 @@ from .lead import (AtThreshold, LeadMode, lateral_energy, lead_modes, open_chann
                    sigma_realspace, mode_numbers, bloch_current, transfer_matrix)
 from .system import Problem, kinetic, lead_coupling, solve_workload
 from .adjoint import total_transmission_and_gradient, total_transmission
+from . import precond

@@ -1,0 +1,1081 @@
+// C ABI of libiobm: context management, validation, mode tables, and the
+// batched preconditioned COCG driver with FP64 iterative refinement.
+//
+// Solver (Sec. II, last part, and Sec. III): the IOBM matrix is complex
+// symmetric (A^T = A for real V, kappa = 0, symmetric Sigma and nonlocal
+// term), so the conjugate-gradient iteration the paper uses is taken in its
+// complex-orthogonal form (COCG: the bilinear form x^T y replaces x^H y).
+// Every right-hand side of a batch carries its own energy and scalars.
+//
+// Lateral plane-wave incident channels exp(i G.r) with G != 0 have
+// b^T b = 0 exactly (the lateral sum of exp(2 i G.r) vanishes), which breaks
+// COCG down at its first step.  The driver therefore solves for the real
+// lateral standing waves cos(G.r) and sin(G.r) of each +-G pair and combines
+// psi_{+-G} = psi_cos +- i psi_sin (exact by linearity).
+//
+// Precision: IOBM_C128 runs COCG in complex128.  IOBM_C64_REFINED keeps the
+// solution and the true residual r = b - A x in complex128 and solves the
+// correction equation A d = r with complex64 COCG (FP64 inner products),
+// x += d, until ||r|| <= tol ||b||.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "internal.h"
+
+// launchers from ops.hip
+hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs,
+                      int side, const ModeData* modes, zd* b);
+int dot_blocks(iobm_ctx c);
+template <typename T>
+hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active, void* part);
+template <typename T, typename TX>
+hipError_t launch_update_xr(iobm_ctx c, cplx<TX>* x, const cplx<T>* p, cplx<T>* r, const cplx<T>* q,
+                            const zd* alpha, int nact, const int* active, void* part);
+template <typename T>
+hipError_t launch_update_p(iobm_ctx c, cplx<T>* p, const cplx<T>* z, const zd* beta, int nact,
+                           const int* active);
+hipError_t launch_finish(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const void* part,
+                         int mode, int nact, const int* active);
+template <typename T>
+hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const int* active);
+template <typename TD, typename TS>
+hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int nact, const int* active);
+template <typename T>
+hipError_t launch_accumulate(iobm_ctx c, zd* x, const cplx<T>* d, int nact, const int* active);
+hipError_t launch_readout(iobm_ctx c, int nrhs, int side, const zd* x, const ModeData* modes,
+                          const int* e_rhs, zd* amp_near, zd* amp_far);
+hipError_t launch_combine(iobm_ctx c, int nreq, const int* req_e, const int* req_mode, const int* req_c,
+                          const int* req_s, const int* req_sgn, const ModeData* modes, const zd* amp_near,
+                          const zd* amp_far, zd* t_out, zd* r_out, double* T, double* R);
+template <typename TO>
+hipError_t launch_combine_psi(iobm_ctx c, int nreq, const zd* x, cplx<TO>* psi, const int* req_c,
+                              const int* req_s, const int* req_sgn);
+// grad.hip
+hipError_t launch_rhs_adjoint(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs,
+                              int side, const ModeData* modes, zd* b);
+hipError_t launch_grad_D(iobm_ctx c, int nE, int nmax, const int* base, const int* chan, const zd* pcoef,
+                         const zd* qcoef, const int* req_mode, const int* req_e, const ModeData* modes,
+                         const zd* tamp, zd* D, const long long* dbase);
+hipError_t launch_grad(iobm_ctx c, int nE, const int* base, const long long* dbase, const zd* D, const zd* u,
+                       const zd* w, double* g);
+
+namespace {
+
+struct Fail {
+  iobm_status s;
+};
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                         \
+      throw Fail{e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation ? IOBM_E_OOM   \
+                                                                              : IOBM_E_DEVICE}; \
+    }                                                                                       \
+  } while (0)
+
+iobm_status fail(iobm_ctx ctx, iobm_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+// ------------------------------------------------------------- scratch pool
+enum Slot {
+  S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_Q, S_D, S_PF, S_PART, S_SCAL, S_IDX, S_AMP, S_TR, S_KB,
+  S_GRAD_U, S_GRAD_D, NSLOT
+};
+
+void* scratch(iobm_ctx ctx, int slot, size_t bytes) {
+  if ((int)ctx->pool.size() < NSLOT) ctx->pool.resize(NSLOT, {nullptr, 0});
+  auto& e = ctx->pool[slot];
+  if (e.second < bytes) {
+    if (e.first) {
+      (void)hipStreamSynchronize(ctx->stream);  // queued work may still use the old buffer
+      (void)hipFree(e.first);
+    }
+    e.first = nullptr;
+    e.second = 0;
+    void* p = nullptr;
+    hipError_t err = hipMalloc(&p, std::max<size_t>(bytes, 256));
+    if (err != hipSuccess) {
+      ctx->err = std::string("hipMalloc: ") + hipGetErrorString(err);
+      throw Fail{IOBM_E_OOM};
+    }
+    e.first = p;
+    e.second = std::max<size_t>(bytes, 256);
+  }
+  return e.first;
+}
+
+// Small index / scalar arrays go through a fixed device arena of 64 regions
+// of 64 KB with a pinned host mirror.  An asynchronous copy reads the pinned
+// mirror when it executes, and queued kernels read the device region when
+// they run, so a region with an upload that the stream has not yet passed
+// is never rewritten: the stream is synchronised first (region_pending).
+const size_t kRegion = 64 * 1024;
+const int kRegions = 64;
+
+void stream_sync(iobm_ctx ctx) {
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    ctx->err = std::string("hipStreamSynchronize: ") + hipGetErrorString(e);
+    throw Fail{IOBM_E_DEVICE};
+  }
+  for (int r = 0; r < kRegions; ++r) ctx->region_pending[r] = 0;
+}
+
+template <typename T>
+T* upload(iobm_ctx ctx, int slot, const std::vector<T>& v, size_t offset_bytes = 0) {
+  (void)slot;
+  const size_t bytes = v.size() * sizeof(T);
+  const size_t region = offset_bytes / 8192;  // offsets below are multiples of 8 KB
+  if (region >= (size_t)kRegions - 1 || bytes > kRegion) {
+    ctx->err = "index array too large (more than 8192 right-hand sides)";
+    throw Fail{IOBM_E_UNSUPPORTED};
+  }
+  if (ctx->region_pending[region]) stream_sync(ctx);
+  T* p = (T*)((char*)ctx->arena_d + region * kRegion);
+  if (bytes) {
+    memcpy((char*)ctx->arena_h + region * kRegion, v.data(), bytes);
+    HIPCHK(hipMemcpyAsync(p, (char*)ctx->arena_h + region * kRegion, bytes, hipMemcpyHostToDevice,
+                          ctx->stream));
+    ctx->region_pending[region] = 1;
+  }
+  return p;
+}
+
+FFTPlan1D make_plan1d(int n) {
+  FFTPlan1D p;
+  p.n = n;
+  p.nstages = 0;
+  int m = n;
+  while (m % 4 == 0) { p.radix[p.nstages++] = 4; m /= 4; }
+  while (m % 2 == 0) { p.radix[p.nstages++] = 2; m /= 2; }
+  for (int f = 3; m > 1; f += 2)
+    while (m % f == 0) { p.radix[p.nstages++] = f; m /= f; }
+  return p;
+}
+
+bool plan_ok(const FFTPlan1D& p) {
+  if (p.nstages > IOBM_FFT_MAXSTAGES) return false;
+  for (int s = 0; s < p.nstages; ++s)
+    if (p.radix[s] > 31) return false;
+  return true;
+}
+
+// --------------------------------------------------------------- modes
+// Ensure the device mode table holds exactly the energies `E` (in order).
+void ensure_modes(iobm_ctx ctx, const std::vector<double>& E) {
+  if (E == ctx->modeE && ctx->modes_d) return;
+  const size_t n = (size_t)E.size() * ctx->g.nxy;
+  if (ctx->modes_cap < n) {
+    if (ctx->modes_d) (void)hipFree(ctx->modes_d);
+    ctx->modes_d = nullptr;
+    ctx->modes_cap = 0;
+    HIPCHK(hipMalloc(&ctx->modes_d, n * sizeof(ModeData)));
+    ctx->modes_cap = n;
+  }
+  double* Ed = upload(ctx, S_IDX, E);
+  HIPCHK(launch_modes(ctx, Ed, (int)E.size(), ctx->modes_d));
+  ctx->modes_h.resize(n);
+  HIPCHK(hipMemcpyAsync(ctx->modes_h.data(), ctx->modes_d, n * sizeof(ModeData), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  stream_sync(ctx);
+  ctx->modeE = E;
+  for (size_t e = 0; e < E.size(); ++e)
+    for (int m = 0; m < ctx->g.nxy; ++m) {
+      const ModeData& md = ctx->modes_h[e * ctx->g.nxy + m];
+      if (md.flags & MODE_THRESHOLD) {
+        ctx->modeE.clear();
+        char buf[160];
+        snprintf(buf, sizeof buf, "energy %.12g is at the threshold of lateral channel %d", E[e], m);
+        ctx->err = buf;
+        throw Fail{IOBM_E_AT_THRESHOLD};
+      }
+      if (md.flags & MODE_FAIL) {
+        ctx->modeE.clear();
+        char buf[160];
+        snprintf(buf, sizeof buf, "mode setup failed at energy %.12g, channel %d", E[e], m);
+        ctx->err = buf;
+        throw Fail{IOBM_E_DEVICE};
+      }
+    }
+}
+
+int neg_mode(const GridDev& g, int m) {
+  int ix = m % g.nx, iy = m / g.nx;
+  return ((g.ny - iy) % g.ny) * g.nx + (g.nx - ix) % g.nx;
+}
+
+// ------------------------------------------------------------ the solver
+struct Batch {
+  int n = 0;                 // right-hand sides
+  std::vector<int> e;        // energy index per rhs
+  std::vector<double> E;     // energy per rhs
+  std::vector<int> mode;     // lateral channel id (canonical member of the +-G pair)
+  std::vector<int> kind;     // 1 cos, 2 sin
+};
+
+struct Request {
+  std::vector<int> e, mode, c, s, sgn;
+};
+
+struct SolveOut {
+  std::vector<int> iters, refin, status;
+  std::vector<double> rel;
+};
+
+// Batched preconditioned COCG on A d = r for the rhs in `act` (type T), with
+// x accumulated in type TX.  Stops a rhs when |r|^2 <= stop2[rhs]; returns
+// iterations per rhs.
+template <typename T, typename TX>
+void cocg(iobm_ctx ctx, const iobm_solve_opts& o, int nb, const int* e_d, const double* E_d, cplx<TX>* x,
+          cplx<T>* r, std::vector<int> act, const std::vector<double>& stop2, std::vector<int>& iters,
+          int max_iter, std::vector<int>& breakdown) {
+  const long long vol = ctx->g.npts;
+  const size_t vb = (size_t)nb * vol * sizeof(cplx<T>);
+  cplx<T>* p = (cplx<T>*)scratch(ctx, S_P, vb);
+  cplx<T>* q = (cplx<T>*)scratch(ctx, S_Q, vb);
+  cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)scratch(ctx, S_Z, vb);
+  cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)scratch(ctx, S_PF, vb) : nullptr;
+  const int nblk = dot_blocks(ctx);
+  void* part = scratch(ctx, S_PART, (size_t)nb * nblk * 32);
+  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * (3 * sizeof(zd) + sizeof(double) + sizeof(int)) + 64);
+  zd* rho = (zd*)sc;
+  zd* alpha = rho + nb;
+  zd* beta = alpha + nb;
+  double* rn2 = (double*)(beta + nb);
+  int* flag = (int*)(rn2 + nb);
+  HIPCHK(hipMemsetAsync(flag, 0, nb * sizeof(int), ctx->stream));
+  if (ctx->kb.ncen > 0) (void)kb_scratch(ctx, kb_proj_bytes(ctx, nb));
+  const ModeData* modes = ctx->modes_d;
+  std::vector<double> rn2_h(nb);
+  std::vector<int> flag_h(nb);
+
+  auto precond = [&](int nact, const int* ad) {
+    if (o.precond == IOBM_PC_TRUNCATED_LAPLACIAN)
+      HIPCHK(launch_precond_laplacian<T>(ctx, o.alpha, r, z, nact, ad));
+    else if (o.precond == IOBM_PC_LATERAL_FFT)
+      HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nact, e_d, modes, ad));
+  };
+  // start: z = P r, p = z, rho = r^T z
+  int nact = (int)act.size();
+  if (nact == 0) return;
+  int* act_d = upload(ctx, S_IDX, act, 64 * 1024);
+  precond(nact, act_d);
+  HIPCHK((launch_convert<T, T>(ctx, z, p, nact, act_d)));
+  HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
+  HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 2, nact, act_d));
+  const int check = std::max(1, o.check_every);
+  int it = 0;
+  while (nact > 0) {
+    for (int k = 0; k < check; ++k) {
+      HIPCHK(launch_apply<T>(ctx, p, q, nact, E_d, e_d, modes, act_d));
+      HIPCHK(launch_dot<T>(ctx, p, q, nact, act_d, part));
+      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 0, nact, act_d));
+      HIPCHK((launch_update_xr<T, TX>(ctx, x, p, r, q, alpha, nact, act_d, part)));
+      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 3, nact, act_d));
+      if (k == check - 1) break;  // convergence test before the next direction
+      precond(nact, act_d);
+      HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
+      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 1, nact, act_d));
+      HIPCHK(launch_update_p<T>(ctx, p, z, beta, nact, act_d));
+    }
+    it += check;
+    HIPCHK(hipMemcpyAsync(rn2_h.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(flag_h.data(), flag, nb * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    std::vector<int> keep;
+    for (int rr : act) {
+      iters[rr] += check;
+      bool done = rn2_h[rr] <= stop2[rr] || !(rn2_h[rr] == rn2_h[rr]);
+      if (flag_h[rr]) {
+        breakdown[rr] = 1;
+        done = true;
+      }
+      if (iters[rr] >= max_iter) done = true;
+      if (!done) keep.push_back(rr);
+    }
+    if (keep.size() != act.size()) {
+      act = keep;
+      nact = (int)act.size();
+      if (nact == 0) break;
+      act_d = upload(ctx, S_IDX, act, 64 * 1024);
+    }
+    // next direction for the survivors
+    precond(nact, act_d);
+    HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
+    HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 1, nact, act_d));
+    HIPCHK(launch_update_p<T>(ctx, p, z, beta, nact, act_d));
+  }
+  (void)it;
+}
+
+// Solve A x = b for a batch (b, x complex128 on the device); fills stats.
+void solve_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const zd* b, zd* x, SolveOut& out) {
+  const int nb = B.n;
+  const long long vol = ctx->g.npts;
+  out.iters.assign(nb, 0);
+  out.refin.assign(nb, 0);
+  out.status.assign(nb, IOBM_OK);
+  out.rel.assign(nb, 0.0);
+  if (nb == 0) return;
+  int* e_d = upload(ctx, S_IDX, B.e, 0);
+  double* E_d = upload(ctx, S_IDX, B.E, 16 * 1024);
+  std::vector<int> all(nb);
+  for (int i = 0; i < nb; ++i) all[i] = i;
+  int* all_d = upload(ctx, S_IDX, all, 32 * 1024);
+  zd* rhi = (zd*)scratch(ctx, S_RHI, (size_t)nb * vol * sizeof(zd));
+  const int nblk = dot_blocks(ctx);
+  void* part = scratch(ctx, S_PART, (size_t)nb * nblk * 32);
+  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * (3 * sizeof(zd) + sizeof(double) + sizeof(int)) + 64);
+  double* rn2 = (double*)((zd*)sc + 3 * nb);
+  int* flag = (int*)(rn2 + nb);
+  zd* dummy = (zd*)sc;
+  std::vector<double> bn2(nb), rn2_h(nb), best(nb, 1e300);
+  std::vector<int> stall(nb, 0), brk(nb, 0);
+
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * vol * sizeof(zd), ctx->stream));
+  HIPCHK(launch_dot<double>(ctx, b, b, nb, all_d, part));
+  HIPCHK(launch_finish(ctx, dummy, dummy, dummy, rn2, flag, part, 3, nb, all_d));
+  HIPCHK(hipMemcpyAsync(bn2.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(rhi, b, (size_t)nb * vol * sizeof(zd), hipMemcpyDeviceToDevice, ctx->stream));
+  stream_sync(ctx);
+  rn2_h = bn2;
+  const double tol2 = o.tol * o.tol;
+  const bool lowp = o.precision == IOBM_C64_REFINED;
+  for (int outer = 0; outer < 64; ++outer) {
+    std::vector<int> act;
+    for (int i = 0; i < nb; ++i) {
+      out.rel[i] = bn2[i] > 0 ? sqrt(rn2_h[i] / bn2[i]) : 0.0;
+      if (bn2[i] == 0 || rn2_h[i] <= tol2 * bn2[i]) continue;
+      if (out.status[i] != IOBM_OK) continue;
+      if (out.iters[i] >= o.max_iter) {
+        out.status[i] = IOBM_E_NOT_CONVERGED;
+        continue;
+      }
+      if (rn2_h[i] < 0.25 * best[i]) {
+        best[i] = rn2_h[i];
+        stall[i] = 0;
+      } else if (++stall[i] >= 3) {
+        out.status[i] = brk[i] ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
+        continue;
+      }
+      act.push_back(i);
+    }
+    if (act.empty()) break;
+    if (outer > 0)
+      for (int i : act) out.refin[i] += 1;
+    // inner stopping threshold on |r_inner|^2
+    std::vector<double> stop2(nb, 0.0);
+    const double itol = lowp ? o.inner_tol : 0.0;
+    for (int i : act) stop2[i] = std::max(itol * itol * rn2_h[i], 0.25 * tol2 * bn2[i]);
+    std::vector<int> used(nb, 0);
+    std::vector<int> act_copy = act;
+    int* act_d = upload(ctx, S_IDX, act, 48 * 1024);
+    if (lowp) {
+      zf* r32 = (zf*)scratch(ctx, S_R, (size_t)nb * vol * sizeof(zf));
+      zf* d32 = (zf*)scratch(ctx, S_D, (size_t)nb * vol * sizeof(zf));
+      HIPCHK((launch_convert<float, double>(ctx, rhi, r32, (int)act.size(), act_d)));
+      HIPCHK((launch_convert<float, double>(ctx, nullptr, d32, (int)act.size(), act_d)));
+      cocg<float, float>(ctx, o, nb, e_d, E_d, d32, r32, act_copy, stop2, used, o.max_iter, brk);
+      act_d = upload(ctx, S_IDX, act, 48 * 1024);
+      HIPCHK(launch_accumulate<float>(ctx, x, d32, (int)act.size(), act_d));
+    } else {
+      zd* d64 = (zd*)scratch(ctx, S_D, (size_t)nb * vol * sizeof(zd));
+      zd* r64 = (zd*)scratch(ctx, S_R, (size_t)nb * vol * sizeof(zd));
+      HIPCHK((launch_convert<double, double>(ctx, rhi, r64, (int)act.size(), act_d)));
+      HIPCHK((launch_convert<double, double>(ctx, nullptr, d64, (int)act.size(), act_d)));
+      cocg<double, double>(ctx, o, nb, e_d, E_d, d64, r64, act_copy, stop2, used, o.max_iter, brk);
+      act_d = upload(ctx, S_IDX, act, 48 * 1024);
+      HIPCHK(launch_accumulate<double>(ctx, x, d64, (int)act.size(), act_d));
+    }
+    for (int i : act) out.iters[i] += used[i];
+    // true residual in FP64: r_hi = b - A x
+    HIPCHK(launch_apply<double>(ctx, x, rhi, (int)act.size(), E_d, e_d, ctx->modes_d, act_d));
+    HIPCHK(launch_residual<double>(ctx, b, rhi, (int)act.size(), act_d));
+    HIPCHK(launch_dot<double>(ctx, rhi, rhi, (int)act.size(), act_d, part));
+    HIPCHK(launch_finish(ctx, dummy, dummy, dummy, rn2, flag, part, 3, (int)act.size(), act_d));
+    HIPCHK(hipMemcpyAsync(rn2_h.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+  }
+  for (int i = 0; i < nb; ++i) {
+    out.rel[i] = bn2[i] > 0 ? sqrt(rn2_h[i] / bn2[i]) : 0.0;
+    if (out.status[i] == IOBM_OK && bn2[i] > 0 && rn2_h[i] > tol2 * bn2[i]) out.status[i] = IOBM_E_NOT_CONVERGED;
+  }
+}
+
+void validate_opts(iobm_ctx ctx, const iobm_solve_opts* o) {
+  if (!o) { ctx->err = "opts is NULL"; throw Fail{IOBM_E_INVALID_ARG}; }
+  if (o->precision != IOBM_C128 && o->precision != IOBM_C64_REFINED) {
+    ctx->err = "unknown precision"; throw Fail{IOBM_E_INVALID_ARG};
+  }
+  if (o->precond < IOBM_PC_NONE || o->precond > IOBM_PC_LATERAL_FFT) {
+    ctx->err = "unknown preconditioner"; throw Fail{IOBM_E_INVALID_ARG};
+  }
+  if (!(o->tol > 0 && o->tol < 1) || !(o->inner_tol > 0 && o->inner_tol < 1) || o->max_iter < 1 ||
+      (o->side != 0 && o->side != 1) || !(o->alpha > 0) || !isfinite(o->alpha)) {
+    ctx->err = "invalid solver option (tol, inner_tol in (0,1), max_iter >= 1, side 0/1, alpha > 0)";
+    throw Fail{IOBM_E_INVALID_ARG};
+  }
+}
+
+// Build the request list and the real-lateral-basis batch.
+void plan_requests(iobm_ctx ctx, int nE, const double* E, const int* ninc, const int* inc, Batch& B,
+                   Request& Q) {
+  const GridDev& g = ctx->g;
+  int pos = 0;
+  for (int e = 0; e < nE; ++e) {
+    std::vector<int> ids;
+    const ModeData* md = &ctx->modes_h[(size_t)e * g.nxy];
+    if (ninc[e] < 0) {
+      for (int m = 0; m < g.nxy; ++m)
+        if (md[m].flags & MODE_OPEN) ids.push_back(m);
+    } else {
+      for (int k = 0; k < ninc[e]; ++k) {
+        int m = inc[pos++];
+        if (m < 0 || m >= g.nxy || !(md[m].flags & MODE_OPEN)) {
+          char buf[128];
+          snprintf(buf, sizeof buf, "channel %d is not open at energy %.12g", m, E[e]);
+          ctx->err = buf;
+          throw Fail{IOBM_E_INVALID_ARG};
+        }
+        ids.push_back(m);
+      }
+    }
+    std::map<std::pair<int, int>, int> basis;  // (canonical mode, kind) -> rhs
+    auto get = [&](int m, int kind) {
+      auto key = std::make_pair(m, kind);
+      auto it = basis.find(key);
+      if (it != basis.end()) return it->second;
+      int id = B.n++;
+      B.e.push_back(e);
+      B.E.push_back(E[e]);
+      B.mode.push_back(m);
+      B.kind.push_back(kind);
+      basis[key] = id;
+      return id;
+    };
+    for (int m : ids) {
+      int nm = neg_mode(g, m);
+      int canon = std::min(m, nm);
+      Q.e.push_back(e);
+      Q.mode.push_back(m);
+      if (nm == m) {
+        Q.c.push_back(get(m, 1));
+        Q.s.push_back(-1);
+        Q.sgn.push_back(0);
+      } else {
+        Q.c.push_back(get(canon, 1));
+        Q.s.push_back(get(canon, 2));
+        Q.sgn.push_back(m == canon ? 1 : -1);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+double* kb_scratch(iobm_ctx c, size_t bytes) {
+  try {
+    return (double*)scratch(c, S_KB, bytes);
+  } catch (Fail&) {
+    return nullptr;
+  }
+}
+
+// ======================================================================= ABI
+extern "C" {
+
+void iobm_default_opts(iobm_solve_opts* o) {
+  if (!o) return;
+  o->precision = IOBM_C64_REFINED;
+  o->precond = IOBM_PC_LATERAL_FFT;
+  o->alpha = 1.8;
+  o->tol = 1e-10;
+  o->inner_tol = 1e-5;
+  o->max_iter = 50000;
+  o->side = 0;
+  o->check_every = 8;
+}
+
+const char* iobm_status_str(iobm_status s) {
+  switch (s) {
+    case IOBM_OK: return "ok";
+    case IOBM_E_INVALID_ARG: return "invalid argument";
+    case IOBM_E_BAD_STATE: return "bad state";
+    case IOBM_E_OOM: return "out of device memory";
+    case IOBM_E_DEVICE: return "device error";
+    case IOBM_E_NOT_CONVERGED: return "not converged";
+    case IOBM_E_BREAKDOWN: return "Krylov breakdown";
+    case IOBM_E_AT_THRESHOLD: return "energy at a channel threshold";
+    case IOBM_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* iobm_last_error(iobm_ctx ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
+  if (!g || !out) return IOBM_E_INVALID_ARG;
+  *out = nullptr;
+  if (g->nf < 1 || g->nf > 3 || g->nx < 2 || g->ny < 2 || g->nz < 2 * g->nf || !(g->hx > 0) ||
+      !(g->hy > 0) || !(g->hz > 0) || !isfinite(g->hx) || !isfinite(g->hy) || !isfinite(g->hz))
+    return IOBM_E_INVALID_ARG;
+  if ((long long)g->nx * g->ny > 4096) return IOBM_E_UNSUPPORTED;
+  iobm_ctx ctx = new iobm_ctx_s();
+  ctx->g.nx = g->nx; ctx->g.ny = g->ny; ctx->g.nz = g->nz; ctx->g.nf = g->nf;
+  ctx->g.nxy = g->nx * g->ny;
+  ctx->g.npts = (long long)ctx->g.nxy * g->nz;
+  ctx->g.hx = g->hx; ctx->g.hy = g->hy; ctx->g.hz = g->hz;
+  ctx->stream = (hipStream_t)stream;
+  // central second-derivative weights (h = 1), orders 2, 4, 6
+  static const double C[4][4] = {{0, 0, 0, 0},
+                                 {-2.0, 1.0, 0, 0},
+                                 {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0, 0},
+                                 {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0}};
+  for (int i = 0; i < 4; ++i) ctx->c[i] = C[g->nf][i];
+  ctx->plan.x = make_plan1d(g->nx);
+  ctx->plan.y = make_plan1d(g->ny);
+  if (!plan_ok(ctx->plan.x) || !plan_ok(ctx->plan.y)) {
+    delete ctx;
+    return IOBM_E_UNSUPPORTED;
+  }
+  try {
+    HIPCHK(hipGetDevice(&ctx->device));
+    std::vector<zd> tx(g->nx), ty(g->ny);
+    std::vector<zf> fx(g->nx), fy(g->ny);
+    for (int k = 0; k < g->nx; ++k) {
+      double a = -2.0 * M_PI * k / g->nx;
+      tx[k] = mk(cos(a), sin(a));
+      fx[k] = mk((float)cos(a), (float)sin(a));
+    }
+    for (int k = 0; k < g->ny; ++k) {
+      double a = -2.0 * M_PI * k / g->ny;
+      ty[k] = mk(cos(a), sin(a));
+      fy[k] = mk((float)cos(a), (float)sin(a));
+    }
+    HIPCHK(hipMalloc(&ctx->twx_d, g->nx * sizeof(zd)));
+    HIPCHK(hipMalloc(&ctx->twy_d, g->ny * sizeof(zd)));
+    HIPCHK(hipMalloc(&ctx->twx_f, g->nx * sizeof(zf)));
+    HIPCHK(hipMalloc(&ctx->twy_f, g->ny * sizeof(zf)));
+    HIPCHK(hipMemcpy(ctx->twx_d, tx.data(), g->nx * sizeof(zd), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->twy_d, ty.data(), g->ny * sizeof(zd), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->twx_f, fx.data(), g->nx * sizeof(zf), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->twy_f, fy.data(), g->ny * sizeof(zf), hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&ctx->arena_d, kRegion * kRegions));
+    HIPCHK(hipHostMalloc(&ctx->arena_h, kRegion * kRegions, hipHostMallocDefault));
+    HIPCHK(hipMalloc(&ctx->V_d, ctx->g.npts * sizeof(double)));
+    HIPCHK(hipMalloc(&ctx->V_f, ctx->g.npts * sizeof(float)));
+  } catch (Fail& f) {
+    iobm_destroy(ctx);
+    return f.s;
+  }
+  *out = ctx;
+  return IOBM_OK;
+}
+
+iobm_status iobm_destroy(iobm_ctx ctx) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& e : ctx->pool)
+    if (e.first) (void)hipFree(e.first);
+  void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->V_d, ctx->V_f, ctx->modes_d,
+                  ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.hD, ctx->arena_d};
+  if (ctx->arena_h) (void)hipHostFree(ctx->arena_h);
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete ctx;
+  return IOBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+__global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, long long n, int* bad) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double v = a[i];
+    if (!isfinite(v)) bad[0] = 1;
+    b[i] = (float)v;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+iobm_status iobm_set_potential(iobm_ctx ctx, const double* V, int32_t on_device) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (!V) return fail(ctx, IOBM_E_INVALID_ARG, "V is NULL");
+  try {
+    const long long n = ctx->g.npts;
+    HIPCHK(hipMemcpyAsync(ctx->V_d, V, n * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+    int* bad = (int*)((char*)ctx->arena_d + 63 * kRegion);
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+    hipLaunchKernelGGL(k_to_float, dim3(256), dim3(256), 0, ctx->stream, ctx->V_d, ctx->V_f, n, bad);
+    HIPCHK(hipGetLastError());
+    int bad_h = 0;
+    HIPCHK(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    if (bad_h) {
+      ctx->have_V = false;
+      return fail(ctx, IOBM_E_INVALID_ARG, "V contains a non-finite value");
+    }
+    ctx->have_V = true;
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_set_nonlocal(iobm_ctx ctx, int32_t ncen, int32_t rank, const int32_t* nsupport,
+                              const int64_t* support_idx, const double* beta, const double* D) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  KBData& kb = ctx->kb;
+  if (ncen < 0 || (ncen > 0 && (rank < 1 || rank > 8 || !nsupport || !support_idx || !beta || !D)))
+    return fail(ctx, IOBM_E_INVALID_ARG, "bad nonlocal arguments");
+  if (ncen * rank > 128) return fail(ctx, IOBM_E_UNSUPPORTED, "more than 128 projectors");
+  // validate
+  long long tot = 0;
+  for (int a = 0; a < ncen; ++a) {
+    if (nsupport[a] < 0) return fail(ctx, IOBM_E_INVALID_ARG, "negative support size");
+    tot += nsupport[a];
+  }
+  for (long long i = 0; i < tot; ++i)
+    if (support_idx[i] < 0 || support_idx[i] >= ctx->g.npts)
+      return fail(ctx, IOBM_E_INVALID_ARG, "support index out of range");
+  for (long long i = 0; i < tot * rank; ++i)
+    if (!isfinite(beta[i])) return fail(ctx, IOBM_E_INVALID_ARG, "non-finite projector value");
+  for (int a = 0; a < ncen; ++a)
+    for (int p = 0; p < rank; ++p)
+      for (int q = 0; q < rank; ++q) {
+        double x = D[(a * rank + p) * rank + q], y = D[(a * rank + q) * rank + p];
+        if (!isfinite(x)) return fail(ctx, IOBM_E_INVALID_ARG, "non-finite D");
+        if (fabs(x - y) > 1e-12 * (fabs(x) + fabs(y) + 1e-300))
+          return fail(ctx, IOBM_E_INVALID_ARG, "D must be symmetric (A must stay complex symmetric)");
+      }
+  // union of supports, dense projector matrix on it
+  std::map<long long, int> uidx;
+  {
+    long long off = 0;
+    for (int a = 0; a < ncen; ++a) {
+      for (int k = 0; k < nsupport[a]; ++k) {
+        long long v = support_idx[off + k];
+        if (!uidx.count(v)) {
+          int id = (int)uidx.size();
+          uidx[v] = id;
+        }
+      }
+      off += nsupport[a];
+    }
+  }
+  // order the union by voxel id for coalesced gathers
+  std::vector<int> uvox;
+  uvox.reserve(uidx.size());
+  {
+    int id = 0;
+    for (auto& kv : uidx) {
+      kv.second = id++;
+      uvox.push_back((int)kv.first);
+    }
+  }
+  const int nproj = ncen * rank;
+  const int npad = std::max(16, (nproj + 15) / 16 * 16);
+  const int nu = (int)uvox.size();
+  std::vector<double> Bm((size_t)nu * npad, 0.0);
+  {
+    long long off = 0, boff = 0;
+    for (int a = 0; a < ncen; ++a) {
+      for (int p = 0; p < rank; ++p)
+        for (int k = 0; k < nsupport[a]; ++k) {
+          int u = uidx[support_idx[off + k]];
+          Bm[(size_t)u * npad + a * rank + p] += beta[boff + (long long)p * nsupport[a] + k];
+        }
+      off += nsupport[a];
+      boff += (long long)rank * nsupport[a];
+    }
+  }
+  const double h3 = ctx->g.hx * ctx->g.hy * ctx->g.hz;
+  std::vector<double> hD((size_t)std::max(1, nproj * nproj), 0.0);
+  for (int a = 0; a < ncen; ++a)
+    for (int p = 0; p < rank; ++p)
+      for (int q = 0; q < rank; ++q)
+        hD[(size_t)(a * rank + p) * nproj + a * rank + q] = h3 * D[(a * rank + p) * rank + q];
+  std::vector<float> Bf(Bm.begin(), Bm.end());
+  try {
+    stream_sync(ctx);
+    void* old[] = {kb.uvox, kb.Bd, kb.Bf, kb.hD};
+    for (void* p : old)
+      if (p) (void)hipFree(p);
+    kb = KBData();
+    if (ncen == 0 || nu == 0) return IOBM_OK;
+    HIPCHK(hipMalloc(&kb.uvox, nu * sizeof(int)));
+    HIPCHK(hipMalloc(&kb.Bd, Bm.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&kb.Bf, Bf.size() * sizeof(float)));
+    HIPCHK(hipMalloc(&kb.hD, hD.size() * sizeof(double)));
+    HIPCHK(hipMemcpy(kb.uvox, uvox.data(), nu * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(kb.Bd, Bm.data(), Bm.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(kb.Bf, Bf.data(), Bf.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(kb.hD, hD.data(), hD.size() * sizeof(double), hipMemcpyHostToDevice));
+    kb.ncen = ncen;
+    kb.rank = rank;
+    kb.nproj = nproj;
+    kb.nproj_pad = npad;
+    kb.nu = nu;
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_channels(iobm_ctx ctx, double E, int32_t* nopen, int32_t* ids, double* kz, double* v) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (!nopen || !isfinite(E)) return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+  try {
+    ensure_modes(ctx, std::vector<double>{E});
+    int n = 0;
+    for (int m = 0; m < ctx->g.nxy; ++m) {
+      const ModeData& md = ctx->modes_h[m];
+      if (!(md.flags & MODE_OPEN)) continue;
+      if (ids) ids[n] = m;
+      if (kz) kz[n] = atan2(md.xp.im, md.xp.re) / ctx->g.hz;
+      if (v) v[n] = md.v;
+      ++n;
+    }
+    *nopen = n;
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_self_energy(iobm_ctx ctx, double E, double* sigma) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (!sigma || !isfinite(E)) return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+  try {
+    ensure_modes(ctx, std::vector<double>{E});
+    const int nf = ctx->g.nf;
+    for (int m = 0; m < ctx->g.nxy; ++m)
+      for (int i = 0; i < nf * nf; ++i) {
+        sigma[2 * ((size_t)m * nf * nf + i)] = ctx->modes_h[m].sig[i].re;
+        sigma[2 * ((size_t)m * nf * nf + i) + 1] = ctx->modes_h[m].sig[i].im;
+      }
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_apply(iobm_ctx ctx, double E, int32_t nrhs, const void* x, void* y, int32_t precision) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (nrhs < 0 || (nrhs > 0 && (!x || !y)) || !isfinite(E) ||
+      (precision != IOBM_C128 && precision != IOBM_C64_REFINED))
+    return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+  if (!ctx->have_V) return fail(ctx, IOBM_E_BAD_STATE, "iobm_set_potential has not been called");
+  if (x == y) return fail(ctx, IOBM_E_INVALID_ARG, "x and y must not overlap");
+  if (nrhs == 0) return IOBM_OK;
+  try {
+    ensure_modes(ctx, std::vector<double>{E});
+    std::vector<int> e(nrhs, 0);
+    std::vector<double> Ev(nrhs, E);
+    int* e_d = upload(ctx, S_IDX, e, 0);
+    double* E_d = upload(ctx, S_IDX, Ev, 32 * 1024);
+    if (ctx->kb.ncen > 0) (void)kb_scratch(ctx, kb_proj_bytes(ctx, nrhs));
+    if (precision == IOBM_C128)
+      HIPCHK(launch_apply<double>(ctx, (const zd*)x, (zd*)y, nrhs, E_d, e_d, ctx->modes_d, nullptr));
+    else
+      HIPCHK(launch_apply<float>(ctx, (const zf*)x, (zf*)y, nrhs, E_d, e_d, ctx->modes_d, nullptr));
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_precondition(iobm_ctx ctx, int32_t precond, double alpha, double E, int32_t nrhs,
+                              const void* r, void* z, int32_t precision) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (nrhs < 0 || (nrhs > 0 && (!r || !z)) || !isfinite(E) || !(alpha > 0) ||
+      (precision != IOBM_C128 && precision != IOBM_C64_REFINED) || precond < 0 || precond > 2)
+    return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+  if (r == z) return fail(ctx, IOBM_E_INVALID_ARG, "r and z must not overlap");
+  if (nrhs == 0) return IOBM_OK;
+  try {
+    const long long vol = ctx->g.npts;
+    if (precond == IOBM_PC_NONE) {
+      size_t es = precision == IOBM_C128 ? sizeof(zd) : sizeof(zf);
+      HIPCHK(hipMemcpyAsync(z, r, (size_t)nrhs * vol * es, hipMemcpyDeviceToDevice, ctx->stream));
+    } else if (precond == IOBM_PC_TRUNCATED_LAPLACIAN) {
+      if (precision == IOBM_C128)
+        HIPCHK(launch_precond_laplacian<double>(ctx, alpha, (const zd*)r, (zd*)z, nrhs, nullptr));
+      else
+        HIPCHK(launch_precond_laplacian<float>(ctx, alpha, (const zf*)r, (zf*)z, nrhs, nullptr));
+    } else {
+      ensure_modes(ctx, std::vector<double>{E});
+      std::vector<int> e(nrhs, 0);
+      int* e_d = upload(ctx, S_IDX, e, 0);
+      if (precision == IOBM_C128) {
+        zd* pf = (zd*)scratch(ctx, S_PF, (size_t)nrhs * vol * sizeof(zd));
+        HIPCHK(launch_precond_fft<double>(ctx, (const zd*)r, (zd*)z, pf, nrhs, e_d, ctx->modes_d, nullptr));
+      } else {
+        zf* pf = (zf*)scratch(ctx, S_PF, (size_t)nrhs * vol * sizeof(zf));
+        HIPCHK(launch_precond_fft<float>(ctx, (const zf*)r, (zf*)z, pf, nrhs, e_d, ctx->modes_d, nullptr));
+      }
+    }
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_rhs(iobm_ctx ctx, double E, int32_t n, const int32_t* ids, int32_t side, void* b) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!ids || !b)) || !isfinite(E) || (side != 0 && side != 1))
+    return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+  if (n == 0) return IOBM_OK;
+  try {
+    ensure_modes(ctx, std::vector<double>{E});
+    for (int k = 0; k < n; ++k)
+      if (ids[k] < 0 || ids[k] >= ctx->g.nxy || !(ctx->modes_h[ids[k]].flags & MODE_OPEN))
+        return fail(ctx, IOBM_E_INVALID_ARG, "channel not open");
+    std::vector<int> e(n, 0), m(ids, ids + n), kind(n, 0);
+    int* e_d = upload(ctx, S_IDX, e, 0);
+    int* m_d = upload(ctx, S_IDX, m, 16 * 1024);
+    int* k_d = upload(ctx, S_IDX, kind, 32 * 1024);
+    HIPCHK(launch_rhs(ctx, n, e_d, m_d, k_d, side, ctx->modes_d, (zd*)b));
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, const double* E,
+                       const int32_t* ninc, const int32_t* inc, void* psi, double* t, double* T, double* R,
+                       iobm_solve_stat* st) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  try {
+    validate_opts(ctx, opts);
+    if (nE < 0 || (nE > 0 && (!E || !ninc))) return fail(ctx, IOBM_E_INVALID_ARG, "bad energy list");
+    if (!ctx->have_V) return fail(ctx, IOBM_E_BAD_STATE, "iobm_set_potential has not been called");
+    int ninc_total = 0;
+    for (int e = 0; e < nE; ++e) {
+      if (!isfinite(E[e])) return fail(ctx, IOBM_E_INVALID_ARG, "non-finite energy");
+      if (ninc[e] > 0) ninc_total += ninc[e];
+    }
+    if (ninc_total > 0 && !inc) return fail(ctx, IOBM_E_INVALID_ARG, "inc is NULL");
+    if (nE == 0) return IOBM_OK;
+    const iobm_solve_opts& o = *opts;
+    ensure_modes(ctx, std::vector<double>(E, E + nE));
+    Batch B;
+    Request Q;
+    plan_requests(ctx, nE, E, ninc, inc, B, Q);
+    const int nb = B.n, nreq = (int)Q.e.size();
+    const long long vol = ctx->g.npts;
+    const int nxy = ctx->g.nxy;
+    zd* b = (zd*)scratch(ctx, S_B, (size_t)nb * vol * sizeof(zd));
+    zd* x = (zd*)scratch(ctx, S_XHI, (size_t)nb * vol * sizeof(zd));
+    {
+      int* e_d = upload(ctx, S_IDX, B.e, 0);
+      int* m_d = upload(ctx, S_IDX, B.mode, 16 * 1024);
+      int* k_d = upload(ctx, S_IDX, B.kind, 32 * 1024);
+      HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b));
+    }
+    SolveOut so;
+    solve_batch(ctx, o, B, b, x, so);
+    // readout of every basis solution, then combination into channels
+    zd* amp = (zd*)scratch(ctx, S_AMP, (size_t)(2 * nb + 2 * nreq) * nxy * sizeof(zd));
+    zd* amp_near = amp;
+    zd* amp_far = amp + (size_t)nb * nxy;
+    zd* t_out = amp + (size_t)2 * nb * nxy;
+    zd* r_out = t_out + (size_t)nreq * nxy;
+    double* TR = (double*)scratch(ctx, S_TR, (size_t)2 * nreq * sizeof(double) + 64);
+    int* e_d = upload(ctx, S_IDX, B.e, 0);
+    HIPCHK(launch_readout(ctx, nb, o.side, x, ctx->modes_d, e_d, amp_near, amp_far));
+    int* qe = upload(ctx, S_IDX, Q.e, 16 * 1024);
+    int* qm = upload(ctx, S_IDX, Q.mode, 24 * 1024);
+    int* qc = upload(ctx, S_IDX, Q.c, 32 * 1024);
+    int* qs = upload(ctx, S_IDX, Q.s, 40 * 1024);
+    int* qg = upload(ctx, S_IDX, Q.sgn, 48 * 1024);
+    HIPCHK(launch_combine(ctx, nreq, qe, qm, qc, qs, qg, ctx->modes_d, amp_near, amp_far, t_out, r_out, TR,
+                          TR + nreq));
+    if (psi) HIPCHK(launch_combine_psi<double>(ctx, nreq, x, (zd*)psi, qc, qs, qg));
+    std::vector<double> TRh(2 * nreq);
+    HIPCHK(hipMemcpyAsync(TRh.data(), TR, 2 * nreq * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<zd> th;
+    if (t) {
+      th.resize((size_t)nreq * nxy);
+      HIPCHK(hipMemcpyAsync(th.data(), t_out, th.size() * sizeof(zd), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    stream_sync(ctx);
+    if (T) for (int c = 0; c < nreq; ++c) T[c] = TRh[c];
+    if (R) for (int c = 0; c < nreq; ++c) R[c] = TRh[nreq + c];
+    if (t) {
+      // per energy: [nopen(E)][ninc_e]
+      size_t off = 0;
+      int c0 = 0;
+      for (int e = 0; e < nE; ++e) {
+        int c1 = c0;
+        while (c1 < nreq && Q.e[c1] == e) ++c1;
+        const ModeData* md = &ctx->modes_h[(size_t)e * nxy];
+        int row = 0;
+        for (int nu = 0; nu < nxy; ++nu) {
+          if (!(md[nu].flags & MODE_OPEN)) continue;
+          for (int c = c0; c < c1; ++c) {
+            zd v = th[(size_t)c * nxy + nu];
+            t[2 * (off + (size_t)row * (c1 - c0) + (c - c0))] = v.re;
+            t[2 * (off + (size_t)row * (c1 - c0) + (c - c0)) + 1] = v.im;
+          }
+          ++row;
+        }
+        off += (size_t)row * (c1 - c0);
+        c0 = c1;
+      }
+    }
+    iobm_status worst = IOBM_OK;
+    for (int c = 0; c < nreq; ++c) {
+      int ic = Q.c[c], is = Q.s[c];
+      int status = so.status[ic];
+      if (is >= 0 && so.status[is] != IOBM_OK) status = so.status[is];
+      if (status != IOBM_OK) worst = (iobm_status)status;
+      if (st) {
+        st[c].iters = so.iters[ic] + (is >= 0 ? so.iters[is] : 0);
+        st[c].refinements = so.refin[ic] + (is >= 0 ? so.refin[is] : 0);
+        st[c].status = status;
+        st[c].pad_ = 0;
+        st[c].rel_residual = std::max(so.rel[ic], is >= 0 ? so.rel[is] : 0.0);
+        st[c].flux_error = TRh[c] + TRh[nreq + c] - 1.0;
+      }
+    }
+    if (worst != IOBM_OK) {
+      ctx->err = "some right-hand sides did not converge";
+      return worst;
+    }
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+}  // extern "C"
+
+extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE,
+                                              const double* E, double* T_total, void* dT_dV) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  try {
+    validate_opts(ctx, opts);
+    if (nE < 1 || !E || !T_total || !dT_dV) return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+    if (!ctx->have_V) return fail(ctx, IOBM_E_BAD_STATE, "iobm_set_potential has not been called");
+    for (int e = 0; e < nE; ++e)
+      if (!isfinite(E[e])) return fail(ctx, IOBM_E_INVALID_ARG, "non-finite energy");
+    const iobm_solve_opts& o = *opts;
+    ensure_modes(ctx, std::vector<double>(E, E + nE));
+    std::vector<int> ninc(nE, -1);
+    Batch B;
+    Request Q;
+    plan_requests(ctx, nE, E, ninc.data(), nullptr, B, Q);
+    const int nb = B.n, nreq = (int)Q.e.size();
+    const long long vol = ctx->g.npts;
+    const int nxy = ctx->g.nxy;
+    *T_total = 0.0;
+    HIPCHK(hipMemsetAsync(dT_dV, 0, (size_t)vol * sizeof(double), ctx->stream));
+    if (nb == 0) {
+      stream_sync(ctx);
+      return IOBM_OK;
+    }
+    zd* b = (zd*)scratch(ctx, S_B, (size_t)nb * vol * sizeof(zd));
+    zd* u = (zd*)scratch(ctx, S_XHI, (size_t)nb * vol * sizeof(zd));
+    zd* w = (zd*)scratch(ctx, S_GRAD_U, (size_t)nb * vol * sizeof(zd));
+    // forward solves
+    {
+      int* e_d = upload(ctx, S_IDX, B.e, 0);
+      int* m_d = upload(ctx, S_IDX, B.mode, 16 * 1024);
+      int* k_d = upload(ctx, S_IDX, B.kind, 32 * 1024);
+      HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b));
+    }
+    SolveOut so;
+    solve_batch(ctx, o, B, b, u, so);
+    zd* amp = (zd*)scratch(ctx, S_AMP, (size_t)(2 * nb + 2 * nreq) * nxy * sizeof(zd));
+    zd* amp_near = amp;
+    zd* amp_far = amp + (size_t)nb * nxy;
+    zd* t_out = amp + (size_t)2 * nb * nxy;
+    zd* r_out = t_out + (size_t)nreq * nxy;
+    double* TR = (double*)scratch(ctx, S_TR, (size_t)2 * nreq * sizeof(double) + 64);
+    int* e_d = upload(ctx, S_IDX, B.e, 0);
+    HIPCHK(launch_readout(ctx, nb, o.side, u, ctx->modes_d, e_d, amp_near, amp_far));
+    int* qe = upload(ctx, S_IDX, Q.e, 16 * 1024);
+    int* qm = upload(ctx, S_IDX, Q.mode, 24 * 1024);
+    int* qc = upload(ctx, S_IDX, Q.c, 32 * 1024);
+    int* qs = upload(ctx, S_IDX, Q.s, 40 * 1024);
+    int* qg = upload(ctx, S_IDX, Q.sgn, 48 * 1024);
+    HIPCHK(launch_combine(ctx, nreq, qe, qm, qc, qs, qg, ctx->modes_d, amp_near, amp_far, t_out, r_out, TR,
+                          TR + nreq));
+    std::vector<double> TRh(2 * nreq);
+    HIPCHK(hipMemcpyAsync(TRh.data(), TR, 2 * nreq * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    double Ttot = 0;
+    for (int c = 0; c < nreq; ++c) Ttot += TRh[c];
+    // adjoint solves: A w_b = l_b in the same real lateral basis
+    {
+      int* e2 = upload(ctx, S_IDX, B.e, 0);
+      int* m2 = upload(ctx, S_IDX, B.mode, 8 * 1024);
+      int* k2 = upload(ctx, S_IDX, B.kind, 56 * 1024);
+      HIPCHK(launch_rhs_adjoint(ctx, nb, e2, m2, k2, o.side, ctx->modes_d, b));
+    }
+    SolveOut sa;
+    solve_batch(ctx, o, B, b, w, sa);
+    // D blocks per energy and the gradient contraction
+    std::vector<int> base(nE + 1, 0);
+    for (int k = 0; k < nb; ++k) base[B.e[k] + 1]++;
+    for (int e = 0; e < nE; ++e) base[e + 1] += base[e];
+    std::vector<long long> dbase(nE, 0);
+    long long dtot = 0;
+    int nmax = 0;
+    for (int e = 0; e < nE; ++e) {
+      int n = base[e + 1] - base[e];
+      dbase[e] = dtot;
+      dtot += (long long)n * n;
+      nmax = std::max(nmax, n);
+    }
+    std::vector<int> chan(2 * nb, -1);
+    std::vector<zd> pc(2 * nb, mk(0.0, 0.0)), qc2(2 * nb, mk(0.0, 0.0));
+    auto add = [&](int k, int c, zd p, zd q) {
+      int s = chan[2 * k] < 0 ? 0 : 1;
+      chan[2 * k + s] = c;
+      pc[2 * k + s] = p;
+      qc2[2 * k + s] = q;
+    };
+    for (int c = 0; c < nreq; ++c) {
+      add(Q.c[c], c, mk(1.0, 0.0), mk(1.0, 0.0));
+      if (Q.s[c] >= 0) {
+        double sg = (double)Q.sgn[c];
+        add(Q.s[c], c, mk(0.0, sg), mk(0.0, -sg));
+      }
+    }
+    zd* Dd = (zd*)scratch(ctx, S_GRAD_D, (size_t)std::max<long long>(1, dtot) * sizeof(zd));
+    int* base_d = upload(ctx, S_IDX, base, 64 * 1024);
+    long long* dbase_d = upload(ctx, S_IDX, dbase, 72 * 1024);
+    int* chan_d = upload(ctx, S_IDX, chan, 80 * 1024);
+    zd* pc_d = upload(ctx, S_IDX, pc, 96 * 1024);
+    zd* qc_d = upload(ctx, S_IDX, qc2, 160 * 1024);
+    int* qm2 = upload(ctx, S_IDX, Q.mode, 168 * 1024);
+    int* qe2 = upload(ctx, S_IDX, Q.e, 176 * 1024);
+    HIPCHK(launch_grad_D(ctx, nE, nmax, base_d, chan_d, pc_d, qc_d, qm2, qe2, ctx->modes_d, t_out, Dd, dbase_d));
+    HIPCHK(launch_grad(ctx, nE, base_d, dbase_d, Dd, u, w, (double*)dT_dV));
+    stream_sync(ctx);
+    *T_total = Ttot;
+    for (int k = 0; k < nb; ++k)
+      if (so.status[k] != IOBM_OK || sa.status[k] != IOBM_OK) {
+        ctx->err = "forward or adjoint solve did not converge";
+        return (iobm_status)(so.status[k] != IOBM_OK ? so.status[k] : sa.status[k]);
+      }
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}

@@ -1,0 +1,105 @@
+// Internal declarations of libiobm (not part of the ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "iobm.h"
+
+// Per (energy, lateral mode) electrode data, FP64.  Produced on the device
+// by the mode-setup kernel from the lead dispersion (Eqs. (12)-(15)
+// generalised to FD order 2*nf).  Plane index conventions: right-electrode
+// blocks act on planes nz-nf+i (i = 0..nf-1); the left electrode is the
+// mirror image.
+struct ModeData {
+  zd sig[9];   // Sigma_R block, row-major nf x nf (Sigma_L = reversed planes)
+  zd q[3];     // monic polynomial of the nf outgoing Bloch roots: x^nf + sum_k q_k x^k
+  zd fb[3];    // flat-wire Green's function filter numerator, d = 0..nf-1 (causal part)
+  zd fbb[3];   // same for the anti-causal part (distances >= 1)
+  zd lr[3];    // readout row: transmitted amplitude at plane nz-nf from planes nz-nf+m
+  zd ll[3];    // readout row: reflected amplitude at plane 0 from planes m
+  zd btil[3];  // right-hand side profile on planes 0..nf-1 (unit incident amplitude)
+  zd xp;       // propagating outgoing root exp(i k_z h_z) (0 if closed)
+  zd kin;      // reflected-basis projection of the incident wave itself
+  double eps;  // lateral kinetic energy
+  double v;    // group velocity of the propagating state (0 if closed)
+  int flags;   // bit 0 open, bit 1 at threshold, bit 2 root failure
+  int pad_;
+};
+
+enum { MODE_OPEN = 1, MODE_THRESHOLD = 2, MODE_FAIL = 4 };
+
+struct ModeArgs {
+  int nx, ny, nf, nE;
+  double hx, hy, hz;
+  double c[4];
+};
+__host__ __device__ void compute_mode(const ModeArgs& A, double E, int m, ModeData* out);
+
+struct KBData {
+  int ncen = 0, rank = 0, nproj = 0;
+  int nu = 0;             // voxels in the union of supports
+  int* uvox = nullptr;    // [nu] flat voxel ids (device)
+  double* Bd = nullptr;   // [nu][nproj_pad] projector values, zero where off-support
+  float* Bf = nullptr;
+  double* hD = nullptr;   // [nproj][nproj] block-diagonal h^3 D (device)
+  int nproj_pad = 0;      // nproj rounded up to the MFMA tile (multiple of 16)
+};
+
+// Device workspace pointers that grow with the number of right-hand sides.
+struct Work {
+  size_t bytes = 0;
+  void* base = nullptr;
+};
+
+struct iobm_ctx_s {
+  GridDev g;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  double c[4];     // central FD weights chat_0..chat_nf (h = 1)
+  FFTPlan2D plan;
+  zd* twx_d = nullptr;  // exp(-2 pi i k / nx), k < nx
+  zd* twy_d = nullptr;
+  zf* twx_f = nullptr;
+  zf* twy_f = nullptr;
+  double* V_d = nullptr;
+  float* V_f = nullptr;
+  bool have_V = false;
+  KBData kb;
+  // cached mode tables for the most recent energy list
+  std::vector<double> modeE;
+  ModeData* modes_d = nullptr;
+  std::vector<ModeData> modes_h;
+  size_t modes_cap = 0;
+  void* arena_d = nullptr;  // small index arrays (device) and their pinned host mirror
+  void* arena_h = nullptr;
+  unsigned char region_pending[64] = {0};
+  // pooled device scratch
+  std::vector<std::pair<void*, size_t>> pool;
+  std::string err;
+};
+
+// ---- launchers (ops.hip / modes.hip / kb.hip) -------------------------------
+struct RhsMap {        // device arrays describing a batch of right-hand sides
+  const int* energy;   // [nrhs] index into the mode table
+  const double* E;     // [nrhs] energy
+};
+
+hipError_t launch_modes(iobm_ctx c, const double* E_d, int nE, ModeData* out);
+
+template <typename T>
+hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
+                        const int* e_rhs, const ModeData* modes, const int* active);
+template <typename T>
+hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z,
+                                    int nrhs, const int* active);
+template <typename T>
+hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch,
+                              int nrhs, const int* e_rhs, const ModeData* modes,
+                              const int* active);
+template <typename T>
+hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, double* proj,
+                           const int* active);
+size_t kb_proj_bytes(iobm_ctx c, int nrhs);
+double* kb_scratch(iobm_ctx c, size_t bytes);  // context-owned scratch for the projector sums

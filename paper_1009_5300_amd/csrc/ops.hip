@@ -1,0 +1,831 @@
+// Volume kernels of libiobm: the IOBM operator, its two preconditioners,
+// right-hand sides, FP64-accumulated Krylov reductions, vector updates and
+// the scattering readout.
+//
+// Layout: a batch of right-hand sides is [rhs][z][y][x] interleaved complex
+// (complex64 or complex128), x fastest.  Kernels that work on a subset of
+// the batch take `active` (slot -> rhs id) and are launched over the slots.
+#include "internal.h"
+
+namespace {
+
+__device__ __forceinline__ int rhs_of(const int* active, int slot) {
+  return active ? active[slot] : slot;
+}
+
+template <typename T> struct Real;
+template <> struct Real<double> { static __device__ __forceinline__ double v(double x) { return x; } };
+template <> struct Real<float> { static __device__ __forceinline__ float v(double x) { return (float)x; } };
+
+template <typename T> __device__ __forceinline__ const T* potential(const double* Vd, const float* Vf);
+template <> __device__ __forceinline__ const double* potential<double>(const double* Vd, const float*) { return Vd; }
+template <> __device__ __forceinline__ const float* potential<float>(const double*, const float* Vf) { return Vf; }
+
+// ------------------------------------------------------------ stencil ---
+// y = (E - V) x - (H_kin) x on the truncated grid (Eqs. (1)-(4), (6)):
+//   A x = (E - V + e0) x + sum_{mu, n=1..nf} w_{mu,n} [x(r + n e_mu) + x(r - n e_mu)],
+//   e0 = (chat_0/2) sum_mu 1/h_mu^2,  w_{mu,n} = chat_n / (2 h_mu^2),
+// lateral neighbours wrap (kappa = 0), z neighbours outside 0..nz-1 dropped.
+// One block owns full lateral planes of one rhs over a chunk of planes.
+struct StencilArgs {
+  int nx, ny, nz, nf, nxy;
+  int zchunk, nchunks;
+  double e0;
+  double wx[4], wy[4], wz[4];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_apply(StencilArgs S, const cplx<T>* __restrict__ x,
+                                               cplx<T>* __restrict__ y, const T* __restrict__ V,
+                                               const double* __restrict__ E_rhs,
+                                               const int* __restrict__ active) {
+  const int slot = blockIdx.x / S.nchunks;
+  const int chunk = blockIdx.x - slot * S.nchunks;
+  const int rhs = rhs_of(active, slot);
+  const long long vol = (long long)S.nxy * S.nz;
+  const cplx<T>* xr = x + rhs * vol;
+  cplx<T>* yr = y + rhs * vol;
+  const T diag0 = Real<T>::v(E_rhs[rhs] + S.e0);
+  const int z0 = chunk * S.zchunk;
+  const int z1 = min(S.nz, z0 + S.zchunk);
+  T wx[4], wy[4], wz[4];
+#pragma unroll
+  for (int n = 1; n <= 3; ++n) { wx[n] = (T)S.wx[n]; wy[n] = (T)S.wy[n]; wz[n] = (T)S.wz[n]; }
+  for (int z = z0; z < z1; ++z) {
+    const cplx<T>* xp = xr + (long long)z * S.nxy;
+    for (int p = threadIdx.x; p < S.nxy; p += blockDim.x) {
+      const int j = p / S.nx;
+      const int i = p - j * S.nx;
+      const cplx<T> c0 = xp[p];
+      const T d = diag0 - V[(long long)z * S.nxy + p];
+      cplx<T> acc = d * c0;
+      for (int n = 1; n <= S.nf; ++n) {
+        int ip = i + n; if (ip >= S.nx) ip -= S.nx;
+        int im = i - n; if (im < 0) im += S.nx;
+        int jp = j + n; if (jp >= S.ny) jp -= S.ny;
+        int jm = j - n; if (jm < 0) jm += S.ny;
+        cplx<T> sx = xp[j * S.nx + ip] + xp[j * S.nx + im];
+        cplx<T> sy = xp[jp * S.nx + i] + xp[jm * S.nx + i];
+        acc = acc + wx[n] * sx + wy[n] * sy;
+        cplx<T> sz = mk<T>(0, 0);
+        if (z + n < S.nz) sz = sz + xp[(long long)n * S.nxy + p];
+        if (z - n >= 0) sz = sz + xp[-(long long)n * S.nxy + p];
+        acc = acc + wz[n] * sz;
+      }
+      yr[(long long)z * S.nxy + p] = acc;
+    }
+  }
+}
+
+// ----------------------------------------------------- electrode term ---
+// y[boundary planes] -= Sigma x[boundary planes], applied in lateral
+// momentum space (Eqs. (14)-(16)): FFT each of the nf planes, mix the planes
+// of every mode with its nf x nf block, inverse FFT, scale by 1/Nxy.
+// Block (slot, side); side 0 = left (planes 0..nf-1, reversed block),
+// side 1 = right (planes nz-nf..nz-1).
+template <typename T>
+__global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __restrict__ x,
+                           cplx<T>* __restrict__ y, const ModeData* __restrict__ modes,
+                           const int* __restrict__ e_rhs, const cplx<T>* __restrict__ twx,
+                           const cplx<T>* __restrict__ twy, const int* __restrict__ active) {
+  extern __shared__ char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int nxy = plan.x.n * plan.y.n;
+  const int slot = blockIdx.x >> 1;
+  const int side = blockIdx.x & 1;
+  const int rhs = rhs_of(active, slot);
+  const long long vol = (long long)nxy * nz;
+  const ModeData* md = modes + (long long)e_rhs[rhs] * nxy;
+  cplx<T>* P[4];
+  for (int k = 0; k <= nf; ++k) P[k] = buf + k * nxy;
+  const int pbase = side ? nz - nf : 0;
+  for (int k = 0; k < nf; ++k) {
+    const cplx<T>* src = x + rhs * vol + (long long)(pbase + k) * nxy;
+    for (int p = threadIdx.x; p < nxy; p += blockDim.x) P[k][p] = src[p];
+    __syncthreads();
+    cplx<T>* res = fft2d_lds(P[k], P[nf], plan, twx, twy, -1);
+    if (res != P[k]) { cplx<T>* t = P[k]; P[k] = P[nf]; P[nf] = t; }
+  }
+  // mode mixing; plane k of the block <-> boundary-plane index i:
+  // right: i = k;  left: i = nf-1-k with the reversed block, i.e. the same
+  // matrix indexed by (nf-1-k, nf-1-l).
+  const T inv = (T)(1.0 / nxy);
+  for (int m = threadIdx.x; m < nxy; m += blockDim.x) {
+    cplx<T> in[3], out[3];
+    for (int k = 0; k < nf; ++k) in[k] = P[k][m];
+    for (int k = 0; k < nf; ++k) {
+      cplx<T> s = mk<T>(0, 0);
+      const int ik = side ? k : nf - 1 - k;
+      for (int l = 0; l < nf; ++l) {
+        const int il = side ? l : nf - 1 - l;
+        s = s + cvt<T>(md[m].sig[ik * nf + il]) * in[l];
+      }
+      out[k] = inv * s;
+    }
+    for (int k = 0; k < nf; ++k) P[k][m] = out[k];
+  }
+  __syncthreads();
+  for (int k = 0; k < nf; ++k) {
+    cplx<T>* res = fft2d_lds(P[k], P[nf], plan, twx, twy, +1);
+    cplx<T>* dst = y + rhs * vol + (long long)(pbase + k) * nxy;
+    for (int p = threadIdx.x; p < nxy; p += blockDim.x) dst[p] = dst[p] - res[p];
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------- Eq. (17) preconditioner ---
+// z = C0 r + C1 sum over the six face neighbours, C0 = 1, C1 = exp(-alpha);
+// lateral neighbours wrap, z neighbours outside the region are zero.
+template <typename T>
+__global__ void __launch_bounds__(256) k_precond_lap(StencilArgs S, T c1, const cplx<T>* __restrict__ r,
+                                                     cplx<T>* __restrict__ z,
+                                                     const int* __restrict__ active) {
+  const int slot = blockIdx.x / S.nchunks;
+  const int chunk = blockIdx.x - slot * S.nchunks;
+  const int rhs = rhs_of(active, slot);
+  const long long vol = (long long)S.nxy * S.nz;
+  const cplx<T>* rr = r + rhs * vol;
+  cplx<T>* zr = z + rhs * vol;
+  const int z0 = chunk * S.zchunk;
+  const int z1 = min(S.nz, z0 + S.zchunk);
+  for (int k = z0; k < z1; ++k) {
+    const cplx<T>* rp = rr + (long long)k * S.nxy;
+    for (int p = threadIdx.x; p < S.nxy; p += blockDim.x) {
+      const int j = p / S.nx;
+      const int i = p - j * S.nx;
+      int ip = i + 1; if (ip >= S.nx) ip -= S.nx;
+      int im = i - 1; if (im < 0) im += S.nx;
+      int jp = j + 1; if (jp >= S.ny) jp -= S.ny;
+      int jm = j - 1; if (jm < 0) jm += S.ny;
+      cplx<T> s = rp[j * S.nx + ip] + rp[j * S.nx + im] + rp[jp * S.nx + i] + rp[jm * S.nx + i];
+      if (k + 1 < S.nz) s = s + rp[S.nxy + p];
+      if (k > 0) s = s + rp[-S.nxy + p];
+      zr[(long long)k * S.nxy + p] = rp[p] + c1 * s;
+    }
+  }
+}
+
+// ------------------------------------------ lateral-Fourier preconditioner ---
+// z = (E - H_0 - Sigma_L - Sigma_R)^-1 r, the exact inverse of the operator
+// of the flat (V = 0) wire: diagonal in the lateral modes (Eq. (16)); along z
+// each mode's inverse is the lead Green's function G(z - z'), applied as a
+// causal plus an anti-causal order-nf recursive filter (coefficients from
+// the mode setup).  One block per rhs sweeps the planes forward (FFT, causal
+// filter, store) and then backward (FFT of the next plane, anti-causal
+// filter, sum, inverse FFT, store).  Each thread owns MPT modes.
+template <typename T, int MPT>
+__global__ void k_precond_fft(FFTPlan2D plan, int nz, int nf, const cplx<T>* __restrict__ r,
+                              cplx<T>* __restrict__ zout, cplx<T>* __restrict__ fwd,
+                              const ModeData* __restrict__ modes, const int* __restrict__ e_rhs,
+                              const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
+                              const int* __restrict__ active) {
+  extern __shared__ char smem_raw[];
+  cplx<T>* bufA = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int nxy = plan.x.n * plan.y.n;
+  cplx<T>* bufB = bufA + nxy;
+  const int rhs = rhs_of(active, blockIdx.x);
+  const long long vol = (long long)nxy * nz;
+  const cplx<T>* rr = r + rhs * vol;
+  cplx<T>* zr = zout + rhs * vol;
+  cplx<T>* fr = fwd + rhs * vol;
+  const ModeData* md = modes + (long long)e_rhs[rhs] * nxy;
+  cplx<T> al[MPT][3], fb[MPT][3], fbb[MPT][3];
+  cplx<T> hf[MPT][3], hr[MPT][3];
+#pragma unroll
+  for (int u = 0; u < MPT; ++u) {
+    const int m = threadIdx.x + u * blockDim.x;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      al[u][k] = fb[u][k] = fbb[u][k] = hf[u][k] = hr[u][k] = mk<T>(0, 0);
+      if (m < nxy && k < nf) {
+        al[u][k] = -cvt<T>(md[m].q[nf - 1 - k]);  // alpha_{k+1} = -q_{nf-1-k}
+        fb[u][k] = cvt<T>(md[m].fb[k]);
+        fbb[u][k] = cvt<T>(md[m].fbb[k]);
+      }
+    }
+  }
+  // forward sweep: F(z) = sum_k alpha_k F(z-k) + sum_k fb_k r~(z-k)
+  for (int z = 0; z < nz; ++z) {
+    const cplx<T>* src = rr + (long long)z * nxy;
+    for (int p = threadIdx.x; p < nxy; p += blockDim.x) bufA[p] = src[p];
+    __syncthreads();
+    cplx<T>* res = fft2d_lds(bufA, bufB, plan, twx, twy, -1);
+#pragma unroll
+    for (int u = 0; u < MPT; ++u) {
+      const int m = threadIdx.x + u * blockDim.x;
+      if (m < nxy) {
+        // shift input history: hr[0] = r~(z), hr[k] = r~(z-k)
+        hr[u][2] = hr[u][1];
+        hr[u][1] = hr[u][0];
+        hr[u][0] = res[m];
+        cplx<T> F = mk<T>(0, 0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (k < nf) F = F + al[u][k] * hf[u][k] + fb[u][k] * hr[u][k];
+        hf[u][2] = hf[u][1];
+        hf[u][1] = hf[u][0];
+        hf[u][0] = F;
+        fr[(long long)z * nxy + m] = F;
+      }
+    }
+    __syncthreads();
+  }
+  // backward sweep: B(z) = sum_k alpha_k B(z+k) + sum_k fbb_k r~(z+1+k)
+#pragma unroll
+  for (int u = 0; u < MPT; ++u)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) hf[u][k] = hr[u][k] = mk<T>(0, 0);
+  const T inv = (T)(1.0 / nxy);
+  for (int z = nz - 1; z >= 0; --z) {
+    cplx<T>* res = nullptr;
+    if (z + 1 < nz) {
+      const cplx<T>* src = rr + (long long)(z + 1) * nxy;
+      for (int p = threadIdx.x; p < nxy; p += blockDim.x) bufA[p] = src[p];
+      __syncthreads();
+      res = fft2d_lds(bufA, bufB, plan, twx, twy, -1);
+    }
+#pragma unroll
+    for (int u = 0; u < MPT; ++u) {
+      const int m = threadIdx.x + u * blockDim.x;
+      cplx<T> val = mk<T>(0, 0);
+      if (m < nxy) {
+        hr[u][2] = hr[u][1];
+        hr[u][1] = hr[u][0];
+        hr[u][0] = res ? res[m] : mk<T>(0, 0);
+        cplx<T> B = mk<T>(0, 0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (k < nf) B = B + al[u][k] * hf[u][k] + fbb[u][k] * hr[u][k];
+        hf[u][2] = hf[u][1];
+        hf[u][1] = hf[u][0];
+        hf[u][0] = B;
+        val = inv * (B + fr[(long long)z * nxy + m]);
+      }
+      // stash for the inverse FFT (all threads finished reading res above
+      // only after the barrier, so write into the other buffer)
+      if (m < nxy) (res == bufA ? bufB : bufA)[m] = val;
+    }
+    __syncthreads();
+    cplx<T>* in = (res == bufA) ? bufB : bufA;
+    cplx<T>* other = (in == bufA) ? bufB : bufA;
+    cplx<T>* out = fft2d_lds(in, other, plan, twx, twy, +1);
+    cplx<T>* dst = zr + (long long)z * nxy;
+    for (int p = threadIdx.x; p < nxy; p += blockDim.x) dst[p] = out[p];
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------- right-hand side ---
+// b on the nf planes facing the source electrode (Eq. (6)):
+//   b(plane i from the source side, r) = btil_i * lat(r),
+// lat = exp(i G.r) (kind 0), cos(G.r) (kind 1) or sin(G.r) (kind 2).
+__device__ __forceinline__ double lateral_phase(int m, int nx, int ny, int p) {
+  const int ix = m % nx, iy = m / nx;
+  const int nux = ix < nx / 2 ? ix : ix - nx;
+  const int nuy = iy < ny / 2 ? iy : iy - ny;
+  const int j = p / nx, i = p - j * nx;
+  // reduce the integer phase first for accuracy
+  long long a = ((long long)nux * i) % nx;
+  long long b = ((long long)nuy * j) % ny;
+  return 2.0 * M_PI * ((double)a / nx + (double)b / ny);
+}
+
+__global__ void k_rhs(int nx, int ny, int nz, int nf, const int* __restrict__ e_rhs,
+                      const int* __restrict__ mode_rhs, const int* __restrict__ kind_rhs,
+                      int side, const ModeData* __restrict__ modes, zd* __restrict__ b) {
+  const int rhs = blockIdx.y;
+  const int nxy = nx * ny;
+  const long long vol = (long long)nxy * nz;
+  const int m = mode_rhs[rhs];
+  const int kind = kind_rhs[rhs];
+  if (m < 0 || m >= nxy) return;  // ids are validated on the host
+  const ModeData& md = modes[(long long)e_rhs[rhs] * nxy + m];
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < vol;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int z = (int)(idx / nxy);
+    const int p = (int)(idx - (long long)z * nxy);
+    const int i = side ? nz - 1 - z : z;
+    zd val = mk(0.0, 0.0);
+    if (i < nf) {
+      double ph = lateral_phase(m, nx, ny, p);
+      double s, c;
+      sincos(ph, &s, &c);
+      zd lat = kind == 0 ? mk(c, s) : (kind == 1 ? mk(c, 0.0) : mk(s, 0.0));
+      val = md.btil[i] * lat;
+    }
+    b[rhs * vol + idx] = val;
+  }
+}
+
+// ------------------------------------------------------- reductions ---
+// Per-rhs partial sums of the bilinear form a^T b (no conjugation, the COCG
+// inner product for the complex-symmetric A) and of |a|^2, accumulated in
+// FP64; one partial per block, combined in fixed order by k_finish.
+struct Partial {
+  double re, im, n2, pad;
+};
+
+template <typename T>
+__device__ __forceinline__ void block_reduce3(double& a, double& b, double& c) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+    c += __shfl_xor(c, off);
+  }
+  __shared__ double sh[3][16];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double ra = 0, rb = 0, rc = 0;
+    for (int i = 0; i < nw; ++i) { ra += sh[0][i]; rb += sh[1][i]; rc += sh[2][i]; }
+    a = ra; b = rb; c = rc;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dot(const cplx<T>* __restrict__ a, const cplx<T>* __restrict__ b,
+                                             long long vol, int nblk, Partial* __restrict__ part,
+                                             const int* __restrict__ active) {
+  const int slot = blockIdx.x / nblk;
+  const int blk = blockIdx.x - slot * nblk;
+  const int rhs = rhs_of(active, slot);
+  const cplx<T>* ar = a + rhs * vol;
+  const cplx<T>* br = b + rhs * vol;
+  const long long per = (vol + nblk - 1) / nblk;
+  const long long i0 = blk * per, i1 = min(vol, i0 + per);
+  double sre = 0, sim = 0, sn = 0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    cplx<T> u = ar[i], v = br[i];
+    double ur = u.re, ui = u.im, vr = v.re, vi = v.im;
+    sre += ur * vr - ui * vi;
+    sim += ur * vi + ui * vr;
+    sn += ur * ur + ui * ui;
+  }
+  block_reduce3<T>(sre, sim, sn);
+  if (threadIdx.x == 0) {
+    Partial P;
+    P.re = sre; P.im = sim; P.n2 = sn; P.pad = 0;
+    part[(long long)rhs * nblk + blk] = P;
+  }
+}
+
+// x += alpha p ; r -= alpha q ; partial |r|^2
+template <typename T, typename TX>
+__global__ void __launch_bounds__(256) k_update_xr(cplx<TX>* __restrict__ x, const cplx<T>* __restrict__ p,
+                                                   cplx<T>* __restrict__ r, const cplx<T>* __restrict__ q,
+                                                   const zd* __restrict__ alpha, long long vol, int nblk,
+                                                   Partial* __restrict__ part,
+                                                   const int* __restrict__ active) {
+  const int slot = blockIdx.x / nblk;
+  const int blk = blockIdx.x - slot * nblk;
+  const int rhs = rhs_of(active, slot);
+  const cplx<T> a = cvt<T>(alpha[rhs]);
+  const long long per = (vol + nblk - 1) / nblk;
+  const long long i0 = blk * per, i1 = min(vol, i0 + per);
+  const long long off = rhs * vol;
+  double sn = 0, d0 = 0, d1 = 0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    cplx<T> pv = p[off + i];
+    cplx<TX> xv = x[off + i];
+    cplx<T> ap = a * pv;
+    x[off + i] = mk<TX>(xv.re + (TX)ap.re, xv.im + (TX)ap.im);
+    cplx<T> rv = r[off + i] - a * q[off + i];
+    r[off + i] = rv;
+    sn += (double)rv.re * rv.re + (double)rv.im * rv.im;
+  }
+  block_reduce3<T>(sn, d0, d1);
+  if (threadIdx.x == 0) {
+    Partial P;
+    P.re = 0; P.im = 0; P.n2 = sn; P.pad = 0;
+    part[(long long)rhs * nblk + blk] = P;
+  }
+}
+
+// p = z + beta p
+template <typename T>
+__global__ void __launch_bounds__(256) k_update_p(cplx<T>* __restrict__ p, const cplx<T>* __restrict__ z,
+                                                  const zd* __restrict__ beta, long long vol,
+                                                  const int* __restrict__ active) {
+  const int rhs = rhs_of(active, blockIdx.y);
+  const cplx<T> b = cvt<T>(beta[rhs]);
+  const long long off = rhs * vol;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x)
+    p[off + i] = z[off + i] + b * p[off + i];
+}
+
+// Scalar steps of COCG, one thread per active rhs.  mode 0: alpha = rho / mu
+// (mu from the partials); mode 1: rho_new from the partials, beta =
+// rho_new / rho, rho = rho_new; mode 2: rho = partial sum (start);
+// every mode also records |.|^2 partial sums into rn2 when requested.
+struct Scal {
+  zd* rho;
+  zd* alpha;
+  zd* beta;
+  double* rn2;   // |r|^2 after the update
+  int* flag;     // breakdown flags
+};
+
+__global__ void k_finish(Scal S, const Partial* __restrict__ part, int nblk, int mode,
+                         const int* __restrict__ active, int nact) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nact) return;
+  const int rhs = rhs_of(active, slot);
+  double re = 0, im = 0, n2 = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const Partial P = part[(long long)rhs * nblk + b];
+    re += P.re;
+    im += P.im;
+    n2 += P.n2;
+  }
+  zd s = mk(re, im);
+  if (mode == 0) {  // mu = p^T q
+    zd rho = S.rho[rhs];
+    double d = re * re + im * im;
+    if (!(d > 0) || !isfinite(d)) {
+      S.alpha[rhs] = mk(0.0, 0.0);
+      S.flag[rhs] = 1;
+    } else {
+      S.alpha[rhs] = mk((rho.re * re + rho.im * im) / d, (rho.im * re - rho.re * im) / d);
+    }
+  } else if (mode == 1) {  // rho_new = r^T z
+    zd rho = S.rho[rhs];
+    double d = rho.re * rho.re + rho.im * rho.im;
+    if (!(d > 0) || !isfinite(re * re + im * im)) {
+      S.beta[rhs] = mk(0.0, 0.0);
+      S.flag[rhs] = 1;
+    } else {
+      S.beta[rhs] = mk((re * rho.re + im * rho.im) / d, (im * rho.re - re * rho.im) / d);
+    }
+    S.rho[rhs] = s;
+  } else if (mode == 2) {
+    S.rho[rhs] = s;
+  } else if (mode == 3) {
+    S.rn2[rhs] = n2;
+  }
+}
+
+// y = b - y  (b nonzero only where the rhs kernel wrote it; stored in full)
+template <typename T>
+__global__ void k_residual(const zd* __restrict__ b, cplx<T>* __restrict__ y, long long vol,
+                           const int* __restrict__ active) {
+  const int rhs = rhs_of(active, blockIdx.y);
+  const long long off = rhs * vol;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x) {
+    zd bv = b[off + i];
+    cplx<T> yv = y[off + i];
+    y[off + i] = mk<T>((T)bv.re - yv.re, (T)bv.im - yv.im);
+  }
+}
+
+// dst (complex64) = src (complex128); dst zeroed when src == nullptr
+template <typename TD, typename TS>
+__global__ void k_convert(const cplx<TS>* __restrict__ src, cplx<TD>* __restrict__ dst, long long vol,
+                          const int* __restrict__ active) {
+  const int rhs = rhs_of(active, blockIdx.y);
+  const long long off = rhs * vol;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[off + i] = src ? mk<TD>((TD)src[off + i].re, (TD)src[off + i].im) : mk<TD>(0, 0);
+}
+
+// x (complex128) += d (complex64 or complex128)
+template <typename T>
+__global__ void k_accumulate(zd* __restrict__ x, const cplx<T>* __restrict__ d, long long vol,
+                             const int* __restrict__ active) {
+  const int rhs = rhs_of(active, blockIdx.y);
+  const long long off = rhs * vol;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x) {
+    zd xv = x[off + i];
+    cplx<T> dv = d[off + i];
+    x[off + i] = mk(xv.re + (double)dv.re, xv.im + (double)dv.im);
+  }
+}
+
+// ------------------------------------------------------------- readout ---
+// Mode amplitudes at the two electrode faces (Eq. (7)): FFT of the nf planes
+// facing each electrode, then for every open mode the propagating component
+// of the outgoing expansion:  far side  a_far[nu] = sum_m lr_m psi~_nu(plane m from the far side),
+//                             near side a_near[nu] = sum_m ll_m psi~_nu(plane m from the near side).
+// Block (rhs, face); face 0 = near (source) side, 1 = far side.
+__global__ void k_readout(FFTPlan2D plan, int nz, int nf, int side, const zd* __restrict__ x,
+                          const ModeData* __restrict__ modes, const int* __restrict__ e_rhs,
+                          const zd* __restrict__ twx, const zd* __restrict__ twy,
+                          zd* __restrict__ amp_near, zd* __restrict__ amp_far) {
+  extern __shared__ char smem_raw[];
+  zd* buf = reinterpret_cast<zd*>(smem_raw);
+  const int nxy = plan.x.n * plan.y.n;
+  const int rhs = blockIdx.x >> 1;
+  const int face = blockIdx.x & 1;
+  const long long vol = (long long)nxy * nz;
+  const ModeData* md = modes + (long long)e_rhs[rhs] * nxy;
+  zd* P[4];
+  for (int k = 0; k <= nf; ++k) P[k] = buf + k * nxy;
+  // plane of index m (m = 0..nf-1) counted from the face: near face of a left
+  // incidence is plane m, far face is plane nz-nf+m; mirrored for side 1.
+  for (int k = 0; k < nf; ++k) {
+    int plane;
+    if (face == 1) plane = side == 0 ? nz - nf + k : nf - 1 - k;
+    else plane = side == 0 ? k : nz - 1 - k;
+    const zd* src = x + rhs * vol + (long long)plane * nxy;
+    for (int p = threadIdx.x; p < nxy; p += blockDim.x) P[k][p] = src[p];
+    __syncthreads();
+    zd* res = fft2d_lds(P[k], P[nf], plan, twx, twy, -1);
+    if (res != P[k]) { zd* t = P[k]; P[k] = P[nf]; P[nf] = t; }
+  }
+  const double inv = 1.0 / nxy;
+  zd* out = (face == 1 ? amp_far : amp_near) + (long long)rhs * nxy;
+  for (int m = threadIdx.x; m < nxy; m += blockDim.x) {
+    zd a = mk(0.0, 0.0);
+    if (md[m].flags & MODE_OPEN) {
+      for (int k = 0; k < nf; ++k) a = a + (face == 1 ? md[m].lr[k] : md[m].ll[k]) * P[k][m];
+      a = inv * a;
+    }
+    out[m] = a;
+  }
+}
+
+// Combine real-lateral-basis solutions into plane-wave channels and form
+// T and R (Landauer-Buttiker, Sec. III):  for request c with basis (ic, is, sgn):
+//   t[nu] = a_far[ic][nu] + i sgn a_far[is][nu]   (is < 0: no sine part)
+//   r[nu] = a_near[..] combined - delta_{nu,mu} kin_mu
+//   T = sum_nu (v_nu / v_mu) |t|^2,  R likewise.
+__global__ void k_combine(int nxy, const int* __restrict__ req_e, const int* __restrict__ req_mode,
+                          const int* __restrict__ req_c, const int* __restrict__ req_s,
+                          const int* __restrict__ req_sgn, const ModeData* __restrict__ modes,
+                          const zd* __restrict__ amp_near, const zd* __restrict__ amp_far,
+                          zd* __restrict__ t_out, zd* __restrict__ r_out, double* __restrict__ T,
+                          double* __restrict__ R) {
+  const int c = blockIdx.x;
+  const int e = req_e[c], mu = req_mode[c];
+  if (mu < 0 || mu >= nxy) return;  // ids are validated on the host
+  const int ic = req_c[c], is = req_s[c];
+  const double sg = (double)req_sgn[c];
+  const ModeData* md = modes + (long long)e * nxy;
+  const double vmu = md[mu].v;
+  double sT = 0, sR = 0, d2 = 0;
+  for (int nu = threadIdx.x; nu < nxy; nu += blockDim.x) {
+    zd tf = amp_far[(long long)ic * nxy + nu];
+    zd rn = amp_near[(long long)ic * nxy + nu];
+    if (is >= 0) {
+      zd tfs = amp_far[(long long)is * nxy + nu];
+      zd rns = amp_near[(long long)is * nxy + nu];
+      tf = tf + mk(-sg * tfs.im, sg * tfs.re);
+      rn = rn + mk(-sg * rns.im, sg * rns.re);
+    }
+    if (nu == mu) rn = rn - md[mu].kin;
+    t_out[(long long)c * nxy + nu] = tf;
+    r_out[(long long)c * nxy + nu] = rn;
+    if (md[nu].flags & MODE_OPEN) {
+      sT += md[nu].v / vmu * norm2(tf);
+      sR += md[nu].v / vmu * norm2(rn);
+    }
+  }
+  block_reduce3<double>(sT, sR, d2);
+  if (threadIdx.x == 0) {
+    T[c] = sT;
+    R[c] = sR;
+  }
+}
+
+// psi[c] = x[ic] + i sgn x[is]
+template <typename TO>
+__global__ void k_combine_psi(const zd* __restrict__ x, cplx<TO>* __restrict__ psi, long long vol,
+                              const int* __restrict__ req_c, const int* __restrict__ req_s,
+                              const int* __restrict__ req_sgn) {
+  const int c = blockIdx.y;
+  const int ic = req_c[c], is = req_s[c];
+  const double sg = (double)req_sgn[c];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x) {
+    zd v = x[(long long)ic * vol + i];
+    if (is >= 0) {
+      zd s = x[(long long)is * vol + i];
+      v = v + mk(-sg * s.im, sg * s.re);
+    }
+    psi[(long long)c * vol + i] = mk<TO>((TO)v.re, (TO)v.im);
+  }
+}
+
+}  // namespace
+
+// =================================================================== host ===
+static StencilArgs stencil_args(iobm_ctx c, int zchunk) {
+  StencilArgs S;
+  S.nx = c->g.nx; S.ny = c->g.ny; S.nz = c->g.nz; S.nf = c->g.nf; S.nxy = c->g.nxy;
+  S.zchunk = zchunk;
+  S.nchunks = (c->g.nz + zchunk - 1) / zchunk;
+  double ihx = 1.0 / (c->g.hx * c->g.hx), ihy = 1.0 / (c->g.hy * c->g.hy), ihz = 1.0 / (c->g.hz * c->g.hz);
+  S.e0 = 0.5 * c->c[0] * (ihx + ihy + ihz);
+  for (int n = 0; n < 4; ++n) {
+    double cn = n <= c->g.nf ? c->c[n] : 0.0;
+    S.wx[n] = 0.5 * cn * ihx;
+    S.wy[n] = 0.5 * cn * ihy;
+    S.wz[n] = 0.5 * cn * ihz;
+  }
+  return S;
+}
+
+template <typename T> static const cplx<T>* twx(iobm_ctx c);
+template <> const zd* twx<double>(iobm_ctx c) { return c->twx_d; }
+template <> const zf* twx<float>(iobm_ctx c) { return c->twx_f; }
+template <typename T> static const cplx<T>* twy(iobm_ctx c);
+template <> const zd* twy<double>(iobm_ctx c) { return c->twy_d; }
+template <> const zf* twy<float>(iobm_ctx c) { return c->twy_f; }
+template <typename T> static const T* Vptr(iobm_ctx c);
+template <> const double* Vptr<double>(iobm_ctx c) { return c->V_d; }
+template <> const float* Vptr<float>(iobm_ctx c) { return c->V_f; }
+
+static int fft_threads(int nxy) {
+  int t = 256;
+  while (t < nxy && t < 1024) t *= 2;
+  if (nxy < 256) t = ((nxy + 63) / 64) * 64;
+  return t;
+}
+
+template <typename T>
+hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
+                        const int* e_rhs, const ModeData* modes, const int* active) {
+  if (nrhs <= 0) return hipSuccess;
+  StencilArgs S = stencil_args(c, 16);
+  hipLaunchKernelGGL(k_apply<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, x, y, Vptr<T>(c),
+                     E_rhs, active);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_boundary<T>, dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan,
+                     c->g.nz, c->g.nf, x, y, modes, e_rhs, twx<T>(c), twy<T>(c), active);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (c->kb.ncen > 0) return launch_kb_apply<T>(c, x, y, nrhs, nullptr, active);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z, int nrhs,
+                                    const int* active) {
+  StencilArgs S = stencil_args(c, 16);
+  hipLaunchKernelGGL(k_precond_lap<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S,
+                     (T)exp(-alpha), r, z, active);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch, int nrhs,
+                              const int* e_rhs, const ModeData* modes, const int* active) {
+  const int nxy = c->g.nxy;
+  int mpt = 1;
+  while (nxy > 1024 * mpt) ++mpt;
+  if (mpt > 4) return hipErrorInvalidValue;
+  int threads = ((nxy + mpt - 1) / mpt + 63) / 64 * 64;
+  size_t sh = 2 * (size_t)nxy * sizeof(cplx<T>);
+#define IOBM_PF(M)                                                                                 \
+  hipLaunchKernelGGL((k_precond_fft<T, M>), dim3(nrhs), dim3(threads), sh, c->stream, c->plan,     \
+                     c->g.nz, c->g.nf, r, z, scratch, modes, e_rhs, twx<T>(c), twy<T>(c), active)
+  switch (mpt) {
+    case 1: IOBM_PF(1); break;
+    case 2: IOBM_PF(2); break;
+    case 3: IOBM_PF(3); break;
+    default: IOBM_PF(4); break;
+  }
+#undef IOBM_PF
+  return hipGetLastError();
+}
+
+template hipError_t launch_apply<double>(iobm_ctx, const zd*, zd*, int, const double*, const int*,
+                                         const ModeData*, const int*);
+template hipError_t launch_apply<float>(iobm_ctx, const zf*, zf*, int, const double*, const int*,
+                                        const ModeData*, const int*);
+template hipError_t launch_precond_laplacian<double>(iobm_ctx, double, const zd*, zd*, int, const int*);
+template hipError_t launch_precond_laplacian<float>(iobm_ctx, double, const zf*, zf*, int, const int*);
+template hipError_t launch_precond_fft<double>(iobm_ctx, const zd*, zd*, zd*, int, const int*,
+                                               const ModeData*, const int*);
+template hipError_t launch_precond_fft<float>(iobm_ctx, const zf*, zf*, zf*, int, const int*,
+                                              const ModeData*, const int*);
+
+// ---- small launchers used by the solver ------------------------------------
+static dim3 vol_grid(long long vol, int nrhs) {
+  long long b = (vol + 255) / 256;
+  if (b > 1024) b = 1024;
+  return dim3((unsigned)b, (unsigned)nrhs);
+}
+
+hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs,
+                      int side, const ModeData* modes, zd* b) {
+  long long vol = c->g.npts;
+  hipLaunchKernelGGL(k_rhs, vol_grid(vol, nrhs), dim3(256), 0, c->stream, c->g.nx, c->g.ny, c->g.nz, c->g.nf,
+                     e_rhs, mode_rhs, kind_rhs, side, modes, b);
+  return hipGetLastError();
+}
+
+int dot_blocks(iobm_ctx c) {
+  long long vol = c->g.npts;
+  long long b = vol / 8192;
+  if (b < 1) b = 1;
+  if (b > 64) b = 64;
+  return (int)b;
+}
+
+template <typename T>
+hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active,
+                      void* part) {
+  int nblk = dot_blocks(c);
+  hipLaunchKernelGGL(k_dot<T>, dim3(nact * nblk), dim3(256), 0, c->stream, a, b, c->g.npts, nblk,
+                     (Partial*)part, active);
+  return hipGetLastError();
+}
+
+template <typename T, typename TX>
+hipError_t launch_update_xr(iobm_ctx c, cplx<TX>* x, const cplx<T>* p, cplx<T>* r, const cplx<T>* q,
+                            const zd* alpha, int nact, const int* active, void* part) {
+  int nblk = dot_blocks(c);
+  hipLaunchKernelGGL((k_update_xr<T, TX>), dim3(nact * nblk), dim3(256), 0, c->stream, x, p, r, q, alpha,
+                     c->g.npts, nblk, (Partial*)part, active);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_update_p(iobm_ctx c, cplx<T>* p, const cplx<T>* z, const zd* beta, int nact,
+                           const int* active) {
+  hipLaunchKernelGGL(k_update_p<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, p, z, beta,
+                     c->g.npts, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const void* part,
+                         int mode, int nact, const int* active) {
+  Scal S;
+  S.rho = rho; S.alpha = alpha; S.beta = beta; S.rn2 = rn2; S.flag = flag;
+  hipLaunchKernelGGL(k_finish, dim3((nact + 127) / 128), dim3(128), 0, c->stream, S, (const Partial*)part,
+                     dot_blocks(c), mode, active, nact);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const int* active) {
+  hipLaunchKernelGGL(k_residual<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, b, y, c->g.npts,
+                     active);
+  return hipGetLastError();
+}
+
+template <typename TD, typename TS>
+hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int nact, const int* active) {
+  hipLaunchKernelGGL((k_convert<TD, TS>), vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, src, dst,
+                     c->g.npts, active);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_accumulate(iobm_ctx c, zd* x, const cplx<T>* d, int nact, const int* active) {
+  hipLaunchKernelGGL(k_accumulate<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, x, d, c->g.npts,
+                     active);
+  return hipGetLastError();
+}
+
+hipError_t launch_readout(iobm_ctx c, int nrhs, int side, const zd* x, const ModeData* modes,
+                          const int* e_rhs, zd* amp_near, zd* amp_far) {
+  size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(zd);
+  hipLaunchKernelGGL(k_readout, dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan, c->g.nz,
+                     c->g.nf, side, x, modes, e_rhs, c->twx_d, c->twy_d, amp_near, amp_far);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(iobm_ctx c, int nreq, const int* req_e, const int* req_mode, const int* req_c,
+                          const int* req_s, const int* req_sgn, const ModeData* modes, const zd* amp_near,
+                          const zd* amp_far, zd* t_out, zd* r_out, double* T, double* R) {
+  hipLaunchKernelGGL(k_combine, dim3(nreq), dim3(256), 0, c->stream, c->g.nxy, req_e, req_mode, req_c, req_s,
+                     req_sgn, modes, amp_near, amp_far, t_out, r_out, T, R);
+  return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_combine_psi(iobm_ctx c, int nreq, const zd* x, cplx<TO>* psi, const int* req_c,
+                              const int* req_s, const int* req_sgn) {
+  hipLaunchKernelGGL(k_combine_psi<TO>, vol_grid(c->g.npts, nreq), dim3(256), 0, c->stream, x, psi,
+                     c->g.npts, req_c, req_s, req_sgn);
+  return hipGetLastError();
+}
+
+template hipError_t launch_dot<double>(iobm_ctx, const zd*, const zd*, int, const int*, void*);
+template hipError_t launch_dot<float>(iobm_ctx, const zf*, const zf*, int, const int*, void*);
+template hipError_t launch_update_xr<double, double>(iobm_ctx, zd*, const zd*, zd*, const zd*, const zd*, int,
+                                                     const int*, void*);
+template hipError_t launch_update_xr<float, float>(iobm_ctx, zf*, const zf*, zf*, const zf*, const zd*, int,
+                                                   const int*, void*);
+template hipError_t launch_update_p<double>(iobm_ctx, zd*, const zd*, const zd*, int, const int*);
+template hipError_t launch_update_p<float>(iobm_ctx, zf*, const zf*, const zd*, int, const int*);
+template hipError_t launch_residual<double>(iobm_ctx, const zd*, zd*, int, const int*);
+template hipError_t launch_residual<float>(iobm_ctx, const zd*, zf*, int, const int*);
+template hipError_t launch_convert<float, double>(iobm_ctx, const zd*, zf*, int, const int*);
+template hipError_t launch_convert<double, double>(iobm_ctx, const zd*, zd*, int, const int*);
+template hipError_t launch_convert<float, float>(iobm_ctx, const zf*, zf*, int, const int*);
+template hipError_t launch_accumulate<float>(iobm_ctx, zd*, const zf*, int, const int*);
+template hipError_t launch_accumulate<double>(iobm_ctx, zd*, const zd*, int, const int*);
+template hipError_t launch_combine_psi<double>(iobm_ctx, int, const zd*, zd*, const int*, const int*,
+                                               const int*);
+template hipError_t launch_combine_psi<float>(iobm_ctx, int, const zd*, zf*, const int*, const int*,
+                                              const int*);

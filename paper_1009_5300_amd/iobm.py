@@ -1,0 +1,260 @@
+"""Python binding of libiobm (ctypes).  Argument marshalling only: every step
+of the scattering solve runs in the library's HIP kernels; PyTorch supplies
+device memory and the current HIP stream.  There is no CPU fallback: if the
+library is missing the import of this module fails.
+
+The functions mirror the C ABI in include/iobm.h (same names without the
+`iobm_` prefix on the Solver methods); see that header for units, layouts
+and error behaviour.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libiobm.so")
+
+C128, C64_REFINED = 0, 1
+PC_NONE, PC_TRUNCATED_LAPLACIAN, PC_LATERAL_FFT = 0, 1, 2
+STATUS = ["ok", "invalid argument", "bad state", "out of device memory", "device error",
+          "not converged", "Krylov breakdown", "energy at a channel threshold", "unsupported"]
+
+
+class IobmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS[status] if 0 <= status < len(STATUS) else status}: {msg}")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double), ("nf", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("alpha", C.c_double),
+                ("tol", C.c_double), ("inner_tol", C.c_double), ("max_iter", C.c_int32),
+                ("side", C.c_int32), ("check_every", C.c_int32)]
+
+
+class SolveStat(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("status", C.c_int32),
+                ("pad_", C.c_int32), ("rel_residual", C.c_double), ("flux_error", C.c_double)]
+
+
+EXPORTS = {
+    "iobm_default_opts": (None, [C.POINTER(SolveOpts)]),
+    "iobm_create": (C.c_int, [C.POINTER(Grid), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "iobm_set_potential": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "iobm_set_nonlocal": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
+    "iobm_channels": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_int32), C.c_void_p,
+                                C.c_void_p, C.c_void_p]),
+    "iobm_self_energy": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
+    "iobm_apply": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    "iobm_precondition": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                    C.c_void_p, C.c_void_p, C.c_int32]),
+    "iobm_rhs": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
+    "iobm_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p]),
+    "iobm_grad_transmission": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p,
+                                         C.POINTER(C.c_double), C.c_void_p]),
+    "iobm_destroy": (C.c_int, [C.c_void_p]),
+    "iobm_status_str": (C.c_char_p, [C.c_int]),
+    "iobm_last_error": (C.c_char_p, [C.c_void_p]),
+}
+
+
+def load(path: str = LIBPATH):
+    if not os.path.exists(path):
+        raise ImportError(f"libiobm is not built ({path} missing); run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().iobm_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a):
+    """Raw pointer of a torch tensor or numpy array (no copy)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Solver:
+    """One transition region (grid) on the current HIP device."""
+
+    def __init__(self, nx, ny, nz, h, nf, stream=None):
+        import torch
+        self.torch = torch
+        self.shape = (nz, ny, nx)
+        hx, hy, hz = (h, h, h) if np.isscalar(h) else h
+        self.grid = Grid(nx, ny, nz, hx, hy, hz, nf)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._ctx = C.c_void_p()
+        self._check(lib().iobm_create(C.byref(self.grid), C.c_void_p(stream), C.byref(self._ctx)), None)
+
+    # -- helpers
+    def _check(self, st, ctx="self"):
+        if st != 0:
+            msg = lib().iobm_last_error(self._ctx if ctx else None)
+            raise IobmError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().iobm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def npts(self):
+        return int(np.prod(self.shape))
+
+    def _dev(self, a, dtype):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(device="cuda", dtype=dtype).contiguous()
+        return t.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+    # -- ABI calls
+    def set_potential(self, V):
+        V = self._dev(V, self.torch.float64).reshape(-1)
+        assert V.numel() == self.npts
+        self._check(lib().iobm_set_potential(self._ctx, _ptr(V), 1))
+        self.torch.cuda.current_stream().synchronize()
+
+    def set_nonlocal(self, nl):
+        if nl is None:
+            self._check(lib().iobm_set_nonlocal(self._ctx, 0, 0, None, None, None, None))
+            return
+        rank = nl.beta[0].shape[0]
+        nsup = np.array([len(s) for s in nl.support], dtype=np.int32)
+        idx = np.ascontiguousarray(np.concatenate(nl.support).astype(np.int64))
+        # per-centre [rank][nsupport] blocks, concatenated
+        beta = np.ascontiguousarray(np.concatenate([np.asarray(b, float).ravel() for b in nl.beta]))
+        D = np.ascontiguousarray(np.stack([np.asarray(d, float) for d in nl.D]))
+        self._check(lib().iobm_set_nonlocal(self._ctx, len(nl.support), rank, _ptr(nsup), _ptr(idx),
+                                            _ptr(beta), _ptr(D)))
+
+    def channels(self, E):
+        n = C.c_int32()
+        cap = self.shape[1] * self.shape[2]
+        ids = np.zeros(cap, np.int32)
+        kz = np.zeros(cap)
+        v = np.zeros(cap)
+        self._check(lib().iobm_channels(self._ctx, float(E), C.byref(n), _ptr(ids), _ptr(kz), _ptr(v)))
+        k = n.value
+        return ids[:k].copy(), kz[:k].copy(), v[:k].copy()
+
+    def self_energy(self, E):
+        nf = self.grid.nf
+        s = np.zeros((self.shape[1] * self.shape[2], nf, nf, 2))
+        self._check(lib().iobm_self_energy(self._ctx, float(E), _ptr(s)))
+        return s[..., 0] + 1j * s[..., 1]
+
+    def apply(self, E, x, precision=C128):
+        t = self.torch
+        x = x.contiguous()
+        y = t.empty_like(x)
+        nrhs = x.numel() // self.npts
+        self._check(lib().iobm_apply(self._ctx, float(E), nrhs, _ptr(x), _ptr(y), precision))
+        return y
+
+    def precondition(self, kind, r, alpha=1.8, E=0.0, precision=C128):
+        r = r.contiguous()
+        z = self.torch.empty_like(r)
+        nrhs = r.numel() // self.npts
+        self._check(lib().iobm_precondition(self._ctx, kind, float(alpha), float(E), nrhs, _ptr(r),
+                                            _ptr(z), precision))
+        return z
+
+    def rhs(self, E, ids, side=0):
+        ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int32))
+        b = self.torch.empty((len(ids),) + self.shape, dtype=self.torch.complex128, device="cuda")
+        self._check(lib().iobm_rhs(self._ctx, float(E), len(ids), _ptr(ids), side, _ptr(b)))
+        return b
+
+    def solve(self, energies, channels=None, opts=None, want_psi=False, want_t=False):
+        """channels: None (every open channel at each energy) or a list with one
+        entry per energy (None = all open, else a list of channel ids)."""
+        energies = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+        nE = len(energies)
+        if channels is None:
+            channels = [None] * nE
+        ninc = np.array([-1 if c is None else len(c) for c in channels], dtype=np.int32)
+        inc = np.ascontiguousarray(np.concatenate(
+            [np.asarray(c, np.int32) for c in channels if c is not None] or [np.zeros(0, np.int32)]
+        ).astype(np.int32))
+        opened = [self.channels(E)[0] for E in energies]
+        counts = [len(opened[e]) if ninc[e] < 0 else ninc[e] for e in range(nE)]
+        nrhs = int(sum(counts))
+        T = np.zeros(nrhs)
+        R = np.zeros(nrhs)
+        st = (SolveStat * max(1, nrhs))()
+        psi = None
+        if want_psi:
+            psi = self.torch.empty((nrhs,) + self.shape, dtype=self.torch.complex128, device="cuda")
+        tlen = sum(len(opened[e]) * counts[e] for e in range(nE))
+        t = np.zeros((max(1, tlen), 2)) if want_t else None
+        o = opts or default_opts()
+        status = lib().iobm_solve(self._ctx, C.byref(o), nE, _ptr(energies), _ptr(ninc), _ptr(inc),
+                                  _ptr(psi), _ptr(t), _ptr(T), _ptr(R), st)
+        stats = [(s.iters, s.refinements, s.status, s.rel_residual, s.flux_error) for s in st[:nrhs]]
+        out = {"T": T, "R": R, "stats": stats, "psi": psi, "status": status,
+               "modes": [opened[e] if ninc[e] < 0 else np.asarray(channels[e]) for e in range(nE)],
+               "open": opened}
+        if want_t:
+            tm, off = [], 0
+            tc = t[:, 0] + 1j * t[:, 1]
+            for e in range(nE):
+                n = len(opened[e]) * counts[e]
+                tm.append(tc[off:off + n].reshape(len(opened[e]), counts[e]))
+                off += n
+            out["t"] = tm
+        if status not in (0,):
+            msg = lib().iobm_last_error(self._ctx)
+            out["error"] = msg.decode() if msg else ""
+            if status not in (5, 6):
+                raise IobmError(status, out["error"])
+        return out
+
+    def grad_transmission(self, energies, opts=None):
+        energies = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+        g = self.torch.empty(self.shape, dtype=self.torch.float64, device="cuda")
+        T = C.c_double()
+        o = opts or default_opts()
+        self._check(lib().iobm_grad_transmission(self._ctx, C.byref(o), len(energies), _ptr(energies),
+                                                 C.byref(T), _ptr(g)))
+        return T.value, g

@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every function declared in
+include/iobm.h; argument validation that happens before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "iobm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(iobm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1009_5300_amd import iobm
+    return iobm.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["iobm_create", "iobm_set_potential", "iobm_set_nonlocal", "iobm_channels",
+              "iobm_self_energy", "iobm_apply", "iobm_precondition", "iobm_rhs", "iobm_solve",
+              "iobm_grad_transmission", "iobm_destroy", "iobm_status_str", "iobm_last_error",
+              "iobm_default_opts"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_every_symbol():
+    from paper_1009_5300_amd import iobm
+    assert set(declared_functions()) == set(iobm.EXPORTS)
+
+
+def test_status_strings_and_default_opts(lib):
+    from paper_1009_5300_amd import iobm
+    assert lib.iobm_status_str(0) == b"ok"
+    assert lib.iobm_status_str(7) == b"energy at a channel threshold"
+    o = iobm.default_opts()
+    assert o.precision == iobm.C64_REFINED and o.precond == iobm.PC_LATERAL_FFT
+    assert o.tol == 1e-10 and abs(o.alpha - 1.8) < 1e-15 and o.max_iter == 50000
+
+
+@pytest.mark.parametrize("bad", [dict(nf=0), dict(nf=4), dict(nx=1), dict(nz=3), dict(hx=0.0),
+                                 dict(hy=-1.0), dict(hz=float("nan"))])
+def test_create_rejects_bad_grids_before_touching_the_device(lib, bad):
+    from paper_1009_5300_amd import iobm
+    kw = dict(nx=8, ny=8, nz=24, hx=0.4, hy=0.4, hz=0.4, nf=2)
+    kw.update(bad)
+    g = iobm.Grid(kw["nx"], kw["ny"], kw["nz"], kw["hx"], kw["hy"], kw["hz"], kw["nf"])
+    ctx = C.c_void_p()
+    assert lib.iobm_create(C.byref(g), None, C.byref(ctx)) == 1
+    assert not ctx.value
+
+
+def test_null_context_is_rejected(lib):
+    assert lib.iobm_destroy(None) == 1
+    assert lib.iobm_set_potential(None, None, 0) == 1

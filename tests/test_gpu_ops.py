@@ -1,0 +1,142 @@
+"""Parity of the individual HIP kernels (through the C ABI) with the CPU
+oracle, on seeded inputs: electrode mode setup, right-hand side, operator,
+both preconditioners.  Sizes span several blocks and ragged tails (lateral
+planes of 120 and 480 points, z chunks of 16 planes over 40)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import Grid, random_field, make
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [Grid(12, 10, 40, 0.4, 2), Grid(24, 20, 40, 0.45, 3), Grid(10, 12, 18, 0.6, 1)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _solver(g, V, nl=None):
+    from paper_1009_5300_amd import iobm
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s.set_potential(V)
+    if nl is not None:
+        s.set_nonlocal(nl)
+    return s
+
+
+def _V(g, seed):
+    return 0.2 * random_field(g.shape, seed, complex_=False)
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
+@pytest.mark.parametrize("E", [0.3, 1.7])
+def test_channels_and_self_energy(torch, g, E):
+    s = _solver(g, np.zeros(g.shape))
+    ids, kz, v = s.channels(E)
+    ref = O.open_channels(g, E)
+    assert list(ids) == list(ref)
+    for m, k in zip(ids, kz):
+        x = O.LeadMode(g, E, m).x_in
+        assert abs(k - np.angle(x) / g.h) < 1e-12
+    sig = s.self_energy(E)
+    for m in range(g.nx * g.ny):
+        S = O.LeadMode(g, E, m).sigma_right()
+        assert np.abs(sig[m] - S).max() <= 1e-12 * np.abs(S).max()
+
+
+def test_threshold_energy_is_rejected(torch):
+    from paper_1009_5300_amd import iobm
+    g = Grid(8, 8, 16, 0.5, 2)
+    s = _solver(g, np.zeros(g.shape))
+    with pytest.raises(iobm.IobmError) as e:
+        s.channels(O.lateral_energy(g, 1))
+    assert e.value.status == 7
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
+def test_rhs(torch, g):
+    E = 1.7
+    s = _solver(g, np.zeros(g.shape))
+    P = O.Problem(g, np.zeros(g.shape))
+    modes = O.open_channels(g, E)
+    for side, sname in ((0, "L"), (1, "R")):
+        b = s.rhs(E, modes, side).cpu().numpy()
+        for k, m in enumerate(modes):
+            ref = P.rhs(E, m, sname).reshape(g.shape)
+            assert np.abs(b[k] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
+@pytest.mark.parametrize("kb", [False, True])
+def test_apply_matches_oracle(torch, g, kb):
+    from paper_1009_5300_amd import iobm
+    from workloads.synth import _kb_projectors
+    V = _V(g, 11)
+    nl = None
+    if kb:
+        rng = np.random.default_rng(5)
+        L = g.nx * g.h
+        centres = [np.array([L / 2, L / 3, 0.3 * g.nz * g.h]), np.array([L / 3, L / 2, 0.6 * g.nz * g.h]),
+                   np.array([0.1, 0.2, 0.2])]  # last one straddles the periodic edge and plane 0
+        nl = _kb_projectors(g, centres, 1.0, 4, rng)
+    s = _solver(g, V, nl)
+    P = O.Problem(g, V, nl)
+    E = 0.9
+    x = random_field((3,) + g.shape, 21)
+    ref = P.apply(E, x.reshape(3, -1)).reshape(x.shape)
+    xt = torch.as_tensor(x, device="cuda")
+    y = s.apply(E, xt, iobm.C128).cpu().numpy()
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    y32 = s.apply(E, xt.to(torch.complex64), iobm.C64_REFINED).cpu().numpy()
+    assert np.abs(y32 - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
+def test_truncated_laplacian_preconditioner(torch, g):
+    from paper_1009_5300_amd import iobm
+    s = _solver(g, np.zeros(g.shape))
+    r = random_field((2,) + g.shape, 3)
+    for alpha in (1.8, 3.0):
+        ref = O.precond.truncated_laplacian(g, r, alpha)
+        z = s.precondition(iobm.PC_TRUNCATED_LAPLACIAN, torch.as_tensor(r, device="cuda"), alpha=alpha).cpu().numpy()
+        assert np.abs(z - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("g", GRIDS, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
+def test_lateral_fft_preconditioner_is_flat_wire_inverse(torch, g):
+    from paper_1009_5300_amd import iobm
+    s = _solver(g, np.zeros(g.shape))
+    E = 1.7
+    r = random_field((2,) + g.shape, 4)
+    ref = O.precond.flat_wire_inverse(g, E, r)
+    rt = torch.as_tensor(r, device="cuda")
+    z = s.precondition(iobm.PC_LATERAL_FFT, rt, E=E).cpu().numpy()
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+    z32 = s.precondition(iobm.PC_LATERAL_FFT, rt.to(torch.complex64), E=E, precision=iobm.C64_REFINED).cpu().numpy()
+    assert np.abs(z32 - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+def test_bad_arguments_return_status(torch):
+    from paper_1009_5300_amd import iobm
+    g = Grid(8, 8, 16, 0.5, 2)
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    with pytest.raises(iobm.IobmError) as e:  # solve before the potential is set
+        s.solve([0.3])
+    assert e.value.status == 2
+    V = np.zeros(g.shape)
+    V[3, 2, 1] = np.nan
+    with pytest.raises(iobm.IobmError) as e:
+        s.set_potential(V)
+    assert e.value.status == 1
+    s.set_potential(np.zeros(g.shape))
+    with pytest.raises(iobm.IobmError) as e:  # closed channel requested
+        s.solve([0.3], channels=[[5]])
+    assert e.value.status == 1
+    with pytest.raises(iobm.IobmError) as e:
+        s.solve([0.3], opts=iobm.default_opts(tol=0.0))
+    assert e.value.status == 1

@@ -47,7 +47,7 @@ def test_fd_order_of_accuracy(nf):
     assert abs(order - 2 * nf) < 0.3
 
 
-# ------------------------------------------------- Eqs. (11)-(15), (A8)
+# ------------------------------------- Eqs. (11)-(15) and the appendix
 def _chi(g, E, mode):
     """Eq. (13) with kappa = 0 (N_f = 1)."""
     nux = O.mode_numbers(g.nx)[mode % g.nx]
@@ -60,8 +60,8 @@ def _chi(g, E, mode):
 def _sigma_closed_form(g, E, mode):
     """Eq. (15): Sigma_nu = -exp(i k_z h) / (2 h^2), with k_z from Eq. (12)
     and the branch rule stated after Eq. (13); for chi > 1 (above the
-    discrete band top) the decaying root of x^2 + 2 chi x + 1 = 0 (Eq. (A8),
-    omega_1 omega_2 = 1) is taken."""
+    discrete band top) the decaying root of x^2 + 2 chi x + 1 = 0 (the
+    appendix's pole pair omega_1, omega_2 with omega_1 omega_2 = 1) is taken."""
     chi = _chi(g, E, mode)
     h = g.h
     if abs(chi) < 1:
