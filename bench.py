@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the IOBM scattering solve on one MI355X.
+
+Workload: the large cross-section wire (48 x 48 x 128 grid, h = 0.4 bohr,
+4th-order FD, jellium electrodes, seeded smooth random V of amplitude
+0.02 Ha), 16 energies with 45-57 open lateral channels each, 768
+scattering states per pass.  One step = one iobm_solve over the whole batch:
+mode setup, right-hand sides, batched complex64 COCG with the lateral-
+Fourier preconditioner and FP64 iterative refinement to ||r|| <= 1e-10 ||b||,
+readout of every transmission amplitude.  V and every work buffer are
+resident on the GPU before the timed region.
+
+Prints one JSON line: solves/s of the whole job, the roofline of the
+dominant kernel and of the stencil operator (HIP events on the solver's
+stream over the timed region), the plain FP64 single-right-hand-side COCG
+on a sample of channels (the comparison point, also the |Delta T| check),
+the paper's Eq. (17) preconditioner on one energy, and the CPU oracle timed
+on a bounded sample of the workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def _kernel_stats(s, cls, per_pass_streams):
+    n, ms, pass_bytes = s.profile_end(cls)
+    if n == 0:
+        return None
+    alg = per_pass_streams * pass_bytes  # algorithmic bytes over all launches
+    avg_ms = ms / n
+    achieved = alg / (ms * 1e-3) / 1e9
+    return {"launches": n, "avg_ms": avg_ms, "alg_bytes_per_launch": alg / n, "achieved_GBps": achieved}
+
+
+def cpu_baseline(seconds_hint=30.0):
+    """The oracle (sparse LU, FP64) on a bounded sample of the workload: the
+    same recipe (48 x 48 cross-section, same V statistics, first energy, all
+    its open channels) on a transition region shortened to 8 planes, the
+    largest the oracle factors in ~tens of seconds.  Returns solves/s."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle as O
+    from workloads import Grid, make
+
+    g = Grid(48, 48, 8, 0.4, 2)
+    w = make(4, g)
+    E = float(w.energies[0])
+    t0 = time.perf_counter()
+    P = O.Problem(g, w.V)
+    modes = O.open_channels(g, E)
+    lu = P.factor(E)
+    psi = P.solve(E, modes, lu=lu, check=False)
+    T = [P.currents(E, m, p)[0] for m, p in zip(modes, psi)]
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    assert np.all(np.isfinite(T))
+    return {"value": len(modes) / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"48x48x8 planes (workload recipe, z shortened from 128), E={E} Ha, "
+                      f"{len(modes)} channels, sparse LU + solves + readout in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip plain-CG and Eq. (17) samples")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the scattering states of different energies are "
+              "independent, and multi-GPU runs are not part of this build (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1009_5300_amd import iobm
+    from workloads import make
+
+    torch.cuda.set_device(0)
+    w = make(4)
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s.set_potential(w.V)
+    opts = iobm.default_opts()
+    for _ in range(args.warmup):
+        out = s.solve(w.energies, opts=opts)
+    torch.cuda.synchronize()
+
+    s.profile_begin([iobm.K_PRECOND_FFT, iobm.K_STENCIL, iobm.K_UPDATE, iobm.K_DOT, iobm.K_BOUNDARY])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = s.solve(w.energies, opts=opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nrhs = len(out["T"])
+    assert out["status"] == 0, out.get("error")
+    value = args.steps * nrhs / (t1 - t0)
+    stats = np.array(out["stats"], dtype=float)
+    # algorithmic streams per launch: stencil and preconditioner read one
+    # vector and write one; the update reads x, p, r, q and writes x, r; the
+    # reductions read two vectors
+    kern = {
+        "precond_fft": _kernel_stats(s, iobm.K_PRECOND_FFT, 2),
+        "stencil": _kernel_stats(s, iobm.K_STENCIL, 2),
+        "update": _kernel_stats(s, iobm.K_UPDATE, 6),
+        "dot": _kernel_stats(s, iobm.K_DOT, 2),
+        "boundary": _kernel_stats(s, iobm.K_BOUNDARY, 3),
+    }
+    s.profile_begin([])
+    dom_name = max((k for k in kern if kern[k]), key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    dom = kern[dom_name]
+    roofline = {"bound": "hbm", "achieved": round(dom["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(dom["achieved_GBps"] / HBM_PEAK_GBPS, 4),
+                "traffic": None, "kernel": dom_name,
+                "avg_launch_ms": round(dom["avg_ms"], 4),
+                "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
+    st = kern["stencil"]
+    stencil = {"achieved": round(st["achieved_GBps"], 1), "unit": "GB/s",
+               "frac": round(st["achieved_GBps"] / HBM_PEAK_GBPS, 4), "avg_launch_ms": round(st["avg_ms"], 4),
+               "alg_bytes_per_launch": st["alg_bytes_per_launch"]}
+
+    result = {
+        "metric": "scattering solves/sec + stencil HBM GB/s at |dT|<=1e-6 vs plain FP64 CG",
+        "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * (t1 - t0) / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": "wide 48x48x128 h=0.4 4th-order FD, 16 energies, 768 scattering states",
+                   "precision": "complex64 COCG, FP64 reductions and refinement to 1e-10",
+                   "preconditioner": "lateral-Fourier (flat-wire inverse)"},
+        "roofline": roofline,
+        "stencil": stencil,
+        "kernels": {k: ({kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()} if v else None)
+                    for k, v in kern.items()},
+        "solve_stats": {"iters_mean": float(stats[:, 0].mean()), "iters_max": int(stats[:, 0].max()),
+                        "refinements_mean": float(stats[:, 1].mean()),
+                        "max_rel_residual": float(stats[:, 3].max()),
+                        "max_flux_error": float(np.abs(stats[:, 4]).max())},
+    }
+
+    if not args.no_extras:
+        # plain FP64 single-right-hand-side COCG (no preconditioner) on a sample
+        # of channels: the comparison point of the metric and the |dT| check
+        plain = iobm.default_opts(precision=iobm.C128, precond=iobm.PC_NONE, check_every=32)
+        Tb = {}
+        k = 0
+        for e, E in enumerate(w.energies):
+            for m in out["modes"][e]:
+                Tb[(e, int(m))] = out["T"][k]
+                k += 1
+        sample = [(0, int(out["modes"][0][0])), (len(w.energies) - 1, int(out["modes"][-1][0]))]
+        dts, iters, dT = [], [], []
+        for e, m in sample:
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            o1 = s.solve([w.energies[e]], channels=[[m]], opts=plain)
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - a)
+            iters.append(o1["stats"][0][0])
+            dT.append(abs(o1["T"][0] - Tb[(e, m)]))
+        result["plain_fp64_cg"] = {"value": round(len(sample) / sum(dts), 4), "unit": "solves/s",
+                                   "sample": f"{len(sample)} channels (lowest channel at the first and "
+                                             f"last energy), one complex128 COCG solve each, no preconditioner",
+                                   "iters": iters, "speedup_of_value": round(value / (len(sample) / sum(dts)), 1)}
+        result["max_dT_vs_plain_fp64_cg"] = float(max(dT))
+        # the paper's Eq. (17) preconditioner, batched complex64 + refinement, one energy
+        e17 = iobm.default_opts(precond=iobm.PC_TRUNCATED_LAPLACIAN, check_every=32)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        o2 = s.solve([w.energies[0]], opts=e17)
+        torch.cuda.synchronize()
+        b = time.perf_counter() - a
+        result["paper_pcg_eq17"] = {"value": round(len(o2["T"]) / b, 3), "unit": "solves/s",
+                                    "sample": f"first energy, {len(o2['T'])} channels, alpha=1.8",
+                                    "iters_mean": float(np.mean([x[0] for x in o2["stats"]])),
+                                    "max_dT_vs_value": float(np.abs(o2["T"] - out["T"][:len(o2["T"])]).max())}
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline()
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,7 +198,25 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
 iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE,
                                    const double* E, double* T_total, void* dT_dV);
 
-/* Number of open channels needed to size outputs (same as iobm_channels). */
+/* Benchmark hook (not part of the method): time the launches of selected
+ * kernel classes with HIP events recorded on the context stream around each
+ * launch.  iobm_profile_begin clears the record and selects the classes
+ * (bit mask of 1 << IOBM_K_*; 0 switches timing off).  iobm_profile_end
+ * synchronises the stream and returns, for one class, the number of timed
+ * launches, their summed duration (ms) and the bytes of one pass over the
+ * vectors they processed (right-hand sides x points x element size); the
+ * record is kept until the next iobm_profile_begin. */
+enum { IOBM_K_STENCIL = 1,      /* FD stencil + (E - V) diagonal */
+       IOBM_K_BOUNDARY = 2,     /* FFT-applied electrode self-energy */
+       IOBM_K_PRECOND_FFT = 3,  /* lateral-Fourier preconditioner */
+       IOBM_K_PRECOND_LAP = 4,  /* Eq. (17) preconditioner */
+       IOBM_K_NONLOCAL = 5,     /* nonlocal projector contraction (MFMA) */
+       IOBM_K_DOT = 6,          /* bilinear / norm reductions */
+       IOBM_K_UPDATE = 7 };     /* x, r update with fused |r|^2 */
+iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask);
+iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
+                             double* pass_bytes);
+
 iobm_status iobm_destroy(iobm_ctx ctx);
 const char* iobm_status_str(iobm_status s);
 const char* iobm_last_error(iobm_ctx ctx);

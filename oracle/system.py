@@ -144,10 +144,11 @@ class Problem:
     def matrix(self, E):
         """Sparse A(E) (bordered by the nonlocal projectors when present)."""
         g = self.g
-        A = (E * sp.identity(g.npts, format="csr") - self.H_loc).astype(complex).tolil()
+        A = (E * sp.identity(g.npts, format="csr") - self.H_loc).astype(complex)
         for side in ("L", "R"):
             s = self.boundary_slice(side)
-            A[s, s] = A[s, s] - self.sigma(E, side)
+            S = sp.coo_matrix(self.sigma(E, side))
+            A = A - sp.csr_matrix((S.data, (S.row + s.start, S.col + s.start)), shape=A.shape)
         A = A.tocsc()
         if self.B is not None:
             C = sp.csc_matrix(np.linalg.inv(self.hD))

@@ -171,8 +171,8 @@ bool plan_ok(const FFTPlan1D& p) {
 
 // --------------------------------------------------------------- modes
 // Ensure the device mode table holds exactly the energies `E` (in order).
-void ensure_modes(iobm_ctx ctx, const std::vector<double>& E) {
-  if (E == ctx->modeE && ctx->modes_d) return;
+void ensure_modes(iobm_ctx ctx, const std::vector<double>& E, bool force = false) {
+  if (!force && E == ctx->modeE && ctx->modes_d) return;
   const size_t n = (size_t)E.size() * ctx->g.nxy;
   if (ctx->modes_cap < n) {
     if (ctx->modes_d) (void)hipFree(ctx->modes_d);
@@ -482,6 +482,30 @@ void plan_requests(iobm_ctx ctx, int nE, const double* E, const int* ninc, const
 
 }  // namespace
 
+void prof_start(iobm_ctx c, int cls) {
+  if (!(c->prof_mask & (1 << cls))) return;
+  if (2 * c->prof_used + 2 > c->prof_ev.size()) {
+    for (int k = 0; k < 128; ++k) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) return;
+      c->prof_ev.push_back(ev);
+    }
+  }
+  (void)hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream);
+}
+
+void prof_stop(iobm_ctx c, int cls, double bytes) {
+  if (!(c->prof_mask & (1 << cls)) || 2 * c->prof_used + 2 > c->prof_ev.size()) return;
+  (void)hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream);
+  if (c->prof_cls.size() <= c->prof_used) {
+    c->prof_cls.resize(c->prof_used + 1);
+    c->prof_bytes.resize(c->prof_used + 1);
+  }
+  c->prof_cls[c->prof_used] = cls;
+  c->prof_bytes[c->prof_used] = bytes;
+  c->prof_used += 1;
+}
+
 double* kb_scratch(iobm_ctx c, size_t bytes) {
   try {
     return (double*)scratch(c, S_KB, bytes);
@@ -581,8 +605,38 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
   return IOBM_OK;
 }
 
+iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_UPDATE + 1)))
+    return fail(ctx, IOBM_E_INVALID_ARG, "bad kernel class mask");
+  ctx->prof_mask = class_mask;
+  ctx->prof_used = 0;
+  return IOBM_OK;
+}
+
+iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
+                             double* pass_bytes) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, IOBM_E_DEVICE, hipGetErrorString(e));
+  double ms = 0, bytes = 0;
+  int n = 0;
+  for (size_t k = 0; k < ctx->prof_used; ++k) {
+    if (ctx->prof_cls[k] != kernel_class) continue;
+    float t = 0;
+    if (hipEventElapsedTime(&t, ctx->prof_ev[2 * k], ctx->prof_ev[2 * k + 1]) == hipSuccess) ms += t;
+    bytes += ctx->prof_bytes[k];
+    ++n;
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
+  if (pass_bytes) *pass_bytes = bytes;
+  return IOBM_OK;
+}
+
 iobm_status iobm_destroy(iobm_ctx ctx) {
   if (!ctx) return IOBM_E_INVALID_ARG;
+  for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   for (auto& e : ctx->pool)
@@ -871,7 +925,7 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
     if (ninc_total > 0 && !inc) return fail(ctx, IOBM_E_INVALID_ARG, "inc is NULL");
     if (nE == 0) return IOBM_OK;
     const iobm_solve_opts& o = *opts;
-    ensure_modes(ctx, std::vector<double>(E, E + nE));
+    ensure_modes(ctx, std::vector<double>(E, E + nE), true);
     Batch B;
     Request Q;
     plan_requests(ctx, nE, E, ninc, inc, B, Q);
@@ -974,7 +1028,7 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
     for (int e = 0; e < nE; ++e)
       if (!isfinite(E[e])) return fail(ctx, IOBM_E_INVALID_ARG, "non-finite energy");
     const iobm_solve_opts& o = *opts;
-    ensure_modes(ctx, std::vector<double>(E, E + nE));
+    ensure_modes(ctx, std::vector<double>(E, E + nE), true);
     std::vector<int> ninc(nE, -1);
     Batch B;
     Request Q;

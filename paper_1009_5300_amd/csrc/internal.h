@@ -75,10 +75,20 @@ struct iobm_ctx_s {
   void* arena_d = nullptr;  // small index arrays (device) and their pinned host mirror
   void* arena_h = nullptr;
   unsigned char region_pending[64] = {0};
+  // kernel timing hook
+  int prof_mask = 0;
+  std::vector<hipEvent_t> prof_ev;  // start/stop pairs
+  std::vector<int> prof_cls;        // class of each pair
+  std::vector<double> prof_bytes;   // pass bytes of each pair
+  size_t prof_used = 0;             // pairs recorded
   // pooled device scratch
   std::vector<std::pair<void*, size_t>> pool;
   std::string err;
 };
+
+// ---- kernel timing hook (api.hip) -------------------------------------------
+void prof_start(iobm_ctx c, int cls);
+void prof_stop(iobm_ctx c, int cls, double units);
 
 // ---- launchers (ops.hip / modes.hip / kb.hip) -------------------------------
 struct RhsMap {        // device arrays describing a batch of right-hand sides

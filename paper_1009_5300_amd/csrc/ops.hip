@@ -652,13 +652,17 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
                         const int* e_rhs, const ModeData* modes, const int* active) {
   if (nrhs <= 0) return hipSuccess;
   StencilArgs S = stencil_args(c, 16);
+  prof_start(c, IOBM_K_STENCIL);
   hipLaunchKernelGGL(k_apply<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, x, y, Vptr<T>(c),
                      E_rhs, active);
+  prof_stop(c, IOBM_K_STENCIL, (double)nrhs * c->g.npts * sizeof(cplx<T>));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(cplx<T>);
+  prof_start(c, IOBM_K_BOUNDARY);
   hipLaunchKernelGGL(k_boundary<T>, dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan,
                      c->g.nz, c->g.nf, x, y, modes, e_rhs, twx<T>(c), twy<T>(c), active);
+  prof_stop(c, IOBM_K_BOUNDARY, (double)nrhs * 2 * c->g.nf * c->g.nxy * sizeof(cplx<T>));
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (c->kb.ncen > 0) return launch_kb_apply<T>(c, x, y, nrhs, nullptr, active);
@@ -669,8 +673,10 @@ template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z, int nrhs,
                                     const int* active) {
   StencilArgs S = stencil_args(c, 16);
+  prof_start(c, IOBM_K_PRECOND_LAP);
   hipLaunchKernelGGL(k_precond_lap<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S,
                      (T)exp(-alpha), r, z, active);
+  prof_stop(c, IOBM_K_PRECOND_LAP, (double)nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -686,6 +692,7 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
 #define IOBM_PF(M)                                                                                 \
   hipLaunchKernelGGL((k_precond_fft<T, M>), dim3(nrhs), dim3(threads), sh, c->stream, c->plan,     \
                      c->g.nz, c->g.nf, r, z, scratch, modes, e_rhs, twx<T>(c), twy<T>(c), active)
+  prof_start(c, IOBM_K_PRECOND_FFT);
   switch (mpt) {
     case 1: IOBM_PF(1); break;
     case 2: IOBM_PF(2); break;
@@ -693,6 +700,7 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
     default: IOBM_PF(4); break;
   }
 #undef IOBM_PF
+  prof_stop(c, IOBM_K_PRECOND_FFT, (double)nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -734,8 +742,10 @@ template <typename T>
 hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active,
                       void* part) {
   int nblk = dot_blocks(c);
+  prof_start(c, IOBM_K_DOT);
   hipLaunchKernelGGL(k_dot<T>, dim3(nact * nblk), dim3(256), 0, c->stream, a, b, c->g.npts, nblk,
                      (Partial*)part, active);
+  prof_stop(c, IOBM_K_DOT, (double)nact * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -743,8 +753,10 @@ template <typename T, typename TX>
 hipError_t launch_update_xr(iobm_ctx c, cplx<TX>* x, const cplx<T>* p, cplx<T>* r, const cplx<T>* q,
                             const zd* alpha, int nact, const int* active, void* part) {
   int nblk = dot_blocks(c);
+  prof_start(c, IOBM_K_UPDATE);
   hipLaunchKernelGGL((k_update_xr<T, TX>), dim3(nact * nblk), dim3(256), 0, c->stream, x, p, r, q, alpha,
                      c->g.npts, nblk, (Partial*)part, active);
+  prof_stop(c, IOBM_K_UPDATE, (double)nact * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ LIBPATH = os.path.join(_HERE, "libiobm.so")
 
 C128, C64_REFINED = 0, 1
 PC_NONE, PC_TRUNCATED_LAPLACIAN, PC_LATERAL_FFT = 0, 1, 2
+K_STENCIL, K_BOUNDARY, K_PRECOND_FFT, K_PRECOND_LAP, K_NONLOCAL, K_DOT, K_UPDATE = range(1, 8)
 STATUS = ["ok", "invalid argument", "bad state", "out of device memory", "device error",
           "not converged", "Krylov breakdown", "energy at a channel threshold", "unsupported"]
 
@@ -63,6 +64,9 @@ EXPORTS = {
                              C.c_void_p]),
     "iobm_grad_transmission": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p,
                                          C.POINTER(C.c_double), C.c_void_p]),
+    "iobm_profile_begin": (C.c_int, [C.c_void_p, C.c_int32]),
+    "iobm_profile_end": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "iobm_destroy": (C.c_int, [C.c_void_p]),
     "iobm_status_str": (C.c_char_p, [C.c_int]),
     "iobm_last_error": (C.c_char_p, [C.c_void_p]),
@@ -168,7 +172,28 @@ class Solver:
         self._check(lib().iobm_set_nonlocal(self._ctx, len(nl.support), rank, _ptr(nsup), _ptr(idx),
                                             _ptr(beta), _ptr(D)))
 
+    def profile_begin(self, classes):
+        mask = 0
+        for k in classes:
+            mask |= 1 << k
+        self._check(lib().iobm_profile_begin(self._ctx, mask))
+
+    def profile_end(self, kernel_class):
+        """(launches, total ms, pass bytes) of one timed kernel class."""
+        n = C.c_int32()
+        ms = C.c_double()
+        b = C.c_double()
+        self._check(lib().iobm_profile_end(self._ctx, kernel_class, C.byref(n), C.byref(ms), C.byref(b)))
+        return n.value, ms.value, b.value
+
     def channels(self, E):
+        key = float(E)
+        cache = self.__dict__.setdefault("_chan_cache", {})
+        if key not in cache:
+            cache[key] = self._channels(key)
+        return tuple(a.copy() for a in cache[key])
+
+    def _channels(self, E):
         n = C.c_int32()
         cap = self.shape[1] * self.shape[2]
         ids = np.zeros(cap, np.int32)

@@ -1,0 +1,98 @@
+"""Adjoint gradient dT_tot/dV (one adjoint solve per outgoing channel with the
+same complex-symmetric operator) against the oracle's LU adjoint and central
+finite differences; torch.autograd wrapper."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import Grid, make
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _fd_voxels(g, grad, n, seed):
+    """n seeded voxels among those with |g| >= 1e-2 max|g| (so that a relative
+    comparison is meaningful)."""
+    rng = np.random.default_rng(seed)
+    cand = np.flatnonzero(np.abs(grad.ravel()) >= 1e-2 * np.abs(grad).max())
+    return rng.choice(cand, min(n, cand.size), replace=False)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gradient_matches_oracle_adjoint_and_fd(torch, precision):
+    from paper_1009_5300_amd import iobm
+    w = make(5, Grid(12, 12, 32, 0.4, 2))
+    g = w.grid
+    Es = [0.2, 0.55]
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s.set_potential(w.V)
+    opts = iobm.default_opts(precision=precision, tol=1e-11)
+    T, dT = s.grad_transmission(Es, opts)
+    dT = dT.cpu().numpy()
+    P = O.Problem(g, w.V)
+    T_ref, g_ref = O.total_transmission_and_gradient(P, Es)
+    assert abs(T - T_ref) <= 1e-6
+    assert np.abs(dT - g_ref).max() <= 1e-4 * np.abs(g_ref).max()
+    # central differences of the GPU forward solve on seeded voxels
+    vox = _fd_voxels(g, g_ref, 8, 1005)
+    d = 1e-4
+    for v in vox:
+        Vp, Vm = w.V.copy(), w.V.copy()
+        Vp.flat[v] += d
+        Vm.flat[v] -= d
+        s.set_potential(Vp)
+        Tp = s.solve(Es, opts=opts)["T"].sum()
+        s.set_potential(Vm)
+        Tm = s.solve(Es, opts=opts)["T"].sum()
+        fd = (Tp - Tm) / (2 * d)
+        assert abs(fd - dT.flat[v]) <= 1e-4 * abs(dT.flat[v]) + 1e-6 * np.abs(g_ref).max()
+    s.set_potential(w.V)
+
+
+def test_autograd_function(torch):
+    from paper_1009_5300_amd import iobm
+    from paper_1009_5300_amd.autograd import transmission
+    w = make(5, Grid(10, 10, 24, 0.4, 2))
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    V = torch.tensor(w.V, dtype=torch.float64, device="cuda", requires_grad=True)
+    T = transmission(V, s, [0.35])
+    (2.0 * T).backward()
+    s2 = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s2.set_potential(w.V)
+    T2, g2 = s2.grad_transmission([0.35])
+    assert abs(T.item() - T2) < 1e-12
+    assert torch.allclose(V.grad, 2.0 * g2, rtol=0, atol=1e-12 * float(g2.abs().max()))
+
+
+def test_gradient_at_full_adjoint_workload(torch):
+    """Workload 5 at its full size (32x32x96, 4 energies, 28 channels): the
+    adjoint gradient against central differences of the GPU forward solve on
+    a sample of the 64 seeded voxels, and the oracle's total transmission."""
+    from paper_1009_5300_amd import iobm
+    w = make(5)
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s.set_potential(w.V)
+    opts = iobm.default_opts(tol=1e-11)
+    T, dT = s.grad_transmission(w.energies, opts)
+    dT = dT.cpu().numpy()
+    vox = _fd_voxels(g, dT, 64, 1005)[:6]
+    d = 1e-4
+    for v in vox:
+        Vp, Vm = w.V.copy(), w.V.copy()
+        Vp.flat[v] += d
+        Vm.flat[v] -= d
+        s.set_potential(Vp)
+        Tp = s.solve(w.energies, opts=opts)["T"].sum()
+        s.set_potential(Vm)
+        Tm = s.solve(w.energies, opts=opts)["T"].sum()
+        fd = (Tp - Tm) / (2 * d)
+        assert abs(fd - dT.flat[v]) <= 1e-4 * abs(dT.flat[v]) + 1e-6 * np.abs(dT).max()
