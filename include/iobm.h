@@ -101,16 +101,19 @@ typedef struct {
   int32_t precond;     /* IOBM_PC_* */
   double alpha;        /* Eq. (17) parameter, C1 = exp(-alpha); default 1.8 */
   double tol;          /* stop when ||b - A psi||_2 <= tol ||b||_2 (FP64); default 1e-10 */
-  double inner_tol;    /* complex64 inner solve relative tolerance; default 1e-5 */
-  int32_t max_iter;    /* total inner iterations per RHS; default 50000 */
+  double inner_tol;    /* IOBM_C64_REFINED: reliable-update factor; the complex64
+                          residual is replaced by the FP64 true residual (and the
+                          correction folded into psi) each time it has fallen by
+                          this factor; default 1e-3 */
+  int32_t max_iter;    /* total COCG iterations per RHS; default 50000 */
   int32_t side;        /* 0: incidence from the left electrode, 1: from the right */
-  int32_t check_every; /* iterations between convergence checks; default 8 */
+  int32_t check_every; /* iterations between host convergence checks; default 2 */
 } iobm_solve_opts;
 
 /* Per right-hand side statistics (the paper's Table 2 counts iterations). */
 typedef struct {
-  int32_t iters;        /* preconditioned COCG iterations (all refinement steps) */
-  int32_t refinements;  /* FP64 residual evaluations after the first */
+  int32_t iters;        /* preconditioned COCG iterations */
+  int32_t refinements;  /* FP64 true-residual evaluations (reliable updates) */
   int32_t status;       /* IOBM_OK or IOBM_E_NOT_CONVERGED / IOBM_E_BREAKDOWN */
   int32_t pad_;
   double rel_residual;  /* final ||b - A psi|| / ||b|| in FP64 */
@@ -121,7 +124,9 @@ typedef struct {
 void iobm_default_opts(iobm_solve_opts* opts);
 
 /* Create a context on the current HIP device.  hip_stream: hipStream_t or NULL.
- * The grid is copied.  Errors: INVALID_ARG (sizes, nf), DEVICE, OOM. */
+ * The grid is copied.  Errors: INVALID_ARG (sizes, nf), UNSUPPORTED
+ * (nx*ny > 4096, nz > 256, or a lateral size with a prime factor > 31),
+ * DEVICE, OOM. */
 iobm_status iobm_create(const iobm_grid* grid, void* hip_stream, iobm_ctx* out);
 
 /* Set the local potential V(r) (Ha), float64 [nz][ny][nx], copied into the

@@ -14,8 +14,10 @@ the unique symmetric stencil that is exact for every polynomial of degree
 solved exactly over the rationals.  c_{mu,n} = chat_|n| / h_mu^2.
 """
 from fractions import Fraction
+from functools import lru_cache
 
 
+@lru_cache(maxsize=None)
 def fd_coefficients_exact(nf: int):
     """[chat_0, ..., chat_nf] as Fractions (dimensionless, h = 1)."""
     if nf < 1:
@@ -38,9 +40,10 @@ def fd_coefficients_exact(nf: int):
             if r != col and rows[r][col] != 0:
                 f = rows[r][col]
                 rows[r] = [a - f * b for a, b in zip(rows[r], rows[col])]
-    return [rows[i][-1] for i in range(n_unk)]
+    return tuple(rows[i][-1] for i in range(n_unk))
 
 
+@lru_cache(maxsize=None)
 def fd_coefficients(nf: int):
     """Same as fd_coefficients_exact, as floats."""
-    return [float(c) for c in fd_coefficients_exact(nf)]
+    return tuple(float(c) for c in fd_coefficients_exact(nf))

@@ -231,94 +231,25 @@ struct SolveOut {
   std::vector<double> rel;
 };
 
-// Batched preconditioned COCG on A d = r for the rhs in `act` (type T), with
-// x accumulated in type TX.  Stops a rhs when |r|^2 <= stop2[rhs]; returns
-// iterations per rhs.
-template <typename T, typename TX>
-void cocg(iobm_ctx ctx, const iobm_solve_opts& o, int nb, const int* e_d, const double* E_d, cplx<TX>* x,
-          cplx<T>* r, std::vector<int> act, const std::vector<double>& stop2, std::vector<int>& iters,
-          int max_iter, std::vector<int>& breakdown) {
-  const long long vol = ctx->g.npts;
-  const size_t vb = (size_t)nb * vol * sizeof(cplx<T>);
-  cplx<T>* p = (cplx<T>*)scratch(ctx, S_P, vb);
-  cplx<T>* q = (cplx<T>*)scratch(ctx, S_Q, vb);
-  cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)scratch(ctx, S_Z, vb);
-  cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)scratch(ctx, S_PF, vb) : nullptr;
-  const int nblk = dot_blocks(ctx);
-  void* part = scratch(ctx, S_PART, (size_t)nb * nblk * 32);
-  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * (3 * sizeof(zd) + sizeof(double) + sizeof(int)) + 64);
-  zd* rho = (zd*)sc;
-  zd* alpha = rho + nb;
-  zd* beta = alpha + nb;
-  double* rn2 = (double*)(beta + nb);
-  int* flag = (int*)(rn2 + nb);
-  HIPCHK(hipMemsetAsync(flag, 0, nb * sizeof(int), ctx->stream));
-  if (ctx->kb.ncen > 0) (void)kb_scratch(ctx, kb_proj_bytes(ctx, nb));
-  const ModeData* modes = ctx->modes_d;
-  std::vector<double> rn2_h(nb);
-  std::vector<int> flag_h(nb);
-
-  auto precond = [&](int nact, const int* ad) {
-    if (o.precond == IOBM_PC_TRUNCATED_LAPLACIAN)
-      HIPCHK(launch_precond_laplacian<T>(ctx, o.alpha, r, z, nact, ad));
-    else if (o.precond == IOBM_PC_LATERAL_FFT)
-      HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nact, e_d, modes, ad));
-  };
-  // start: z = P r, p = z, rho = r^T z
-  int nact = (int)act.size();
-  if (nact == 0) return;
-  int* act_d = upload(ctx, S_IDX, act, 64 * 1024);
-  precond(nact, act_d);
-  HIPCHK((launch_convert<T, T>(ctx, z, p, nact, act_d)));
-  HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
-  HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 2, nact, act_d));
-  const int check = std::max(1, o.check_every);
-  int it = 0;
-  while (nact > 0) {
-    for (int k = 0; k < check; ++k) {
-      HIPCHK(launch_apply<T>(ctx, p, q, nact, E_d, e_d, modes, act_d));
-      HIPCHK(launch_dot<T>(ctx, p, q, nact, act_d, part));
-      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 0, nact, act_d));
-      HIPCHK((launch_update_xr<T, TX>(ctx, x, p, r, q, alpha, nact, act_d, part)));
-      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 3, nact, act_d));
-      if (k == check - 1) break;  // convergence test before the next direction
-      precond(nact, act_d);
-      HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
-      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 1, nact, act_d));
-      HIPCHK(launch_update_p<T>(ctx, p, z, beta, nact, act_d));
-    }
-    it += check;
-    HIPCHK(hipMemcpyAsync(rn2_h.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(flag_h.data(), flag, nb * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    stream_sync(ctx);
-    std::vector<int> keep;
-    for (int rr : act) {
-      iters[rr] += check;
-      bool done = rn2_h[rr] <= stop2[rr] || !(rn2_h[rr] == rn2_h[rr]);
-      if (flag_h[rr]) {
-        breakdown[rr] = 1;
-        done = true;
-      }
-      if (iters[rr] >= max_iter) done = true;
-      if (!done) keep.push_back(rr);
-    }
-    if (keep.size() != act.size()) {
-      act = keep;
-      nact = (int)act.size();
-      if (nact == 0) break;
-      act_d = upload(ctx, S_IDX, act, 64 * 1024);
-    }
-    // next direction for the survivors
-    precond(nact, act_d);
-    HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
-    HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 1, nact, act_d));
-    HIPCHK(launch_update_p<T>(ctx, p, z, beta, nact, act_d));
-  }
-  (void)it;
-}
-
-// Solve A x = b for a batch (b, x complex128 on the device); fills stats.
-void solve_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const zd* b, zd* x, SolveOut& out) {
+// Batched preconditioned COCG with FP64 residual replacement (mixed precision).
+//
+// The Krylov recurrences run in type T (complex64 or complex128) on the
+// correction d of the FP64 solution x: q = A p, alpha = rho / p^T q,
+// d += alpha p, r -= alpha q, z = P r, beta = (r^T z) / rho, p = z + beta p,
+// with every inner product accumulated in FP64.  When the recursively
+// updated residual of a right-hand side has fallen by the factor `delta`
+// (opts.inner_tol) since its last update, or below the target, the
+// correction is folded into x in FP64 (x += d, d = 0), the true residual
+// r_hi = b - A x is formed with the complex128 operator, the iterated
+// residual is replaced by it and the direction restarts (p = z).  Keeping
+// the old direction across the replacement is fragile once the
+// preconditioner itself runs in complex64 (some states diverged), and with
+// a strong preconditioner the restarts cost no extra iterations.  A
+// right-hand side is done when its true residual is <= tol ||b||; a
+// breakdown (vanishing rho or p^T q) or a diverging iterated residual
+// forces an early replacement.
+template <typename T>
+void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const zd* b, zd* x, SolveOut& out) {
   const int nb = B.n;
   const long long vol = ctx->g.npts;
   out.iters.assign(nb, 0);
@@ -326,89 +257,172 @@ void solve_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const z
   out.status.assign(nb, IOBM_OK);
   out.rel.assign(nb, 0.0);
   if (nb == 0) return;
+  const size_t vb = (size_t)nb * vol * sizeof(cplx<T>);
   int* e_d = upload(ctx, S_IDX, B.e, 0);
   double* E_d = upload(ctx, S_IDX, B.E, 16 * 1024);
   std::vector<int> all(nb);
   for (int i = 0; i < nb; ++i) all[i] = i;
   int* all_d = upload(ctx, S_IDX, all, 32 * 1024);
   zd* rhi = (zd*)scratch(ctx, S_RHI, (size_t)nb * vol * sizeof(zd));
+  cplx<T>* d = (cplx<T>*)scratch(ctx, S_D, vb);
+  cplx<T>* r = (cplx<T>*)scratch(ctx, S_R, vb);
+  cplx<T>* p = (cplx<T>*)scratch(ctx, S_P, vb);
+  cplx<T>* q = (cplx<T>*)scratch(ctx, S_Q, vb);
+  cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)scratch(ctx, S_Z, vb);
+  cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)scratch(ctx, S_PF, vb) : nullptr;
   const int nblk = dot_blocks(ctx);
   void* part = scratch(ctx, S_PART, (size_t)nb * nblk * 32);
-  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * (3 * sizeof(zd) + sizeof(double) + sizeof(int)) + 64);
-  double* rn2 = (double*)((zd*)sc + 3 * nb);
-  int* flag = (int*)(rn2 + nb);
-  zd* dummy = (zd*)sc;
-  std::vector<double> bn2(nb), rn2_h(nb), best(nb, 1e300);
-  std::vector<int> stall(nb, 0), brk(nb, 0);
-
-  HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * vol * sizeof(zd), ctx->stream));
-  HIPCHK(launch_dot<double>(ctx, b, b, nb, all_d, part));
-  HIPCHK(launch_finish(ctx, dummy, dummy, dummy, rn2, flag, part, 3, nb, all_d));
-  HIPCHK(hipMemcpyAsync(bn2.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipMemcpyAsync(rhi, b, (size_t)nb * vol * sizeof(zd), hipMemcpyDeviceToDevice, ctx->stream));
-  stream_sync(ctx);
-  rn2_h = bn2;
+  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * (3 * sizeof(zd) + 2 * sizeof(double) + sizeof(int)) + 64);
+  zd* rho = (zd*)sc;
+  zd* alpha = rho + nb;
+  zd* beta = alpha + nb;
+  double* rn2 = (double*)(beta + nb);
+  double* tn2 = rn2 + nb;
+  int* flag = (int*)(tn2 + nb);
+  if (ctx->kb.ncen > 0) (void)kb_scratch(ctx, kb_proj_bytes(ctx, nb));
+  const ModeData* modes = ctx->modes_d;
+  const bool lowp = sizeof(T) == sizeof(float);
   const double tol2 = o.tol * o.tol;
-  const bool lowp = o.precision == IOBM_C64_REFINED;
-  for (int outer = 0; outer < 64; ++outer) {
-    std::vector<int> act;
-    for (int i = 0; i < nb; ++i) {
-      out.rel[i] = bn2[i] > 0 ? sqrt(rn2_h[i] / bn2[i]) : 0.0;
-      if (bn2[i] == 0 || rn2_h[i] <= tol2 * bn2[i]) continue;
-      if (out.status[i] != IOBM_OK) continue;
-      if (out.iters[i] >= o.max_iter) {
-        out.status[i] = IOBM_E_NOT_CONVERGED;
-        continue;
-      }
-      if (rn2_h[i] < 0.25 * best[i]) {
-        best[i] = rn2_h[i];
-        stall[i] = 0;
-      } else if (++stall[i] >= 3) {
-        out.status[i] = brk[i] ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
-        continue;
-      }
-      act.push_back(i);
-    }
-    if (act.empty()) break;
-    if (outer > 0)
-      for (int i : act) out.refin[i] += 1;
-    // inner stopping threshold on |r_inner|^2
-    std::vector<double> stop2(nb, 0.0);
-    const double itol = lowp ? o.inner_tol : 0.0;
-    for (int i : act) stop2[i] = std::max(itol * itol * rn2_h[i], 0.25 * tol2 * bn2[i]);
-    std::vector<int> used(nb, 0);
-    std::vector<int> act_copy = act;
-    int* act_d = upload(ctx, S_IDX, act, 48 * 1024);
-    if (lowp) {
-      zf* r32 = (zf*)scratch(ctx, S_R, (size_t)nb * vol * sizeof(zf));
-      zf* d32 = (zf*)scratch(ctx, S_D, (size_t)nb * vol * sizeof(zf));
-      HIPCHK((launch_convert<float, double>(ctx, rhi, r32, (int)act.size(), act_d)));
-      HIPCHK((launch_convert<float, double>(ctx, nullptr, d32, (int)act.size(), act_d)));
-      cocg<float, float>(ctx, o, nb, e_d, E_d, d32, r32, act_copy, stop2, used, o.max_iter, brk);
-      act_d = upload(ctx, S_IDX, act, 48 * 1024);
-      HIPCHK(launch_accumulate<float>(ctx, x, d32, (int)act.size(), act_d));
-    } else {
-      zd* d64 = (zd*)scratch(ctx, S_D, (size_t)nb * vol * sizeof(zd));
-      zd* r64 = (zd*)scratch(ctx, S_R, (size_t)nb * vol * sizeof(zd));
-      HIPCHK((launch_convert<double, double>(ctx, rhi, r64, (int)act.size(), act_d)));
-      HIPCHK((launch_convert<double, double>(ctx, nullptr, d64, (int)act.size(), act_d)));
-      cocg<double, double>(ctx, o, nb, e_d, E_d, d64, r64, act_copy, stop2, used, o.max_iter, brk);
-      act_d = upload(ctx, S_IDX, act, 48 * 1024);
-      HIPCHK(launch_accumulate<double>(ctx, x, d64, (int)act.size(), act_d));
-    }
-    for (int i : act) out.iters[i] += used[i];
-    // true residual in FP64: r_hi = b - A x
-    HIPCHK(launch_apply<double>(ctx, x, rhi, (int)act.size(), E_d, e_d, ctx->modes_d, act_d));
-    HIPCHK(launch_residual<double>(ctx, b, rhi, (int)act.size(), act_d));
-    HIPCHK(launch_dot<double>(ctx, rhi, rhi, (int)act.size(), act_d, part));
-    HIPCHK(launch_finish(ctx, dummy, dummy, dummy, rn2, flag, part, 3, (int)act.size(), act_d));
-    HIPCHK(hipMemcpyAsync(rn2_h.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  const double delta2 = lowp ? o.inner_tol * o.inner_tol : 0.0;
+  const int check = std::max(1, o.check_every);
+
+  auto precond = [&](int nact, const int* ad) {
+    if (o.precond == IOBM_PC_TRUNCATED_LAPLACIAN)
+      HIPCHK(launch_precond_laplacian<T>(ctx, o.alpha, r, z, nact, ad));
+    else if (o.precond == IOBM_PC_LATERAL_FFT)
+      HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nact, e_d, modes, ad));
+  };
+  // true residual r_hi = b - A x for the listed rhs; |r_hi|^2 -> host
+  std::vector<double> tn2_h(nb), rn2_h(nb), bn2(nb);
+  std::vector<int> flag_h(nb);
+  auto true_residual = [&](const std::vector<int>& lst, int region) {
+    int* ld = upload(ctx, S_IDX, lst, (size_t)region * 8192);
+    const int n = (int)lst.size();
+    HIPCHK(launch_apply<double>(ctx, x, rhi, n, E_d, e_d, modes, ld));
+    HIPCHK(launch_residual<double>(ctx, b, rhi, n, ld));
+    HIPCHK(launch_dot<double>(ctx, rhi, rhi, n, ld, part));
+    HIPCHK(launch_finish(ctx, rho, alpha, beta, tn2, flag, part, 3, n, ld));
+    HIPCHK(hipMemcpyAsync(tn2_h.data(), tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     stream_sync(ctx);
+    return ld;
+  };
+
+  // start: x = 0, r_hi = b, d = 0, r = r_hi, z = P r, p = z, rho = r^T z
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * vol * sizeof(zd), ctx->stream));
+  HIPCHK(hipMemsetAsync(flag, 0, nb * sizeof(int), ctx->stream));
+  HIPCHK(launch_dot<double>(ctx, b, b, nb, all_d, part));
+  HIPCHK(launch_finish(ctx, rho, alpha, beta, tn2, flag, part, 3, nb, all_d));
+  HIPCHK(hipMemcpyAsync(bn2.data(), tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  stream_sync(ctx);
+  std::vector<int> act;
+  for (int i = 0; i < nb; ++i)
+    if (bn2[i] > 0) act.push_back(i);
+  std::vector<double> maxr2(nb), best(nb), last(nb);
+  std::vector<int> stall(nb, 0);
+  for (int i = 0; i < nb; ++i) maxr2[i] = best[i] = last[i] = bn2[i];
+  tn2_h = bn2;
+  if (act.empty()) return;
+  int nact = (int)act.size();
+  int* act_d = upload(ctx, S_IDX, act, 64 * 1024);
+  HIPCHK((launch_convert<T, double>(ctx, b, r, nact, act_d)));
+  HIPCHK((launch_convert<T, double>(ctx, nullptr, d, nact, act_d)));
+  HIPCHK(hipMemcpyAsync(rhi, b, (size_t)nb * vol * sizeof(zd), hipMemcpyDeviceToDevice, ctx->stream));
+  precond(nact, act_d);
+  HIPCHK((launch_convert<T, T>(ctx, z, p, nact, act_d)));
+  HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
+  HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 2, nact, act_d));
+
+  while (nact > 0) {
+    for (int k = 0; k < check; ++k) {
+      HIPCHK(launch_apply<T>(ctx, p, q, nact, E_d, e_d, modes, act_d));
+      HIPCHK(launch_dot<T>(ctx, p, q, nact, act_d, part));
+      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 0, nact, act_d));
+      HIPCHK((launch_update_xr<T, T>(ctx, d, p, r, q, alpha, nact, act_d, part)));
+      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 3, nact, act_d));
+      if (k == check - 1) break;
+      precond(nact, act_d);
+      HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
+      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 1, nact, act_d));
+      HIPCHK(launch_update_p<T>(ctx, p, z, beta, nact, act_d));
+    }
+    HIPCHK(hipMemcpyAsync(rn2_h.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(flag_h.data(), flag, nb * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    // which rhs fold their correction into x and refresh the residual
+    std::vector<int> upd, restart;
+    for (int i : act) {
+      out.iters[i] += check;
+      const double r2 = rn2_h[i];
+      const bool bad = flag_h[i] || !(r2 == r2) || r2 > 1e4 * maxr2[i];  // breakdown or divergence
+      if (bad || r2 <= 0.25 * tol2 * bn2[i] || r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter) upd.push_back(i);
+      else maxr2[i] = std::max(maxr2[i], r2);
+      if (bad) restart.push_back(i);
+    }
+    std::vector<int> keep;
+    if (!upd.empty()) {
+      int* ud = upload(ctx, S_IDX, upd, 48 * 1024);
+      const int nu = (int)upd.size();
+      HIPCHK(launch_accumulate<T>(ctx, x, d, nu, ud));
+      true_residual(upd, 7);
+      std::vector<int> cont;  // updated rhs that go on iterating
+      for (int i : upd) {
+        out.refin[i] += 1;
+        const double t2 = tn2_h[i];
+        if (t2 <= tol2 * bn2[i]) continue;  // converged
+        if (out.iters[i] >= o.max_iter) { out.status[i] = IOBM_E_NOT_CONVERGED; continue; }
+        if (t2 < 0.25 * best[i]) { best[i] = t2; stall[i] = 0; }
+        else if (++stall[i] >= 6) {
+          out.status[i] = flag_h[i] ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
+          continue;
+        }
+        cont.push_back(i);
+        maxr2[i] = t2;
+        if (!flag_h[i]) restart.push_back(i);
+      }
+      if (!cont.empty()) {
+        int* cd = upload(ctx, S_IDX, cont, 56 * 1024);
+        HIPCHK((launch_convert<T, double>(ctx, rhi, r, (int)cont.size(), cd)));
+        HIPCHK((launch_convert<T, double>(ctx, nullptr, d, (int)cont.size(), cd)));
+      }
+      std::vector<char> gone(nb, 1);
+      for (int i : act) gone[i] = 0;
+      for (int i : upd) gone[i] = 1;
+      for (int i : cont) gone[i] = 0;
+      for (int i : act)
+        if (!gone[i]) keep.push_back(i);
+    } else {
+      keep = act;
+    }
+    if (keep.size() != act.size()) {
+      act = keep;
+      nact = (int)act.size();
+      if (nact == 0) break;
+      act_d = upload(ctx, S_IDX, act, 64 * 1024);
+    }
+    // next direction; a restarted rhs takes p = z
+    precond(nact, act_d);
+    HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
+    HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 1, nact, act_d));
+    if (!restart.empty()) {
+      std::vector<int> rs;
+      for (int i : restart)
+        if (std::find(act.begin(), act.end(), i) != act.end()) rs.push_back(i);
+      if (!rs.empty()) {
+        int* rd = upload(ctx, S_IDX, rs, 40 * 1024);
+        HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 4, (int)rs.size(), rd));
+      }
+    }
+    HIPCHK(launch_update_p<T>(ctx, p, z, beta, nact, act_d));
   }
   for (int i = 0; i < nb; ++i) {
-    out.rel[i] = bn2[i] > 0 ? sqrt(rn2_h[i] / bn2[i]) : 0.0;
-    if (out.status[i] == IOBM_OK && bn2[i] > 0 && rn2_h[i] > tol2 * bn2[i]) out.status[i] = IOBM_E_NOT_CONVERGED;
+    out.rel[i] = bn2[i] > 0 ? sqrt(tn2_h[i] / bn2[i]) : 0.0;
+    if (out.status[i] == IOBM_OK && bn2[i] > 0 && tn2_h[i] > tol2 * bn2[i]) out.status[i] = IOBM_E_NOT_CONVERGED;
   }
+}
+
+void solve_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const zd* b, zd* x, SolveOut& out) {
+  if (o.precision == IOBM_C64_REFINED) solve_rhs_batch<float>(ctx, o, B, b, x, out);
+  else solve_rhs_batch<double>(ctx, o, B, b, x, out);
 }
 
 void validate_opts(iobm_ctx ctx, const iobm_solve_opts* o) {
@@ -420,6 +434,7 @@ void validate_opts(iobm_ctx ctx, const iobm_solve_opts* o) {
     ctx->err = "unknown preconditioner"; throw Fail{IOBM_E_INVALID_ARG};
   }
   if (!(o->tol > 0 && o->tol < 1) || !(o->inner_tol > 0 && o->inner_tol < 1) || o->max_iter < 1 ||
+      o->check_every < 1 ||
       (o->side != 0 && o->side != 1) || !(o->alpha > 0) || !isfinite(o->alpha)) {
     ctx->err = "invalid solver option (tol, inner_tol in (0,1), max_iter >= 1, side 0/1, alpha > 0)";
     throw Fail{IOBM_E_INVALID_ARG};
@@ -523,10 +538,10 @@ void iobm_default_opts(iobm_solve_opts* o) {
   o->precond = IOBM_PC_LATERAL_FFT;
   o->alpha = 1.8;
   o->tol = 1e-10;
-  o->inner_tol = 1e-5;
+  o->inner_tol = 1e-3;
   o->max_iter = 50000;
   o->side = 0;
-  o->check_every = 8;
+  o->check_every = 2;
 }
 
 const char* iobm_status_str(iobm_status s) {
@@ -552,7 +567,7 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
   if (g->nf < 1 || g->nf > 3 || g->nx < 2 || g->ny < 2 || g->nz < 2 * g->nf || !(g->hx > 0) ||
       !(g->hy > 0) || !(g->hz > 0) || !isfinite(g->hx) || !isfinite(g->hy) || !isfinite(g->hz))
     return IOBM_E_INVALID_ARG;
-  if ((long long)g->nx * g->ny > 4096) return IOBM_E_UNSUPPORTED;
+  if ((long long)g->nx * g->ny > 4096 || g->nz > 256) return IOBM_E_UNSUPPORTED;
   iobm_ctx ctx = new iobm_ctx_s();
   ctx->g.nx = g->nx; ctx->g.ny = g->ny; ctx->g.nz = g->nz; ctx->g.nf = g->nf;
   ctx->g.nxy = g->nx * g->ny;

@@ -75,6 +75,8 @@ struct iobm_ctx_s {
   void* arena_d = nullptr;  // small index arrays (device) and their pinned host mirror
   void* arena_h = nullptr;
   unsigned char region_pending[64] = {0};
+  // tuned launch shapes (0 = default rule)
+  int tune_zf_c64 = 0, tune_zf_c128 = 0;
   // kernel timing hook
   int prof_mask = 0;
   std::vector<hipEvent_t> prof_ev;  // start/stop pairs

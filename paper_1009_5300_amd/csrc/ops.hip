@@ -167,112 +167,226 @@ __global__ void __launch_bounds__(256) k_precond_lap(StencilArgs S, T c1, const 
 
 // ------------------------------------------ lateral-Fourier preconditioner ---
 // z = (E - H_0 - Sigma_L - Sigma_R)^-1 r, the exact inverse of the operator
-// of the flat (V = 0) wire: diagonal in the lateral modes (Eq. (16)); along z
-// each mode's inverse is the lead Green's function G(z - z'), applied as a
-// causal plus an anti-causal order-nf recursive filter (coefficients from
-// the mode setup).  One block per rhs sweeps the planes forward (FFT, causal
-// filter, store) and then backward (FFT of the next plane, anti-causal
-// filter, sum, inverse FFT, store).  Each thread owns MPT modes.
-template <typename T, int MPT>
-__global__ void k_precond_fft(FFTPlan2D plan, int nz, int nf, const cplx<T>* __restrict__ r,
-                              cplx<T>* __restrict__ zout, cplx<T>* __restrict__ fwd,
-                              const ModeData* __restrict__ modes, const int* __restrict__ e_rhs,
-                              const cplx<T>* __restrict__ twx, const cplx<T>* __restrict__ twy,
-                              const int* __restrict__ active) {
+// of the flat (V = 0) wire.  It is diagonal in the lateral modes (Eq. (16));
+// along z each mode's inverse is the lead Green's function G(z - z'), which
+// obeys the outgoing recurrence, so it is applied as a causal plus an
+// anti-causal order-nf recursive filter (coefficients from the mode setup).
+// Three passes, each with ample parallelism:
+//   1. k_fft_planes: forward 2D FFT of every plane (one block per plane),
+//   2. k_zfilter: per mode, the two recursions along z on an LDS tile of
+//      [nz][MB] modes of one rhs,
+//   3. k_fft_planes: inverse 2D FFT in place, scaled by 1/Nxy.
+
+// Batched 2D FFT of the planes of the active rhs; block = (slot, plane).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fft_planes(FFTPlan2D plan, int nz, const cplx<T>* in,
+                                                    cplx<T>* out, const cplx<T>* __restrict__ twx,
+                                                    const cplx<T>* __restrict__ twy, int sign, T scale,
+                                                    const int* __restrict__ active) {
   extern __shared__ char smem_raw[];
   cplx<T>* bufA = reinterpret_cast<cplx<T>*>(smem_raw);
   const int nxy = plan.x.n * plan.y.n;
   cplx<T>* bufB = bufA + nxy;
-  const int rhs = rhs_of(active, blockIdx.x);
-  const long long vol = (long long)nxy * nz;
-  const cplx<T>* rr = r + rhs * vol;
-  cplx<T>* zr = zout + rhs * vol;
-  cplx<T>* fr = fwd + rhs * vol;
-  const ModeData* md = modes + (long long)e_rhs[rhs] * nxy;
-  cplx<T> al[MPT][3], fb[MPT][3], fbb[MPT][3];
-  cplx<T> hf[MPT][3], hr[MPT][3];
+  const int slot = blockIdx.x / nz;
+  const int z = blockIdx.x - slot * nz;
+  const int rhs = rhs_of(active, slot);
+  const long long off = (long long)rhs * nxy * nz + (long long)z * nxy;
+  for (int p = threadIdx.x; p < nxy; p += blockDim.x) bufA[p] = in[off + p];
+  __syncthreads();
+  cplx<T>* res = fft2d_lds(bufA, bufB, plan, twx, twy, sign);
+  for (int p = threadIdx.x; p < nxy; p += blockDim.x) out[off + p] = scale * res[p];
+}
+
+// Recursive z filter in mode space.  Thread (mode m, chunk c) owns planes
+// [c L, c L + L) of one mode of one rhs, held in registers:
+//   causal      F(z) = sum_k alpha_k F(z-k) + sum_k fb_k  r(z-k)
+//   anti-causal B(z) = sum_k alpha_k B(z+k) + sum_k fbb_k r(z+1+k)
+//   out(z) = F(z) + B(z),   alpha_k = -q_{nf-k}.
+// Each chunk first runs both recursions from a zero state (the inputs of
+// neighbouring planes are read as halo).  By linearity the missing part is
+// the homogeneous response to the true state entering the chunk; those
+// states follow from a short scan over the chunks with the state
+// propagator M^L (M = companion matrix of the outgoing recurrence), and
+// each thread then adds the homogeneous responses.  Block = 64 modes x C
+// chunks (C <= 8) of one rhs.
+template <typename T>
+__device__ __forceinline__ void small_matvec(const cplx<T>* M, const cplx<T>* v, cplx<T>* out, int nf) {
 #pragma unroll
-  for (int u = 0; u < MPT; ++u) {
-    const int m = threadIdx.x + u * blockDim.x;
+  for (int i = 0; i < 3; ++i) {
+    cplx<T> s = mk<T>(0, 0);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      al[u][k] = fb[u][k] = fbb[u][k] = hf[u][k] = hr[u][k] = mk<T>(0, 0);
-      if (m < nxy && k < nf) {
-        al[u][k] = -cvt<T>(md[m].q[nf - 1 - k]);  // alpha_{k+1} = -q_{nf-1-k}
-        fb[u][k] = cvt<T>(md[m].fb[k]);
-        fbb[u][k] = cvt<T>(md[m].fbb[k]);
-      }
+    for (int j = 0; j < 3; ++j)
+      if (i < nf && j < nf) s = s + M[i * 3 + j] * v[j];
+    out[i] = s;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void small_matmul(const cplx<T>* A, const cplx<T>* B, cplx<T>* C, int nf) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cplx<T> s = mk<T>(0, 0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (i < nf && j < nf && k < nf) s = s + A[i * 3 + k] * B[k * 3 + j];
+      C[i * 3 + j] = s;
+    }
+}
+
+// M^n for the state S = (F(z), F(z-1), ..., F(z-nf+1)): S(z+1) = M S(z).
+template <typename T>
+__device__ void state_power(const cplx<T>* al, int nf, int n, cplx<T>* P) {
+  cplx<T> M[9], R[9], tmp[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) { M[i] = mk<T>(0, 0); R[i] = mk<T>(0, 0); }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) M[j] = al[j];
+  M[1 * 3 + 0] = mk<T>(1, 0);
+  M[2 * 3 + 1] = mk<T>(1, 0);
+  for (int i = 0; i < 3; ++i) R[i * 4] = mk<T>(1, 0);
+  while (n > 0) {
+    if (n & 1) {
+      small_matmul(R, M, tmp, nf);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R[i] = tmp[i];
+    }
+    n >>= 1;
+    if (n) {
+      small_matmul(M, M, tmp, nf);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) M[i] = tmp[i];
     }
   }
-  // forward sweep: F(z) = sum_k alpha_k F(z-k) + sum_k fb_k r~(z-k)
-  for (int z = 0; z < nz; ++z) {
-    const cplx<T>* src = rr + (long long)z * nxy;
-    for (int p = threadIdx.x; p < nxy; p += blockDim.x) bufA[p] = src[p];
-    __syncthreads();
-    cplx<T>* res = fft2d_lds(bufA, bufB, plan, twx, twy, -1);
 #pragma unroll
-    for (int u = 0; u < MPT; ++u) {
-      const int m = threadIdx.x + u * blockDim.x;
-      if (m < nxy) {
-        // shift input history: hr[0] = r~(z), hr[k] = r~(z-k)
-        hr[u][2] = hr[u][1];
-        hr[u][1] = hr[u][0];
-        hr[u][0] = res[m];
-        cplx<T> F = mk<T>(0, 0);
+  for (int i = 0; i < 9; ++i) P[i] = R[i];
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(512) k_zfilter(int nz, int nf, int nxy, const cplx<T>* __restrict__ in,
+                                                  cplx<T>* __restrict__ out, const ModeData* __restrict__ modes,
+                                                  const int* __restrict__ e_rhs, const int* __restrict__ active) {
+  extern __shared__ char smem_raw[];
+  const int C = blockDim.y;
+  cplx<T>* sc = reinterpret_cast<cplx<T>*>(smem_raw);  // [C][64][3] causal end states
+  cplx<T>* sb = sc + (size_t)C * 64 * 3;                // [C][64][3] anti-causal begin states
+  const int nmb = (nxy + 63) / 64;
+  const int slot = blockIdx.x / nmb;
+  const int m = (blockIdx.x - slot * nmb) * 64 + threadIdx.x;
+  const int c = threadIdx.y;
+  const int rhs = rhs_of(active, slot);
+  const long long base = (long long)rhs * nxy * nz;
+  const bool live = m < nxy;
+  const int z0 = c * L;
+  cplx<T> al[3], fb[3], fbb[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          if (k < nf) F = F + al[u][k] * hf[u][k] + fb[u][k] * hr[u][k];
-        hf[u][2] = hf[u][1];
-        hf[u][1] = hf[u][0];
-        hf[u][0] = F;
-        fr[(long long)z * nxy + m] = F;
+  for (int k = 0; k < 3; ++k) al[k] = fb[k] = fbb[k] = mk<T>(0, 0);
+  if (live) {
+    const ModeData& md = modes[(long long)e_rhs[rhs] * nxy + m];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (k < nf) {
+        al[k] = -cvt<T>(md.q[nf - 1 - k]);
+        fb[k] = cvt<T>(md.fb[k]);
+        fbb[k] = cvt<T>(md.fbb[k]);
       }
-    }
-    __syncthreads();
   }
-  // backward sweep: B(z) = sum_k alpha_k B(z+k) + sum_k fbb_k r~(z+1+k)
+  // inputs of planes z0-2 .. z0+L+2
+  cplx<T> rr[L + 5];
 #pragma unroll
-  for (int u = 0; u < MPT; ++u)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) hf[u][k] = hr[u][k] = mk<T>(0, 0);
-  const T inv = (T)(1.0 / nxy);
-  for (int z = nz - 1; z >= 0; --z) {
-    cplx<T>* res = nullptr;
-    if (z + 1 < nz) {
-      const cplx<T>* src = rr + (long long)(z + 1) * nxy;
-      for (int p = threadIdx.x; p < nxy; p += blockDim.x) bufA[p] = src[p];
-      __syncthreads();
-      res = fft2d_lds(bufA, bufB, plan, twx, twy, -1);
-    }
-#pragma unroll
-    for (int u = 0; u < MPT; ++u) {
-      const int m = threadIdx.x + u * blockDim.x;
-      cplx<T> val = mk<T>(0, 0);
-      if (m < nxy) {
-        hr[u][2] = hr[u][1];
-        hr[u][1] = hr[u][0];
-        hr[u][0] = res ? res[m] : mk<T>(0, 0);
-        cplx<T> B = mk<T>(0, 0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          if (k < nf) B = B + al[u][k] * hf[u][k] + fbb[u][k] * hr[u][k];
-        hf[u][2] = hf[u][1];
-        hf[u][1] = hf[u][0];
-        hf[u][0] = B;
-        val = inv * (B + fr[(long long)z * nxy + m]);
-      }
-      // stash for the inverse FFT (all threads finished reading res above
-      // only after the barrier, so write into the other buffer)
-      if (m < nxy) (res == bufA ? bufB : bufA)[m] = val;
-    }
-    __syncthreads();
-    cplx<T>* in = (res == bufA) ? bufB : bufA;
-    cplx<T>* other = (in == bufA) ? bufB : bufA;
-    cplx<T>* out = fft2d_lds(in, other, plan, twx, twy, +1);
-    cplx<T>* dst = zr + (long long)z * nxy;
-    for (int p = threadIdx.x; p < nxy; p += blockDim.x) dst[p] = out[p];
-    __syncthreads();
+  for (int i = 0; i < L + 5; ++i) {
+    const int z = z0 - 2 + i;
+    rr[i] = (live && z >= 0 && z < nz) ? in[base + (long long)z * nxy + m] : mk<T>(0, 0);
   }
+  cplx<T> y[L];
+  // causal pass from a zero state
+  cplx<T> h0 = mk<T>(0, 0), h1 = mk<T>(0, 0), h2 = mk<T>(0, 0);
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    cplx<T> F = al[0] * h0 + al[1] * h1 + al[2] * h2 + fb[0] * rr[i + 2] + fb[1] * rr[i + 1] + fb[2] * rr[i];
+    h2 = h1;
+    h1 = h0;
+    h0 = (z0 + i < nz) ? F : mk<T>(0, 0);
+    y[i] = h0;
+  }
+  // chunk end state, (F(e), F(e-1), F(e-2)) at e = z0+L-1 (planes past nz are zero)
+  const int sidx = (c * 64 + threadIdx.x) * 3;
+  sc[sidx + 0] = h0;
+  sc[sidx + 1] = h1;
+  sc[sidx + 2] = h2;
+  // anti-causal pass from a zero state
+  h0 = h1 = h2 = mk<T>(0, 0);
+#pragma unroll
+  for (int i = L - 1; i >= 0; --i) {
+    cplx<T> B = al[0] * h0 + al[1] * h1 + al[2] * h2 + fbb[0] * rr[i + 3] + fbb[1] * rr[i + 4] +
+                fbb[2] * rr[i + 5];
+    h2 = h1;
+    h1 = h0;
+    h0 = (z0 + i < nz) ? B : mk<T>(0, 0);
+    y[i] = y[i] + h0;
+  }
+  sb[sidx + 0] = h0;  // (B(z0), B(z0+1), B(z0+2))
+  sb[sidx + 1] = h1;
+  sb[sidx + 2] = h2;
+  __syncthreads();
+  // scan over chunks: sc[c] <- true end state of chunk c, sb[c] <- true begin state
+  if (c == 0 && live && C > 1) {
+    cplx<T> ML[9], prev[3], tmp[3];
+    state_power(al, nf, L, ML);
+    prev[0] = prev[1] = prev[2] = mk<T>(0, 0);
+    for (int cc = 0; cc < C - 1; ++cc) {
+      cplx<T>* S = sc + (cc * 64 + threadIdx.x) * 3;
+      small_matvec(ML, prev, tmp, nf);
+      for (int k = 0; k < 3; ++k) prev[k] = S[k] + tmp[k];
+      for (int k = 0; k < 3; ++k) S[k] = prev[k];
+    }
+    // anti-causal: the last chunk may be shorter
+    const int Llast = nz - (C - 1) * L;
+    cplx<T> Mlast[9];
+    state_power(al, nf, Llast, Mlast);
+    prev[0] = prev[1] = prev[2] = mk<T>(0, 0);
+    for (int cc = C - 1; cc >= 1; --cc) {
+      cplx<T>* S = sb + (cc * 64 + threadIdx.x) * 3;
+      small_matvec(cc == C - 1 ? Mlast : ML, prev, tmp, nf);
+      for (int k = 0; k < 3; ++k) prev[k] = S[k] + tmp[k];
+      for (int k = 0; k < 3; ++k) S[k] = prev[k];
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  // homogeneous responses to the true incoming states
+  if (c > 0) {
+    const cplx<T>* S = sc + ((c - 1) * 64 + threadIdx.x) * 3;
+    h0 = S[0];
+    h1 = S[1];
+    h2 = S[2];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      cplx<T> F = al[0] * h0 + al[1] * h1 + al[2] * h2;
+      h2 = h1;
+      h1 = h0;
+      h0 = F;
+      y[i] = y[i] + F;
+    }
+  }
+  if (c < C - 1) {
+    const cplx<T>* S = sb + ((c + 1) * 64 + threadIdx.x) * 3;
+    h0 = S[0];
+    h1 = S[1];
+    h2 = S[2];
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+      cplx<T> B = al[0] * h0 + al[1] * h1 + al[2] * h2;
+      h2 = h1;
+      h1 = h0;
+      h0 = B;
+      y[i] = y[i] + B;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < L; ++i)
+    if (z0 + i < nz) out[base + (long long)(z0 + i) * nxy + m] = y[i];
 }
 
 // --------------------------------------------------------- right-hand side ---
@@ -416,10 +530,11 @@ __global__ void __launch_bounds__(256) k_update_p(cplx<T>* __restrict__ p, const
     p[off + i] = z[off + i] + b * p[off + i];
 }
 
-// Scalar steps of COCG, one thread per active rhs.  mode 0: alpha = rho / mu
-// (mu from the partials); mode 1: rho_new from the partials, beta =
-// rho_new / rho, rho = rho_new; mode 2: rho = partial sum (start);
-// every mode also records |.|^2 partial sums into rn2 when requested.
+// Scalar steps of COCG, one thread per active rhs, from the block partials
+// (fixed summation order): mode 0: alpha = rho / mu with mu = p^T q;
+// mode 1: beta = rho_new / rho, rho = rho_new with rho_new = r^T z;
+// mode 2: rho = r^T z (start); mode 3: rn2 = |.|^2; mode 4: restart
+// (rho = r^T z, beta = 0, breakdown flag cleared).
 struct Scal {
   zd* rho;
   zd* alpha;
@@ -462,6 +577,10 @@ __global__ void k_finish(Scal S, const Partial* __restrict__ part, int nblk, int
     S.rho[rhs] = s;
   } else if (mode == 2) {
     S.rho[rhs] = s;
+  } else if (mode == 4) {  // restart: rho = r^T z, beta = 0, clear the breakdown flag
+    S.rho[rhs] = s;
+    S.beta[rhs] = mk(0.0, 0.0);
+    S.flag[rhs] = 0;
   } else if (mode == 3) {
     S.rn2[rhs] = n2;
   }
@@ -681,27 +800,55 @@ hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, 
 }
 
 template <typename T>
+hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
+                             const int* active) {
+  size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
+                     twx<T>(c), twy<T>(c), sign, (T)scale, active);
+  return hipGetLastError();
+}
+
+// chunk length of the z filter (tuned per context and precision)
+template <typename T>
+static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* out, int nrhs, const int* e_rhs,
+                                 const ModeData* modes, const int* active) {
+  const int nxy = c->g.nxy, nz = c->g.nz;
+  const int nmb = (nxy + 63) / 64;
+  const int C = (nz + L - 1) / L;
+  size_t sh = 2 * (size_t)C * 64 * 3 * sizeof(cplx<T>);
+#define IOBM_ZF(LL)                                                                                 \
+  hipLaunchKernelGGL((k_zfilter<T, LL>), dim3(nrhs * nmb), dim3(64, C), sh, c->stream, nz, c->g.nf, nxy, in, \
+                     out, modes, e_rhs, active)
+  switch (L) {
+    case 8: IOBM_ZF(8); break;
+    case 16: IOBM_ZF(16); break;
+    default: IOBM_ZF(32); break;
+  }
+#undef IOBM_ZF
+  return hipGetLastError();
+}
+
+template <typename T>
+static int zfilter_chunk(iobm_ctx c) {
+  const int tuned = sizeof(T) == 8 ? c->tune_zf_c128 : c->tune_zf_c64;
+  if (tuned > 0) return tuned;
+  // at most 8 chunks (512 threads per block)
+  int L = 16;
+  if ((c->g.nz + L - 1) / L > 8) L = 32;
+  return L;
+}
+
+template <typename T>
 hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch, int nrhs,
                               const int* e_rhs, const ModeData* modes, const int* active) {
-  const int nxy = c->g.nxy;
-  int mpt = 1;
-  while (nxy > 1024 * mpt) ++mpt;
-  if (mpt > 4) return hipErrorInvalidValue;
-  int threads = ((nxy + mpt - 1) / mpt + 63) / 64 * 64;
-  size_t sh = 2 * (size_t)nxy * sizeof(cplx<T>);
-#define IOBM_PF(M)                                                                                 \
-  hipLaunchKernelGGL((k_precond_fft<T, M>), dim3(nrhs), dim3(threads), sh, c->stream, c->plan,     \
-                     c->g.nz, c->g.nf, r, z, scratch, modes, e_rhs, twx<T>(c), twy<T>(c), active)
+  const int L = zfilter_chunk<T>(c);
+  if ((c->g.nz + L - 1) / L > 8) return hipErrorInvalidValue;
   prof_start(c, IOBM_K_PRECOND_FFT);
-  switch (mpt) {
-    case 1: IOBM_PF(1); break;
-    case 2: IOBM_PF(2); break;
-    case 3: IOBM_PF(3); break;
-    default: IOBM_PF(4); break;
-  }
-#undef IOBM_PF
+  hipError_t err = launch_fft_planes<T>(c, r, scratch, -1, 1.0, nrhs, active);
+  if (err == hipSuccess) err = launch_zfilter<T>(c, L, scratch, z, nrhs, e_rhs, modes, active);
+  if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active);
   prof_stop(c, IOBM_K_PRECOND_FFT, (double)nrhs * c->g.npts * sizeof(cplx<T>));
-  return hipGetLastError();
+  return err;
 }
 
 template hipError_t launch_apply<double>(iobm_ctx, const zd*, zd*, int, const double*, const int*,

@@ -48,6 +48,7 @@ def test_status_strings_and_default_opts(lib):
     o = iobm.default_opts()
     assert o.precision == iobm.C64_REFINED and o.precond == iobm.PC_LATERAL_FFT
     assert o.tol == 1e-10 and abs(o.alpha - 1.8) < 1e-15 and o.max_iter == 50000
+    assert o.inner_tol == 1e-3 and o.check_every == 2
 
 
 @pytest.mark.parametrize("bad", [dict(nf=0), dict(nf=4), dict(nx=1), dict(nz=3), dict(hx=0.0),

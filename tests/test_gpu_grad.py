@@ -40,7 +40,10 @@ def test_gradient_matches_oracle_adjoint_and_fd(torch, precision):
     T_ref, g_ref = O.total_transmission_and_gradient(P, Es)
     assert abs(T - T_ref) <= 1e-6
     assert np.abs(dT - g_ref).max() <= 1e-4 * np.abs(g_ref).max()
-    # central differences of the GPU forward solve on seeded voxels
+    # central differences of the GPU forward solve on seeded voxels; the
+    # differenced solves run in complex128 to 1e-13 so that their own error
+    # (|dT| / delta) stays far below the tolerance
+    fd_opts = iobm.default_opts(precision=iobm.C128, tol=1e-13)
     vox = _fd_voxels(g, g_ref, 8, 1005)
     d = 1e-4
     for v in vox:
@@ -48,9 +51,9 @@ def test_gradient_matches_oracle_adjoint_and_fd(torch, precision):
         Vp.flat[v] += d
         Vm.flat[v] -= d
         s.set_potential(Vp)
-        Tp = s.solve(Es, opts=opts)["T"].sum()
+        Tp = s.solve(Es, opts=fd_opts)["T"].sum()
         s.set_potential(Vm)
-        Tm = s.solve(Es, opts=opts)["T"].sum()
+        Tm = s.solve(Es, opts=fd_opts)["T"].sum()
         fd = (Tp - Tm) / (2 * d)
         assert abs(fd - dT.flat[v]) <= 1e-4 * abs(dT.flat[v]) + 1e-6 * np.abs(g_ref).max()
     s.set_potential(w.V)
@@ -82,6 +85,7 @@ def test_gradient_at_full_adjoint_workload(torch):
     s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
     s.set_potential(w.V)
     opts = iobm.default_opts(tol=1e-11)
+    fd_opts = iobm.default_opts(precision=iobm.C128, tol=1e-13)
     T, dT = s.grad_transmission(w.energies, opts)
     dT = dT.cpu().numpy()
     vox = _fd_voxels(g, dT, 64, 1005)[:6]
@@ -91,8 +95,8 @@ def test_gradient_at_full_adjoint_workload(torch):
         Vp.flat[v] += d
         Vm.flat[v] -= d
         s.set_potential(Vp)
-        Tp = s.solve(w.energies, opts=opts)["T"].sum()
+        Tp = s.solve(w.energies, opts=fd_opts)["T"].sum()
         s.set_potential(Vm)
-        Tm = s.solve(w.energies, opts=opts)["T"].sum()
+        Tm = s.solve(w.energies, opts=fd_opts)["T"].sum()
         fd = (Tp - Tm) / (2 * d)
         assert abs(fd - dT.flat[v]) <= 1e-4 * abs(dT.flat[v]) + 1e-6 * np.abs(dT).max()

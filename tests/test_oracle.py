@@ -31,7 +31,7 @@ def _golden_fd():
 
 @pytest.mark.parametrize("nf", [1, 2, 3])
 def test_fd_coefficients_match_printed_and_textbook_values(nf):
-    assert O.fd_coefficients_exact(nf) == _golden_fd()[nf]
+    assert list(O.fd_coefficients_exact(nf)) == _golden_fd()[nf]
 
 
 @pytest.mark.parametrize("nf", [1, 2, 3])
