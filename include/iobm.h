@@ -211,13 +211,14 @@ iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, in
  * launches, their summed duration (ms) and the bytes of one pass over the
  * vectors they processed (right-hand sides x points x element size); the
  * record is kept until the next iobm_profile_begin. */
-enum { IOBM_K_STENCIL = 1,      /* FD stencil + (E - V) diagonal */
+enum { IOBM_K_STENCIL = 1,      /* FD stencil + (E - V) diagonal, complex64 */
        IOBM_K_BOUNDARY = 2,     /* FFT-applied electrode self-energy */
        IOBM_K_PRECOND_FFT = 3,  /* lateral-Fourier preconditioner */
        IOBM_K_PRECOND_LAP = 4,  /* Eq. (17) preconditioner */
        IOBM_K_NONLOCAL = 5,     /* nonlocal projector contraction (MFMA) */
        IOBM_K_DOT = 6,          /* bilinear / norm reductions */
-       IOBM_K_UPDATE = 7 };     /* x, r update with fused |r|^2 */
+       IOBM_K_UPDATE = 7,       /* x, r update with fused |r|^2 */
+       IOBM_K_STENCIL_C128 = 8 };/* FD stencil, complex128 (FP64 residuals) */
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask);
 iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
                              double* pass_bytes);

@@ -327,6 +327,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   HIPCHK((launch_convert<T, double>(ctx, b, r, nact, act_d)));
   HIPCHK((launch_convert<T, double>(ctx, nullptr, d, nact, act_d)));
   HIPCHK(hipMemcpyAsync(rhi, b, (size_t)nb * vol * sizeof(zd), hipMemcpyDeviceToDevice, ctx->stream));
+  autotune<T>(ctx, r, q, pf, nact, E_d, e_d, modes, act_d);
   precond(nact, act_d);
   HIPCHK((launch_convert<T, T>(ctx, z, p, nact, act_d)));
   HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
@@ -622,7 +623,7 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
 
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask) {
   if (!ctx) return IOBM_E_INVALID_ARG;
-  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_UPDATE + 1)))
+  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_STENCIL_C128 + 1)))
     return fail(ctx, IOBM_E_INVALID_ARG, "bad kernel class mask");
   ctx->prof_mask = class_mask;
   ctx->prof_used = 0;

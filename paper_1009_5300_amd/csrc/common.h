@@ -189,3 +189,51 @@ __device__ cplx<T>* fft2d_lds(cplx<T>* a, cplx<T>* b, const FFTPlan2D& p, const 
   }
   return src;
 }
+
+// ------------------------------------------------ in-register 1D FFT ------
+// Length-N transform held in registers (N known at compile time), same
+// Stockham stages as above with every index a compile-time constant.
+constexpr int pick_radix(int m) {
+  return m % 4 == 0 ? 4 : (m % 2 == 0 ? 2 : (m % 3 == 0 ? 3 : (m % 5 == 0 ? 5 : m)));
+}
+constexpr int count_stages(int n) {
+  int c = 0;
+  for (int m = n; m > 1; m /= pick_radix(m)) ++c;
+  return c;
+}
+
+template <typename T, int N, int Ns>
+__device__ __forceinline__ void reg_fft_stages(cplx<T>* a, cplx<T>* b, const cplx<T>* tw, int sign) {
+  if constexpr (Ns < N) {
+    constexpr int R = pick_radix(N / Ns);
+    constexpr int per = N / R;
+    constexpr int tstep = N / (Ns * R);
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+      const int k = j % Ns;
+      cplx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cplx<T> x = a[j + r * per];
+        if (r && k) x = x * twid(tw, (r * k * tstep) % N, sign);
+        v[r] = x;
+      }
+      dft_small<T, R>(v, tw, N, sign);
+      const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) b[idxD + r * Ns] = v[r];
+    }
+    reg_fft_stages<T, N, Ns * R>(b, a, tw, sign);
+  }
+}
+
+// x <- DFT_N(x), sign -1 forward / +1 inverse (unnormalised); tw[k] = exp(-2 pi i k / N)
+template <typename T, int N>
+__device__ __forceinline__ void reg_fft(cplx<T>* x, const cplx<T>* tw, int sign) {
+  cplx<T> y[N];
+  reg_fft_stages<T, N, 1>(x, y, tw, sign);
+  if constexpr (count_stages(N) % 2 == 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = y[i];
+  }
+}

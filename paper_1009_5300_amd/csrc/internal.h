@@ -77,6 +77,11 @@ struct iobm_ctx_s {
   unsigned char region_pending[64] = {0};
   // tuned launch shapes (0 = default rule)
   int tune_zf_c64 = 0, tune_zf_c128 = 0;
+  int tune_fft_generic = 0;  // 1: always use the LDS Stockham plane FFT
+  int tune_stencil_simple = 0;  // 1: cache-based stencil instead of the 2.5D one
+  int tune_ppt_c64 = 0, tune_ppt_c128 = 0;  // 2.5D stencil points per thread (0 = default)
+  int tune_zc_c64 = 0, tune_zc_c128 = 0;    // 2.5D stencil planes per block (0 = 32)
+  bool tuned_c64 = false, tuned_c128 = false;
   // kernel timing hook
   int prof_mask = 0;
   std::vector<hipEvent_t> prof_ev;  // start/stop pairs
@@ -113,5 +118,8 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
 template <typename T>
 hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, double* proj,
                            const int* active);
+template <typename T>
+void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
+              const int* e_rhs, const ModeData* modes, const int* active);
 size_t kb_proj_bytes(iobm_ctx c, int nrhs);
 double* kb_scratch(iobm_ctx c, size_t bytes);  // context-owned scratch for the projector sums

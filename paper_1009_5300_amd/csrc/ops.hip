@@ -77,6 +77,92 @@ __global__ void __launch_bounds__(256) k_apply(StencilArgs S, const cplx<T>* __r
   }
 }
 
+// 2.5D variant: a block owns all points of the lateral plane (up to MAXP per
+// thread) of one rhs over a chunk of planes.  The current plane sits in LDS
+// (double buffered, one barrier per plane) for the lateral neighbours; the
+// z neighbours come from a per-thread register queue of 2 NF + 2 planes,
+// which also prefetches the plane after the leading one.  Each x element is
+// read from memory once per chunk (plus 2 NF halo planes), each y written once.
+template <typename T, int NF, int MAXP>
+__global__ void __launch_bounds__(1024) k_apply25(StencilArgs S, const cplx<T>* __restrict__ x,
+                                                 cplx<T>* __restrict__ y, const T* __restrict__ V,
+                                                 const double* __restrict__ E_rhs,
+                                                 const int* __restrict__ active) {
+  extern __shared__ char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);  // [2][nxy]
+  constexpr int Q = 2 * NF + 2;
+  const int nxy = S.nxy, nz = S.nz;
+  const int slot = blockIdx.x / S.nchunks;
+  const int chunk = blockIdx.x - slot * S.nchunks;
+  const int rhs = rhs_of(active, slot);
+  const long long vol = (long long)nxy * nz;
+  const cplx<T>* xr = x + rhs * vol;
+  cplx<T>* yr = y + rhs * vol;
+  const T diag0 = Real<T>::v(E_rhs[rhs] + S.e0);
+  const int z0 = chunk * S.zchunk;
+  const int z1 = min(nz, z0 + S.zchunk);
+  T wx[NF + 1], wy[NF + 1], wz[NF + 1];
+#pragma unroll
+  for (int n = 1; n <= NF; ++n) { wx[n] = (T)S.wx[n]; wy[n] = (T)S.wy[n]; wz[n] = (T)S.wz[n]; }
+  cplx<T> q[Q][MAXP];  // q[NF + d][u] = x(z + d) at the thread's point u
+  T vq[2][MAXP];       // V(z), V(z + 1)
+  auto ld = [&](int z, int u) -> cplx<T> {
+    const int p = threadIdx.x + u * blockDim.x;
+    return (p < nxy && z >= 0 && z < nz) ? xr[(long long)z * nxy + p] : mk<T>(0, 0);
+  };
+#pragma unroll
+  for (int d = 0; d < Q - 1; ++d)
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) q[d][u] = ld(z0 - NF + d, u);
+#pragma unroll
+  for (int u = 0; u < MAXP; ++u) {
+    const int p = threadIdx.x + u * blockDim.x;
+    vq[0][u] = p < nxy ? V[(long long)z0 * nxy + p] : (T)0;
+  }
+  for (int z = z0; z < z1; ++z) {
+    const int b = (z - z0) & 1;
+    // prefetch plane z + NF + 1 and V(z + 1)
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) {
+      q[Q - 1][u] = ld(z + NF + 1, u);
+      const int p = threadIdx.x + u * blockDim.x;
+      vq[1][u] = (p < nxy && z + 1 < nz) ? V[(long long)(z + 1) * nxy + p] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) {
+      const int p = threadIdx.x + u * blockDim.x;
+      if (p < nxy) buf[b * nxy + p] = q[NF][u];
+    }
+    __syncthreads();
+    const cplx<T>* pl = buf + b * nxy;
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) {
+      const int p = threadIdx.x + u * blockDim.x;
+      if (p < nxy) {
+        const int j = p / S.nx;
+        const int i = p - j * S.nx;
+        cplx<T> acc = (diag0 - vq[0][u]) * q[NF][u];
+#pragma unroll
+        for (int n = 1; n <= NF; ++n) {
+          int ip = i + n; if (ip >= S.nx) ip -= S.nx;
+          int im = i - n; if (im < 0) im += S.nx;
+          int jp = j + n; if (jp >= S.ny) jp -= S.ny;
+          int jm = j - n; if (jm < 0) jm += S.ny;
+          acc = acc + wx[n] * (pl[j * S.nx + ip] + pl[j * S.nx + im]) + wy[n] * (pl[jp * S.nx + i] + pl[jm * S.nx + i]) +
+                wz[n] * (q[NF + n][u] + q[NF - n][u]);
+        }
+        yr[(long long)z * nxy + p] = acc;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < Q - 1; ++d)
+#pragma unroll
+      for (int u = 0; u < MAXP; ++u) q[d][u] = q[d + 1][u];
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) vq[0][u] = vq[1][u];
+  }
+}
+
 // ----------------------------------------------------- electrode term ---
 // y[boundary planes] -= Sigma x[boundary planes], applied in lateral
 // momentum space (Eqs. (14)-(16)): FFT each of the nf planes, mix the planes
@@ -195,6 +281,90 @@ __global__ void __launch_bounds__(256) k_fft_planes(FFTPlan2D plan, int nz, cons
   __syncthreads();
   cplx<T>* res = fft2d_lds(bufA, bufB, plan, twx, twy, sign);
   for (int p = threadIdx.x; p < nxy; p += blockDim.x) out[off + p] = scale * res[p];
+}
+
+// Square planes (N x N, N in a fixed list): each thread transforms one row
+// and then one column held in registers; the plane goes through LDS once
+// (padded rows, N + 1, against bank conflicts).  PPB planes per block.  The
+// global loads and stores move pairs of elements (16 bytes for complex64)
+// and every thread issues all of its loads before the first LDS store, so
+// that the few threads of a block keep many requests in flight.
+template <typename T> struct Pair;
+template <> struct Pair<float> { typedef float4 type; static constexpr int n = 2; };
+template <> struct Pair<double> { typedef double2 type; static constexpr int n = 1; };
+
+template <typename T, int N, int PPB>
+__global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes, const cplx<T>* in, cplx<T>* out,
+                                                           const cplx<T>* __restrict__ tw, int sign, T scale,
+                                                           const int* __restrict__ active) {
+  typedef typename Pair<T>::type VT;
+  constexpr int PE = Pair<T>::n;          // elements per vector access
+  constexpr int NN = N * N;
+  constexpr int NV = PPB * NN / PE;       // vector accesses per block
+  constexpr int BLK = N * PPB;
+  constexpr int EPT = (NV + BLK - 1) / BLK;
+  __shared__ cplx<T> sm[PPB][N][N + 1];
+  const long long vol = (long long)NN * nz;
+  const int g0 = blockIdx.x * PPB;
+  long long poff[PPB];
+  bool pok[PPB];
+#pragma unroll
+  for (int q = 0; q < PPB; ++q) {
+    const int gp = g0 + q;
+    pok[q] = gp < nplanes;
+    const int slot = pok[q] ? gp / nz : 0, z = pok[q] ? gp - slot * nz : 0;
+    poff[q] = (long long)rhs_of(active, slot) * vol + (long long)z * NN;
+  }
+  VT buf[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int v = threadIdx.x + e * BLK;
+    const int q = v / (NN / PE), w = v - q * (NN / PE);
+    if (v < NV && pok[q]) buf[e] = reinterpret_cast<const VT*>(in + poff[q])[w];
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int v = threadIdx.x + e * BLK;
+    const int q = v / (NN / PE), w = v - q * (NN / PE);
+    if (v < NV) {
+      const cplx<T>* c = reinterpret_cast<const cplx<T>*>(&buf[e]);
+#pragma unroll
+      for (int k = 0; k < PE; ++k) {
+        const int el = w * PE + k;
+        sm[q][el / N][el % N] = c[k];
+      }
+    }
+  }
+  __syncthreads();
+  const int pl = threadIdx.x / N, li = threadIdx.x - pl * N;
+  cplx<T> v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = sm[pl][li][i];  // row li
+  reg_fft<T, N>(v, tw, sign);
+#pragma unroll
+  for (int i = 0; i < N; ++i) sm[pl][li][i] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = sm[pl][i][li];  // column li
+  reg_fft<T, N>(v, tw, sign);
+#pragma unroll
+  for (int i = 0; i < N; ++i) sm[pl][i][li] = scale * v[i];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int vv = threadIdx.x + e * BLK;
+    const int q = vv / (NN / PE), w = vv - q * (NN / PE);
+    if (vv < NV && pok[q]) {
+      VT o;
+      cplx<T>* c = reinterpret_cast<cplx<T>*>(&o);
+#pragma unroll
+      for (int k = 0; k < PE; ++k) {
+        const int el = w * PE + k;
+        c[k] = sm[q][el / N][el % N];
+      }
+      reinterpret_cast<VT*>(out + poff[q])[w] = o;
+    }
+  }
 }
 
 // Recursive z filter in mode space.  Thread (mode m, chunk c) owns planes
@@ -766,15 +936,75 @@ static int fft_threads(int nxy) {
   return t;
 }
 
+// 2.5D stencil launch shape: points per thread (1, 2, 4 or 9; the block is
+// ceil(nxy / ppt) threads rounded to a wavefront, at most 1024) and planes
+// per block.  Chosen by the autotuner below, else a default rule.
+template <typename T>
+static bool launch_apply25_shape(iobm_ctx c, int ppt, int zc, const cplx<T>* x, cplx<T>* y, int nrhs,
+                                 const double* E_rhs, const int* active) {
+  const int nxy = c->g.nxy;
+  const int threads = ((nxy + ppt - 1) / ppt + 63) / 64 * 64;
+  if (threads > 1024 || ppt * threads < nxy) return false;
+  StencilArgs S = stencil_args(c, zc);
+  size_t sh = 2 * (size_t)nxy * sizeof(cplx<T>);
+  dim3 grid(nrhs * S.nchunks), blk(threads);
+#define IOBM_A25(NF, MP) hipLaunchKernelGGL((k_apply25<T, NF, MP>), grid, blk, sh, c->stream, S, x, y, Vptr<T>(c), E_rhs, active)
+#define IOBM_A25P(NF)                     \
+  if (ppt == 1) IOBM_A25(NF, 1);          \
+  else if (ppt == 2) IOBM_A25(NF, 2);     \
+  else if (ppt == 4) IOBM_A25(NF, 4);     \
+  else IOBM_A25(NF, 9);
+  switch (c->g.nf) {
+    case 1: IOBM_A25P(1); break;
+    case 2: IOBM_A25P(2); break;
+    default: IOBM_A25P(3); break;
+  }
+#undef IOBM_A25P
+#undef IOBM_A25
+  return true;
+}
+
+template <typename T> static int& tuned_ppt(iobm_ctx c) { return sizeof(T) == 4 ? c->tune_ppt_c64 : c->tune_ppt_c128; }
+template <typename T> static int& tuned_zc(iobm_ctx c) { return sizeof(T) == 4 ? c->tune_zc_c64 : c->tune_zc_c128; }
+
+static int default_ppt(int nxy, bool f32) {
+  const int want = f32 ? 4 : 2;  // keeps the register queue small enough for several waves per SIMD
+  int ppt = want;
+  while ((nxy + ppt - 1) / ppt > 1024) ppt = ppt == 1 ? 2 : (ppt == 2 ? 4 : 9);
+  if (ppt > 9 || (nxy + 8) / 9 > 1024) return 0;
+  return ppt;
+}
+
+template <typename T>
+static bool launch_apply25(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
+                           const int* active) {
+  if (c->tune_stencil_simple) return false;
+  int ppt = tuned_ppt<T>(c), zc = tuned_zc<T>(c);
+  if (ppt <= 0) ppt = default_ppt(c->g.nxy, sizeof(T) == 4);
+  if (zc <= 0) zc = 32;
+  if (ppt <= 0) return false;
+  return launch_apply25_shape<T>(c, ppt, zc, x, y, nrhs, E_rhs, active);
+}
+
+// Autotuner: time every admissible (points per thread, planes per block)
+// shape of the 2.5D stencil and every z-filter chunk length once on the
+// caller's own batch (x -> y, y is scratch), keep the fastest per precision.
+template <typename T>
+void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
+              const int* e_rhs, const ModeData* modes, const int* active);
+
 template <typename T>
 hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
                         const int* e_rhs, const ModeData* modes, const int* active) {
   if (nrhs <= 0) return hipSuccess;
-  StencilArgs S = stencil_args(c, 16);
-  prof_start(c, IOBM_K_STENCIL);
-  hipLaunchKernelGGL(k_apply<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, x, y, Vptr<T>(c),
-                     E_rhs, active);
-  prof_stop(c, IOBM_K_STENCIL, (double)nrhs * c->g.npts * sizeof(cplx<T>));
+  const int cls = sizeof(T) == 4 ? IOBM_K_STENCIL : IOBM_K_STENCIL_C128;
+  prof_start(c, cls);
+  if (!launch_apply25<T>(c, x, y, nrhs, E_rhs, active)) {
+    StencilArgs S = stencil_args(c, 16);
+    hipLaunchKernelGGL(k_apply<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, x, y, Vptr<T>(c),
+                       E_rhs, active);
+  }
+  prof_stop(c, cls, (double)nrhs * c->g.npts * sizeof(cplx<T>));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(cplx<T>);
@@ -799,12 +1029,38 @@ hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, 
   return hipGetLastError();
 }
 
+template <typename T, int N, int PPB>
+static void launch_fft_reg(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
+                           const int* active) {
+  const int nplanes = nrhs * c->g.nz;
+  hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB>), dim3((nplanes + PPB - 1) / PPB), dim3(N * PPB), 0, c->stream,
+                     c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active);
+}
+
+// planes per block of the register FFT: enough threads for a wavefront or two
+template <typename T>
+static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
+                             const int* active) {
+  if (c->g.nx != c->g.ny || c->tune_fft_generic) return false;
+  switch (c->g.nx) {
+    case 8: launch_fft_reg<T, 8, 16>(c, in, out, sign, scale, nrhs, active); return true;
+    case 12: launch_fft_reg<T, 12, 8>(c, in, out, sign, scale, nrhs, active); return true;
+    case 16: launch_fft_reg<T, 16, 8>(c, in, out, sign, scale, nrhs, active); return true;
+    case 24: launch_fft_reg<T, 24, 4>(c, in, out, sign, scale, nrhs, active); return true;
+    case 32: launch_fft_reg<T, 32, 4>(c, in, out, sign, scale, nrhs, active); return true;
+    case 48: launch_fft_reg<T, 48, 2>(c, in, out, sign, scale, nrhs, active); return true;
+    default: return false;
+  }
+}
+
 template <typename T>
 hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                              const int* active) {
-  size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
-                     twx<T>(c), twy<T>(c), sign, (T)scale, active);
+  if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active)) {
+    size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
+    hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
+                       twx<T>(c), twy<T>(c), sign, (T)scale, active);
+  }
   return hipGetLastError();
 }
 
@@ -850,6 +1106,57 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
   prof_stop(c, IOBM_K_PRECOND_FFT, (double)nrhs * c->g.npts * sizeof(cplx<T>));
   return err;
 }
+
+template <typename T>
+void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
+              const int* e_rhs, const ModeData* modes, const int* active) {
+  bool& done = sizeof(T) == 4 ? c->tuned_c64 : c->tuned_c128;
+  if (done || nrhs <= 0) return;
+  done = true;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return;
+  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+  auto timed = [&](auto&& fn) -> float {
+    fn();  // warm-up (first launch of a shape)
+    (void)hipEventRecord(a, c->stream);
+    fn();
+    fn();
+    (void)hipEventRecord(b, c->stream);
+    float ms = 1e30f;
+    if (hipEventSynchronize(b) == hipSuccess && hipGetLastError() == hipSuccess) (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+  };
+  if (!c->tune_stencil_simple) {
+    float best = 1e30f;
+    int bp = 0, bz = 0;
+    for (int ppt : {1, 2, 4, 9})
+      for (int zc : {16, 32, 64}) {
+        const int threads = ((c->g.nxy + ppt - 1) / ppt + 63) / 64 * 64;
+        if (threads > 1024 || (sizeof(T) == 8 && ppt == 9)) continue;
+        if (zc > c->g.nz && zc != 16) continue;
+        float t = timed([&] { launch_apply25_shape<T>(c, ppt, zc, x, y, nrhs, E_rhs, active); });
+        if (t < best) { best = t; bp = ppt; bz = zc; }
+      }
+    if (bp > 0) { tuned_ppt<T>(c) = bp; tuned_zc<T>(c) = bz; }
+  }
+  if (scratch) {
+    float best = 1e30f;
+    int bl = 0;
+    for (int L : {8, 16, 32}) {
+      if ((c->g.nz + L - 1) / L > 8) continue;
+      float t = timed([&] { (void)launch_zfilter<T>(c, L, scratch, y, nrhs, e_rhs, modes, active); });
+      if (t < best) { best = t; bl = L; }
+    }
+    if (bl > 0) (sizeof(T) == 4 ? c->tune_zf_c64 : c->tune_zf_c128) = bl;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+}
+
+template void autotune<float>(iobm_ctx, const zf*, zf*, zf*, int, const double*, const int*, const ModeData*,
+                              const int*);
+template void autotune<double>(iobm_ctx, const zd*, zd*, zd*, int, const double*, const int*, const ModeData*,
+                               const int*);
 
 template hipError_t launch_apply<double>(iobm_ctx, const zd*, zd*, int, const double*, const int*,
                                          const ModeData*, const int*);

@@ -140,3 +140,38 @@ def test_bad_arguments_return_status(torch):
     with pytest.raises(iobm.IobmError) as e:
         s.solve([0.3], opts=iobm.default_opts(tol=0.0))
     assert e.value.status == 1
+
+
+SQUARE = [Grid(8, 8, 24, 0.4, 1), Grid(16, 16, 20, 0.4, 2), Grid(24, 24, 16, 0.35, 3), Grid(12, 12, 40, 0.4, 2)]
+
+
+@pytest.mark.parametrize("g", SQUARE, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
+def test_lateral_fft_preconditioner_square_planes(torch, g):
+    """Square lateral planes take the in-register FFT path."""
+    from paper_1009_5300_amd import iobm
+    s = _solver(g, np.zeros(g.shape))
+    E = 1.1
+    r = random_field((2,) + g.shape, 8)
+    ref = O.precond.flat_wire_inverse(g, E, r)
+    rt = torch.as_tensor(r, device="cuda")
+    z = s.precondition(iobm.PC_LATERAL_FFT, rt, E=E).cpu().numpy()
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+    z32 = s.precondition(iobm.PC_LATERAL_FFT, rt.to(torch.complex64), E=E, precision=iobm.C64_REFINED).cpu().numpy()
+    assert np.abs(z32 - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,nz", [(32, 96), (48, 128)])
+def test_lateral_fft_preconditioner_inverts_flat_operator(torch, n, nz):
+    """At the workloads' cross-sections (any size): P (A_0 x) = x, with A_0 x
+    the oracle's flat-wire operator applied to a seeded x."""
+    from paper_1009_5300_amd import iobm
+    g = Grid(n, n, nz, 0.4, 2)
+    s = _solver(g, np.zeros(g.shape))
+    E = 0.8
+    x = random_field((1,) + g.shape, 9)
+    y = O.Problem(g, np.zeros(g.shape)).apply(E, x.reshape(1, -1)).reshape(x.shape)
+    z = s.precondition(iobm.PC_LATERAL_FFT, torch.as_tensor(y, device="cuda"), E=E).cpu().numpy()
+    assert np.abs(z - x).max() <= 1e-9 * np.abs(x).max()
+    z32 = s.precondition(iobm.PC_LATERAL_FFT, torch.as_tensor(y, device="cuda").to(torch.complex64), E=E,
+                         precision=iobm.C64_REFINED).cpu().numpy()
+    assert np.abs(z32 - x).max() <= 1e-3 * np.abs(x).max()
