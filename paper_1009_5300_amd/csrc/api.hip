@@ -36,11 +36,9 @@ hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, 
 template <typename T, typename TX>
 hipError_t launch_update_xr(iobm_ctx c, cplx<TX>* x, const cplx<T>* p, cplx<T>* r, const cplx<T>* q,
                             const zd* alpha, int nact, const int* active, void* part);
-template <typename T>
-hipError_t launch_update_p(iobm_ctx c, cplx<T>* p, const cplx<T>* z, const zd* beta, int nact,
-                           const int* active);
-hipError_t launch_finish(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const void* part,
-                         int mode, int nact, const int* active);
+enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3 };
+hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const Partial* pa,
+                          int na, const Partial* pb, int nb, int mode, int nact, const int* active);
 template <typename T>
 hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const int* active);
 template <typename TD, typename TS>
@@ -87,8 +85,8 @@ iobm_status fail(iobm_ctx ctx, iobm_status s, const std::string& msg) {
 
 // ------------------------------------------------------------- scratch pool
 enum Slot {
-  S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_Q, S_D, S_PF, S_PART, S_SCAL, S_IDX, S_AMP, S_TR, S_KB,
-  S_GRAD_U, S_GRAD_D, NSLOT
+  S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_P2, S_Q, S_D, S_PF, S_PART, S_PARTA, S_PARTZ, S_SCAL, S_IDX, S_AMP,
+  S_TR, S_KB, S_GRAD_U, S_GRAD_D, NSLOT
 };
 
 void* scratch(iobm_ctx ctx, int slot, size_t bytes) {
@@ -266,12 +264,18 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   zd* rhi = (zd*)scratch(ctx, S_RHI, (size_t)nb * vol * sizeof(zd));
   cplx<T>* d = (cplx<T>*)scratch(ctx, S_D, vb);
   cplx<T>* r = (cplx<T>*)scratch(ctx, S_R, vb);
-  cplx<T>* p = (cplx<T>*)scratch(ctx, S_P, vb);
+  cplx<T>* pa = (cplx<T>*)scratch(ctx, S_P, vb);   // direction, two buffers used in turn
+  cplx<T>* pb = (cplx<T>*)scratch(ctx, S_P2, vb);
   cplx<T>* q = (cplx<T>*)scratch(ctx, S_Q, vb);
   cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)scratch(ctx, S_Z, vb);
   cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)scratch(ctx, S_PF, vb) : nullptr;
   const int nblk = dot_blocks(ctx);
-  void* part = scratch(ctx, S_PART, (size_t)nb * nblk * 32);
+  const int nz_slots = precond_slots(ctx, o.precond);
+  Partial* part = (Partial*)scratch(ctx, S_PART, (size_t)nb * nblk * sizeof(Partial));
+  Partial* part_pq = (Partial*)scratch(ctx, S_PARTA, (size_t)nb * PQ_SLOTS * sizeof(Partial));
+  Partial* part_rz = o.precond == IOBM_PC_NONE
+                         ? part
+                         : (Partial*)scratch(ctx, S_PARTZ, (size_t)nb * nz_slots * sizeof(Partial));
   char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * (3 * sizeof(zd) + 2 * sizeof(double) + sizeof(int)) + 64);
   zd* rho = (zd*)sc;
   zd* alpha = rho + nb;
@@ -286,11 +290,15 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   const double delta2 = lowp ? o.inner_tol * o.inner_tol : 0.0;
   const int check = std::max(1, o.check_every);
 
+  // z = P r for the listed rhs, with the partials of r^T z in part_rz (for
+  // P = I they come from a separate reduction)
   auto precond = [&](int nact, const int* ad) {
     if (o.precond == IOBM_PC_TRUNCATED_LAPLACIAN)
-      HIPCHK(launch_precond_laplacian<T>(ctx, o.alpha, r, z, nact, ad));
+      HIPCHK(launch_precond_laplacian<T>(ctx, o.alpha, r, z, nact, ad, part_rz));
     else if (o.precond == IOBM_PC_LATERAL_FFT)
-      HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nact, e_d, modes, ad));
+      HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nact, e_d, modes, ad, part_rz));
+    else
+      HIPCHK(launch_dot<T>(ctx, r, r, nact, ad, part_rz));
   };
   // true residual r_hi = b - A x for the listed rhs; |r_hi|^2 -> host
   std::vector<double> tn2_h(nb), rn2_h(nb), bn2(nb);
@@ -301,17 +309,18 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     HIPCHK(launch_apply<double>(ctx, x, rhi, n, E_d, e_d, modes, ld));
     HIPCHK(launch_residual<double>(ctx, b, rhi, n, ld));
     HIPCHK(launch_dot<double>(ctx, rhi, rhi, n, ld, part));
-    HIPCHK(launch_finish(ctx, rho, alpha, beta, tn2, flag, part, 3, n, ld));
+    HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld));
     HIPCHK(hipMemcpyAsync(tn2_h.data(), tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     stream_sync(ctx);
     return ld;
   };
 
-  // start: x = 0, r_hi = b, d = 0, r = r_hi, z = P r, p = z, rho = r^T z
+  // start: x = 0, r_hi = b, d = 0, r = r_hi, z = P r, rho = r^T z, beta = 0
   HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * vol * sizeof(zd), ctx->stream));
   HIPCHK(hipMemsetAsync(flag, 0, nb * sizeof(int), ctx->stream));
+  HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   HIPCHK(launch_dot<double>(ctx, b, b, nb, all_d, part));
-  HIPCHK(launch_finish(ctx, rho, alpha, beta, tn2, flag, part, 3, nb, all_d));
+  HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, nb, all_d));
   HIPCHK(hipMemcpyAsync(bn2.data(), tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   stream_sync(ctx);
   std::vector<int> act;
@@ -327,93 +336,87 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   HIPCHK((launch_convert<T, double>(ctx, b, r, nact, act_d)));
   HIPCHK((launch_convert<T, double>(ctx, nullptr, d, nact, act_d)));
   HIPCHK(hipMemcpyAsync(rhi, b, (size_t)nb * vol * sizeof(zd), hipMemcpyDeviceToDevice, ctx->stream));
-  autotune<T>(ctx, r, q, pf, nact, E_d, e_d, modes, act_d);
+  if (!(lowp ? ctx->tuned_c64 : ctx->tuned_c128)) {
+    // the shapes are timed on the fused operator with p_old = 0 and a
+    // nonzero beta (0x3F bytes: 4.8e-4), so that every stream is read
+    HIPCHK(hipMemsetAsync(pa, 0, vb, ctx->stream));
+    HIPCHK(hipMemsetAsync(beta, 0x3F, nb * sizeof(zd), ctx->stream));
+    ApplyFuse<T> TF{r, pa, beta, pb, part_pq};
+    autotune<T>(ctx, r, q, pf, nact, E_d, e_d, modes, act_d, &TF);
+    HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
+  }
   precond(nact, act_d);
-  HIPCHK((launch_convert<T, T>(ctx, z, p, nact, act_d)));
-  HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
-  HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 2, nact, act_d));
+  HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nact, act_d));
 
+  // One iteration is three passes over the batch:
+  //   operator:  p_new = z + beta p_old, q = A p_new, partials of p_new^T q
+  //   update:    d += alpha p_new, r -= alpha q, partials of |r|^2 (and r^T r)
+  //   precond:   z = P r, partials of r^T z
+  // with the scalar steps (alpha; beta, rho, |r|^2) in between.
+  cplx<T>* pold = pa;
+  cplx<T>* pnew = pb;
   while (nact > 0) {
     for (int k = 0; k < check; ++k) {
-      HIPCHK(launch_apply<T>(ctx, p, q, nact, E_d, e_d, modes, act_d));
-      HIPCHK(launch_dot<T>(ctx, p, q, nact, act_d, part));
-      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 0, nact, act_d));
-      HIPCHK((launch_update_xr<T, T>(ctx, d, p, r, q, alpha, nact, act_d, part)));
-      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 3, nact, act_d));
-      if (k == check - 1) break;
-      precond(nact, act_d);
-      HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
-      HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 1, nact, act_d));
-      HIPCHK(launch_update_p<T>(ctx, p, z, beta, nact, act_d));
+      ApplyFuse<T> F{z, pold, beta, pnew, part_pq};
+      HIPCHK(launch_apply<T>(ctx, nullptr, q, nact, E_d, e_d, modes, act_d, &F));
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_pq, PQ_SLOTS, nullptr, 0, FIN_ALPHA, nact, act_d));
+      HIPCHK((launch_update_xr<T, T>(ctx, d, pnew, r, q, alpha, nact, act_d, part)));
+      if (o.precond != IOBM_PC_NONE) precond(nact, act_d);  // P = I: r^T r came with the update
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, part, nblk, FIN_BETA, nact, act_d));
+      std::swap(pold, pnew);
     }
     HIPCHK(hipMemcpyAsync(rn2_h.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipMemcpyAsync(flag_h.data(), flag, nb * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     stream_sync(ctx);
     // which rhs fold their correction into x and refresh the residual
-    std::vector<int> upd, restart;
+    std::vector<int> upd;
     for (int i : act) {
       out.iters[i] += check;
       const double r2 = rn2_h[i];
       const bool bad = flag_h[i] || !(r2 == r2) || r2 > 1e4 * maxr2[i];  // breakdown or divergence
       if (bad || r2 <= 0.25 * tol2 * bn2[i] || r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter) upd.push_back(i);
       else maxr2[i] = std::max(maxr2[i], r2);
-      if (bad) restart.push_back(i);
     }
+    if (upd.empty()) continue;
+    int* ud = upload(ctx, S_IDX, upd, 48 * 1024);
+    const int nu = (int)upd.size();
+    HIPCHK(launch_accumulate<T>(ctx, x, d, nu, ud));
+    true_residual(upd, 7);
+    std::vector<int> cont;  // updated rhs that go on iterating, from a restart
+    for (int i : upd) {
+      out.refin[i] += 1;
+      const double t2 = tn2_h[i];
+      if (t2 <= tol2 * bn2[i]) continue;  // converged
+      if (out.iters[i] >= o.max_iter) { out.status[i] = IOBM_E_NOT_CONVERGED; continue; }
+      if (t2 < 0.25 * best[i]) { best[i] = t2; stall[i] = 0; }
+      else if (++stall[i] >= 6) {
+        out.status[i] = flag_h[i] ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
+        continue;
+      }
+      cont.push_back(i);
+      maxr2[i] = t2;
+    }
+    if (!cont.empty()) {
+      // r = r_hi, d = 0, z = P r, rho = r^T z, beta = 0 (p_new = z next)
+      int* cd = upload(ctx, S_IDX, cont, 56 * 1024);
+      const int nc = (int)cont.size();
+      HIPCHK((launch_convert<T, double>(ctx, rhi, r, nc, cd)));
+      HIPCHK((launch_convert<T, double>(ctx, nullptr, d, nc, cd)));
+      precond(nc, cd);
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nc, cd));
+    }
+    std::vector<char> gone(nb, 0);
+    for (int i : upd) gone[i] = 1;
+    for (int i : cont) gone[i] = 0;
     std::vector<int> keep;
-    if (!upd.empty()) {
-      int* ud = upload(ctx, S_IDX, upd, 48 * 1024);
-      const int nu = (int)upd.size();
-      HIPCHK(launch_accumulate<T>(ctx, x, d, nu, ud));
-      true_residual(upd, 7);
-      std::vector<int> cont;  // updated rhs that go on iterating
-      for (int i : upd) {
-        out.refin[i] += 1;
-        const double t2 = tn2_h[i];
-        if (t2 <= tol2 * bn2[i]) continue;  // converged
-        if (out.iters[i] >= o.max_iter) { out.status[i] = IOBM_E_NOT_CONVERGED; continue; }
-        if (t2 < 0.25 * best[i]) { best[i] = t2; stall[i] = 0; }
-        else if (++stall[i] >= 6) {
-          out.status[i] = flag_h[i] ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
-          continue;
-        }
-        cont.push_back(i);
-        maxr2[i] = t2;
-        if (!flag_h[i]) restart.push_back(i);
-      }
-      if (!cont.empty()) {
-        int* cd = upload(ctx, S_IDX, cont, 56 * 1024);
-        HIPCHK((launch_convert<T, double>(ctx, rhi, r, (int)cont.size(), cd)));
-        HIPCHK((launch_convert<T, double>(ctx, nullptr, d, (int)cont.size(), cd)));
-      }
-      std::vector<char> gone(nb, 1);
-      for (int i : act) gone[i] = 0;
-      for (int i : upd) gone[i] = 1;
-      for (int i : cont) gone[i] = 0;
-      for (int i : act)
-        if (!gone[i]) keep.push_back(i);
-    } else {
-      keep = act;
-    }
+    for (int i : act)
+      if (!gone[i]) keep.push_back(i);
     if (keep.size() != act.size()) {
       act = keep;
       nact = (int)act.size();
       if (nact == 0) break;
       act_d = upload(ctx, S_IDX, act, 64 * 1024);
     }
-    // next direction; a restarted rhs takes p = z
-    precond(nact, act_d);
-    HIPCHK(launch_dot<T>(ctx, r, z, nact, act_d, part));
-    HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 1, nact, act_d));
-    if (!restart.empty()) {
-      std::vector<int> rs;
-      for (int i : restart)
-        if (std::find(act.begin(), act.end(), i) != act.end()) rs.push_back(i);
-      if (!rs.empty()) {
-        int* rd = upload(ctx, S_IDX, rs, 40 * 1024);
-        HIPCHK(launch_finish(ctx, rho, alpha, beta, rn2, flag, part, 4, (int)rs.size(), rd));
-      }
-    }
-    HIPCHK(launch_update_p<T>(ctx, p, z, beta, nact, act_d));
   }
   for (int i = 0; i < nb; ++i) {
     out.rel[i] = bn2[i] > 0 ? sqrt(tn2_h[i] / bn2[i]) : 0.0;

@@ -105,21 +105,52 @@ struct RhsMap {        // device arrays describing a batch of right-hand sides
 
 hipError_t launch_modes(iobm_ctx c, const double* E_d, int nE, ModeData* out);
 
+// Per-rhs FP64 partial sums of a bilinear form u^T v (re, im) and of |u|^2
+// (n2), one per block, combined in a fixed order.
+struct Partial {
+  double re, im, n2, pad;
+};
+
+// Slots of the per-rhs partials of mu = p^T A p written by the fused
+// operator: stencil chunks [0, PQ_STENCIL_MAX), the two electrode faces at
+// PQ_BOUNDARY and PQ_BOUNDARY + 1, the nonlocal term at PQ_KB.  Unused
+// slots hold zeros (the buffer is cleared once per solve).
+enum { PQ_STENCIL_MAX = 64, PQ_BOUNDARY = 64, PQ_KB = 66, PQ_SLOTS = 68 };
+
+// Fused COCG direction update for launch_apply: the operand is
+// pnew = z + beta p_old (beta per rhs; p_old is not read where beta = 0),
+// written to pnew, and the partials of pnew^T (A pnew) go to part.
+template <typename T>
+struct ApplyFuse {
+  const cplx<T>* z;
+  const cplx<T>* pold;
+  const zd* beta;
+  cplx<T>* pnew;
+  Partial* part;  // [rhs][PQ_SLOTS]
+};
+
 template <typename T>
 hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
-                        const int* e_rhs, const ModeData* modes, const int* active);
+                        const int* e_rhs, const ModeData* modes, const int* active,
+                        const ApplyFuse<T>* fuse = nullptr);
+// The preconditioners optionally write the per-rhs partials of r^T z to
+// dpart (precond_slots(c, pc) per rhs).
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z,
-                                    int nrhs, const int* active);
+                                    int nrhs, const int* active, Partial* dpart = nullptr);
 template <typename T>
 hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch,
                               int nrhs, const int* e_rhs, const ModeData* modes,
-                              const int* active);
+                              const int* active, Partial* dpart = nullptr);
+int precond_slots(iobm_ctx c, int precond);
 template <typename T>
-hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, double* proj,
+hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, Partial* pq_part,
                            const int* active);
+// Times the admissible stencil shapes (on the fused operator when `fuse` is
+// given; its buffers are overwritten) and z-filter chunk lengths once per
+// context and precision.
 template <typename T>
 void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
-              const int* e_rhs, const ModeData* modes, const int* active);
+              const int* e_rhs, const ModeData* modes, const int* active, const ApplyFuse<T>* fuse = nullptr);
 size_t kb_proj_bytes(iobm_ctx c, int nrhs);
 double* kb_scratch(iobm_ctx c, size_t bytes);  // context-owned scratch for the projector sums

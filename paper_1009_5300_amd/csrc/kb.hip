@@ -84,12 +84,16 @@ __global__ void __launch_bounds__(64) k_kb_project(KBData kb, long long vol, int
   }
 }
 
-// Sum the K-split partials in fixed order, then W = (h^3 D) C, FP64.
+// Sum the K-split partials in fixed order, then W = (h^3 D) C, FP64.  With
+// pq set, also the nonlocal part of x^T (A x), which is -C^T W, to
+// pq[rhs][PQ_KB].
 __global__ void k_kb_scale(KBData kb, int nact, int ksplit, const double* __restrict__ part,
-                           double* __restrict__ W) {
+                           double* __restrict__ W, Partial* __restrict__ pq,
+                           const int* __restrict__ active) {
   const int slot = blockIdx.x;
   const int p = threadIdx.x;
   __shared__ double C[2 * 128];
+  __shared__ double Wsh[2 * 128];
   if (p < kb.nproj_pad) {
     double re = 0, im = 0;
     for (int s = 0; s < ksplit; ++s) {
@@ -111,6 +115,20 @@ __global__ void k_kb_scale(KBData kb, int nact, int ksplit, const double* __rest
     }
     W[((long long)slot * kb.nproj_pad + p) * 2] = re;
     W[((long long)slot * kb.nproj_pad + p) * 2 + 1] = im;
+    Wsh[2 * p] = re;
+    Wsh[2 * p + 1] = im;
+  }
+  if (!pq) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double re = 0, im = 0;
+    for (int q = 0; q < kb.nproj; ++q) {
+      re -= C[2 * q] * Wsh[2 * q] - C[2 * q + 1] * Wsh[2 * q + 1];
+      im -= C[2 * q] * Wsh[2 * q + 1] + C[2 * q + 1] * Wsh[2 * q];
+    }
+    Partial P;
+    P.re = re; P.im = im; P.n2 = 0; P.pad = 0;
+    pq[(long long)(active ? active[slot] : slot) * PQ_SLOTS + PQ_KB] = P;
   }
 }
 
@@ -156,9 +174,8 @@ size_t kb_proj_bytes(iobm_ctx c, int nrhs) {
 }
 
 template <typename T>
-hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, double* proj,
+hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, Partial* pq_part,
                            const int* active) {
-  (void)proj;
   const KBData& kb = c->kb;
   const int ks = kb_ksplit(kb);
   size_t part_elems = (size_t)ks * nrhs * kb.nproj_pad * 2;
@@ -172,7 +189,7 @@ hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, d
   prof_stop(c, IOBM_K_NONLOCAL, (double)nrhs * kb.nu * sizeof(cplx<T>));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_kb_scale, dim3(nrhs), dim3(128), 0, c->stream, kb, nrhs, ks, part, W);
+  hipLaunchKernelGGL(k_kb_scale, dim3(nrhs), dim3(128), 0, c->stream, kb, nrhs, ks, part, W, pq_part, active);
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   int bx = (kb.nu + 255) / 256;
@@ -182,5 +199,5 @@ hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, d
   return hipGetLastError();
 }
 
-template hipError_t launch_kb_apply<double>(iobm_ctx, const zd*, zd*, int, double*, const int*);
-template hipError_t launch_kb_apply<float>(iobm_ctx, const zf*, zf*, int, double*, const int*);
+template hipError_t launch_kb_apply<double>(iobm_ctx, const zd*, zd*, int, Partial*, const int*);
+template hipError_t launch_kb_apply<float>(iobm_ctx, const zf*, zf*, int, Partial*, const int*);

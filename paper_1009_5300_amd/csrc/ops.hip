@@ -13,6 +13,52 @@ __device__ __forceinline__ int rhs_of(const int* active, int slot) {
   return active ? active[slot] : slot;
 }
 
+// ------------------------------------------------------- reductions ---
+// Per-rhs partial sums of the bilinear form a^T b (no conjugation, the COCG
+// inner product for the complex-symmetric A) and of |a|^2, accumulated in
+// FP64; one partial per block, combined in fixed order by k_finish2.
+// block_reduce3 needs a block of whole wavefronts; the result is in thread 0.
+__device__ __forceinline__ void block_reduce3(double& a, double& b, double& c) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+    c += __shfl_xor(c, off);
+  }
+  __shared__ double sh[3][16];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double ra = 0, rb = 0, rc = 0;
+    for (int i = 0; i < nw; ++i) { ra += sh[0][i]; rb += sh[1][i]; rc += sh[2][i]; }
+    a = ra; b = rb; c = rc;
+  }
+}
+
+// Block sum of two values for a block of BLK >= 64 threads that need not be
+// whole wavefronts: staged through LDS, the first wavefront sums strided
+// entries and then reduces across its lanes.  Result in thread 0.
+template <int BLK>
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  static_assert(BLK >= 64, "block_sum2 needs at least one full wavefront");
+  __shared__ double red[2][BLK];
+  __syncthreads();
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double x = 0, y = 0;
+    for (int i = threadIdx.x; i < BLK; i += 64) { x += red[0][i]; y += red[1][i]; }
+    for (int off = 32; off > 0; off >>= 1) {
+      x += __shfl_xor(x, off);
+      y += __shfl_xor(y, off);
+    }
+    a = x;
+    b = y;
+  }
+}
+
 template <typename T> struct Real;
 template <> struct Real<double> { static __device__ __forceinline__ double v(double x) { return x; } };
 template <> struct Real<float> { static __device__ __forceinline__ float v(double x) { return (float)x; } };
@@ -34,45 +80,82 @@ struct StencilArgs {
   double wx[4], wy[4], wz[4];
 };
 
+// Optional fusion of the COCG direction update into the operator: the
+// operand is p_new = z + beta p_old (written to pnew for the block's own
+// planes), and the block's partial p_new^T y goes to part[rhs][np] at the
+// block's chunk index.
+template <typename T>
+struct FuseP {
+  const cplx<T>* z = nullptr;
+  const cplx<T>* pold = nullptr;
+  const zd* beta = nullptr;
+  cplx<T>* pnew = nullptr;
+  Partial* part = nullptr;
+  int np = 0;
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply(StencilArgs S, const cplx<T>* __restrict__ x,
                                                cplx<T>* __restrict__ y, const T* __restrict__ V,
                                                const double* __restrict__ E_rhs,
-                                               const int* __restrict__ active) {
+                                               const int* __restrict__ active, FuseP<T> F) {
   const int slot = blockIdx.x / S.nchunks;
   const int chunk = blockIdx.x - slot * S.nchunks;
   const int rhs = rhs_of(active, slot);
   const long long vol = (long long)S.nxy * S.nz;
-  const cplx<T>* xr = x + rhs * vol;
+  const cplx<T>* xr = x ? x + rhs * vol : nullptr;
   cplx<T>* yr = y + rhs * vol;
+  const cplx<T>* zr = F.z ? F.z + rhs * vol : nullptr;
+  const cplx<T>* pr = F.pold ? F.pold + rhs * vol : nullptr;
+  const cplx<T> bt = F.z ? cvt<T>(F.beta[rhs]) : mk<T>(0, 0);
+  const bool use_p = F.z && (bt.re != (T)0 || bt.im != (T)0);
+  auto val = [&](long long o) -> cplx<T> {
+    if (!zr) return xr[o];
+    cplx<T> v = zr[o];
+    if (use_p) v = v + bt * pr[o];
+    return v;
+  };
   const T diag0 = Real<T>::v(E_rhs[rhs] + S.e0);
   const int z0 = chunk * S.zchunk;
   const int z1 = min(S.nz, z0 + S.zchunk);
   T wx[4], wy[4], wz[4];
 #pragma unroll
   for (int n = 1; n <= 3; ++n) { wx[n] = (T)S.wx[n]; wy[n] = (T)S.wy[n]; wz[n] = (T)S.wz[n]; }
+  double s_re = 0, s_im = 0;
   for (int z = z0; z < z1; ++z) {
-    const cplx<T>* xp = xr + (long long)z * S.nxy;
+    const long long zo = (long long)z * S.nxy;
     for (int p = threadIdx.x; p < S.nxy; p += blockDim.x) {
       const int j = p / S.nx;
       const int i = p - j * S.nx;
-      const cplx<T> c0 = xp[p];
-      const T d = diag0 - V[(long long)z * S.nxy + p];
+      const cplx<T> c0 = val(zo + p);
+      if (F.pnew) F.pnew[rhs * vol + zo + p] = c0;
+      const T d = diag0 - V[zo + p];
       cplx<T> acc = d * c0;
       for (int n = 1; n <= S.nf; ++n) {
         int ip = i + n; if (ip >= S.nx) ip -= S.nx;
         int im = i - n; if (im < 0) im += S.nx;
         int jp = j + n; if (jp >= S.ny) jp -= S.ny;
         int jm = j - n; if (jm < 0) jm += S.ny;
-        cplx<T> sx = xp[j * S.nx + ip] + xp[j * S.nx + im];
-        cplx<T> sy = xp[jp * S.nx + i] + xp[jm * S.nx + i];
+        cplx<T> sx = val(zo + j * S.nx + ip) + val(zo + j * S.nx + im);
+        cplx<T> sy = val(zo + jp * S.nx + i) + val(zo + jm * S.nx + i);
         acc = acc + wx[n] * sx + wy[n] * sy;
         cplx<T> sz = mk<T>(0, 0);
-        if (z + n < S.nz) sz = sz + xp[(long long)n * S.nxy + p];
-        if (z - n >= 0) sz = sz + xp[-(long long)n * S.nxy + p];
+        if (z + n < S.nz) sz = sz + val(zo + (long long)n * S.nxy + p);
+        if (z - n >= 0) sz = sz + val(zo - (long long)n * S.nxy + p);
         acc = acc + wz[n] * sz;
       }
-      yr[(long long)z * S.nxy + p] = acc;
+      yr[zo + p] = acc;
+      s_re += (double)c0.re * acc.re - (double)c0.im * acc.im;
+      s_im += (double)c0.re * acc.im + (double)c0.im * acc.re;
+    }
+  }
+  if (F.part) {
+    double dummy = 0;
+    block_reduce3(s_re, s_im, dummy);
+    if (threadIdx.x == 0) {
+      Partial P;
+      P.re = s_re; P.im = s_im; P.n2 = 0; P.pad = 0;
+      F.part[(long long)rhs * F.np + chunk] = P;
     }
   }
 }
@@ -83,11 +166,18 @@ __global__ void __launch_bounds__(256) k_apply(StencilArgs S, const cplx<T>* __r
 // z neighbours come from a per-thread register queue of 2 NF + 2 planes,
 // which also prefetches the plane after the leading one.  Each x element is
 // read from memory once per chunk (plus 2 NF halo planes), each y written once.
-template <typename T, int NF, int MAXP>
-__global__ void __launch_bounds__(1024) k_apply25(StencilArgs S, const cplx<T>* __restrict__ x,
+// Largest block of each points-per-thread variant (any nxy <= 4096 has an
+// admissible variant); the bound sets the compiler's register budget.
+template <int MAXP>
+struct A25 {
+  static constexpr int max_threads = MAXP == 4 ? 640 : (MAXP == 9 ? 512 : 1024);
+};
+
+template <typename T, int NF, int MAXP, bool FU>
+__global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs S, const cplx<T>* __restrict__ x,
                                                  cplx<T>* __restrict__ y, const T* __restrict__ V,
                                                  const double* __restrict__ E_rhs,
-                                                 const int* __restrict__ active) {
+                                                 const int* __restrict__ active, FuseP<T> F) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);  // [2][nxy]
   constexpr int Q = 2 * NF + 2;
@@ -96,7 +186,7 @@ __global__ void __launch_bounds__(1024) k_apply25(StencilArgs S, const cplx<T>* 
   const int chunk = blockIdx.x - slot * S.nchunks;
   const int rhs = rhs_of(active, slot);
   const long long vol = (long long)nxy * nz;
-  const cplx<T>* xr = x + rhs * vol;
+  const cplx<T>* xr = x ? x + rhs * vol : nullptr;
   cplx<T>* yr = y + rhs * vol;
   const T diag0 = Real<T>::v(E_rhs[rhs] + S.e0);
   const int z0 = chunk * S.zchunk;
@@ -106,10 +196,24 @@ __global__ void __launch_bounds__(1024) k_apply25(StencilArgs S, const cplx<T>* 
   for (int n = 1; n <= NF; ++n) { wx[n] = (T)S.wx[n]; wy[n] = (T)S.wy[n]; wz[n] = (T)S.wz[n]; }
   cplx<T> q[Q][MAXP];  // q[NF + d][u] = x(z + d) at the thread's point u
   T vq[2][MAXP];       // V(z), V(z + 1)
+  // fused direction update: x = z + beta p_old, formed while loading
+  const cplx<T>* zr = FU ? F.z + rhs * vol : nullptr;
+  const cplx<T>* pr = FU ? F.pold + rhs * vol : nullptr;
+  const cplx<T> bt = FU ? cvt<T>(F.beta[rhs]) : mk<T>(0, 0);
+  const bool use_p = FU && (bt.re != (T)0 || bt.im != (T)0);
   auto ld = [&](int z, int u) -> cplx<T> {
     const int p = threadIdx.x + u * blockDim.x;
-    return (p < nxy && z >= 0 && z < nz) ? xr[(long long)z * nxy + p] : mk<T>(0, 0);
+    if (!(p < nxy && z >= 0 && z < nz)) return mk<T>(0, 0);
+    const long long o = (long long)z * nxy + p;
+    if constexpr (!FU) {
+      return xr[o];
+    } else {
+      cplx<T> v = zr[o];
+      if (use_p) v = v + bt * pr[o];
+      return v;
+    }
   };
+  double s_re = 0, s_im = 0;
 #pragma unroll
   for (int d = 0; d < Q - 1; ++d)
 #pragma unroll
@@ -131,7 +235,10 @@ __global__ void __launch_bounds__(1024) k_apply25(StencilArgs S, const cplx<T>* 
 #pragma unroll
     for (int u = 0; u < MAXP; ++u) {
       const int p = threadIdx.x + u * blockDim.x;
-      if (p < nxy) buf[b * nxy + p] = q[NF][u];
+      if (p < nxy) {
+        buf[b * nxy + p] = q[NF][u];
+        if constexpr (FU) F.pnew[rhs * vol + (long long)z * nxy + p] = q[NF][u];
+      }
     }
     __syncthreads();
     const cplx<T>* pl = buf + b * nxy;
@@ -152,6 +259,11 @@ __global__ void __launch_bounds__(1024) k_apply25(StencilArgs S, const cplx<T>* 
                 wz[n] * (q[NF + n][u] + q[NF - n][u]);
         }
         yr[(long long)z * nxy + p] = acc;
+        if constexpr (FU) {
+          const cplx<T> c = q[NF][u];
+          s_re += (double)c.re * acc.re - (double)c.im * acc.im;
+          s_im += (double)c.re * acc.im + (double)c.im * acc.re;
+        }
       }
     }
 #pragma unroll
@@ -160,6 +272,15 @@ __global__ void __launch_bounds__(1024) k_apply25(StencilArgs S, const cplx<T>* 
       for (int u = 0; u < MAXP; ++u) q[d][u] = q[d + 1][u];
 #pragma unroll
     for (int u = 0; u < MAXP; ++u) vq[0][u] = vq[1][u];
+  }
+  if constexpr (FU) {
+    double dummy = 0;
+    block_reduce3(s_re, s_im, dummy);
+    if (threadIdx.x == 0) {
+      Partial P;
+      P.re = s_re; P.im = s_im; P.n2 = 0; P.pad = 0;
+      F.part[(long long)rhs * F.np + chunk] = P;
+    }
   }
 }
 
@@ -173,7 +294,8 @@ template <typename T>
 __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __restrict__ x,
                            cplx<T>* __restrict__ y, const ModeData* __restrict__ modes,
                            const int* __restrict__ e_rhs, const cplx<T>* __restrict__ twx,
-                           const cplx<T>* __restrict__ twy, const int* __restrict__ active) {
+                           const cplx<T>* __restrict__ twy, const int* __restrict__ active,
+                           Partial* __restrict__ part, int np, int pslot) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int nxy = plan.x.n * plan.y.n;
@@ -211,11 +333,30 @@ __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __rest
     for (int k = 0; k < nf; ++k) P[k][m] = out[k];
   }
   __syncthreads();
+  double s_re = 0, s_im = 0;
   for (int k = 0; k < nf; ++k) {
     cplx<T>* res = fft2d_lds(P[k], P[nf], plan, twx, twy, +1);
     cplx<T>* dst = y + rhs * vol + (long long)(pbase + k) * nxy;
-    for (int p = threadIdx.x; p < nxy; p += blockDim.x) dst[p] = dst[p] - res[p];
+    const cplx<T>* src = x + rhs * vol + (long long)(pbase + k) * nxy;
+    for (int p = threadIdx.x; p < nxy; p += blockDim.x) {
+      const cplx<T> r = res[p];
+      dst[p] = dst[p] - r;
+      if (part) {  // x^T (y change) = -x^T Sigma x on this face
+        const cplx<T> c = src[p];
+        s_re -= (double)c.re * r.re - (double)c.im * r.im;
+        s_im -= (double)c.re * r.im + (double)c.im * r.re;
+      }
+    }
     __syncthreads();
+  }
+  if (part) {
+    double dummy = 0;
+    block_reduce3(s_re, s_im, dummy);
+    if (threadIdx.x == 0) {
+      Partial Pp;
+      Pp.re = s_re; Pp.im = s_im; Pp.n2 = 0; Pp.pad = 0;
+      part[(long long)rhs * np + pslot + side] = Pp;
+    }
   }
 }
 
@@ -225,7 +366,8 @@ __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __rest
 template <typename T>
 __global__ void __launch_bounds__(256) k_precond_lap(StencilArgs S, T c1, const cplx<T>* __restrict__ r,
                                                      cplx<T>* __restrict__ z,
-                                                     const int* __restrict__ active) {
+                                                     const int* __restrict__ active,
+                                                     Partial* __restrict__ dpart) {
   const int slot = blockIdx.x / S.nchunks;
   const int chunk = blockIdx.x - slot * S.nchunks;
   const int rhs = rhs_of(active, slot);
@@ -234,6 +376,7 @@ __global__ void __launch_bounds__(256) k_precond_lap(StencilArgs S, T c1, const 
   cplx<T>* zr = z + rhs * vol;
   const int z0 = chunk * S.zchunk;
   const int z1 = min(S.nz, z0 + S.zchunk);
+  double s_re = 0, s_im = 0;
   for (int k = z0; k < z1; ++k) {
     const cplx<T>* rp = rr + (long long)k * S.nxy;
     for (int p = threadIdx.x; p < S.nxy; p += blockDim.x) {
@@ -246,7 +389,19 @@ __global__ void __launch_bounds__(256) k_precond_lap(StencilArgs S, T c1, const 
       cplx<T> s = rp[j * S.nx + ip] + rp[j * S.nx + im] + rp[jp * S.nx + i] + rp[jm * S.nx + i];
       if (k + 1 < S.nz) s = s + rp[S.nxy + p];
       if (k > 0) s = s + rp[-S.nxy + p];
-      zr[(long long)k * S.nxy + p] = rp[p] + c1 * s;
+      const cplx<T> c = rp[p], v = c + c1 * s;
+      zr[(long long)k * S.nxy + p] = v;
+      s_re += (double)c.re * v.re - (double)c.im * v.im;
+      s_im += (double)c.re * v.im + (double)c.im * v.re;
+    }
+  }
+  if (dpart) {
+    double dummy = 0;
+    block_reduce3(s_re, s_im, dummy);
+    if (threadIdx.x == 0) {
+      Partial P;
+      P.re = s_re; P.im = s_im; P.n2 = 0; P.pad = 0;
+      dpart[(long long)rhs * S.nchunks + chunk] = P;
     }
   }
 }
@@ -268,7 +423,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_fft_planes(FFTPlan2D plan, int nz, const cplx<T>* in,
                                                     cplx<T>* out, const cplx<T>* __restrict__ twx,
                                                     const cplx<T>* __restrict__ twy, int sign, T scale,
-                                                    const int* __restrict__ active) {
+                                                    const int* __restrict__ active,
+                                                    const cplx<T>* __restrict__ dvec,
+                                                    Partial* __restrict__ dpart) {
   extern __shared__ char smem_raw[];
   cplx<T>* bufA = reinterpret_cast<cplx<T>*>(smem_raw);
   const int nxy = plan.x.n * plan.y.n;
@@ -280,7 +437,24 @@ __global__ void __launch_bounds__(256) k_fft_planes(FFTPlan2D plan, int nz, cons
   for (int p = threadIdx.x; p < nxy; p += blockDim.x) bufA[p] = in[off + p];
   __syncthreads();
   cplx<T>* res = fft2d_lds(bufA, bufB, plan, twx, twy, sign);
-  for (int p = threadIdx.x; p < nxy; p += blockDim.x) out[off + p] = scale * res[p];
+  double a = 0, b = 0, dummy = 0;
+  for (int p = threadIdx.x; p < nxy; p += blockDim.x) {
+    const cplx<T> v = scale * res[p];
+    out[off + p] = v;
+    if (dpart) {
+      const cplx<T> d = dvec[off + p];
+      a += (double)v.re * d.re - (double)v.im * d.im;
+      b += (double)v.re * d.im + (double)v.im * d.re;
+    }
+  }
+  if (dpart) {
+    block_reduce3(a, b, dummy);
+    if (threadIdx.x == 0) {
+      Partial P;
+      P.re = a; P.im = b; P.n2 = 0; P.pad = 0;
+      dpart[(long long)rhs * nz + z] = P;
+    }
+  }
 }
 
 // Square planes (N x N, N in a fixed list): each thread transforms one row
@@ -296,7 +470,9 @@ template <> struct Pair<double> { typedef double2 type; static constexpr int n =
 template <typename T, int N, int PPB>
 __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes, const cplx<T>* in, cplx<T>* out,
                                                            const cplx<T>* __restrict__ tw, int sign, T scale,
-                                                           const int* __restrict__ active) {
+                                                           const int* __restrict__ active,
+                                                           const cplx<T>* __restrict__ dvec,
+                                                           Partial* __restrict__ dpart) {
   typedef typename Pair<T>::type VT;
   constexpr int PE = Pair<T>::n;          // elements per vector access
   constexpr int NN = N * N;
@@ -350,6 +526,9 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
 #pragma unroll
   for (int i = 0; i < N; ++i) sm[pl][i][li] = scale * v[i];
   __syncthreads();
+  double ds_re[PPB], ds_im[PPB];
+#pragma unroll
+  for (int q = 0; q < PPB; ++q) ds_re[q] = ds_im[q] = 0;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int vv = threadIdx.x + e * BLK;
@@ -363,6 +542,32 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
         c[k] = sm[q][el / N][el % N];
       }
       reinterpret_cast<VT*>(out + poff[q])[w] = o;
+      if (dpart) {  // bilinear out^T dvec, per plane
+        VT dv = reinterpret_cast<const VT*>(dvec + poff[q])[w];
+        const cplx<T>* d = reinterpret_cast<const cplx<T>*>(&dv);
+#pragma unroll
+        for (int k = 0; k < PE; ++k)
+#pragma unroll
+          for (int qq = 0; qq < PPB; ++qq)
+            if (qq == q) {
+              ds_re[qq] += (double)c[k].re * d[k].re - (double)c[k].im * d[k].im;
+              ds_im[qq] += (double)c[k].re * d[k].im + (double)c[k].im * d[k].re;
+            }
+      }
+    }
+  }
+  if (dpart) {
+#pragma unroll
+    for (int q = 0; q < PPB; ++q) {
+      double a = ds_re[q], b = ds_im[q];
+      block_sum2<BLK>(a, b);
+      if (threadIdx.x == 0 && pok[q]) {
+        const int gp = g0 + q;
+        const int slot = gp / nz, z = gp - slot * nz;
+        Partial P;
+        P.re = a; P.im = b; P.n2 = 0; P.pad = 0;
+        dpart[(long long)rhs_of(active, slot) * nz + z] = P;
+      }
     }
   }
 }
@@ -601,33 +806,6 @@ __global__ void k_rhs(int nx, int ny, int nz, int nf, const int* __restrict__ e_
   }
 }
 
-// ------------------------------------------------------- reductions ---
-// Per-rhs partial sums of the bilinear form a^T b (no conjugation, the COCG
-// inner product for the complex-symmetric A) and of |a|^2, accumulated in
-// FP64; one partial per block, combined in fixed order by k_finish.
-struct Partial {
-  double re, im, n2, pad;
-};
-
-template <typename T>
-__device__ __forceinline__ void block_reduce3(double& a, double& b, double& c) {
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_xor(a, off);
-    b += __shfl_xor(b, off);
-    c += __shfl_xor(c, off);
-  }
-  __shared__ double sh[3][16];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    double ra = 0, rb = 0, rc = 0;
-    for (int i = 0; i < nw; ++i) { ra += sh[0][i]; rb += sh[1][i]; rc += sh[2][i]; }
-    a = ra; b = rb; c = rc;
-  }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256) k_dot(const cplx<T>* __restrict__ a, const cplx<T>* __restrict__ b,
                                              long long vol, int nblk, Partial* __restrict__ part,
@@ -647,7 +825,7 @@ __global__ void __launch_bounds__(256) k_dot(const cplx<T>* __restrict__ a, cons
     sim += ur * vi + ui * vr;
     sn += ur * ur + ui * ui;
   }
-  block_reduce3<T>(sre, sim, sn);
+  block_reduce3(sre, sim, sn);
   if (threadIdx.x == 0) {
     Partial P;
     P.re = sre; P.im = sim; P.n2 = sn; P.pad = 0;
@@ -678,33 +856,18 @@ __global__ void __launch_bounds__(256) k_update_xr(cplx<TX>* __restrict__ x, con
     cplx<T> rv = r[off + i] - a * q[off + i];
     r[off + i] = rv;
     sn += (double)rv.re * rv.re + (double)rv.im * rv.im;
+    d0 += (double)rv.re * rv.re - (double)rv.im * rv.im;  // r^T r (for P = I)
+    d1 += 2.0 * (double)rv.re * rv.im;
   }
-  block_reduce3<T>(sn, d0, d1);
+  block_reduce3(sn, d0, d1);
   if (threadIdx.x == 0) {
     Partial P;
-    P.re = 0; P.im = 0; P.n2 = sn; P.pad = 0;
+    P.re = d0; P.im = d1; P.n2 = sn; P.pad = 0;
     part[(long long)rhs * nblk + blk] = P;
   }
 }
 
-// p = z + beta p
-template <typename T>
-__global__ void __launch_bounds__(256) k_update_p(cplx<T>* __restrict__ p, const cplx<T>* __restrict__ z,
-                                                  const zd* __restrict__ beta, long long vol,
-                                                  const int* __restrict__ active) {
-  const int rhs = rhs_of(active, blockIdx.y);
-  const cplx<T> b = cvt<T>(beta[rhs]);
-  const long long off = rhs * vol;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
-       i += (long long)gridDim.x * blockDim.x)
-    p[off + i] = z[off + i] + b * p[off + i];
-}
-
-// Scalar steps of COCG, one thread per active rhs, from the block partials
-// (fixed summation order): mode 0: alpha = rho / mu with mu = p^T q;
-// mode 1: beta = rho_new / rho, rho = rho_new with rho_new = r^T z;
-// mode 2: rho = r^T z (start); mode 3: rn2 = |.|^2; mode 4: restart
-// (rho = r^T z, beta = 0, breakdown flag cleared).
+// Per-rhs scalars of COCG (device arrays indexed by rhs id).
 struct Scal {
   zd* rho;
   zd* alpha;
@@ -713,46 +876,64 @@ struct Scal {
   int* flag;     // breakdown flags
 };
 
-__global__ void k_finish(Scal S, const Partial* __restrict__ part, int nblk, int mode,
-                         const int* __restrict__ active, int nact) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nact) return;
+// Scalar steps of the fused iteration, one wavefront per active rhs: the
+// partials of each rhs are summed lane-strided and then across the lanes,
+// a fixed order.
+//   FIN_ALPHA    mu = sum pa (p^T A p); alpha = rho / mu (breakdown: alpha = 0, flag)
+//   FIN_BETA     rho' = sum pa (r^T z); beta = rho' / rho; rho = rho';
+//                rn2 = sum pb.n2 (|r|^2 written by the update)
+//   FIN_RESTART  rho = sum pa (r^T z); beta = 0; flag cleared
+//   FIN_NORM     rn2 = sum pa.n2
+enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3 };
+
+__global__ void __launch_bounds__(256) k_finish2(Scal S, const Partial* __restrict__ pa, int na,
+                                                 const Partial* __restrict__ pb, int nb, int mode,
+                                                 const int* __restrict__ active, int nact) {
+  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slot >= nact) return;  // whole wavefronts
   const int rhs = rhs_of(active, slot);
   double re = 0, im = 0, n2 = 0;
-  for (int b = 0; b < nblk; ++b) {
-    const Partial P = part[(long long)rhs * nblk + b];
+  for (int k = lane; k < na; k += 64) {
+    const Partial P = pa[(long long)rhs * na + k];
     re += P.re;
     im += P.im;
-    n2 += P.n2;
+    if (mode == FIN_NORM) n2 += P.n2;
   }
-  zd s = mk(re, im);
-  if (mode == 0) {  // mu = p^T q
-    zd rho = S.rho[rhs];
-    double d = re * re + im * im;
+  if (pb)
+    for (int k = lane; k < nb; k += 64) n2 += pb[(long long)rhs * nb + k].n2;
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off);
+    im += __shfl_xor(im, off);
+    n2 += __shfl_xor(n2, off);
+  }
+  if (lane != 0) return;
+  if (mode == FIN_ALPHA) {
+    const zd rho = S.rho[rhs];
+    const double d = re * re + im * im;
     if (!(d > 0) || !isfinite(d)) {
       S.alpha[rhs] = mk(0.0, 0.0);
       S.flag[rhs] = 1;
     } else {
       S.alpha[rhs] = mk((rho.re * re + rho.im * im) / d, (rho.im * re - rho.re * im) / d);
     }
-  } else if (mode == 1) {  // rho_new = r^T z
-    zd rho = S.rho[rhs];
-    double d = rho.re * rho.re + rho.im * rho.im;
+  } else if (mode == FIN_BETA) {
+    const zd rho = S.rho[rhs];
+    const double d = rho.re * rho.re + rho.im * rho.im;
     if (!(d > 0) || !isfinite(re * re + im * im)) {
       S.beta[rhs] = mk(0.0, 0.0);
       S.flag[rhs] = 1;
     } else {
       S.beta[rhs] = mk((re * rho.re + im * rho.im) / d, (im * rho.re - re * rho.im) / d);
     }
-    S.rho[rhs] = s;
-  } else if (mode == 2) {
-    S.rho[rhs] = s;
-  } else if (mode == 4) {  // restart: rho = r^T z, beta = 0, clear the breakdown flag
-    S.rho[rhs] = s;
+    S.rho[rhs] = mk(re, im);
+    S.rn2[rhs] = n2;
+  } else if (mode == FIN_NORM) {
+    S.rn2[rhs] = n2;
+  } else {
+    S.rho[rhs] = mk(re, im);
     S.beta[rhs] = mk(0.0, 0.0);
     S.flag[rhs] = 0;
-  } else if (mode == 3) {
-    S.rn2[rhs] = n2;
   }
 }
 
@@ -874,7 +1055,7 @@ __global__ void k_combine(int nxy, const int* __restrict__ req_e, const int* __r
       sR += md[nu].v / vmu * norm2(rn);
     }
   }
-  block_reduce3<double>(sT, sR, d2);
+  block_reduce3(sT, sR, d2);
   if (threadIdx.x == 0) {
     T[c] = sT;
     R[c] = sR;
@@ -936,24 +1117,35 @@ static int fft_threads(int nxy) {
   return t;
 }
 
+static int a25_max_threads(int ppt) {
+  return ppt == 4 ? A25<4>::max_threads : (ppt == 9 ? A25<9>::max_threads : A25<1>::max_threads);
+}
+
 // 2.5D stencil launch shape: points per thread (1, 2, 4 or 9; the block is
 // ceil(nxy / ppt) threads rounded to a wavefront, at most 1024) and planes
 // per block.  Chosen by the autotuner below, else a default rule.
 template <typename T>
 static bool launch_apply25_shape(iobm_ctx c, int ppt, int zc, const cplx<T>* x, cplx<T>* y, int nrhs,
-                                 const double* E_rhs, const int* active) {
+                                 const double* E_rhs, const int* active, const FuseP<T>& F) {
   const int nxy = c->g.nxy;
   const int threads = ((nxy + ppt - 1) / ppt + 63) / 64 * 64;
-  if (threads > 1024 || ppt * threads < nxy) return false;
+  if (threads > a25_max_threads(ppt) || ppt * threads < nxy) return false;
   StencilArgs S = stencil_args(c, zc);
+  if (S.nchunks > PQ_STENCIL_MAX) return false;
   size_t sh = 2 * (size_t)nxy * sizeof(cplx<T>);
   dim3 grid(nrhs * S.nchunks), blk(threads);
-#define IOBM_A25(NF, MP) hipLaunchKernelGGL((k_apply25<T, NF, MP>), grid, blk, sh, c->stream, S, x, y, Vptr<T>(c), E_rhs, active)
+#define IOBM_A25(NF, MP)                                                                                      \
+  if (F.z)                                                                                                    \
+    hipLaunchKernelGGL((k_apply25<T, NF, MP, true>), grid, blk, sh, c->stream, S, x, y, Vptr<T>(c), E_rhs,     \
+                       active, F);                                                                            \
+  else                                                                                                        \
+    hipLaunchKernelGGL((k_apply25<T, NF, MP, false>), grid, blk, sh, c->stream, S, x, y, Vptr<T>(c), E_rhs,    \
+                       active, F)
 #define IOBM_A25P(NF)                     \
-  if (ppt == 1) IOBM_A25(NF, 1);          \
-  else if (ppt == 2) IOBM_A25(NF, 2);     \
-  else if (ppt == 4) IOBM_A25(NF, 4);     \
-  else IOBM_A25(NF, 9);
+  if (ppt == 1) { IOBM_A25(NF, 1); }      \
+  else if (ppt == 2) { IOBM_A25(NF, 2); } \
+  else if (ppt == 4) { IOBM_A25(NF, 4); } \
+  else { IOBM_A25(NF, 9); }
   switch (c->g.nf) {
     case 1: IOBM_A25P(1); break;
     case 2: IOBM_A25P(2); break;
@@ -968,41 +1160,43 @@ template <typename T> static int& tuned_ppt(iobm_ctx c) { return sizeof(T) == 4 
 template <typename T> static int& tuned_zc(iobm_ctx c) { return sizeof(T) == 4 ? c->tune_zc_c64 : c->tune_zc_c128; }
 
 static int default_ppt(int nxy, bool f32) {
-  const int want = f32 ? 4 : 2;  // keeps the register queue small enough for several waves per SIMD
-  int ppt = want;
-  while ((nxy + ppt - 1) / ppt > 1024) ppt = ppt == 1 ? 2 : (ppt == 2 ? 4 : 9);
-  if (ppt > 9 || (nxy + 8) / 9 > 1024) return 0;
-  return ppt;
+  // small enough a register queue for several waves per SIMD
+  for (int ppt : {f32 ? 4 : 2, 4, 9}) {
+    const int threads = ((nxy + ppt - 1) / ppt + 63) / 64 * 64;
+    if (threads <= a25_max_threads(ppt)) return ppt;
+  }
+  return 0;
 }
 
 template <typename T>
 static bool launch_apply25(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
-                           const int* active) {
+                           const int* active, const FuseP<T>& F) {
   if (c->tune_stencil_simple) return false;
   int ppt = tuned_ppt<T>(c), zc = tuned_zc<T>(c);
   if (ppt <= 0) ppt = default_ppt(c->g.nxy, sizeof(T) == 4);
   if (zc <= 0) zc = 32;
   if (ppt <= 0) return false;
-  return launch_apply25_shape<T>(c, ppt, zc, x, y, nrhs, E_rhs, active);
+  return launch_apply25_shape<T>(c, ppt, zc, x, y, nrhs, E_rhs, active, F);
 }
-
-// Autotuner: time every admissible (points per thread, planes per block)
-// shape of the 2.5D stencil and every z-filter chunk length once on the
-// caller's own batch (x -> y, y is scratch), keep the fastest per precision.
-template <typename T>
-void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
-              const int* e_rhs, const ModeData* modes, const int* active);
 
 template <typename T>
 hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
-                        const int* e_rhs, const ModeData* modes, const int* active) {
+                        const int* e_rhs, const ModeData* modes, const int* active,
+                        const ApplyFuse<T>* fuse) {
   if (nrhs <= 0) return hipSuccess;
+  FuseP<T> F;
+  if (fuse) {
+    F.z = fuse->z; F.pold = fuse->pold; F.beta = fuse->beta; F.pnew = fuse->pnew;
+    F.part = fuse->part; F.np = PQ_SLOTS;
+    x = fuse->pnew;  // the electrode and nonlocal terms read the assembled operand
+  }
   const int cls = sizeof(T) == 4 ? IOBM_K_STENCIL : IOBM_K_STENCIL_C128;
   prof_start(c, cls);
-  if (!launch_apply25<T>(c, x, y, nrhs, E_rhs, active)) {
+  if (!launch_apply25<T>(c, fuse ? nullptr : x, y, nrhs, E_rhs, active, F)) {
     StencilArgs S = stencil_args(c, 16);
-    hipLaunchKernelGGL(k_apply<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, x, y, Vptr<T>(c),
-                       E_rhs, active);
+    if (S.nchunks > PQ_STENCIL_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_apply<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, fuse ? nullptr : x, y,
+                       Vptr<T>(c), E_rhs, active, F);
   }
   prof_stop(c, cls, (double)nrhs * c->g.npts * sizeof(cplx<T>));
   hipError_t err = hipGetLastError();
@@ -1010,56 +1204,59 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
   size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(cplx<T>);
   prof_start(c, IOBM_K_BOUNDARY);
   hipLaunchKernelGGL(k_boundary<T>, dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan,
-                     c->g.nz, c->g.nf, x, y, modes, e_rhs, twx<T>(c), twy<T>(c), active);
+                     c->g.nz, c->g.nf, x, y, modes, e_rhs, twx<T>(c), twy<T>(c), active, F.part, (int)PQ_SLOTS,
+                     (int)PQ_BOUNDARY);
   prof_stop(c, IOBM_K_BOUNDARY, (double)nrhs * 2 * c->g.nf * c->g.nxy * sizeof(cplx<T>));
   err = hipGetLastError();
   if (err != hipSuccess) return err;
-  if (c->kb.ncen > 0) return launch_kb_apply<T>(c, x, y, nrhs, nullptr, active);
+  if (c->kb.ncen > 0) return launch_kb_apply<T>(c, x, y, nrhs, F.part, active);
   return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z, int nrhs,
-                                    const int* active) {
+                                    const int* active, Partial* dpart) {
   StencilArgs S = stencil_args(c, 16);
   prof_start(c, IOBM_K_PRECOND_LAP);
   hipLaunchKernelGGL(k_precond_lap<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S,
-                     (T)exp(-alpha), r, z, active);
+                     (T)exp(-alpha), r, z, active, dpart);
   prof_stop(c, IOBM_K_PRECOND_LAP, (double)nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
 template <typename T, int N, int PPB>
 static void launch_fft_reg(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
-                           const int* active) {
+                           const int* active, const cplx<T>* dvec, Partial* dpart) {
   const int nplanes = nrhs * c->g.nz;
   hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB>), dim3((nplanes + PPB - 1) / PPB), dim3(N * PPB), 0, c->stream,
-                     c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active);
+                     c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active, dvec, dpart);
 }
 
 // planes per block of the register FFT: enough threads for a wavefront or two
 template <typename T>
 static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
-                             const int* active) {
+                             const int* active, const cplx<T>* dvec, Partial* dpart) {
   if (c->g.nx != c->g.ny || c->tune_fft_generic) return false;
   switch (c->g.nx) {
-    case 8: launch_fft_reg<T, 8, 16>(c, in, out, sign, scale, nrhs, active); return true;
-    case 12: launch_fft_reg<T, 12, 8>(c, in, out, sign, scale, nrhs, active); return true;
-    case 16: launch_fft_reg<T, 16, 8>(c, in, out, sign, scale, nrhs, active); return true;
-    case 24: launch_fft_reg<T, 24, 4>(c, in, out, sign, scale, nrhs, active); return true;
-    case 32: launch_fft_reg<T, 32, 4>(c, in, out, sign, scale, nrhs, active); return true;
-    case 48: launch_fft_reg<T, 48, 2>(c, in, out, sign, scale, nrhs, active); return true;
+    case 8: launch_fft_reg<T, 8, 16>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
+    case 12: launch_fft_reg<T, 12, 8>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
+    case 16: launch_fft_reg<T, 16, 8>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
+    case 24: launch_fft_reg<T, 24, 4>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
+    case 32: launch_fft_reg<T, 32, 4>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
+    case 48: launch_fft_reg<T, 48, 2>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
     default: return false;
   }
 }
 
+// Batched plane FFTs; with dpart set, also the per-plane partials of
+// out^T dvec (dpart[rhs][z]).
 template <typename T>
 hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
-                             const int* active) {
-  if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active)) {
+                             const int* active, const cplx<T>* dvec = nullptr, Partial* dpart = nullptr) {
+  if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, dvec, dpart)) {
     size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
     hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
-                       twx<T>(c), twy<T>(c), sign, (T)scale, active);
+                       twx<T>(c), twy<T>(c), sign, (T)scale, active, dvec, dpart);
   }
   return hipGetLastError();
 }
@@ -1096,20 +1293,23 @@ static int zfilter_chunk(iobm_ctx c) {
 
 template <typename T>
 hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch, int nrhs,
-                              const int* e_rhs, const ModeData* modes, const int* active) {
+                              const int* e_rhs, const ModeData* modes, const int* active, Partial* dpart) {
   const int L = zfilter_chunk<T>(c);
   if ((c->g.nz + L - 1) / L > 8) return hipErrorInvalidValue;
   prof_start(c, IOBM_K_PRECOND_FFT);
   hipError_t err = launch_fft_planes<T>(c, r, scratch, -1, 1.0, nrhs, active);
   if (err == hipSuccess) err = launch_zfilter<T>(c, L, scratch, z, nrhs, e_rhs, modes, active);
-  if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active);
+  if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active, r, dpart);
   prof_stop(c, IOBM_K_PRECOND_FFT, (double)nrhs * c->g.npts * sizeof(cplx<T>));
   return err;
 }
 
+// Autotuner: time every admissible (points per thread, planes per block)
+// shape of the 2.5D stencil and every z-filter chunk length once on the
+// caller's own batch (x -> y, y is scratch), keep the fastest per precision.
 template <typename T>
 void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
-              const int* e_rhs, const ModeData* modes, const int* active) {
+              const int* e_rhs, const ModeData* modes, const int* active, const ApplyFuse<T>* fuse) {
   bool& done = sizeof(T) == 4 ? c->tuned_c64 : c->tuned_c128;
   if (done || nrhs <= 0) return;
   done = true;
@@ -1127,14 +1327,20 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
     return ms;
   };
   if (!c->tune_stencil_simple) {
+    // the shape is timed on the operator as the iteration runs it
+    FuseP<T> F;
+    if (fuse) {
+      F.z = fuse->z; F.pold = fuse->pold; F.beta = fuse->beta; F.pnew = fuse->pnew;
+      F.part = fuse->part; F.np = PQ_SLOTS;
+    }
     float best = 1e30f;
     int bp = 0, bz = 0;
     for (int ppt : {1, 2, 4, 9})
       for (int zc : {16, 32, 64}) {
         const int threads = ((c->g.nxy + ppt - 1) / ppt + 63) / 64 * 64;
-        if (threads > 1024 || (sizeof(T) == 8 && ppt == 9)) continue;
+        if (threads > a25_max_threads(ppt) || (sizeof(T) == 8 && ppt == 9)) continue;
         if (zc > c->g.nz && zc != 16) continue;
-        float t = timed([&] { launch_apply25_shape<T>(c, ppt, zc, x, y, nrhs, E_rhs, active); });
+        float t = timed([&] { launch_apply25_shape<T>(c, ppt, zc, fuse ? nullptr : x, y, nrhs, E_rhs, active, F); });
         if (t < best) { best = t; bp = ppt; bz = zc; }
       }
     if (bp > 0) { tuned_ppt<T>(c) = bp; tuned_zc<T>(c) = bz; }
@@ -1154,20 +1360,29 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
 }
 
 template void autotune<float>(iobm_ctx, const zf*, zf*, zf*, int, const double*, const int*, const ModeData*,
-                              const int*);
+                              const int*, const ApplyFuse<float>*);
 template void autotune<double>(iobm_ctx, const zd*, zd*, zd*, int, const double*, const int*, const ModeData*,
-                               const int*);
+                               const int*, const ApplyFuse<double>*);
 
 template hipError_t launch_apply<double>(iobm_ctx, const zd*, zd*, int, const double*, const int*,
-                                         const ModeData*, const int*);
+                                         const ModeData*, const int*, const ApplyFuse<double>*);
 template hipError_t launch_apply<float>(iobm_ctx, const zf*, zf*, int, const double*, const int*,
-                                        const ModeData*, const int*);
-template hipError_t launch_precond_laplacian<double>(iobm_ctx, double, const zd*, zd*, int, const int*);
-template hipError_t launch_precond_laplacian<float>(iobm_ctx, double, const zf*, zf*, int, const int*);
+                                        const ModeData*, const int*, const ApplyFuse<float>*);
+template hipError_t launch_precond_laplacian<double>(iobm_ctx, double, const zd*, zd*, int, const int*, Partial*);
+template hipError_t launch_precond_laplacian<float>(iobm_ctx, double, const zf*, zf*, int, const int*, Partial*);
 template hipError_t launch_precond_fft<double>(iobm_ctx, const zd*, zd*, zd*, int, const int*,
-                                               const ModeData*, const int*);
+                                               const ModeData*, const int*, Partial*);
 template hipError_t launch_precond_fft<float>(iobm_ctx, const zf*, zf*, zf*, int, const int*,
-                                              const ModeData*, const int*);
+                                              const ModeData*, const int*, Partial*);
+
+// partials of r^T z per rhs written by each preconditioner (P = I: the
+// update kernel's r^T r, one per reduction block)
+int dot_blocks(iobm_ctx c);
+int precond_slots(iobm_ctx c, int precond) {
+  if (precond == IOBM_PC_LATERAL_FFT) return c->g.nz;
+  if (precond == IOBM_PC_TRUNCATED_LAPLACIAN) return (c->g.nz + 15) / 16;
+  return dot_blocks(c);
+}
 
 // ---- small launchers used by the solver ------------------------------------
 static dim3 vol_grid(long long vol, int nrhs) {
@@ -1214,20 +1429,13 @@ hipError_t launch_update_xr(iobm_ctx c, cplx<TX>* x, const cplx<T>* p, cplx<T>* 
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_update_p(iobm_ctx c, cplx<T>* p, const cplx<T>* z, const zd* beta, int nact,
-                           const int* active) {
-  hipLaunchKernelGGL(k_update_p<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, p, z, beta,
-                     c->g.npts, active);
-  return hipGetLastError();
-}
-
-hipError_t launch_finish(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const void* part,
-                         int mode, int nact, const int* active) {
+hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const Partial* pa,
+                          int na, const Partial* pb, int nb, int mode, int nact, const int* active) {
+  if (nact <= 0) return hipSuccess;
   Scal S;
   S.rho = rho; S.alpha = alpha; S.beta = beta; S.rn2 = rn2; S.flag = flag;
-  hipLaunchKernelGGL(k_finish, dim3((nact + 127) / 128), dim3(128), 0, c->stream, S, (const Partial*)part,
-                     dot_blocks(c), mode, active, nact);
+  hipLaunchKernelGGL(k_finish2, dim3((nact + 3) / 4), dim3(256), 0, c->stream, S, pa, na, pb, nb, mode, active,
+                     nact);
   return hipGetLastError();
 }
 
@@ -1282,8 +1490,6 @@ template hipError_t launch_update_xr<double, double>(iobm_ctx, zd*, const zd*, z
                                                      const int*, void*);
 template hipError_t launch_update_xr<float, float>(iobm_ctx, zf*, const zf*, zf*, const zf*, const zd*, int,
                                                    const int*, void*);
-template hipError_t launch_update_p<double>(iobm_ctx, zd*, const zd*, const zd*, int, const int*);
-template hipError_t launch_update_p<float>(iobm_ctx, zf*, const zf*, const zd*, int, const int*);
 template hipError_t launch_residual<double>(iobm_ctx, const zd*, zd*, int, const int*);
 template hipError_t launch_residual<float>(iobm_ctx, const zd*, zf*, int, const int*);
 template hipError_t launch_convert<float, double>(iobm_ctx, const zd*, zf*, int, const int*);
