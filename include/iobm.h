@@ -208,20 +208,28 @@ iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, in
  * launch.  iobm_profile_begin clears the record and selects the classes
  * (bit mask of 1 << IOBM_K_*; 0 switches timing off).  iobm_profile_end
  * synchronises the stream and returns, for one class, the number of timed
- * launches, their summed duration (ms) and the bytes of one pass over the
- * vectors they processed (right-hand sides x points x element size); the
- * record is kept until the next iobm_profile_begin. */
-enum { IOBM_K_STENCIL = 1,      /* FD stencil + (E - V) diagonal, complex64 */
-       IOBM_K_BOUNDARY = 2,     /* FFT-applied electrode self-energy */
-       IOBM_K_PRECOND_FFT = 3,  /* lateral-Fourier preconditioner */
+ * launches, their summed duration (ms) and their summed algorithmic bytes:
+ * per launch, every vector the launch must read or write, counted once
+ * (shared tables such as V and the mode data not counted).  The record is
+ * kept until the next iobm_profile_begin.  Classes of one kernel each,
+ * except IOBM_K_PRECOND_FFT, which spans the three launches of the
+ * lateral-Fourier preconditioner (algorithmic bytes: read r, write z). */
+enum { IOBM_K_STENCIL = 1,      /* stencil in the iteration precision; with the
+                                   fused direction update: read z, p_old,
+                                   write p_new, y; else read x, write y */
+       IOBM_K_BOUNDARY = 2,     /* electrode term on the 2 nf face planes */
+       IOBM_K_PRECOND_FFT = 3,  /* the whole lateral-Fourier preconditioner */
        IOBM_K_PRECOND_LAP = 4,  /* Eq. (17) preconditioner */
        IOBM_K_NONLOCAL = 5,     /* nonlocal projector contraction (MFMA) */
        IOBM_K_DOT = 6,          /* bilinear / norm reductions */
-       IOBM_K_UPDATE = 7,       /* x, r update with fused |r|^2 */
-       IOBM_K_STENCIL_C128 = 8 };/* FD stencil, complex128 (FP64 residuals) */
+       IOBM_K_UPDATE = 7,       /* d += alpha p, r -= alpha q, |r|^2 partials */
+       IOBM_K_STENCIL_C128 = 8, /* stencil in complex128 (FP64 residuals) */
+       IOBM_K_FFT_PLANES = 9,   /* one batched 2D plane FFT of the preconditioner */
+       IOBM_K_ZFILTER = 10,     /* the z recursion of the preconditioner */
+       IOBM_K_ACCUMULATE = 11 };/* x += d, d = 0 (refinement) */
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask);
 iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
-                             double* pass_bytes);
+                             double* alg_bytes);
 
 iobm_status iobm_destroy(iobm_ctx ctx);
 const char* iobm_status_str(iobm_status s);

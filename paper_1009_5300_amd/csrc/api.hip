@@ -44,7 +44,11 @@ hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const 
 template <typename TD, typename TS>
 hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int nact, const int* active);
 template <typename T>
-hipError_t launch_accumulate(iobm_ctx c, zd* x, const cplx<T>* d, int nact, const int* active);
+hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, int nact, const int* active);
+template <typename TR>
+hipError_t launch_refresh(iobm_ctx c, const zd* x, const zd* b, zd* rface, cplx<TR>* r, int nrhs,
+                          const double* E_rhs, const int* e_rhs, const ModeData* modes, const int* active,
+                          Partial* part);
 hipError_t launch_readout(iobm_ctx c, int nrhs, int side, const zd* x, const ModeData* modes,
                           const int* e_rhs, zd* amp_near, zd* amp_far);
 hipError_t launch_combine(iobm_ctx c, int nreq, const int* req_e, const int* req_mode, const int* req_c,
@@ -85,7 +89,7 @@ iobm_status fail(iobm_ctx ctx, iobm_status s, const std::string& msg) {
 
 // ------------------------------------------------------------- scratch pool
 enum Slot {
-  S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_P2, S_Q, S_D, S_PF, S_PART, S_PARTA, S_PARTZ, S_SCAL, S_IDX, S_AMP,
+  S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_P2, S_Q, S_D, S_PF, S_PART, S_PARTA, S_PARTZ, S_PARTR, S_SCAL, S_IDX, S_AMP,
   S_TR, S_KB, S_GRAD_U, S_GRAD_D, NSLOT
 };
 
@@ -276,6 +280,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   Partial* part_rz = o.precond == IOBM_PC_NONE
                          ? part
                          : (Partial*)scratch(ctx, S_PARTZ, (size_t)nb * nz_slots * sizeof(Partial));
+  Partial* part_rn = (Partial*)scratch(ctx, S_PARTR, (size_t)nb * PQ_SLOTS * sizeof(Partial));
   char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * (3 * sizeof(zd) + 2 * sizeof(double) + sizeof(int)) + 64);
   zd* rho = (zd*)sc;
   zd* alpha = rho + nb;
@@ -300,25 +305,35 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     else
       HIPCHK(launch_dot<T>(ctx, r, r, nact, ad, part_rz));
   };
-  // true residual r_hi = b - A x for the listed rhs; |r_hi|^2 -> host
+  // Refinement of the listed rhs: x += d, d = 0, r = b - A x in FP64 (stored
+  // in the iteration precision; the FP64 face planes pass through r_hi), and
+  // |r|^2 -> host.  With a nonlocal term the residual is formed in full in
+  // r_hi first, since its back-projection comes after the stencil.
   std::vector<double> tn2_h(nb), rn2_h(nb), bn2(nb);
   std::vector<int> flag_h(nb);
-  auto true_residual = [&](const std::vector<int>& lst, int region) {
+  auto refresh = [&](const std::vector<int>& lst, int region) {
     int* ld = upload(ctx, S_IDX, lst, (size_t)region * 8192);
     const int n = (int)lst.size();
-    HIPCHK(launch_apply<double>(ctx, x, rhi, n, E_d, e_d, modes, ld));
-    HIPCHK(launch_residual<double>(ctx, b, rhi, n, ld));
-    HIPCHK(launch_dot<double>(ctx, rhi, rhi, n, ld, part));
-    HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld));
+    HIPCHK(launch_accumulate<T>(ctx, x, d, n, ld));
+    if (ctx->kb.ncen == 0) {
+      HIPCHK(launch_refresh<T>(ctx, x, b, rhi, r, n, E_d, e_d, modes, ld, part_rn));
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part_rn, PQ_SLOTS, nullptr, 0, FIN_NORM, n, ld));
+    } else {
+      HIPCHK(launch_apply<double>(ctx, x, rhi, n, E_d, e_d, modes, ld));
+      HIPCHK(launch_residual<double>(ctx, b, rhi, n, ld));
+      HIPCHK(launch_dot<double>(ctx, rhi, rhi, n, ld, part));
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld));
+      HIPCHK((launch_convert<T, double>(ctx, rhi, r, n, ld)));
+    }
     HIPCHK(hipMemcpyAsync(tn2_h.data(), tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     stream_sync(ctx);
-    return ld;
   };
 
   // start: x = 0, r_hi = b, d = 0, r = r_hi, z = P r, rho = r^T z, beta = 0
   HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * vol * sizeof(zd), ctx->stream));
   HIPCHK(hipMemsetAsync(flag, 0, nb * sizeof(int), ctx->stream));
   HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
+  HIPCHK(hipMemsetAsync(part_rn, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   HIPCHK(launch_dot<double>(ctx, b, b, nb, all_d, part));
   HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, nb, all_d));
   HIPCHK(hipMemcpyAsync(bn2.data(), tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -335,7 +350,6 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   int* act_d = upload(ctx, S_IDX, act, 64 * 1024);
   HIPCHK((launch_convert<T, double>(ctx, b, r, nact, act_d)));
   HIPCHK((launch_convert<T, double>(ctx, nullptr, d, nact, act_d)));
-  HIPCHK(hipMemcpyAsync(rhi, b, (size_t)nb * vol * sizeof(zd), hipMemcpyDeviceToDevice, ctx->stream));
   if (!(lowp ? ctx->tuned_c64 : ctx->tuned_c128)) {
     // the shapes are timed on the fused operator with p_old = 0 and a
     // nonzero beta (0x3F bytes: 4.8e-4), so that every stream is read
@@ -378,10 +392,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       else maxr2[i] = std::max(maxr2[i], r2);
     }
     if (upd.empty()) continue;
-    int* ud = upload(ctx, S_IDX, upd, 48 * 1024);
-    const int nu = (int)upd.size();
-    HIPCHK(launch_accumulate<T>(ctx, x, d, nu, ud));
-    true_residual(upd, 7);
+    refresh(upd, 7);
     std::vector<int> cont;  // updated rhs that go on iterating, from a restart
     for (int i : upd) {
       out.refin[i] += 1;
@@ -397,11 +408,9 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       maxr2[i] = t2;
     }
     if (!cont.empty()) {
-      // r = r_hi, d = 0, z = P r, rho = r^T z, beta = 0 (p_new = z next)
+      // z = P r, rho = r^T z, beta = 0 (p_new = z next)
       int* cd = upload(ctx, S_IDX, cont, 56 * 1024);
       const int nc = (int)cont.size();
-      HIPCHK((launch_convert<T, double>(ctx, rhi, r, nc, cd)));
-      HIPCHK((launch_convert<T, double>(ctx, nullptr, d, nc, cd)));
       precond(nc, cd);
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nc, cd));
     }
@@ -501,28 +510,30 @@ void plan_requests(iobm_ctx ctx, int nE, const double* E, const int* ninc, const
 
 }  // namespace
 
-void prof_start(iobm_ctx c, int cls) {
-  if (!(c->prof_mask & (1 << cls))) return;
+int prof_start(iobm_ctx c, int cls) {
+  if (!(c->prof_mask & (1 << cls))) return -1;
   if (2 * c->prof_used + 2 > c->prof_ev.size()) {
     for (int k = 0; k < 128; ++k) {
       hipEvent_t ev;
-      if (hipEventCreate(&ev) != hipSuccess) return;
+      if (hipEventCreate(&ev) != hipSuccess) return -1;
       c->prof_ev.push_back(ev);
     }
   }
-  (void)hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream);
+  const size_t rec = c->prof_used++;
+  if (c->prof_cls.size() <= rec) {
+    c->prof_cls.resize(rec + 1);
+    c->prof_bytes.resize(rec + 1);
+  }
+  c->prof_cls[rec] = cls;
+  c->prof_bytes[rec] = 0;
+  (void)hipEventRecord(c->prof_ev[2 * rec], c->stream);
+  return (int)rec;
 }
 
-void prof_stop(iobm_ctx c, int cls, double bytes) {
-  if (!(c->prof_mask & (1 << cls)) || 2 * c->prof_used + 2 > c->prof_ev.size()) return;
-  (void)hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream);
-  if (c->prof_cls.size() <= c->prof_used) {
-    c->prof_cls.resize(c->prof_used + 1);
-    c->prof_bytes.resize(c->prof_used + 1);
-  }
-  c->prof_cls[c->prof_used] = cls;
-  c->prof_bytes[c->prof_used] = bytes;
-  c->prof_used += 1;
+void prof_stop(iobm_ctx c, int rec, double alg_bytes) {
+  if (rec < 0 || (size_t)rec >= c->prof_used) return;
+  (void)hipEventRecord(c->prof_ev[2 * rec + 1], c->stream);
+  c->prof_bytes[rec] = alg_bytes;
 }
 
 double* kb_scratch(iobm_ctx c, size_t bytes) {
@@ -626,7 +637,7 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
 
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask) {
   if (!ctx) return IOBM_E_INVALID_ARG;
-  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_STENCIL_C128 + 1)))
+  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_ACCUMULATE + 1)))
     return fail(ctx, IOBM_E_INVALID_ARG, "bad kernel class mask");
   ctx->prof_mask = class_mask;
   ctx->prof_used = 0;
@@ -634,7 +645,7 @@ iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask) {
 }
 
 iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
-                             double* pass_bytes) {
+                             double* alg_bytes) {
   if (!ctx) return IOBM_E_INVALID_ARG;
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return fail(ctx, IOBM_E_DEVICE, hipGetErrorString(e));
@@ -649,7 +660,7 @@ iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launch
   }
   if (launches) *launches = n;
   if (total_ms) *total_ms = ms;
-  if (pass_bytes) *pass_bytes = bytes;
+  if (alg_bytes) *alg_bytes = bytes;
   return IOBM_OK;
 }
 

@@ -94,8 +94,12 @@ struct iobm_ctx_s {
 };
 
 // ---- kernel timing hook (api.hip) -------------------------------------------
-void prof_start(iobm_ctx c, int cls);
-void prof_stop(iobm_ctx c, int cls, double units);
+// prof_start records a start event for one launch of class cls and returns
+// its record (or -1 when the class is not timed); prof_stop records the end
+// and the launch's algorithmic bytes (every vector it must read or write,
+// once).  Records may nest.
+int prof_start(iobm_ctx c, int cls);
+void prof_stop(iobm_ctx c, int rec, double alg_bytes);
 
 // ---- launchers (ops.hip / modes.hip / kb.hip) -------------------------------
 struct RhsMap {        // device arrays describing a batch of right-hand sides

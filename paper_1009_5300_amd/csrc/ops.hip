@@ -80,55 +80,128 @@ struct StencilArgs {
   double wx[4], wy[4], wz[4];
 };
 
-// Optional fusion of the COCG direction update into the operator: the
-// operand is p_new = z + beta p_old (written to pnew for the block's own
-// planes), and the block's partial p_new^T y goes to part[rhs][np] at the
-// block's chunk index.
+// Operand and epilogue policies of the stencil kernels.  bind() selects the
+// rhs, load(o) returns the operand at flat offset o of that rhs, center()
+// sees the operand of each point the block owns, store() takes the operand
+// and the stencil result of that point, and finish() runs once per block
+// (every thread; it may synchronise the block).
 template <typename T>
-struct FuseP {
-  const cplx<T>* z = nullptr;
-  const cplx<T>* pold = nullptr;
-  const zd* beta = nullptr;
-  cplx<T>* pnew = nullptr;
-  Partial* part = nullptr;
-  int np = 0;
+struct OpPlain {  // y = A_st x
+  const cplx<T>* x;
+  cplx<T>* y;
+  __device__ __forceinline__ void bind(int rhs, long long vol) { x += rhs * vol; y += rhs * vol; }
+  __device__ __forceinline__ cplx<T> load(long long o) const { return x[o]; }
+  __device__ __forceinline__ void center(long long, cplx<T>) {}
+  __device__ __forceinline__ void store(int, long long o, cplx<T>, cplx<T> acc) { y[o] = acc; }
+  __device__ __forceinline__ void finish(int, int) {}
 };
 
+// COCG direction update fused into the operator: the operand is
+// p_new = z + beta p_old (p_old not read where beta = 0), written to pnew for
+// the block's own points; the block's partial of p_new^T y goes to
+// part[rhs][chunk] (PQ_SLOTS per rhs).
 template <typename T>
-__global__ void __launch_bounds__(256) k_apply(StencilArgs S, const cplx<T>* __restrict__ x,
-                                               cplx<T>* __restrict__ y, const T* __restrict__ V,
+struct OpFuseP {
+  const cplx<T>* z;
+  const cplx<T>* pold;
+  const zd* beta;
+  cplx<T>* pnew;
+  cplx<T>* y;
+  Partial* part;
+  cplx<T> bt;
+  bool use_p;
+  double s_re, s_im;
+  __device__ __forceinline__ void bind(int rhs, long long vol) {
+    z += rhs * vol; pold += rhs * vol; pnew += rhs * vol; y += rhs * vol;
+    bt = cvt<T>(beta[rhs]);
+    use_p = bt.re != (T)0 || bt.im != (T)0;
+    s_re = s_im = 0;
+  }
+  __device__ __forceinline__ cplx<T> load(long long o) const {
+    cplx<T> v = z[o];
+    if (use_p) v = v + bt * pold[o];
+    return v;
+  }
+  __device__ __forceinline__ void center(long long o, cplx<T> v) { pnew[o] = v; }
+  __device__ __forceinline__ void store(int, long long o, cplx<T> c, cplx<T> acc) {
+    y[o] = acc;
+    s_re += (double)c.re * acc.re - (double)c.im * acc.im;
+    s_im += (double)c.re * acc.im + (double)c.im * acc.re;
+  }
+  __device__ __forceinline__ void finish(int rhs, int chunk) {
+    double dummy = 0;
+    block_reduce3(s_re, s_im, dummy);
+    if (threadIdx.x == 0) {
+      Partial P;
+      P.re = s_re; P.im = s_im; P.n2 = 0; P.pad = 0;
+      part[(long long)rhs * PQ_SLOTS + chunk] = P;
+    }
+  }
+};
+
+// FP64 residual of the refinement, r = b - A x, with b supported on the
+// 2 nf electrode-face planes only (true of every right-hand side the solver
+// builds).  Interior planes: r = -A_st x, stored in the iteration precision
+// TR, with the block's partial of |r|^2 (FP64, from the complex128 values)
+// in part[rhs][chunk].  Face planes: b - A_st x is kept in complex128 in
+// rface for the electrode kernel, which adds Sigma x and finishes them.
+template <typename TR>
+struct OpRefresh {
+  const zd* x;
+  const zd* b;
+  zd* rface;
+  cplx<TR>* r;
+  Partial* part;
+  int nz, nf, nxy;
+  double s_n2;
+  __device__ __forceinline__ void bind(int rhs, long long vol) {
+    x += rhs * vol; b += rhs * vol; rface += rhs * vol; r += rhs * vol;
+    s_n2 = 0;
+  }
+  __device__ __forceinline__ zd load(long long o) const { return x[o]; }
+  __device__ __forceinline__ void center(long long, zd) {}
+  __device__ __forceinline__ void store(int zz, long long o, zd, zd acc) {
+    if (zz < nf || zz >= nz - nf) {
+      rface[o] = b[o] - acc;
+    } else {
+      r[o] = cvt<TR>(-acc);
+      s_n2 += acc.re * acc.re + acc.im * acc.im;
+    }
+  }
+  __device__ __forceinline__ void finish(int rhs, int chunk) {
+    double d0 = 0, d1 = 0;
+    block_reduce3(s_n2, d0, d1);
+    if (threadIdx.x == 0) {
+      Partial P;
+      P.re = 0; P.im = 0; P.n2 = s_n2; P.pad = 0;
+      part[(long long)rhs * PQ_SLOTS + chunk] = P;
+    }
+  }
+};
+
+// Cache-based stencil (any plane size): one thread per point of a chunk of
+// planes, every neighbour read from memory.
+template <typename T, class Op>
+__global__ void __launch_bounds__(256) k_apply(StencilArgs S, Op op, const T* __restrict__ V,
                                                const double* __restrict__ E_rhs,
-                                               const int* __restrict__ active, FuseP<T> F) {
+                                               const int* __restrict__ active) {
   const int slot = blockIdx.x / S.nchunks;
   const int chunk = blockIdx.x - slot * S.nchunks;
   const int rhs = rhs_of(active, slot);
-  const long long vol = (long long)S.nxy * S.nz;
-  const cplx<T>* xr = x ? x + rhs * vol : nullptr;
-  cplx<T>* yr = y + rhs * vol;
-  const cplx<T>* zr = F.z ? F.z + rhs * vol : nullptr;
-  const cplx<T>* pr = F.pold ? F.pold + rhs * vol : nullptr;
-  const cplx<T> bt = F.z ? cvt<T>(F.beta[rhs]) : mk<T>(0, 0);
-  const bool use_p = F.z && (bt.re != (T)0 || bt.im != (T)0);
-  auto val = [&](long long o) -> cplx<T> {
-    if (!zr) return xr[o];
-    cplx<T> v = zr[o];
-    if (use_p) v = v + bt * pr[o];
-    return v;
-  };
+  op.bind(rhs, (long long)S.nxy * S.nz);
   const T diag0 = Real<T>::v(E_rhs[rhs] + S.e0);
   const int z0 = chunk * S.zchunk;
   const int z1 = min(S.nz, z0 + S.zchunk);
   T wx[4], wy[4], wz[4];
 #pragma unroll
   for (int n = 1; n <= 3; ++n) { wx[n] = (T)S.wx[n]; wy[n] = (T)S.wy[n]; wz[n] = (T)S.wz[n]; }
-  double s_re = 0, s_im = 0;
   for (int z = z0; z < z1; ++z) {
     const long long zo = (long long)z * S.nxy;
     for (int p = threadIdx.x; p < S.nxy; p += blockDim.x) {
       const int j = p / S.nx;
       const int i = p - j * S.nx;
-      const cplx<T> c0 = val(zo + p);
-      if (F.pnew) F.pnew[rhs * vol + zo + p] = c0;
+      const cplx<T> c0 = op.load(zo + p);
+      op.center(zo + p, c0);
       const T d = diag0 - V[zo + p];
       cplx<T> acc = d * c0;
       for (int n = 1; n <= S.nf; ++n) {
@@ -136,48 +209,39 @@ __global__ void __launch_bounds__(256) k_apply(StencilArgs S, const cplx<T>* __r
         int im = i - n; if (im < 0) im += S.nx;
         int jp = j + n; if (jp >= S.ny) jp -= S.ny;
         int jm = j - n; if (jm < 0) jm += S.ny;
-        cplx<T> sx = val(zo + j * S.nx + ip) + val(zo + j * S.nx + im);
-        cplx<T> sy = val(zo + jp * S.nx + i) + val(zo + jm * S.nx + i);
+        cplx<T> sx = op.load(zo + j * S.nx + ip) + op.load(zo + j * S.nx + im);
+        cplx<T> sy = op.load(zo + jp * S.nx + i) + op.load(zo + jm * S.nx + i);
         acc = acc + wx[n] * sx + wy[n] * sy;
         cplx<T> sz = mk<T>(0, 0);
-        if (z + n < S.nz) sz = sz + val(zo + (long long)n * S.nxy + p);
-        if (z - n >= 0) sz = sz + val(zo - (long long)n * S.nxy + p);
+        if (z + n < S.nz) sz = sz + op.load(zo + (long long)n * S.nxy + p);
+        if (z - n >= 0) sz = sz + op.load(zo - (long long)n * S.nxy + p);
         acc = acc + wz[n] * sz;
       }
-      yr[zo + p] = acc;
-      s_re += (double)c0.re * acc.re - (double)c0.im * acc.im;
-      s_im += (double)c0.re * acc.im + (double)c0.im * acc.re;
+      op.store(z, zo + p, c0, acc);
     }
   }
-  if (F.part) {
-    double dummy = 0;
-    block_reduce3(s_re, s_im, dummy);
-    if (threadIdx.x == 0) {
-      Partial P;
-      P.re = s_re; P.im = s_im; P.n2 = 0; P.pad = 0;
-      F.part[(long long)rhs * F.np + chunk] = P;
-    }
-  }
+  op.finish(rhs, chunk);
 }
 
 // 2.5D variant: a block owns all points of the lateral plane (up to MAXP per
 // thread) of one rhs over a chunk of planes.  The current plane sits in LDS
 // (double buffered, one barrier per plane) for the lateral neighbours; the
 // z neighbours come from a per-thread register queue of 2 NF + 2 planes,
-// which also prefetches the plane after the leading one.  Each x element is
-// read from memory once per chunk (plus 2 NF halo planes), each y written once.
+// which also prefetches the plane after the leading one.  Each operand
+// element is read from memory once per chunk (plus 2 NF halo planes), each
+// result written once.
+
 // Largest block of each points-per-thread variant (any nxy <= 4096 has an
 // admissible variant); the bound sets the compiler's register budget.
 template <int MAXP>
 struct A25 {
-  static constexpr int max_threads = MAXP == 4 ? 640 : (MAXP == 9 ? 512 : 1024);
+  static constexpr int max_threads = MAXP == 3 ? 768 : (MAXP == 4 ? 640 : (MAXP == 9 ? 512 : 1024));
 };
 
-template <typename T, int NF, int MAXP, bool FU>
-__global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs S, const cplx<T>* __restrict__ x,
-                                                 cplx<T>* __restrict__ y, const T* __restrict__ V,
-                                                 const double* __restrict__ E_rhs,
-                                                 const int* __restrict__ active, FuseP<T> F) {
+template <typename T, int NF, int MAXP, class Op>
+__global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs S, Op op, const T* __restrict__ V,
+                                                                    const double* __restrict__ E_rhs,
+                                                                    const int* __restrict__ active) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);  // [2][nxy]
   constexpr int Q = 2 * NF + 2;
@@ -185,35 +249,20 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
   const int slot = blockIdx.x / S.nchunks;
   const int chunk = blockIdx.x - slot * S.nchunks;
   const int rhs = rhs_of(active, slot);
-  const long long vol = (long long)nxy * nz;
-  const cplx<T>* xr = x ? x + rhs * vol : nullptr;
-  cplx<T>* yr = y + rhs * vol;
+  op.bind(rhs, (long long)nxy * nz);
   const T diag0 = Real<T>::v(E_rhs[rhs] + S.e0);
   const int z0 = chunk * S.zchunk;
   const int z1 = min(nz, z0 + S.zchunk);
   T wx[NF + 1], wy[NF + 1], wz[NF + 1];
 #pragma unroll
   for (int n = 1; n <= NF; ++n) { wx[n] = (T)S.wx[n]; wy[n] = (T)S.wy[n]; wz[n] = (T)S.wz[n]; }
-  cplx<T> q[Q][MAXP];  // q[NF + d][u] = x(z + d) at the thread's point u
+  cplx<T> q[Q][MAXP];  // q[NF + d][u] = operand(z + d) at the thread's point u
   T vq[2][MAXP];       // V(z), V(z + 1)
-  // fused direction update: x = z + beta p_old, formed while loading
-  const cplx<T>* zr = FU ? F.z + rhs * vol : nullptr;
-  const cplx<T>* pr = FU ? F.pold + rhs * vol : nullptr;
-  const cplx<T> bt = FU ? cvt<T>(F.beta[rhs]) : mk<T>(0, 0);
-  const bool use_p = FU && (bt.re != (T)0 || bt.im != (T)0);
   auto ld = [&](int z, int u) -> cplx<T> {
     const int p = threadIdx.x + u * blockDim.x;
     if (!(p < nxy && z >= 0 && z < nz)) return mk<T>(0, 0);
-    const long long o = (long long)z * nxy + p;
-    if constexpr (!FU) {
-      return xr[o];
-    } else {
-      cplx<T> v = zr[o];
-      if (use_p) v = v + bt * pr[o];
-      return v;
-    }
+    return op.load((long long)z * nxy + p);
   };
-  double s_re = 0, s_im = 0;
 #pragma unroll
   for (int d = 0; d < Q - 1; ++d)
 #pragma unroll
@@ -237,7 +286,7 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
       const int p = threadIdx.x + u * blockDim.x;
       if (p < nxy) {
         buf[b * nxy + p] = q[NF][u];
-        if constexpr (FU) F.pnew[rhs * vol + (long long)z * nxy + p] = q[NF][u];
+        op.center((long long)z * nxy + p, q[NF][u]);
       }
     }
     __syncthreads();
@@ -258,12 +307,7 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
           acc = acc + wx[n] * (pl[j * S.nx + ip] + pl[j * S.nx + im]) + wy[n] * (pl[jp * S.nx + i] + pl[jm * S.nx + i]) +
                 wz[n] * (q[NF + n][u] + q[NF - n][u]);
         }
-        yr[(long long)z * nxy + p] = acc;
-        if constexpr (FU) {
-          const cplx<T> c = q[NF][u];
-          s_re += (double)c.re * acc.re - (double)c.im * acc.im;
-          s_im += (double)c.re * acc.im + (double)c.im * acc.re;
-        }
+        op.store(z, (long long)z * nxy + p, q[NF][u], acc);
       }
     }
 #pragma unroll
@@ -273,15 +317,7 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
 #pragma unroll
     for (int u = 0; u < MAXP; ++u) vq[0][u] = vq[1][u];
   }
-  if constexpr (FU) {
-    double dummy = 0;
-    block_reduce3(s_re, s_im, dummy);
-    if (threadIdx.x == 0) {
-      Partial P;
-      P.re = s_re; P.im = s_im; P.n2 = 0; P.pad = 0;
-      F.part[(long long)rhs * F.np + chunk] = P;
-    }
-  }
+  op.finish(rhs, chunk);
 }
 
 // ----------------------------------------------------- electrode term ---
@@ -289,10 +325,14 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
 // momentum space (Eqs. (14)-(16)): FFT each of the nf planes, mix the planes
 // of every mode with its nf x nf block, inverse FFT, scale by 1/Nxy.
 // Block (slot, side); side 0 = left (planes 0..nf-1, reversed block),
-// side 1 = right (planes nz-nf..nz-1).
-template <typename T>
+// side 1 = right (planes nz-nf..nz-1).  With part set, the block's partial
+// of x^T (its change of y) goes to part[rhs][pslot + side].  With rout set
+// (the refinement residual), y holds b - A_st x on the faces and the block
+// writes rout = y + Sigma x in precision TR and the partial of |rout|^2.
+template <typename T, typename TR>
 __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __restrict__ x,
-                           cplx<T>* __restrict__ y, const ModeData* __restrict__ modes,
+                           cplx<T>* __restrict__ y, cplx<TR>* __restrict__ rout,
+                           const ModeData* __restrict__ modes,
                            const int* __restrict__ e_rhs, const cplx<T>* __restrict__ twx,
                            const cplx<T>* __restrict__ twy, const int* __restrict__ active,
                            Partial* __restrict__ part, int np, int pslot) {
@@ -333,28 +373,32 @@ __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __rest
     for (int k = 0; k < nf; ++k) P[k][m] = out[k];
   }
   __syncthreads();
-  double s_re = 0, s_im = 0;
+  double s_re = 0, s_im = 0, s_n2 = 0;
   for (int k = 0; k < nf; ++k) {
     cplx<T>* res = fft2d_lds(P[k], P[nf], plan, twx, twy, +1);
-    cplx<T>* dst = y + rhs * vol + (long long)(pbase + k) * nxy;
-    const cplx<T>* src = x + rhs * vol + (long long)(pbase + k) * nxy;
+    const long long po = rhs * vol + (long long)(pbase + k) * nxy;
     for (int p = threadIdx.x; p < nxy; p += blockDim.x) {
       const cplx<T> r = res[p];
-      dst[p] = dst[p] - r;
-      if (part) {  // x^T (y change) = -x^T Sigma x on this face
-        const cplx<T> c = src[p];
-        s_re -= (double)c.re * r.re - (double)c.im * r.im;
-        s_im -= (double)c.re * r.im + (double)c.im * r.re;
+      if (rout) {
+        const cplx<T> v = y[po + p] + r;
+        rout[po + p] = cvt<TR>(v);
+        s_n2 += (double)v.re * v.re + (double)v.im * v.im;
+      } else {
+        y[po + p] = y[po + p] - r;
+        if (part) {  // x^T (y change) = -x^T Sigma x on this face
+          const cplx<T> c = x[po + p];
+          s_re -= (double)c.re * r.re - (double)c.im * r.im;
+          s_im -= (double)c.re * r.im + (double)c.im * r.re;
+        }
       }
     }
     __syncthreads();
   }
   if (part) {
-    double dummy = 0;
-    block_reduce3(s_re, s_im, dummy);
+    block_reduce3(s_re, s_im, s_n2);
     if (threadIdx.x == 0) {
       Partial Pp;
-      Pp.re = s_re; Pp.im = s_im; Pp.n2 = 0; Pp.pad = 0;
+      Pp.re = s_re; Pp.im = s_im; Pp.n2 = s_n2; Pp.pad = 0;
       part[(long long)rhs * np + pslot + side] = Pp;
     }
   }
@@ -962,9 +1006,9 @@ __global__ void k_convert(const cplx<TS>* __restrict__ src, cplx<TD>* __restrict
     dst[off + i] = src ? mk<TD>((TD)src[off + i].re, (TD)src[off + i].im) : mk<TD>(0, 0);
 }
 
-// x (complex128) += d (complex64 or complex128)
+// x (complex128) += d (complex64 or complex128), then d = 0
 template <typename T>
-__global__ void k_accumulate(zd* __restrict__ x, const cplx<T>* __restrict__ d, long long vol,
+__global__ void k_accumulate(zd* __restrict__ x, cplx<T>* __restrict__ d, long long vol,
                              const int* __restrict__ active) {
   const int rhs = rhs_of(active, blockIdx.y);
   const long long off = rhs * vol;
@@ -973,6 +1017,7 @@ __global__ void k_accumulate(zd* __restrict__ x, const cplx<T>* __restrict__ d, 
     zd xv = x[off + i];
     cplx<T> dv = d[off + i];
     x[off + i] = mk(xv.re + (double)dv.re, xv.im + (double)dv.im);
+    d[off + i] = mk<T>(0, 0);
   }
 }
 
@@ -1118,15 +1163,21 @@ static int fft_threads(int nxy) {
 }
 
 static int a25_max_threads(int ppt) {
-  return ppt == 4 ? A25<4>::max_threads : (ppt == 9 ? A25<9>::max_threads : A25<1>::max_threads);
+  switch (ppt) {
+    case 3: return A25<3>::max_threads;
+    case 4: return A25<4>::max_threads;
+    case 9: return A25<9>::max_threads;
+    default: return A25<1>::max_threads;
+  }
 }
 
-// 2.5D stencil launch shape: points per thread (1, 2, 4 or 9; the block is
-// ceil(nxy / ppt) threads rounded to a wavefront, at most 1024) and planes
-// per block.  Chosen by the autotuner below, else a default rule.
-template <typename T>
-static bool launch_apply25_shape(iobm_ctx c, int ppt, int zc, const cplx<T>* x, cplx<T>* y, int nrhs,
-                                 const double* E_rhs, const int* active, const FuseP<T>& F) {
+// 2.5D stencil launch shape: points per thread (1, 2, 3, 4 or 9; the block is
+// ceil(nxy / ppt) threads rounded to a wavefront, at most the variant's
+// bound) and planes per block.  Chosen by the autotuner below, else a
+// default rule.
+template <typename T, class Op>
+static bool launch_apply25_shape(iobm_ctx c, int ppt, int zc, const Op& op, int nrhs, const double* E_rhs,
+                                 const int* active) {
   const int nxy = c->g.nxy;
   const int threads = ((nxy + ppt - 1) / ppt + 63) / 64 * 64;
   if (threads > a25_max_threads(ppt) || ppt * threads < nxy) return false;
@@ -1134,16 +1185,12 @@ static bool launch_apply25_shape(iobm_ctx c, int ppt, int zc, const cplx<T>* x, 
   if (S.nchunks > PQ_STENCIL_MAX) return false;
   size_t sh = 2 * (size_t)nxy * sizeof(cplx<T>);
   dim3 grid(nrhs * S.nchunks), blk(threads);
-#define IOBM_A25(NF, MP)                                                                                      \
-  if (F.z)                                                                                                    \
-    hipLaunchKernelGGL((k_apply25<T, NF, MP, true>), grid, blk, sh, c->stream, S, x, y, Vptr<T>(c), E_rhs,     \
-                       active, F);                                                                            \
-  else                                                                                                        \
-    hipLaunchKernelGGL((k_apply25<T, NF, MP, false>), grid, blk, sh, c->stream, S, x, y, Vptr<T>(c), E_rhs,    \
-                       active, F)
+#define IOBM_A25(NF, MP) \
+  hipLaunchKernelGGL((k_apply25<T, NF, MP, Op>), grid, blk, sh, c->stream, S, op, Vptr<T>(c), E_rhs, active)
 #define IOBM_A25P(NF)                     \
   if (ppt == 1) { IOBM_A25(NF, 1); }      \
   else if (ppt == 2) { IOBM_A25(NF, 2); } \
+  else if (ppt == 3) { IOBM_A25(NF, 3); } \
   else if (ppt == 4) { IOBM_A25(NF, 4); } \
   else { IOBM_A25(NF, 9); }
   switch (c->g.nf) {
@@ -1161,22 +1208,48 @@ template <typename T> static int& tuned_zc(iobm_ctx c) { return sizeof(T) == 4 ?
 
 static int default_ppt(int nxy, bool f32) {
   // small enough a register queue for several waves per SIMD
-  for (int ppt : {f32 ? 4 : 2, 4, 9}) {
+  for (int ppt : {f32 ? 4 : 2, 3, 4, 9}) {
     const int threads = ((nxy + ppt - 1) / ppt + 63) / 64 * 64;
     if (threads <= a25_max_threads(ppt)) return ppt;
   }
   return 0;
 }
 
-template <typename T>
-static bool launch_apply25(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
-                           const int* active, const FuseP<T>& F) {
-  if (c->tune_stencil_simple) return false;
-  int ppt = tuned_ppt<T>(c), zc = tuned_zc<T>(c);
-  if (ppt <= 0) ppt = default_ppt(c->g.nxy, sizeof(T) == 4);
-  if (zc <= 0) zc = 32;
-  if (ppt <= 0) return false;
-  return launch_apply25_shape<T>(c, ppt, zc, x, y, nrhs, E_rhs, active, F);
+// The stencil with any policy: the 2.5D kernel at the tuned (or default)
+// shape, else the cache-based one.
+template <typename T, class Op>
+static hipError_t launch_stencil(iobm_ctx c, const Op& op, int nrhs, const double* E_rhs, const int* active,
+                                 double bytes_per_point) {
+  const int rec = prof_start(c, sizeof(T) == 4 ? IOBM_K_STENCIL : IOBM_K_STENCIL_C128);
+  bool done = false;
+  if (!c->tune_stencil_simple) {
+    int ppt = tuned_ppt<T>(c), zc = tuned_zc<T>(c);
+    if (ppt <= 0) ppt = default_ppt(c->g.nxy, sizeof(T) == 4);
+    if (zc <= 0) zc = 32;
+    if (ppt > 0) done = launch_apply25_shape<T, Op>(c, ppt, zc, op, nrhs, E_rhs, active);
+  }
+  if (!done) {
+    StencilArgs S = stencil_args(c, 16);
+    if (S.nchunks > PQ_STENCIL_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_apply<T, Op>), dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, op, Vptr<T>(c), E_rhs,
+                       active);
+  }
+  prof_stop(c, rec, bytes_per_point * nrhs * c->g.npts);
+  return hipGetLastError();
+}
+
+// The electrode term of the operator on the 2 nf face planes (see k_boundary).
+// Algorithmic bytes: read x and y, write y (or the residual) on the faces.
+template <typename T, typename TR>
+static hipError_t launch_boundary(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<TR>* rout, int nrhs,
+                                  const int* e_rhs, const ModeData* modes, const int* active, Partial* part) {
+  size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(cplx<T>);
+  const int rec = prof_start(c, IOBM_K_BOUNDARY);
+  hipLaunchKernelGGL((k_boundary<T, TR>), dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan,
+                     c->g.nz, c->g.nf, x, y, rout, modes, e_rhs, twx<T>(c), twy<T>(c), active, part, (int)PQ_SLOTS,
+                     (int)PQ_BOUNDARY);
+  prof_stop(c, rec, (double)nrhs * 2 * c->g.nf * c->g.nxy * (2 * sizeof(cplx<T>) + sizeof(cplx<TR>)));
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -1184,43 +1257,49 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
                         const int* e_rhs, const ModeData* modes, const int* active,
                         const ApplyFuse<T>* fuse) {
   if (nrhs <= 0) return hipSuccess;
-  FuseP<T> F;
+  hipError_t err;
+  Partial* part = nullptr;
   if (fuse) {
-    F.z = fuse->z; F.pold = fuse->pold; F.beta = fuse->beta; F.pnew = fuse->pnew;
-    F.part = fuse->part; F.np = PQ_SLOTS;
+    OpFuseP<T> op{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part};
+    err = launch_stencil<T>(c, op, nrhs, E_rhs, active, 4.0 * sizeof(cplx<T>));
     x = fuse->pnew;  // the electrode and nonlocal terms read the assembled operand
+    part = fuse->part;
+  } else {
+    OpPlain<T> op{x, y};
+    err = launch_stencil<T>(c, op, nrhs, E_rhs, active, 2.0 * sizeof(cplx<T>));
   }
-  const int cls = sizeof(T) == 4 ? IOBM_K_STENCIL : IOBM_K_STENCIL_C128;
-  prof_start(c, cls);
-  if (!launch_apply25<T>(c, fuse ? nullptr : x, y, nrhs, E_rhs, active, F)) {
-    StencilArgs S = stencil_args(c, 16);
-    if (S.nchunks > PQ_STENCIL_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_apply<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, fuse ? nullptr : x, y,
-                       Vptr<T>(c), E_rhs, active, F);
-  }
-  prof_stop(c, cls, (double)nrhs * c->g.npts * sizeof(cplx<T>));
-  hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(cplx<T>);
-  prof_start(c, IOBM_K_BOUNDARY);
-  hipLaunchKernelGGL(k_boundary<T>, dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan,
-                     c->g.nz, c->g.nf, x, y, modes, e_rhs, twx<T>(c), twy<T>(c), active, F.part, (int)PQ_SLOTS,
-                     (int)PQ_BOUNDARY);
-  prof_stop(c, IOBM_K_BOUNDARY, (double)nrhs * 2 * c->g.nf * c->g.nxy * sizeof(cplx<T>));
-  err = hipGetLastError();
+  err = launch_boundary<T, T>(c, x, y, nullptr, nrhs, e_rhs, modes, active, part);
   if (err != hipSuccess) return err;
-  if (c->kb.ncen > 0) return launch_kb_apply<T>(c, x, y, nrhs, F.part, active);
+  if (c->kb.ncen > 0) return launch_kb_apply<T>(c, x, y, nrhs, part, active);
   return hipSuccess;
 }
+
+template <typename TR>
+hipError_t launch_refresh(iobm_ctx c, const zd* x, const zd* b, zd* rface, cplx<TR>* r, int nrhs,
+                          const double* E_rhs, const int* e_rhs, const ModeData* modes, const int* active,
+                          Partial* part) {
+  if (nrhs <= 0) return hipSuccess;
+  if (c->kb.ncen > 0) return hipErrorNotSupported;
+  OpRefresh<TR> op{x, b, rface, r, part, c->g.nz, c->g.nf, c->g.nxy};
+  hipError_t err = launch_stencil<double>(c, op, nrhs, E_rhs, active, (double)sizeof(zd) + sizeof(cplx<TR>));
+  if (err != hipSuccess) return err;
+  return launch_boundary<double, TR>(c, x, rface, r, nrhs, e_rhs, modes, active, part);
+}
+
+template hipError_t launch_refresh<float>(iobm_ctx, const zd*, const zd*, zd*, zf*, int, const double*, const int*,
+                                          const ModeData*, const int*, Partial*);
+template hipError_t launch_refresh<double>(iobm_ctx, const zd*, const zd*, zd*, zd*, int, const double*, const int*,
+                                           const ModeData*, const int*, Partial*);
 
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z, int nrhs,
                                     const int* active, Partial* dpart) {
   StencilArgs S = stencil_args(c, 16);
-  prof_start(c, IOBM_K_PRECOND_LAP);
+  const int rec = prof_start(c, IOBM_K_PRECOND_LAP);
   hipLaunchKernelGGL(k_precond_lap<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S,
                      (T)exp(-alpha), r, z, active, dpart);
-  prof_stop(c, IOBM_K_PRECOND_LAP, (double)nrhs * c->g.npts * sizeof(cplx<T>));
+  prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -1253,11 +1332,13 @@ static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int si
 template <typename T>
 hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                              const int* active, const cplx<T>* dvec = nullptr, Partial* dpart = nullptr) {
+  const int rec = prof_start(c, IOBM_K_FFT_PLANES);
   if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, dvec, dpart)) {
     size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
     hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
                        twx<T>(c), twy<T>(c), sign, (T)scale, active, dvec, dpart);
   }
+  prof_stop(c, rec, (dpart ? 3.0 : 2.0) * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -1269,6 +1350,7 @@ static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* 
   const int nmb = (nxy + 63) / 64;
   const int C = (nz + L - 1) / L;
   size_t sh = 2 * (size_t)C * 64 * 3 * sizeof(cplx<T>);
+  const int rec = prof_start(c, IOBM_K_ZFILTER);
 #define IOBM_ZF(LL)                                                                                 \
   hipLaunchKernelGGL((k_zfilter<T, LL>), dim3(nrhs * nmb), dim3(64, C), sh, c->stream, nz, c->g.nf, nxy, in, \
                      out, modes, e_rhs, active)
@@ -1278,6 +1360,7 @@ static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* 
     default: IOBM_ZF(32); break;
   }
 #undef IOBM_ZF
+  prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -1296,11 +1379,11 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
                               const int* e_rhs, const ModeData* modes, const int* active, Partial* dpart) {
   const int L = zfilter_chunk<T>(c);
   if ((c->g.nz + L - 1) / L > 8) return hipErrorInvalidValue;
-  prof_start(c, IOBM_K_PRECOND_FFT);
+  const int rec = prof_start(c, IOBM_K_PRECOND_FFT);
   hipError_t err = launch_fft_planes<T>(c, r, scratch, -1, 1.0, nrhs, active);
   if (err == hipSuccess) err = launch_zfilter<T>(c, L, scratch, z, nrhs, e_rhs, modes, active);
   if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active, r, dpart);
-  prof_stop(c, IOBM_K_PRECOND_FFT, (double)nrhs * c->g.npts * sizeof(cplx<T>));
+  prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
   return err;
 }
 
@@ -1328,19 +1411,20 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
   };
   if (!c->tune_stencil_simple) {
     // the shape is timed on the operator as the iteration runs it
-    FuseP<T> F;
-    if (fuse) {
-      F.z = fuse->z; F.pold = fuse->pold; F.beta = fuse->beta; F.pnew = fuse->pnew;
-      F.part = fuse->part; F.np = PQ_SLOTS;
-    }
     float best = 1e30f;
     int bp = 0, bz = 0;
-    for (int ppt : {1, 2, 4, 9})
+    for (int ppt : {1, 2, 3, 4, 9})
       for (int zc : {16, 32, 64}) {
         const int threads = ((c->g.nxy + ppt - 1) / ppt + 63) / 64 * 64;
         if (threads > a25_max_threads(ppt) || (sizeof(T) == 8 && ppt == 9)) continue;
         if (zc > c->g.nz && zc != 16) continue;
-        float t = timed([&] { launch_apply25_shape<T>(c, ppt, zc, fuse ? nullptr : x, y, nrhs, E_rhs, active, F); });
+        float t = timed([&] {
+          if (fuse)
+            launch_apply25_shape<T>(c, ppt, zc, OpFuseP<T>{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part},
+                                    nrhs, E_rhs, active);
+          else
+            launch_apply25_shape<T>(c, ppt, zc, OpPlain<T>{x, y}, nrhs, E_rhs, active);
+        });
         if (t < best) { best = t; bp = ppt; bz = zc; }
       }
     if (bp > 0) { tuned_ppt<T>(c) = bp; tuned_zc<T>(c) = bz; }
@@ -1411,10 +1495,10 @@ template <typename T>
 hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active,
                       void* part) {
   int nblk = dot_blocks(c);
-  prof_start(c, IOBM_K_DOT);
+  const int rec = prof_start(c, IOBM_K_DOT);
   hipLaunchKernelGGL(k_dot<T>, dim3(nact * nblk), dim3(256), 0, c->stream, a, b, c->g.npts, nblk,
                      (Partial*)part, active);
-  prof_stop(c, IOBM_K_DOT, (double)nact * c->g.npts * sizeof(cplx<T>));
+  prof_stop(c, rec, (a == b ? 1.0 : 2.0) * nact * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -1422,10 +1506,10 @@ template <typename T, typename TX>
 hipError_t launch_update_xr(iobm_ctx c, cplx<TX>* x, const cplx<T>* p, cplx<T>* r, const cplx<T>* q,
                             const zd* alpha, int nact, const int* active, void* part) {
   int nblk = dot_blocks(c);
-  prof_start(c, IOBM_K_UPDATE);
+  const int rec = prof_start(c, IOBM_K_UPDATE);
   hipLaunchKernelGGL((k_update_xr<T, TX>), dim3(nact * nblk), dim3(256), 0, c->stream, x, p, r, q, alpha,
                      c->g.npts, nblk, (Partial*)part, active);
-  prof_stop(c, IOBM_K_UPDATE, (double)nact * c->g.npts * sizeof(cplx<T>));
+  prof_stop(c, rec, 4.0 * nact * c->g.npts * sizeof(cplx<T>) + 2.0 * nact * c->g.npts * sizeof(cplx<TX>));
   return hipGetLastError();
 }
 
@@ -1454,9 +1538,11 @@ hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int na
 }
 
 template <typename T>
-hipError_t launch_accumulate(iobm_ctx c, zd* x, const cplx<T>* d, int nact, const int* active) {
+hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, int nact, const int* active) {
+  const int rec = prof_start(c, IOBM_K_ACCUMULATE);
   hipLaunchKernelGGL(k_accumulate<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, x, d, c->g.npts,
                      active);
+  prof_stop(c, rec, 2.0 * nact * c->g.npts * (sizeof(zd) + sizeof(cplx<T>)));
   return hipGetLastError();
 }
 
@@ -1495,8 +1581,8 @@ template hipError_t launch_residual<float>(iobm_ctx, const zd*, zf*, int, const 
 template hipError_t launch_convert<float, double>(iobm_ctx, const zd*, zf*, int, const int*);
 template hipError_t launch_convert<double, double>(iobm_ctx, const zd*, zd*, int, const int*);
 template hipError_t launch_convert<float, float>(iobm_ctx, const zf*, zf*, int, const int*);
-template hipError_t launch_accumulate<float>(iobm_ctx, zd*, const zf*, int, const int*);
-template hipError_t launch_accumulate<double>(iobm_ctx, zd*, const zd*, int, const int*);
+template hipError_t launch_accumulate<float>(iobm_ctx, zd*, zf*, int, const int*);
+template hipError_t launch_accumulate<double>(iobm_ctx, zd*, zd*, int, const int*);
 template hipError_t launch_combine_psi<double>(iobm_ctx, int, const zd*, zd*, const int*, const int*,
                                                const int*);
 template hipError_t launch_combine_psi<float>(iobm_ctx, int, const zd*, zf*, const int*, const int*,

@@ -19,7 +19,8 @@ LIBPATH = os.path.join(_HERE, "libiobm.so")
 
 C128, C64_REFINED = 0, 1
 PC_NONE, PC_TRUNCATED_LAPLACIAN, PC_LATERAL_FFT = 0, 1, 2
-K_STENCIL, K_BOUNDARY, K_PRECOND_FFT, K_PRECOND_LAP, K_NONLOCAL, K_DOT, K_UPDATE, K_STENCIL_C128 = range(1, 9)
+(K_STENCIL, K_BOUNDARY, K_PRECOND_FFT, K_PRECOND_LAP, K_NONLOCAL, K_DOT, K_UPDATE, K_STENCIL_C128,
+ K_FFT_PLANES, K_ZFILTER, K_ACCUMULATE) = range(1, 12)
 STATUS = ["ok", "invalid argument", "bad state", "out of device memory", "device error",
           "not converged", "Krylov breakdown", "energy at a channel threshold", "unsupported"]
 
@@ -179,7 +180,7 @@ class Solver:
         self._check(lib().iobm_profile_begin(self._ctx, mask))
 
     def profile_end(self, kernel_class):
-        """(launches, total ms, pass bytes) of one timed kernel class."""
+        """(launches, total ms, algorithmic bytes) of one timed kernel class."""
         n = C.c_int32()
         ms = C.c_double()
         b = C.c_double()
