@@ -36,18 +36,25 @@ __device__ __forceinline__ void block_reduce3(double& a, double& b, double& c) {
   }
 }
 
-// Block sum of two values for a block of BLK >= 64 threads that need not be
-// whole wavefronts: staged through LDS, the first wavefront sums strided
-// entries and then reduces across its lanes.  Result in thread 0.
+// Block sum of two values for a block of BLK threads that need not be whole
+// wavefronts: staged through LDS, the first wavefront sums strided entries
+// and then reduces across its lanes (a block smaller than a wavefront is
+// summed by thread 0).  Result in thread 0.
 template <int BLK>
 __device__ __forceinline__ void block_sum2(double& a, double& b) {
-  static_assert(BLK >= 64, "block_sum2 needs at least one full wavefront");
   __shared__ double red[2][BLK];
   __syncthreads();
   red[0][threadIdx.x] = a;
   red[1][threadIdx.x] = b;
   __syncthreads();
-  if (threadIdx.x < 64) {
+  if constexpr (BLK < 64) {  // less than a wavefront: thread 0 sums in order
+    if (threadIdx.x == 0) {
+      double x = 0, y = 0;
+      for (int i = 0; i < BLK; ++i) { x += red[0][i]; y += red[1][i]; }
+      a = x;
+      b = y;
+    }
+  } else if (threadIdx.x < 64) {
     double x = 0, y = 0;
     for (int i = threadIdx.x; i < BLK; i += 64) { x += red[0][i]; y += red[1][i]; }
     for (int off = 32; off > 0; off >>= 1) {
@@ -400,6 +407,103 @@ __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __rest
       Partial Pp;
       Pp.re = s_re; Pp.im = s_im; Pp.n2 = s_n2; Pp.pad = 0;
       part[(long long)rhs * np + pslot + side] = Pp;
+    }
+  }
+}
+
+// Square planes (N x N, N in the register-FFT list): the NF face planes of
+// one side sit in LDS (padded rows); N threads per plane transform its rows
+// and then its columns in registers, both ways.  Same contract as
+// k_boundary.  Block partials are staged in LDS and summed by thread 0 in
+// thread order (blocks can be smaller than a wavefront).
+template <typename T, typename TR, int N, int NF>
+__global__ void __launch_bounds__(N * NF) k_boundary_reg(int nz, const cplx<T>* __restrict__ x,
+                                                        cplx<T>* __restrict__ y, cplx<TR>* __restrict__ rout,
+                                                        const ModeData* __restrict__ modes,
+                                                        const int* __restrict__ e_rhs,
+                                                        const cplx<T>* __restrict__ tw,
+                                                        const int* __restrict__ active,
+                                                        Partial* __restrict__ part, int np, int pslot) {
+  constexpr int NN = N * N, BLK = N * NF;
+  __shared__ cplx<T> sm[NF][N][N + 1];
+  __shared__ double red[3][BLK];
+  const int slot = blockIdx.x >> 1;
+  const int side = blockIdx.x & 1;
+  const int rhs = rhs_of(active, slot);
+  const ModeData* md = modes + (long long)e_rhs[rhs] * NN;
+  const int pbase = side ? nz - NF : 0;
+  const long long off = (long long)rhs * NN * nz + (long long)pbase * NN;  // NF consecutive planes
+  for (int i = threadIdx.x; i < NF * NN; i += BLK) {
+    const int k = i / NN, e = i - k * NN;
+    sm[k][e / N][e % N] = x[off + i];
+  }
+  __syncthreads();
+  const int k = threadIdx.x / N, li = threadIdx.x - k * N;
+  cplx<T> v[N];
+  auto rows_cols = [&](int sign) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = sm[k][li][i];
+    reg_fft<T, N>(v, tw, sign);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sm[k][li][i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = sm[k][i][li];
+    reg_fft<T, N>(v, tw, sign);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sm[k][i][li] = v[i];
+    __syncthreads();
+  };
+  rows_cols(-1);
+  // mode mixing, mode m = ky N + kx at sm[.][ky][kx]; plane k <-> boundary
+  // index i as in k_boundary
+  const T inv = (T)(1.0 / NN);
+  for (int m = threadIdx.x; m < NN; m += BLK) {
+    const int r = m / N, cc = m - r * N;
+    cplx<T> in[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) in[l] = sm[l][r][cc];
+#pragma unroll
+    for (int kk = 0; kk < NF; ++kk) {
+      const int ik = side ? kk : NF - 1 - kk;
+      cplx<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int l = 0; l < NF; ++l) {
+        const int il = side ? l : NF - 1 - l;
+        acc = acc + cvt<T>(md[m].sig[ik * NF + il]) * in[l];
+      }
+      sm[kk][r][cc] = inv * acc;
+    }
+  }
+  __syncthreads();
+  rows_cols(+1);
+  double s_re = 0, s_im = 0, s_n2 = 0;
+  for (int i = threadIdx.x; i < NF * NN; i += BLK) {
+    const int kk = i / NN, e = i - kk * NN;
+    const cplx<T> res = sm[kk][e / N][e % N];
+    if (rout) {
+      const cplx<T> val = y[off + i] + res;
+      rout[off + i] = cvt<TR>(val);
+      s_n2 += (double)val.re * val.re + (double)val.im * val.im;
+    } else {
+      y[off + i] = y[off + i] - res;
+      if (part) {
+        const cplx<T> c = x[off + i];
+        s_re -= (double)c.re * res.re - (double)c.im * res.im;
+        s_im -= (double)c.re * res.im + (double)c.im * res.re;
+      }
+    }
+  }
+  if (part) {
+    red[0][threadIdx.x] = s_re;
+    red[1][threadIdx.x] = s_im;
+    red[2][threadIdx.x] = s_n2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Partial P;
+      P.re = P.im = P.n2 = P.pad = 0;
+      for (int t = 0; t < BLK; ++t) { P.re += red[0][t]; P.im += red[1][t]; P.n2 += red[2][t]; }
+      part[(long long)rhs * np + pslot + side] = P;
     }
   }
 }
@@ -1240,14 +1344,41 @@ static hipError_t launch_stencil(iobm_ctx c, const Op& op, int nrhs, const doubl
 
 // The electrode term of the operator on the 2 nf face planes (see k_boundary).
 // Algorithmic bytes: read x and y, write y (or the residual) on the faces.
+template <typename T, typename TR, int N>
+static void launch_boundary_reg(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<TR>* rout, int nrhs,
+                                const int* e_rhs, const ModeData* modes, const int* active, Partial* part) {
+#define IOBM_BREG(NF)                                                                                         \
+  hipLaunchKernelGGL((k_boundary_reg<T, TR, N, NF>), dim3(2 * nrhs), dim3(N * NF), 0, c->stream, c->g.nz, x, y, \
+                     rout, modes, e_rhs, twx<T>(c), active, part, (int)PQ_SLOTS, (int)PQ_BOUNDARY)
+  switch (c->g.nf) {
+    case 1: IOBM_BREG(1); break;
+    case 2: IOBM_BREG(2); break;
+    default: IOBM_BREG(3); break;
+  }
+#undef IOBM_BREG
+}
+
 template <typename T, typename TR>
 static hipError_t launch_boundary(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<TR>* rout, int nrhs,
                                   const int* e_rhs, const ModeData* modes, const int* active, Partial* part) {
   size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(cplx<T>);
   const int rec = prof_start(c, IOBM_K_BOUNDARY);
-  hipLaunchKernelGGL((k_boundary<T, TR>), dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan,
-                     c->g.nz, c->g.nf, x, y, rout, modes, e_rhs, twx<T>(c), twy<T>(c), active, part, (int)PQ_SLOTS,
-                     (int)PQ_BOUNDARY);
+  bool reg = c->g.nx == c->g.ny && !c->tune_fft_generic;
+  if (reg) {
+    switch (c->g.nx) {
+      case 8: launch_boundary_reg<T, TR, 8>(c, x, y, rout, nrhs, e_rhs, modes, active, part); break;
+      case 12: launch_boundary_reg<T, TR, 12>(c, x, y, rout, nrhs, e_rhs, modes, active, part); break;
+      case 16: launch_boundary_reg<T, TR, 16>(c, x, y, rout, nrhs, e_rhs, modes, active, part); break;
+      case 24: launch_boundary_reg<T, TR, 24>(c, x, y, rout, nrhs, e_rhs, modes, active, part); break;
+      case 32: launch_boundary_reg<T, TR, 32>(c, x, y, rout, nrhs, e_rhs, modes, active, part); break;
+      case 48: launch_boundary_reg<T, TR, 48>(c, x, y, rout, nrhs, e_rhs, modes, active, part); break;
+      default: reg = false;
+    }
+  }
+  if (!reg)
+    hipLaunchKernelGGL((k_boundary<T, TR>), dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan,
+                       c->g.nz, c->g.nf, x, y, rout, modes, e_rhs, twx<T>(c), twy<T>(c), active, part,
+                       (int)PQ_SLOTS, (int)PQ_BOUNDARY);
   prof_stop(c, rec, (double)nrhs * 2 * c->g.nf * c->g.nxy * (2 * sizeof(cplx<T>) + sizeof(cplx<TR>)));
   return hipGetLastError();
 }
@@ -1311,7 +1442,8 @@ static void launch_fft_reg(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign
                      c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active, dvec, dpart);
 }
 
-// planes per block of the register FFT: enough threads for a wavefront or two
+// planes per block of the register FFT (measured: one plane per block is
+// fastest at 48 x 48)
 template <typename T>
 static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                              const int* active, const cplx<T>* dvec, Partial* dpart) {
@@ -1322,7 +1454,7 @@ static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int si
     case 16: launch_fft_reg<T, 16, 8>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
     case 24: launch_fft_reg<T, 24, 4>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
     case 32: launch_fft_reg<T, 32, 4>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
-    case 48: launch_fft_reg<T, 48, 2>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
+    case 48: launch_fft_reg<T, 48, 1>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
     default: return false;
   }
 }

@@ -71,7 +71,11 @@ def test_rhs(torch, g):
             assert np.abs(b[k] - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("g", GRIDS, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
+# square lateral planes take the in-register FFT path of the electrode term
+APPLY_GRIDS = GRIDS + [Grid(8, 8, 24, 0.4, 1), Grid(16, 16, 20, 0.4, 2), Grid(24, 24, 16, 0.35, 3)]
+
+
+@pytest.mark.parametrize("g", APPLY_GRIDS, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
 @pytest.mark.parametrize("kb", [False, True])
 def test_apply_matches_oracle(torch, g, kb):
     from paper_1009_5300_amd import iobm
