@@ -29,6 +29,54 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+# HBM traffic of the dominant kernel, measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy kernel), kept with
+# the git blob ids of the sources it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
+KERNEL_SOURCES = ["paper_1009_5300_amd/csrc/ops.hip", "paper_1009_5300_amd/csrc/common.h"]
+
+
+def _blob_id(path):
+    import hashlib
+    data = open(os.path.join(ROOT, path), "rb").read()
+    return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
+
+
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if there is none or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("kernel_class") != kernel:
+        return None
+    for src in KERNEL_SOURCES:
+        if rec.get("blob " + src) != _blob_id(src):
+            return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(gib=1.0, reps=4):
+    """A plain device copy of known size (the counter calibration run):
+    reads and writes `gib` GiB per launch."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                                           "launches": reps}}), flush=True)
 
 
 def _kernel_stats(s, cls):
@@ -77,7 +125,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip plain-CG and Eq. (17) samples")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy kernel of known size (for the HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the scattering states of different energies are "
               "independent, and multi-GPU runs are not part of this build (use --gpus 1).",
@@ -139,7 +192,7 @@ def main():
     dom = kern[dom_name]
     roofline = {"bound": "hbm", "achieved": round(dom["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(dom["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                "traffic": None, "kernel": dom_name,
+                "traffic": _measured_traffic(dom_name), "kernel": dom_name,
                 "avg_launch_ms": round(dom["avg_ms"], 4),
                 "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
     st = kern["stencil"]
@@ -169,7 +222,8 @@ def main():
         "setup_s": round(t_setup, 3),
         "kernels": {k: ({kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()} if v else None)
                     for k, v in list(kern.items()) + [("precond_fft_whole", precond)]},
-        "solve_stats": {"iters_mean": float(stats[:, 0].mean()), "iters_max": int(stats[:, 0].max()),
+        "solve_stats": {"per": "channel (cos + sin standing-wave solves of a +-G pair summed)",
+                        "iters_mean": float(stats[:, 0].mean()), "iters_max": int(stats[:, 0].max()),
                         "refinements_mean": float(stats[:, 1].mean()),
                         "max_rel_residual": float(stats[:, 3].max()),
                         "max_flux_error": float(np.abs(stats[:, 4]).max())},

@@ -110,7 +110,9 @@ typedef struct {
   int32_t check_every; /* iterations between host convergence checks; default 2 */
 } iobm_solve_opts;
 
-/* Per right-hand side statistics (the paper's Table 2 counts iterations). */
+/* Per (energy, incident channel) statistics (the paper's Table 2 counts
+ * iterations).  A channel with G != 0 is solved as the cos and sin standing
+ * waves of its +-G pair; its counts are the sums over those two solves. */
 typedef struct {
   int32_t iters;        /* preconditioned COCG iterations */
   int32_t refinements;  /* FP64 true-residual evaluations (reliable updates) */
