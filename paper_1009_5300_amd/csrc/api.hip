@@ -603,6 +603,7 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
   }
   try {
     HIPCHK(hipGetDevice(&ctx->device));
+    HIPCHK(hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     std::vector<zd> tx(g->nx), ty(g->ny);
     std::vector<zf> fx(g->nx), fy(g->ny);
     for (int k = 0; k < g->nx; ++k) {

@@ -57,6 +57,7 @@ struct iobm_ctx_s {
   GridDev g;
   hipStream_t stream = nullptr;
   int device = 0;
+  int num_cu = 256;  // compute units of the device
   double c[4];     // central FD weights chat_0..chat_nf (h = 1)
   FFTPlan2D plan;
   zd* twx_d = nullptr;  // exp(-2 pi i k / nx), k < nx

@@ -88,20 +88,36 @@ struct StencilArgs {
 };
 
 // Operand and epilogue policies of the stencil kernels.  bind() selects the
-// rhs, load(o) returns the operand at flat offset o of that rhs, center()
+// rhs, load(o) returns the operand at flat offset o of that rhs (load_raw and
+// combine split it into the memory reads and the arithmetic, for prefetching
+// lookahead planes ahead), center()
 // sees the operand of each point the block owns, store() takes the operand
 // and the stencil result of that point, and finish() runs once per block
 // (every thread; it may synchronise the block).
 template <typename T>
 struct OpPlain {  // y = A_st x
+  typedef cplx<T> Raw;
+  static constexpr int lookahead = 2;
   const cplx<T>* x;
   cplx<T>* y;
   __device__ __forceinline__ void bind(int rhs, long long vol) { x += rhs * vol; y += rhs * vol; }
   __device__ __forceinline__ cplx<T> load(long long o) const { return x[o]; }
+  __device__ __forceinline__ Raw load_raw(long long o) const { return x[o]; }
+  __device__ __forceinline__ cplx<T> combine(Raw r, bool ok) const { return ok ? r : mk<T>(0, 0); }
   __device__ __forceinline__ void center(long long, cplx<T>) {}
   __device__ __forceinline__ void store(int, long long o, cplx<T>, cplx<T> acc) { y[o] = acc; }
-  __device__ __forceinline__ void finish(int, int) {}
+  __device__ __forceinline__ void finish(int, int, int) {}
 };
+
+// The number of z chunks of a launch depends on the batch size, so the
+// chunk-0 block of each rhs zeroes the stencil slots past the last chunk.
+__device__ __forceinline__ void clear_unused_slots(Partial* part, int rhs, int chunk, int nchunks) {
+  if (chunk == 0 && (int)threadIdx.x < PQ_STENCIL_MAX - nchunks) {
+    Partial Z;
+    Z.re = Z.im = Z.n2 = Z.pad = 0;
+    part[(long long)rhs * PQ_SLOTS + nchunks + threadIdx.x] = Z;
+  }
+}
 
 // COCG direction update fused into the operator: the operand is
 // p_new = z + beta p_old (p_old not read where beta = 0), written to pnew for
@@ -109,12 +125,17 @@ struct OpPlain {  // y = A_st x
 // part[rhs][chunk] (PQ_SLOTS per rhs).
 template <typename T>
 struct OpFuseP {
+  struct Raw {
+    cplx<T> z, p;
+  };
+  static constexpr int lookahead = sizeof(T) == 4 ? 2 : 1;
   const cplx<T>* z;
   const cplx<T>* pold;
   const zd* beta;
   cplx<T>* pnew;
   cplx<T>* y;
   Partial* part;
+  const cplx<T>* psrc;
   cplx<T> bt;
   bool use_p;
   double s_re, s_im;
@@ -122,6 +143,7 @@ struct OpFuseP {
     z += rhs * vol; pold += rhs * vol; pnew += rhs * vol; y += rhs * vol;
     bt = cvt<T>(beta[rhs]);
     use_p = bt.re != (T)0 || bt.im != (T)0;
+    psrc = use_p ? pold : z;
     s_re = s_im = 0;
   }
   __device__ __forceinline__ cplx<T> load(long long o) const {
@@ -129,13 +151,22 @@ struct OpFuseP {
     if (use_p) v = v + bt * pold[o];
     return v;
   }
+  __device__ __forceinline__ Raw load_raw(long long o) const {
+    Raw r;
+    r.z = z[o];
+    r.p = psrc[o];  // psrc = z where beta = 0: a cache hit, not a second stream
+    return r;
+  }
+  __device__ __forceinline__ cplx<T> combine(const Raw& r, bool ok) const {
+    return ok ? (use_p ? r.z + bt * r.p : r.z) : mk<T>(0, 0);
+  }
   __device__ __forceinline__ void center(long long o, cplx<T> v) { pnew[o] = v; }
   __device__ __forceinline__ void store(int, long long o, cplx<T> c, cplx<T> acc) {
     y[o] = acc;
     s_re += (double)c.re * acc.re - (double)c.im * acc.im;
     s_im += (double)c.re * acc.im + (double)c.im * acc.re;
   }
-  __device__ __forceinline__ void finish(int rhs, int chunk) {
+  __device__ __forceinline__ void finish(int rhs, int chunk, int nchunks) {
     double dummy = 0;
     block_reduce3(s_re, s_im, dummy);
     if (threadIdx.x == 0) {
@@ -143,6 +174,7 @@ struct OpFuseP {
       P.re = s_re; P.im = s_im; P.n2 = 0; P.pad = 0;
       part[(long long)rhs * PQ_SLOTS + chunk] = P;
     }
+    clear_unused_slots(part, rhs, chunk, nchunks);
   }
 };
 
@@ -154,6 +186,8 @@ struct OpFuseP {
 // rface for the electrode kernel, which adds Sigma x and finishes them.
 template <typename TR>
 struct OpRefresh {
+  typedef zd Raw;
+  static constexpr int lookahead = 1;
   const zd* x;
   const zd* b;
   zd* rface;
@@ -166,6 +200,8 @@ struct OpRefresh {
     s_n2 = 0;
   }
   __device__ __forceinline__ zd load(long long o) const { return x[o]; }
+  __device__ __forceinline__ Raw load_raw(long long o) const { return x[o]; }
+  __device__ __forceinline__ zd combine(Raw r, bool ok) const { return ok ? r : mk(0.0, 0.0); }
   __device__ __forceinline__ void center(long long, zd) {}
   __device__ __forceinline__ void store(int zz, long long o, zd, zd acc) {
     if (zz < nf || zz >= nz - nf) {
@@ -175,7 +211,7 @@ struct OpRefresh {
       s_n2 += acc.re * acc.re + acc.im * acc.im;
     }
   }
-  __device__ __forceinline__ void finish(int rhs, int chunk) {
+  __device__ __forceinline__ void finish(int rhs, int chunk, int nchunks) {
     double d0 = 0, d1 = 0;
     block_reduce3(s_n2, d0, d1);
     if (threadIdx.x == 0) {
@@ -183,6 +219,7 @@ struct OpRefresh {
       P.re = 0; P.im = 0; P.n2 = s_n2; P.pad = 0;
       part[(long long)rhs * PQ_SLOTS + chunk] = P;
     }
+    clear_unused_slots(part, rhs, chunk, nchunks);
   }
 };
 
@@ -227,7 +264,7 @@ __global__ void __launch_bounds__(256) k_apply(StencilArgs S, Op op, const T* __
       op.store(z, zo + p, c0, acc);
     }
   }
-  op.finish(rhs, chunk);
+  op.finish(rhs, chunk, S.nchunks);
 }
 
 // 2.5D variant: a block owns all points of the lateral plane (up to MAXP per
@@ -249,9 +286,11 @@ template <typename T, int NF, int MAXP, class Op>
 __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs S, Op op, const T* __restrict__ V,
                                                                     const double* __restrict__ E_rhs,
                                                                     const int* __restrict__ active) {
+  typedef typename Op::Raw Raw;
+  constexpr int W = 2 * NF + 1;  // planes of the z window
+  constexpr int LA = Op::lookahead;
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);  // [2][nxy]
-  constexpr int Q = 2 * NF + 2;
   const int nxy = S.nxy, nz = S.nz;
   const int slot = blockIdx.x / S.nchunks;
   const int chunk = blockIdx.x - slot * S.nchunks;
@@ -263,37 +302,43 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
   T wx[NF + 1], wy[NF + 1], wz[NF + 1];
 #pragma unroll
   for (int n = 1; n <= NF; ++n) { wx[n] = (T)S.wx[n]; wy[n] = (T)S.wy[n]; wz[n] = (T)S.wz[n]; }
-  cplx<T> q[Q][MAXP];  // q[NF + d][u] = operand(z + d) at the thread's point u
-  T vq[2][MAXP];       // V(z), V(z + 1)
-  auto ld = [&](int z, int u) -> cplx<T> {
-    const int p = threadIdx.x + u * blockDim.x;
-    if (!(p < nxy && z >= 0 && z < nz)) return mk<T>(0, 0);
-    return op.load((long long)z * nxy + p);
+  // At step z: w[d][u] = operand(z - NF + d) at the thread's point u; pre[k][u]
+  // holds the raw loads of plane z + NF + 1 + k, issued LA steps ahead and
+  // combined into the window only when it advances, so that no step waits
+  // on loads it has just issued.
+  cplx<T> w[W][MAXP];
+  Raw pre[LA][MAXP];
+  T vq[2][MAXP];  // V(z), V(z + 1)
+  // Loads are unconditional from clamped (always valid) addresses, and planes
+  // outside 0..nz-1 or points past nxy are masked where the value is
+  // combined: a load under a branch makes the compiler wait for it (and for
+  // every load issued before it) at the branch's end.
+  auto off = [&](int z, int u) -> long long {
+    const int p = min((int)(threadIdx.x + u * blockDim.x), nxy - 1);
+    return (long long)min(max(z, 0), nz - 1) * nxy + p;
+  };
+  auto valid = [&](int z, int u) -> bool {
+    return (int)(threadIdx.x + u * blockDim.x) < nxy && z >= 0 && z < nz;
   };
 #pragma unroll
-  for (int d = 0; d < Q - 1; ++d)
+  for (int d = 0; d < W; ++d)
 #pragma unroll
-    for (int u = 0; u < MAXP; ++u) q[d][u] = ld(z0 - NF + d, u);
+    for (int u = 0; u < MAXP; ++u) w[d][u] = op.combine(op.load_raw(off(z0 - NF + d, u)), valid(z0 - NF + d, u));
 #pragma unroll
-  for (int u = 0; u < MAXP; ++u) {
-    const int p = threadIdx.x + u * blockDim.x;
-    vq[0][u] = p < nxy ? V[(long long)z0 * nxy + p] : (T)0;
-  }
+  for (int k = 0; k < LA; ++k)
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) pre[k][u] = op.load_raw(off(z0 + NF + 1 + k, u));
+#pragma unroll
+  for (int u = 0; u < MAXP; ++u) vq[0][u] = V[off(z0, u)];
   for (int z = z0; z < z1; ++z) {
     const int b = (z - z0) & 1;
-    // prefetch plane z + NF + 1 and V(z + 1)
-#pragma unroll
-    for (int u = 0; u < MAXP; ++u) {
-      q[Q - 1][u] = ld(z + NF + 1, u);
-      const int p = threadIdx.x + u * blockDim.x;
-      vq[1][u] = (p < nxy && z + 1 < nz) ? V[(long long)(z + 1) * nxy + p] : (T)0;
-    }
 #pragma unroll
     for (int u = 0; u < MAXP; ++u) {
       const int p = threadIdx.x + u * blockDim.x;
+      vq[1][u] = V[off(z + 1, u)];  // unused past the last plane
       if (p < nxy) {
-        buf[b * nxy + p] = q[NF][u];
-        op.center((long long)z * nxy + p, q[NF][u]);
+        buf[b * nxy + p] = w[NF][u];
+        op.center((long long)z * nxy + p, w[NF][u]);
       }
     }
     __syncthreads();
@@ -304,7 +349,7 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
       if (p < nxy) {
         const int j = p / S.nx;
         const int i = p - j * S.nx;
-        cplx<T> acc = (diag0 - vq[0][u]) * q[NF][u];
+        cplx<T> acc = (diag0 - vq[0][u]) * w[NF][u];
 #pragma unroll
         for (int n = 1; n <= NF; ++n) {
           int ip = i + n; if (ip >= S.nx) ip -= S.nx;
@@ -312,19 +357,24 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
           int jp = j + n; if (jp >= S.ny) jp -= S.ny;
           int jm = j - n; if (jm < 0) jm += S.ny;
           acc = acc + wx[n] * (pl[j * S.nx + ip] + pl[j * S.nx + im]) + wy[n] * (pl[jp * S.nx + i] + pl[jm * S.nx + i]) +
-                wz[n] * (q[NF + n][u] + q[NF - n][u]);
+                wz[n] * (w[NF + n][u] + w[NF - n][u]);
         }
-        op.store(z, (long long)z * nxy + p, q[NF][u], acc);
+        op.store(z, (long long)z * nxy + p, w[NF][u], acc);
       }
     }
+    // advance the window; issue the loads of plane z + NF + 1 + LA
 #pragma unroll
-    for (int d = 0; d < Q - 1; ++d)
+    for (int u = 0; u < MAXP; ++u) {
 #pragma unroll
-      for (int u = 0; u < MAXP; ++u) q[d][u] = q[d + 1][u];
+      for (int d = 0; d < W - 1; ++d) w[d][u] = w[d + 1][u];
+      w[W - 1][u] = op.combine(pre[0][u], valid(z + NF + 1, u));
 #pragma unroll
-    for (int u = 0; u < MAXP; ++u) vq[0][u] = vq[1][u];
+      for (int k = 0; k < LA - 1; ++k) pre[k][u] = pre[k + 1][u];
+      pre[LA - 1][u] = op.load_raw(off(z + NF + 1 + LA, u));
+      vq[0][u] = vq[1][u];
+    }
   }
-  op.finish(rhs, chunk);
+  op.finish(rhs, chunk, S.nchunks);
 }
 
 // ----------------------------------------------------- electrode term ---
@@ -1330,6 +1380,10 @@ static hipError_t launch_stencil(iobm_ctx c, const Op& op, int nrhs, const doubl
     int ppt = tuned_ppt<T>(c), zc = tuned_zc<T>(c);
     if (ppt <= 0) ppt = default_ppt(c->g.nxy, sizeof(T) == 4);
     if (zc <= 0) zc = 32;
+    // a small batch (the tail of a solve, a small refinement subset) gets
+    // shorter chunks, so that there are blocks for every compute unit and no
+    // block walks a long chunk alone
+    while (zc > 8 && (long long)nrhs * ((c->g.nz + zc - 1) / zc) < 2LL * c->num_cu) zc /= 2;
     if (ppt > 0) done = launch_apply25_shape<T, Op>(c, ppt, zc, op, nrhs, E_rhs, active);
   }
   if (!done) {
