@@ -183,8 +183,20 @@ void ensure_modes(iobm_ctx ctx, const std::vector<double>& E, bool force = false
     HIPCHK(hipMalloc(&ctx->modes_d, n * sizeof(ModeData)));
     ctx->modes_cap = n;
   }
+  const size_t ns = n * ctx->g.nf * ctx->g.nf;
+  if (ctx->sig_cap < ns) {
+    if (ctx->sig_d) (void)hipFree(ctx->sig_d);
+    if (ctx->sig_f) (void)hipFree(ctx->sig_f);
+    ctx->sig_d = nullptr;
+    ctx->sig_f = nullptr;
+    ctx->sig_cap = 0;
+    HIPCHK(hipMalloc(&ctx->sig_d, ns * sizeof(zd)));
+    HIPCHK(hipMalloc(&ctx->sig_f, ns * sizeof(zf)));
+    ctx->sig_cap = ns;
+  }
   double* Ed = upload(ctx, S_IDX, E);
   HIPCHK(launch_modes(ctx, Ed, (int)E.size(), ctx->modes_d));
+  HIPCHK(launch_sigma_tables(ctx, (int)E.size(), ctx->modes_d, ctx->sig_d, ctx->sig_f));
   ctx->modes_h.resize(n);
   HIPCHK(hipMemcpyAsync(ctx->modes_h.data(), ctx->modes_d, n * sizeof(ModeData), hipMemcpyDeviceToHost,
                         ctx->stream));
@@ -672,7 +684,8 @@ iobm_status iobm_destroy(iobm_ctx ctx) {
   else (void)hipDeviceSynchronize();
   for (auto& e : ctx->pool)
     if (e.first) (void)hipFree(e.first);
-  void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->V_d, ctx->V_f, ctx->modes_d,
+  void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->V_d, ctx->V_f, ctx->modes_d, ctx->sig_d,
+                  ctx->sig_f,
                   ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.hD, ctx->arena_d};
   if (ctx->arena_h) (void)hipHostFree(ctx->arena_h);
   for (void* p : ptrs)

@@ -73,6 +73,11 @@ struct iobm_ctx_s {
   ModeData* modes_d = nullptr;
   std::vector<ModeData> modes_h;
   size_t modes_cap = 0;
+  // Sigma_R blocks of the same energies, [energy][nf * nf][mode], in both
+  // precisions (coalesced reads for the electrode kernels)
+  zd* sig_d = nullptr;
+  zf* sig_f = nullptr;
+  size_t sig_cap = 0;
   void* arena_d = nullptr;  // small index arrays (device) and their pinned host mirror
   void* arena_h = nullptr;
   unsigned char region_pending[64] = {0};
@@ -109,6 +114,7 @@ struct RhsMap {        // device arrays describing a batch of right-hand sides
 };
 
 hipError_t launch_modes(iobm_ctx c, const double* E_d, int nE, ModeData* out);
+hipError_t launch_sigma_tables(iobm_ctx c, int nE, const ModeData* modes, zd* sig_d, zf* sig_f);
 
 // Per-rhs FP64 partial sums of a bilinear form u^T v (re, im) and of |u|^2
 // (n2), one per block, combined in a fixed order.

@@ -372,3 +372,32 @@ hipError_t launch_modes(iobm_ctx ctx, const double* E_d, int nE, ModeData* out) 
   hipLaunchKernelGGL(k_modes, dim3((unsigned)blocks), dim3(threads), 0, ctx->stream, A, E_d, out);
   return hipGetLastError();
 }
+
+namespace {
+// Sigma_R blocks copied out of the mode table into [energy][nf * nf][mode]
+// order, in complex128 and complex64.
+__global__ void k_sigma_tables(int nE, int nxy, int nf, const ModeData* __restrict__ modes, zd* __restrict__ sd,
+                               zf* __restrict__ sf) {
+  const int nk = nf * nf;
+  const long long n = (long long)nE * nk * nxy;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(i % nxy);
+    const long long ek = i / nxy;
+    const int k = (int)(ek % nk);
+    const int e = (int)(ek / nk);
+    const zd v = modes[(long long)e * nxy + m].sig[k];
+    sd[i] = v;
+    sf[i] = mk<float>((float)v.re, (float)v.im);
+  }
+}
+}  // namespace
+
+hipError_t launch_sigma_tables(iobm_ctx ctx, int nE, const ModeData* modes, zd* sig_d, zf* sig_f) {
+  const long long n = (long long)nE * ctx->g.nf * ctx->g.nf * ctx->g.nxy;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_sigma_tables, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, nE, ctx->g.nxy, ctx->g.nf,
+                     modes, sig_d, sig_f);
+  return hipGetLastError();
+}

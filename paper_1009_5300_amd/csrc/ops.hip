@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
 template <typename T, typename TR>
 __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __restrict__ x,
                            cplx<T>* __restrict__ y, cplx<TR>* __restrict__ rout,
-                           const ModeData* __restrict__ modes,
+                           const cplx<T>* __restrict__ sig,
                            const int* __restrict__ e_rhs, const cplx<T>* __restrict__ twx,
                            const cplx<T>* __restrict__ twy, const int* __restrict__ active,
                            Partial* __restrict__ part, int np, int pslot) {
@@ -400,7 +400,7 @@ __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __rest
   const int side = blockIdx.x & 1;
   const int rhs = rhs_of(active, slot);
   const long long vol = (long long)nxy * nz;
-  const ModeData* md = modes + (long long)e_rhs[rhs] * nxy;
+  const cplx<T>* sg = sig + (long long)e_rhs[rhs] * nf * nf * nxy;  // [k][mode]
   cplx<T>* P[4];
   for (int k = 0; k <= nf; ++k) P[k] = buf + k * nxy;
   const int pbase = side ? nz - nf : 0;
@@ -423,7 +423,7 @@ __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __rest
       const int ik = side ? k : nf - 1 - k;
       for (int l = 0; l < nf; ++l) {
         const int il = side ? l : nf - 1 - l;
-        s = s + cvt<T>(md[m].sig[ik * nf + il]) * in[l];
+        s = s + sg[(long long)(ik * nf + il) * nxy + m] * in[l];
       }
       out[k] = inv * s;
     }
@@ -469,7 +469,7 @@ __global__ void k_boundary(FFTPlan2D plan, int nz, int nf, const cplx<T>* __rest
 template <typename T, typename TR, int N, int NF>
 __global__ void __launch_bounds__(N * NF) k_boundary_reg(int nz, const cplx<T>* __restrict__ x,
                                                         cplx<T>* __restrict__ y, cplx<TR>* __restrict__ rout,
-                                                        const ModeData* __restrict__ modes,
+                                                        const cplx<T>* __restrict__ sig,
                                                         const int* __restrict__ e_rhs,
                                                         const cplx<T>* __restrict__ tw,
                                                         const int* __restrict__ active,
@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(N * NF) k_boundary_reg(int nz, const cplx<T>* 
   const int slot = blockIdx.x >> 1;
   const int side = blockIdx.x & 1;
   const int rhs = rhs_of(active, slot);
-  const ModeData* md = modes + (long long)e_rhs[rhs] * NN;
+  const cplx<T>* sg = sig + (long long)e_rhs[rhs] * NF * NF * NN;  // [k][mode]
   const int pbase = side ? nz - NF : 0;
   const long long off = (long long)rhs * NN * nz + (long long)pbase * NN;  // NF consecutive planes
   for (int i = threadIdx.x; i < NF * NN; i += BLK) {
@@ -508,6 +508,7 @@ __global__ void __launch_bounds__(N * NF) k_boundary_reg(int nz, const cplx<T>* 
   // mode mixing, mode m = ky N + kx at sm[.][ky][kx]; plane k <-> boundary
   // index i as in k_boundary
   const T inv = (T)(1.0 / NN);
+#pragma unroll 4
   for (int m = threadIdx.x; m < NN; m += BLK) {
     const int r = m / N, cc = m - r * N;
     cplx<T> in[NF];
@@ -520,7 +521,7 @@ __global__ void __launch_bounds__(N * NF) k_boundary_reg(int nz, const cplx<T>* 
 #pragma unroll
       for (int l = 0; l < NF; ++l) {
         const int il = side ? l : NF - 1 - l;
-        acc = acc + cvt<T>(md[m].sig[ik * NF + il]) * in[l];
+        acc = acc + sg[(ik * NF + il) * NN + m] * in[l];
       }
       sm[kk][r][cc] = inv * acc;
     }
@@ -1305,6 +1306,9 @@ template <> const zf* twx<float>(iobm_ctx c) { return c->twx_f; }
 template <typename T> static const cplx<T>* twy(iobm_ctx c);
 template <> const zd* twy<double>(iobm_ctx c) { return c->twy_d; }
 template <> const zf* twy<float>(iobm_ctx c) { return c->twy_f; }
+template <typename T> static const cplx<T>* sigtab(iobm_ctx c);
+template <> const zd* sigtab<double>(iobm_ctx c) { return c->sig_d; }
+template <> const zf* sigtab<float>(iobm_ctx c) { return c->sig_f; }
 template <typename T> static const T* Vptr(iobm_ctx c);
 template <> const double* Vptr<double>(iobm_ctx c) { return c->V_d; }
 template <> const float* Vptr<float>(iobm_ctx c) { return c->V_f; }
@@ -1403,7 +1407,7 @@ static void launch_boundary_reg(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T
                                 const int* e_rhs, const ModeData* modes, const int* active, Partial* part) {
 #define IOBM_BREG(NF)                                                                                         \
   hipLaunchKernelGGL((k_boundary_reg<T, TR, N, NF>), dim3(2 * nrhs), dim3(N * NF), 0, c->stream, c->g.nz, x, y, \
-                     rout, modes, e_rhs, twx<T>(c), active, part, (int)PQ_SLOTS, (int)PQ_BOUNDARY)
+                     rout, sigtab<T>(c), e_rhs, twx<T>(c), active, part, (int)PQ_SLOTS, (int)PQ_BOUNDARY)
   switch (c->g.nf) {
     case 1: IOBM_BREG(1); break;
     case 2: IOBM_BREG(2); break;
@@ -1431,7 +1435,7 @@ static hipError_t launch_boundary(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx
   }
   if (!reg)
     hipLaunchKernelGGL((k_boundary<T, TR>), dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan,
-                       c->g.nz, c->g.nf, x, y, rout, modes, e_rhs, twx<T>(c), twy<T>(c), active, part,
+                       c->g.nz, c->g.nf, x, y, rout, sigtab<T>(c), e_rhs, twx<T>(c), twy<T>(c), active, part,
                        (int)PQ_SLOTS, (int)PQ_BOUNDARY);
   prof_stop(c, rec, (double)nrhs * 2 * c->g.nf * c->g.nxy * (2 * sizeof(cplx<T>) + sizeof(cplx<TR>)));
   return hipGetLastError();
