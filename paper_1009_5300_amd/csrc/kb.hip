@@ -184,10 +184,10 @@ hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, P
   double* W = part + part_elems;
   const int ngroups = (nrhs + 7) / 8;
   dim3 g1(ngroups * (kb.nproj_pad / 16) * ks);
-  const int rec = prof_start(c, IOBM_K_NONLOCAL);
+  const int rec = prof_start(c, sizeof(T) == 4 ? IOBM_K_NONLOCAL : IOBM_K_NONLOCAL_C128);
   hipLaunchKernelGGL(k_kb_project<T>, g1, dim3(64), 0, c->stream, kb, c->g.npts, nrhs, ks, x, part, active);
-  // the operand on the union of supports and the projector table once
-  prof_stop(c, rec, (double)nrhs * kb.nu * sizeof(cplx<T>) + (double)kb.nu * kb.nproj_pad * sizeof(T));
+  // algorithmic flops of the real GEMM: M = projectors, N = 2 nrhs, K = support
+  prof_stop(c, rec, 2.0 * kb.nproj * (2.0 * nrhs) * kb.nu);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_kb_scale, dim3(nrhs), dim3(128), 0, c->stream, kb, nrhs, ks, part, W, pq_part, active);

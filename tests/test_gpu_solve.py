@@ -129,3 +129,42 @@ def test_iteration_counts_follow_the_preconditioner(torch):
         assert np.abs(res[pc][2] - res[0][2]).max() < 1e-7 * np.abs(res[0][2]).max()
     assert res[1][0].mean() < res[0][0].mean()
     assert res[2][0].mean() < 0.1 * res[1][0].mean()
+
+
+def _channel_T_matrix(s, out, e, E):
+    """T_{nu mu} = (v_nu / v_mu) |t_{nu mu}|^2 over the open channels at E."""
+    _, _, v = s.channels(E)
+    t = out["t"][e]
+    return (v[:, None] / v[None, :]) * np.abs(t) ** 2
+
+
+@pytest.mark.parametrize("cfg", [4, 3], ids=["wide_48x48x128", "chain_kb_24x24x96"])
+def test_full_size_invariants(torch, cfg):
+    """Workloads 4 and 3 at their full sizes, every energy and open channel in
+    one batch with the default options (the configuration bench.py times for
+    workload 4; workload 3 adds the nonlocal term on MFMA).  The oracle cannot
+    factor these grids, so the checks are properties that hold at any size:
+    every state converges, T + R = 1 per channel, and reciprocity: time
+    reversal maps the lateral channel G to -G, so the channel-resolved
+    transmission from the right is T^R_{-mu, -nu} = T^L_{nu mu}, which also
+    equates the total transmissions."""
+    from paper_1009_5300_amd import iobm
+    w = make(cfg)
+    s = _solver(w)
+    outs = {}
+    for side in (0, 1):
+        out = s.solve(w.energies, opts=iobm.default_opts(side=side), want_t=True)
+        assert out["status"] == 0, out.get("error")
+        st = np.array(out["stats"], dtype=float)
+        assert st[:, 3].max() <= 1e-10  # FP64 residual
+        assert np.abs(st[:, 4]).max() < 1e-8  # T + R - 1
+        outs[side] = out
+    g = w.grid
+    for e, E in enumerate(w.energies):
+        TL = _channel_T_matrix(s, outs[0], e, E)
+        TR = _channel_T_matrix(s, outs[1], e, E)
+        ids = [int(m) for m in outs[0]["open"][e]]
+        pos = {m: i for i, m in enumerate(ids)}
+        neg = [pos[((g.ny - m // g.nx) % g.ny) * g.nx + (g.nx - m % g.nx) % g.nx] for m in ids]
+        assert np.abs(TL - TR[np.ix_(neg, neg)].T).max() <= 1e-8
+        assert abs(TL.sum() - TR.sum()) <= 1e-8
