@@ -152,6 +152,20 @@ T* upload(iobm_ctx ctx, int slot, const std::vector<T>& v, size_t offset_bytes =
   return p;
 }
 
+// Pinned host buffer for device-to-host read-backs of per-rhs scalars (a
+// copy into pageable memory would be staged and serialised by the runtime).
+void* pinned_readback(iobm_ctx ctx, size_t bytes) {
+  if (ctx->rb_cap < bytes) {
+    stream_sync(ctx);  // an earlier read-back may still target the old buffer
+    if (ctx->rb_h) (void)hipHostFree(ctx->rb_h);
+    ctx->rb_h = nullptr;
+    ctx->rb_cap = 0;
+    HIPCHK(hipHostMalloc(&ctx->rb_h, bytes, hipHostMallocDefault));
+    ctx->rb_cap = bytes;
+  }
+  return ctx->rb_h;
+}
+
 FFTPlan1D make_plan1d(int n) {
   FFTPlan1D p;
   p.n = n;
@@ -173,6 +187,8 @@ bool plan_ok(const FFTPlan1D& p) {
 
 // --------------------------------------------------------------- modes
 // Ensure the device mode table holds exactly the energies `E` (in order).
+// Only the mode flags come back to the host; the full records are copied on
+// demand (host_modes) by the calls that report them.
 void ensure_modes(iobm_ctx ctx, const std::vector<double>& E, bool force = false) {
   if (!force && E == ctx->modeE && ctx->modes_d) return;
   const size_t n = (size_t)E.size() * ctx->g.nxy;
@@ -187,39 +203,55 @@ void ensure_modes(iobm_ctx ctx, const std::vector<double>& E, bool force = false
   if (ctx->sig_cap < ns) {
     if (ctx->sig_d) (void)hipFree(ctx->sig_d);
     if (ctx->sig_f) (void)hipFree(ctx->sig_f);
+    if (ctx->mode_flags_d) (void)hipFree(ctx->mode_flags_d);
     ctx->sig_d = nullptr;
     ctx->sig_f = nullptr;
+    ctx->mode_flags_d = nullptr;
     ctx->sig_cap = 0;
     HIPCHK(hipMalloc(&ctx->sig_d, ns * sizeof(zd)));
     HIPCHK(hipMalloc(&ctx->sig_f, ns * sizeof(zf)));
+    HIPCHK(hipMalloc(&ctx->mode_flags_d, n * sizeof(int)));
     ctx->sig_cap = ns;
   }
+  ctx->modeE.clear();
+  ctx->modes_h_valid = false;
   double* Ed = upload(ctx, S_IDX, E);
   HIPCHK(launch_modes(ctx, Ed, (int)E.size(), ctx->modes_d));
-  HIPCHK(launch_sigma_tables(ctx, (int)E.size(), ctx->modes_d, ctx->sig_d, ctx->sig_f));
-  ctx->modes_h.resize(n);
-  HIPCHK(hipMemcpyAsync(ctx->modes_h.data(), ctx->modes_d, n * sizeof(ModeData), hipMemcpyDeviceToHost,
-                        ctx->stream));
+  HIPCHK(launch_sigma_tables(ctx, (int)E.size(), ctx->modes_d, ctx->sig_d, ctx->sig_f, ctx->mode_flags_d));
+  int* fh = (int*)pinned_readback(ctx, n * sizeof(int));
+  HIPCHK(hipMemcpyAsync(fh, ctx->mode_flags_d, n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   stream_sync(ctx);
-  ctx->modeE = E;
+  ctx->mode_flags_h.assign(fh, fh + n);
   for (size_t e = 0; e < E.size(); ++e)
     for (int m = 0; m < ctx->g.nxy; ++m) {
-      const ModeData& md = ctx->modes_h[e * ctx->g.nxy + m];
-      if (md.flags & MODE_THRESHOLD) {
-        ctx->modeE.clear();
+      const int fl = ctx->mode_flags_h[e * ctx->g.nxy + m];
+      if (fl & MODE_THRESHOLD) {
         char buf[160];
         snprintf(buf, sizeof buf, "energy %.12g is at the threshold of lateral channel %d", E[e], m);
         ctx->err = buf;
         throw Fail{IOBM_E_AT_THRESHOLD};
       }
-      if (md.flags & MODE_FAIL) {
-        ctx->modeE.clear();
+      if (fl & MODE_FAIL) {
         char buf[160];
         snprintf(buf, sizeof buf, "mode setup failed at energy %.12g, channel %d", E[e], m);
         ctx->err = buf;
         throw Fail{IOBM_E_DEVICE};
       }
     }
+  ctx->modeE = E;
+}
+
+// The full mode records of the current table on the host.
+const ModeData* host_modes(iobm_ctx ctx) {
+  if (!ctx->modes_h_valid) {
+    const size_t n = ctx->modeE.size() * (size_t)ctx->g.nxy;
+    ctx->modes_h.resize(n);
+    HIPCHK(hipMemcpyAsync(ctx->modes_h.data(), ctx->modes_d, n * sizeof(ModeData), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    stream_sync(ctx);
+    ctx->modes_h_valid = true;
+  }
+  return ctx->modes_h.data();
 }
 
 int neg_mode(const GridDev& g, int m) {
@@ -293,13 +325,21 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
                          ? part
                          : (Partial*)scratch(ctx, S_PARTZ, (size_t)nb * nz_slots * sizeof(Partial));
   Partial* part_rn = (Partial*)scratch(ctx, S_PARTR, (size_t)nb * PQ_SLOTS * sizeof(Partial));
-  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * (3 * sizeof(zd) + 2 * sizeof(double) + sizeof(int)) + 64);
+  // per-rhs scalars; |r|^2 and the breakdown flags are adjacent so that one
+  // copy brings both to the host at a convergence check
+  const size_t nb8 = ((size_t)nb + 1) & ~(size_t)1;
+  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + sizeof(int)) + 64);
   zd* rho = (zd*)sc;
   zd* alpha = rho + nb;
   zd* beta = alpha + nb;
   double* rn2 = (double*)(beta + nb);
-  double* tn2 = rn2 + nb;
-  int* flag = (int*)(tn2 + nb);
+  int* flag = (int*)(rn2 + nb);
+  double* tn2 = (double*)(flag + nb8);
+  const size_t check_bytes = (size_t)nb * sizeof(double) + (size_t)nb * sizeof(int);
+  char* rbh = (char*)pinned_readback(ctx, check_bytes + nb8 * sizeof(int) + (size_t)nb * sizeof(double) + 64);
+  const double* rn2_h = (const double*)rbh;
+  const int* flag_h = (const int*)(rbh + (size_t)nb * sizeof(double));
+  double* tn2_pin = (double*)(rbh + (size_t)nb * sizeof(double) + nb8 * sizeof(int));
   if (ctx->kb.ncen > 0) (void)kb_scratch(ctx, kb_proj_bytes(ctx, nb));
   const ModeData* modes = ctx->modes_d;
   const bool lowp = sizeof(T) == sizeof(float);
@@ -321,8 +361,12 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   // in the iteration precision; the FP64 face planes pass through r_hi), and
   // |r|^2 -> host.  With a nonlocal term the residual is formed in full in
   // r_hi first, since its back-projection comes after the stencil.
-  std::vector<double> tn2_h(nb), rn2_h(nb), bn2(nb);
-  std::vector<int> flag_h(nb);
+  std::vector<double> tn2_h(nb), bn2(nb);
+  auto read_tn2 = [&](std::vector<double>& dst) {
+    HIPCHK(hipMemcpyAsync(tn2_pin, tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    memcpy(dst.data(), tn2_pin, nb * sizeof(double));
+  };
   auto refresh = [&](const std::vector<int>& lst, int region) {
     int* ld = upload(ctx, S_IDX, lst, (size_t)region * 8192);
     const int n = (int)lst.size();
@@ -337,8 +381,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld));
       HIPCHK((launch_convert<T, double>(ctx, rhi, r, n, ld)));
     }
-    HIPCHK(hipMemcpyAsync(tn2_h.data(), tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    stream_sync(ctx);
+    read_tn2(tn2_h);
   };
 
   // start: x = 0, r_hi = b, d = 0, r = r_hi, z = P r, rho = r^T z, beta = 0
@@ -348,8 +391,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   HIPCHK(hipMemsetAsync(part_rn, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   HIPCHK(launch_dot<double>(ctx, b, b, nb, all_d, part));
   HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, nb, all_d));
-  HIPCHK(hipMemcpyAsync(bn2.data(), tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  stream_sync(ctx);
+  read_tn2(bn2);
   std::vector<int> act;
   for (int i = 0; i < nb; ++i)
     if (bn2[i] > 0) act.push_back(i);
@@ -391,8 +433,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, part, nblk, FIN_BETA, nact, act_d));
       std::swap(pold, pnew);
     }
-    HIPCHK(hipMemcpyAsync(rn2_h.data(), rn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(flag_h.data(), flag, nb * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(rbh, rn2, check_bytes, hipMemcpyDeviceToHost, ctx->stream));
     stream_sync(ctx);
     // which rhs fold their correction into x and refresh the residual
     std::vector<int> upd;
@@ -419,25 +460,22 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       cont.push_back(i);
       maxr2[i] = t2;
     }
-    if (!cont.empty()) {
-      // z = P r, rho = r^T z, beta = 0 (p_new = z next)
-      int* cd = upload(ctx, S_IDX, cont, 56 * 1024);
-      const int nc = (int)cont.size();
-      precond(nc, cd);
-      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nc, cd));
-    }
     std::vector<char> gone(nb, 0);
     for (int i : upd) gone[i] = 1;
     for (int i : cont) gone[i] = 0;
-    std::vector<int> keep;
+    std::vector<int> lists(cont);  // one upload: [restarted rhs | new active list]
     for (int i : act)
-      if (!gone[i]) keep.push_back(i);
-    if (keep.size() != act.size()) {
-      act = keep;
-      nact = (int)act.size();
-      if (nact == 0) break;
-      act_d = upload(ctx, S_IDX, act, 64 * 1024);
+      if (!gone[i]) lists.push_back(i);
+    const int nc = (int)cont.size();
+    int* ld = upload(ctx, S_IDX, lists, 64 * 1024);
+    if (nc > 0) {
+      // z = P r, rho = r^T z, beta = 0 (p_new = z next)
+      precond(nc, ld);
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nc, ld));
     }
+    act.assign(lists.begin() + nc, lists.end());
+    nact = (int)act.size();
+    act_d = ld + nc;  // the old list's region was rewritten
   }
   for (int i = 0; i < nb; ++i) {
     out.rel[i] = bn2[i] > 0 ? sqrt(tn2_h[i] / bn2[i]) : 0.0;
@@ -473,14 +511,14 @@ void plan_requests(iobm_ctx ctx, int nE, const double* E, const int* ninc, const
   int pos = 0;
   for (int e = 0; e < nE; ++e) {
     std::vector<int> ids;
-    const ModeData* md = &ctx->modes_h[(size_t)e * g.nxy];
+    const int* fl = &ctx->mode_flags_h[(size_t)e * g.nxy];
     if (ninc[e] < 0) {
       for (int m = 0; m < g.nxy; ++m)
-        if (md[m].flags & MODE_OPEN) ids.push_back(m);
+        if (fl[m] & MODE_OPEN) ids.push_back(m);
     } else {
       for (int k = 0; k < ninc[e]; ++k) {
         int m = inc[pos++];
-        if (m < 0 || m >= g.nxy || !(md[m].flags & MODE_OPEN)) {
+        if (m < 0 || m >= g.nxy || !(fl[m] & MODE_OPEN)) {
           char buf[128];
           snprintf(buf, sizeof buf, "channel %d is not open at energy %.12g", m, E[e]);
           ctx->err = buf;
@@ -685,9 +723,10 @@ iobm_status iobm_destroy(iobm_ctx ctx) {
   for (auto& e : ctx->pool)
     if (e.first) (void)hipFree(e.first);
   void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->V_d, ctx->V_f, ctx->modes_d, ctx->sig_d,
-                  ctx->sig_f,
+                  ctx->sig_f, ctx->mode_flags_d,
                   ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.hD, ctx->arena_d};
   if (ctx->arena_h) (void)hipHostFree(ctx->arena_h);
+  if (ctx->rb_h) (void)hipHostFree(ctx->rb_h);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete ctx;
@@ -840,7 +879,7 @@ iobm_status iobm_channels(iobm_ctx ctx, double E, int32_t* nopen, int32_t* ids, 
     ensure_modes(ctx, std::vector<double>{E});
     int n = 0;
     for (int m = 0; m < ctx->g.nxy; ++m) {
-      const ModeData& md = ctx->modes_h[m];
+      const ModeData& md = host_modes(ctx)[m];
       if (!(md.flags & MODE_OPEN)) continue;
       if (ids) ids[n] = m;
       if (kz) kz[n] = atan2(md.xp.im, md.xp.re) / ctx->g.hz;
@@ -862,8 +901,8 @@ iobm_status iobm_self_energy(iobm_ctx ctx, double E, double* sigma) {
     const int nf = ctx->g.nf;
     for (int m = 0; m < ctx->g.nxy; ++m)
       for (int i = 0; i < nf * nf; ++i) {
-        sigma[2 * ((size_t)m * nf * nf + i)] = ctx->modes_h[m].sig[i].re;
-        sigma[2 * ((size_t)m * nf * nf + i) + 1] = ctx->modes_h[m].sig[i].im;
+        sigma[2 * ((size_t)m * nf * nf + i)] = host_modes(ctx)[m].sig[i].re;
+        sigma[2 * ((size_t)m * nf * nf + i) + 1] = host_modes(ctx)[m].sig[i].im;
       }
   } catch (Fail& f) {
     return f.s;
@@ -940,7 +979,7 @@ iobm_status iobm_rhs(iobm_ctx ctx, double E, int32_t n, const int32_t* ids, int3
   try {
     ensure_modes(ctx, std::vector<double>{E});
     for (int k = 0; k < n; ++k)
-      if (ids[k] < 0 || ids[k] >= ctx->g.nxy || !(ctx->modes_h[ids[k]].flags & MODE_OPEN))
+      if (ids[k] < 0 || ids[k] >= ctx->g.nxy || !(ctx->mode_flags_h[ids[k]] & MODE_OPEN))
         return fail(ctx, IOBM_E_INVALID_ARG, "channel not open");
     std::vector<int> e(n, 0), m(ids, ids + n), kind(n, 0);
     int* e_d = upload(ctx, S_IDX, e, 0);
@@ -1020,10 +1059,10 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
       for (int e = 0; e < nE; ++e) {
         int c1 = c0;
         while (c1 < nreq && Q.e[c1] == e) ++c1;
-        const ModeData* md = &ctx->modes_h[(size_t)e * nxy];
+        const int* fl = &ctx->mode_flags_h[(size_t)e * nxy];
         int row = 0;
         for (int nu = 0; nu < nxy; ++nu) {
-          if (!(md[nu].flags & MODE_OPEN)) continue;
+          if (!(fl[nu] & MODE_OPEN)) continue;
           for (int c = c0; c < c1; ++c) {
             zd v = th[(size_t)c * nxy + nu];
             t[2 * (off + (size_t)row * (c1 - c0) + (c - c0))] = v.re;

@@ -78,8 +78,13 @@ struct iobm_ctx_s {
   zd* sig_d = nullptr;
   zf* sig_f = nullptr;
   size_t sig_cap = 0;
+  int* mode_flags_d = nullptr;       // ModeData::flags of the same table, [energy][mode]
+  std::vector<int> mode_flags_h;     // host copy (the solve path needs only these)
+  bool modes_h_valid = false;        // modes_h is copied from the device on demand
   void* arena_d = nullptr;  // small index arrays (device) and their pinned host mirror
   void* arena_h = nullptr;
+  void* rb_h = nullptr;     // pinned host buffer for the solver's per-rhs read-backs
+  size_t rb_cap = 0;
   unsigned char region_pending[64] = {0};
   // tuned launch shapes (0 = default rule)
   int tune_zf_c64 = 0, tune_zf_c128 = 0;
@@ -114,7 +119,7 @@ struct RhsMap {        // device arrays describing a batch of right-hand sides
 };
 
 hipError_t launch_modes(iobm_ctx c, const double* E_d, int nE, ModeData* out);
-hipError_t launch_sigma_tables(iobm_ctx c, int nE, const ModeData* modes, zd* sig_d, zf* sig_f);
+hipError_t launch_sigma_tables(iobm_ctx c, int nE, const ModeData* modes, zd* sig_d, zf* sig_f, int* flags);
 
 // Per-rhs FP64 partial sums of a bilinear form u^T v (re, im) and of |u|^2
 // (n2), one per block, combined in a fixed order.

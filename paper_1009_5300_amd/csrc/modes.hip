@@ -375,10 +375,13 @@ hipError_t launch_modes(iobm_ctx ctx, const double* E_d, int nE, ModeData* out) 
 
 namespace {
 // Sigma_R blocks copied out of the mode table into [energy][nf * nf][mode]
-// order, in complex128 and complex64.
+// order, in complex128 and complex64, and the mode flags into [energy][mode].
 __global__ void k_sigma_tables(int nE, int nxy, int nf, const ModeData* __restrict__ modes, zd* __restrict__ sd,
-                               zf* __restrict__ sf) {
+                               zf* __restrict__ sf, int* __restrict__ flags) {
   const int nk = nf * nf;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)nE * nxy;
+       i += (long long)gridDim.x * blockDim.x)
+    flags[i] = modes[i].flags;
   const long long n = (long long)nE * nk * nxy;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const int m = (int)(i % nxy);
@@ -392,12 +395,12 @@ __global__ void k_sigma_tables(int nE, int nxy, int nf, const ModeData* __restri
 }
 }  // namespace
 
-hipError_t launch_sigma_tables(iobm_ctx ctx, int nE, const ModeData* modes, zd* sig_d, zf* sig_f) {
+hipError_t launch_sigma_tables(iobm_ctx ctx, int nE, const ModeData* modes, zd* sig_d, zf* sig_f, int* flags) {
   const long long n = (long long)nE * ctx->g.nf * ctx->g.nf * ctx->g.nxy;
   long long blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_sigma_tables, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, nE, ctx->g.nxy, ctx->g.nf,
-                     modes, sig_d, sig_f);
+                     modes, sig_d, sig_f, flags);
   return hipGetLastError();
 }
