@@ -666,11 +666,17 @@ template <typename T> struct Pair;
 template <> struct Pair<float> { typedef float4 type; static constexpr int n = 2; };
 template <> struct Pair<double> { typedef double2 type; static constexpr int n = 1; };
 
-template <typename T, int N, int PPB>
+// With mvec and dpart set (the inverse transform of the preconditioner),
+// the block also writes, per plane, the partial of the bilinear form
+// sum_x r(x) out(x), taken in mode space by Parseval:
+//   sum_x r(x) out(x) = scale * sum_k R(-k) in(k),   R = forward FFT of r = mvec,
+// from loads issued together with those of the input (a real-space dot
+// would read r after the transforms, with its latency exposed).
+template <typename T, int N, int PPB, bool DOT>
 __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes, const cplx<T>* in, cplx<T>* out,
                                                            const cplx<T>* __restrict__ tw, int sign, T scale,
                                                            const int* __restrict__ active,
-                                                           const cplx<T>* __restrict__ dvec,
+                                                           const cplx<T>* __restrict__ mvec,
                                                            Partial* __restrict__ dpart) {
   typedef typename Pair<T>::type VT;
   constexpr int PE = Pair<T>::n;          // elements per vector access
@@ -691,11 +697,74 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
     poff[q] = (long long)rhs_of(active, slot) * vol + (long long)z * NN;
   }
   VT buf[EPT];
+  double ds_re[PPB], ds_im[PPB];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int v = threadIdx.x + e * BLK;
-    const int q = v / (NN / PE), w = v - q * (NN / PE);
-    if (v < NV && pok[q]) buf[e] = reinterpret_cast<const VT*>(in + poff[q])[w];
+  for (int q = 0; q < PPB; ++q) ds_re[q] = ds_im[q] = 0;
+  if constexpr (DOT) {
+    // R and the first half of the input in flight together, R staged in LDS,
+    // then the second half: at most one and a half planes in registers
+    constexpr int H = EPT / 2;
+    VT mb[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int v = threadIdx.x + e * BLK;
+      const int q = v / (NN / PE), w = v - q * (NN / PE);
+      if (v < NV && pok[q]) mb[e] = reinterpret_cast<const VT*>(mvec + poff[q])[w];
+    }
+#pragma unroll
+    for (int e = 0; e < H; ++e) {
+      const int v = threadIdx.x + e * BLK;
+      const int q = v / (NN / PE), w = v - q * (NN / PE);
+      if (v < NV && pok[q]) buf[e] = reinterpret_cast<const VT*>(in + poff[q])[w];
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {  // stage R in LDS
+      const int v = threadIdx.x + e * BLK;
+      const int q = v / (NN / PE), w = v - q * (NN / PE);
+      if (v < NV) {
+        const cplx<T>* c = reinterpret_cast<const cplx<T>*>(&mb[e]);
+#pragma unroll
+        for (int k = 0; k < PE; ++k) {
+          const int el = w * PE + k;
+          sm[q][el / N][el % N] = c[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int e = H; e < EPT; ++e) {
+      const int v = threadIdx.x + e * BLK;
+      const int q = v / (NN / PE), w = v - q * (NN / PE);
+      if (v < NV && pok[q]) buf[e] = reinterpret_cast<const VT*>(in + poff[q])[w];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {  // sum_k R(-k) in(k), mode k = (ky, kx) at row ky, column kx
+      const int v = threadIdx.x + e * BLK;
+      const int q = v / (NN / PE), w = v - q * (NN / PE);
+      if (v < NV && pok[q]) {
+        const cplx<T>* c = reinterpret_cast<const cplx<T>*>(&buf[e]);
+#pragma unroll
+        for (int k = 0; k < PE; ++k) {
+          const int el = w * PE + k;
+          const int ky = el / N, kx = el % N;
+          const cplx<T> rm = sm[q][(N - ky) % N][(N - kx) % N];
+#pragma unroll
+          for (int qq = 0; qq < PPB; ++qq)
+            if (qq == q) {
+              ds_re[qq] += (double)c[k].re * rm.re - (double)c[k].im * rm.im;
+              ds_im[qq] += (double)c[k].re * rm.im + (double)c[k].im * rm.re;
+            }
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int v = threadIdx.x + e * BLK;
+      const int q = v / (NN / PE), w = v - q * (NN / PE);
+      if (v < NV && pok[q]) buf[e] = reinterpret_cast<const VT*>(in + poff[q])[w];
+    }
   }
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -725,9 +794,6 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
 #pragma unroll
   for (int i = 0; i < N; ++i) sm[pl][i][li] = scale * v[i];
   __syncthreads();
-  double ds_re[PPB], ds_im[PPB];
-#pragma unroll
-  for (int q = 0; q < PPB; ++q) ds_re[q] = ds_im[q] = 0;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int vv = threadIdx.x + e * BLK;
@@ -741,24 +807,12 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
         c[k] = sm[q][el / N][el % N];
       }
       reinterpret_cast<VT*>(out + poff[q])[w] = o;
-      if (dpart) {  // bilinear out^T dvec, per plane
-        VT dv = reinterpret_cast<const VT*>(dvec + poff[q])[w];
-        const cplx<T>* d = reinterpret_cast<const cplx<T>*>(&dv);
-#pragma unroll
-        for (int k = 0; k < PE; ++k)
-#pragma unroll
-          for (int qq = 0; qq < PPB; ++qq)
-            if (qq == q) {
-              ds_re[qq] += (double)c[k].re * d[k].re - (double)c[k].im * d[k].im;
-              ds_im[qq] += (double)c[k].re * d[k].im + (double)c[k].im * d[k].re;
-            }
-      }
     }
   }
-  if (dpart) {
+  if constexpr (DOT) {
 #pragma unroll
     for (int q = 0; q < PPB; ++q) {
-      double a = ds_re[q], b = ds_im[q];
+      double a = (double)scale * ds_re[q], b = (double)scale * ds_im[q];
       block_sum2<BLK>(a, b);
       if (threadIdx.x == 0 && pok[q]) {
         const int gp = g0 + q;
@@ -1494,36 +1548,42 @@ hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, 
 
 template <typename T, int N, int PPB>
 static void launch_fft_reg(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
-                           const int* active, const cplx<T>* dvec, Partial* dpart) {
+                           const int* active, const cplx<T>* mvec, Partial* dpart) {
   const int nplanes = nrhs * c->g.nz;
-  hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB>), dim3((nplanes + PPB - 1) / PPB), dim3(N * PPB), 0, c->stream,
-                     c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active, dvec, dpart);
+  if (dpart)
+    hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB, true>), dim3((nplanes + PPB - 1) / PPB), dim3(N * PPB), 0,
+                       c->stream, c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active, mvec, dpart);
+  else
+    hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB, false>), dim3((nplanes + PPB - 1) / PPB), dim3(N * PPB), 0,
+                       c->stream, c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active, mvec, dpart);
 }
 
 // planes per block of the register FFT (measured: one plane per block is
 // fastest at 48 x 48)
 template <typename T>
 static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
-                             const int* active, const cplx<T>* dvec, Partial* dpart) {
+                             const int* active, const cplx<T>* mvec, Partial* dpart) {
   if (c->g.nx != c->g.ny || c->tune_fft_generic) return false;
   switch (c->g.nx) {
-    case 8: launch_fft_reg<T, 8, 16>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
-    case 12: launch_fft_reg<T, 12, 8>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
-    case 16: launch_fft_reg<T, 16, 8>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
-    case 24: launch_fft_reg<T, 24, 4>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
-    case 32: launch_fft_reg<T, 32, 4>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
-    case 48: launch_fft_reg<T, 48, 1>(c, in, out, sign, scale, nrhs, active, dvec, dpart); return true;
+    case 8: launch_fft_reg<T, 8, 16>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
+    case 12: launch_fft_reg<T, 12, 8>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
+    case 16: launch_fft_reg<T, 16, 8>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
+    case 24: launch_fft_reg<T, 24, 4>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
+    case 32: launch_fft_reg<T, 32, 4>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
+    case 48: launch_fft_reg<T, 48, 1>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
     default: return false;
   }
 }
 
 // Batched plane FFTs; with dpart set, also the per-plane partials of
-// out^T dvec (dpart[rhs][z]).
+// out^T r (dpart[rhs][z]): from r itself (dvec) in the LDS kernel, by
+// Parseval from mvec = the forward FFT of r in the register kernel.
 template <typename T>
 hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
-                             const int* active, const cplx<T>* dvec = nullptr, Partial* dpart = nullptr) {
+                             const int* active, const cplx<T>* dvec = nullptr, const cplx<T>* mvec = nullptr,
+                             Partial* dpart = nullptr) {
   const int rec = prof_start(c, IOBM_K_FFT_PLANES);
-  if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, dvec, dpart)) {
+  if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, mvec, dpart)) {
     size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
     hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
                        twx<T>(c), twy<T>(c), sign, (T)scale, active, dvec, dpart);
@@ -1572,7 +1632,7 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
   const int rec = prof_start(c, IOBM_K_PRECOND_FFT);
   hipError_t err = launch_fft_planes<T>(c, r, scratch, -1, 1.0, nrhs, active);
   if (err == hipSuccess) err = launch_zfilter<T>(c, L, scratch, z, nrhs, e_rhs, modes, active);
-  if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active, r, dpart);
+  if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active, r, scratch, dpart);
   prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
   return err;
 }
