@@ -891,8 +891,8 @@ __device__ void state_power(const cplx<T>* al, int nf, int n, cplx<T>* P) {
   for (int i = 0; i < 9; ++i) P[i] = R[i];
 }
 
-template <typename T, int L>
-__global__ void __launch_bounds__(512) k_zfilter(int nz, int nf, int nxy, const cplx<T>* __restrict__ in,
+template <typename T, int L, int NF>
+__global__ void __launch_bounds__(512) k_zfilter(int nz, int nf_unused, int nxy, const cplx<T>* __restrict__ in,
                                                   cplx<T>* __restrict__ out, const ModeData* __restrict__ modes,
                                                   const int* __restrict__ e_rhs, const int* __restrict__ active) {
   extern __shared__ char smem_raw[];
@@ -902,23 +902,25 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nf, int nxy, const 
   const int nmb = (nxy + 63) / 64;
   const int slot = blockIdx.x / nmb;
   const int m = (blockIdx.x - slot * nmb) * 64 + threadIdx.x;
-  const int c = threadIdx.y;
+  // one wavefront per chunk: the chunk index (and every plane offset below)
+  // is wave-uniform, which keeps the load addresses in scalar registers
+  const int c = __builtin_amdgcn_readfirstlane(threadIdx.y);
   const int rhs = rhs_of(active, slot);
   const long long base = (long long)rhs * nxy * nz;
   const bool live = m < nxy;
   const int z0 = c * L;
+  constexpr int nf = NF;
   cplx<T> al[3], fb[3], fbb[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) al[k] = fb[k] = fbb[k] = mk<T>(0, 0);
   if (live) {
     const ModeData& md = modes[(long long)e_rhs[rhs] * nxy + m];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      if (k < nf) {
-        al[k] = -cvt<T>(md.q[nf - 1 - k]);
-        fb[k] = cvt<T>(md.fb[k]);
-        fbb[k] = cvt<T>(md.fbb[k]);
-      }
+    for (int k = 0; k < NF; ++k) {
+      al[k] = -cvt<T>(md.q[nf - 1 - k]);
+      fb[k] = cvt<T>(md.fb[k]);
+      fbb[k] = cvt<T>(md.fbb[k]);
+    }
   }
   // inputs of planes z0-2 .. z0+L+2
   cplx<T> rr[L + 5];
@@ -932,7 +934,9 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nf, int nxy, const 
   cplx<T> h0 = mk<T>(0, 0), h1 = mk<T>(0, 0), h2 = mk<T>(0, 0);
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    cplx<T> F = al[0] * h0 + al[1] * h1 + al[2] * h2 + fb[0] * rr[i + 2] + fb[1] * rr[i + 1] + fb[2] * rr[i];
+    cplx<T> F = al[0] * h0 + fb[0] * rr[i + 2];
+    if (NF > 1) F = F + al[1] * h1 + fb[1] * rr[i + 1];
+    if (NF > 2) F = F + al[2] * h2 + fb[2] * rr[i];
     h2 = h1;
     h1 = h0;
     h0 = (z0 + i < nz) ? F : mk<T>(0, 0);
@@ -947,8 +951,9 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nf, int nxy, const 
   h0 = h1 = h2 = mk<T>(0, 0);
 #pragma unroll
   for (int i = L - 1; i >= 0; --i) {
-    cplx<T> B = al[0] * h0 + al[1] * h1 + al[2] * h2 + fbb[0] * rr[i + 3] + fbb[1] * rr[i + 4] +
-                fbb[2] * rr[i + 5];
+    cplx<T> B = al[0] * h0 + fbb[0] * rr[i + 3];
+    if (NF > 1) B = B + al[1] * h1 + fbb[1] * rr[i + 4];
+    if (NF > 2) B = B + al[2] * h2 + fbb[2] * rr[i + 5];
     h2 = h1;
     h1 = h0;
     h0 = (z0 + i < nz) ? B : mk<T>(0, 0);
@@ -991,7 +996,9 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nf, int nxy, const 
     h2 = S[2];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      cplx<T> F = al[0] * h0 + al[1] * h1 + al[2] * h2;
+      cplx<T> F = al[0] * h0;
+      if (NF > 1) F = F + al[1] * h1;
+      if (NF > 2) F = F + al[2] * h2;
       h2 = h1;
       h1 = h0;
       h0 = F;
@@ -1005,7 +1012,9 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nf, int nxy, const 
     h2 = S[2];
 #pragma unroll
     for (int i = L - 1; i >= 0; --i) {
-      cplx<T> B = al[0] * h0 + al[1] * h1 + al[2] * h2;
+      cplx<T> B = al[0] * h0;
+      if (NF > 1) B = B + al[1] * h1;
+      if (NF > 2) B = B + al[2] * h2;
       h2 = h1;
       h1 = h0;
       h0 = B;
@@ -1601,15 +1610,22 @@ static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* 
   const int C = (nz + L - 1) / L;
   size_t sh = 2 * (size_t)C * 64 * 3 * sizeof(cplx<T>);
   const int rec = prof_start(c, IOBM_K_ZFILTER);
-#define IOBM_ZF(LL)                                                                                 \
-  hipLaunchKernelGGL((k_zfilter<T, LL>), dim3(nrhs * nmb), dim3(64, C), sh, c->stream, nz, c->g.nf, nxy, in, \
+#define IOBM_ZF2(LL, NFF)                                                                                  \
+  hipLaunchKernelGGL((k_zfilter<T, LL, NFF>), dim3(nrhs * nmb), dim3(64, C), sh, c->stream, nz, c->g.nf, nxy, in, \
                      out, modes, e_rhs, active)
+#define IOBM_ZF(LL)                                   \
+  switch (c->g.nf) {                                  \
+    case 1: IOBM_ZF2(LL, 1); break;                   \
+    case 2: IOBM_ZF2(LL, 2); break;                   \
+    default: IOBM_ZF2(LL, 3); break;                  \
+  }
   switch (L) {
     case 8: IOBM_ZF(8); break;
     case 16: IOBM_ZF(16); break;
     default: IOBM_ZF(32); break;
   }
 #undef IOBM_ZF
+#undef IOBM_ZF2
   prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
