@@ -228,10 +228,11 @@ enum { IOBM_K_STENCIL = 1,      /* stencil in the iteration precision; with the
        IOBM_K_DOT = 6,          /* bilinear / norm reductions */
        IOBM_K_UPDATE = 7,       /* d += alpha p, r -= alpha q, |r|^2 partials */
        IOBM_K_STENCIL_C128 = 8, /* stencil in complex128 (FP64 residuals) */
-       IOBM_K_FFT_PLANES = 9,   /* one batched 2D plane FFT of the preconditioner */
+       IOBM_K_FFT_PLANES = 9,   /* forward batched 2D plane FFT of the preconditioner */
        IOBM_K_ZFILTER = 10,     /* the z recursion of the preconditioner */
        IOBM_K_ACCUMULATE = 11,  /* x += d, d = 0 (refinement) */
-       IOBM_K_NONLOCAL_C128 = 12 };/* as IOBM_K_NONLOCAL, complex128 (flops) */
+       IOBM_K_NONLOCAL_C128 = 12, /* as IOBM_K_NONLOCAL, complex128 (flops) */
+       IOBM_K_FFT_PLANES_DOT = 13 };/* inverse plane FFT with the r^T z partials */
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask);
 iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
                              double* alg_bytes);

@@ -688,7 +688,7 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
 
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask) {
   if (!ctx) return IOBM_E_INVALID_ARG;
-  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_NONLOCAL_C128 + 1)))
+  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_FFT_PLANES_DOT + 1)))
     return fail(ctx, IOBM_E_INVALID_ARG, "bad kernel class mask");
   ctx->prof_mask = class_mask;
   ctx->prof_used = 0;

@@ -1591,7 +1591,7 @@ template <typename T>
 hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                              const int* active, const cplx<T>* dvec = nullptr, const cplx<T>* mvec = nullptr,
                              Partial* dpart = nullptr) {
-  const int rec = prof_start(c, IOBM_K_FFT_PLANES);
+  const int rec = prof_start(c, dpart ? IOBM_K_FFT_PLANES_DOT : IOBM_K_FFT_PLANES);
   if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, mvec, dpart)) {
     size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
     hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
