@@ -182,6 +182,56 @@ def chain_workload(args):
     }), flush=True)
 
 
+def na_sweep(atoms=(3, 4, 5, 6, 7, 8)):
+    """The paper's preconditioner experiment (Sec. III, Table 2) on the
+    synthetic Na-like wires: average COCG iterations per incident wave at the
+    jellium Fermi level without a preconditioner, with Eq. (17) at
+    alpha = 3.0, 2.4, 1.8, and with the lateral-Fourier preconditioner;
+    complex128 iterations, convergence checked after every iteration, FP64
+    residual 1e-10.  One COCG solve per cos / sin standing wave, so a +-G
+    channel pair counts its two solves once each."""
+    import numpy as np
+    import torch
+
+    from paper_1009_5300_amd import iobm
+    from workloads import na_wire
+
+    torch.cuda.set_device(0)
+    cases = [("none", iobm.PC_NONE, 1.8), ("alpha=3.0", iobm.PC_TRUNCATED_LAPLACIAN, 3.0),
+             ("alpha=2.4", iobm.PC_TRUNCATED_LAPLACIAN, 2.4), ("alpha=1.8", iobm.PC_TRUNCATED_LAPLACIAN, 1.8),
+             ("lateral_fft", iobm.PC_LATERAL_FFT, 1.8)]
+    rows = []
+    for n in atoms:
+        w = na_wire(n)
+        g = w.grid
+        s = iobm.Solver(g.nx, g.ny, g.nz, (g.h, g.h, w.extra["hz"]), g.nf)
+        s.set_potential(w.V)
+        row = {"n_atom": n, "nz": g.nz}
+        Tref = None
+        for name, pc, alpha in cases:
+            o = iobm.default_opts(precision=iobm.C128, precond=pc, alpha=alpha, check_every=1, max_iter=400000)
+            t0 = time.perf_counter()
+            out = s.solve(w.energies, opts=o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ids = [int(m) for m in out["modes"][0]]
+            wgt = [1.0 if ((g.ny - m // g.nx) % g.ny) * g.nx + (g.nx - m % g.nx) % g.nx == m else 0.5 for m in ids]
+            iters = sum(st[0] * c for st, c in zip(out["stats"], wgt)) / len(ids)
+            row[name] = {"iters_per_wave": round(iters, 1), "status": int(out["status"]), "s": round(dt, 3)}
+            if Tref is None:
+                Tref = out["T"]
+                row["channels"] = len(ids)
+                row["T_total"] = float(out["T"].sum())
+            else:
+                row[name]["max_dT"] = float(np.abs(out["T"] - Tref).max())
+        rows.append(row)
+    mean = {name: float(np.mean([r[name]["iters_per_wave"] for r in rows])) for name, _, _ in cases}
+    print(json.dumps({"experiment": "preconditioner sweep on synthetic Na-like wires (Table 2 analogue)",
+                      "energy_Ha": float(na_wire(atoms[0]).energies[0]), "rows": rows,
+                      "mean_iters_per_wave": {k: round(v, 1) for k, v in mean.items()},
+                      "speedup_vs_none": {k: round(mean["none"] / v, 2) for k, v in mean.items()}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,15 +241,19 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip plain-CG and Eq. (17) samples")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for the HBM counter calibration)")
-    ap.add_argument("--workload", type=int, default=4, choices=[3, 4],
+    ap.add_argument("--workload", default="4", choices=["3", "4", "na"],
                     help="4: the headline wide-wire batch (default); 3: the atomic chain with the nonlocal "
-                         "term on MFMA (secondary measurement)")
+                         "term on MFMA (secondary measurement); na: iteration counts of the paper's "
+                         "preconditioner experiment on synthetic Na-like wires")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.gpus == 1 and args.workload == 3:
+    if args.gpus == 1 and args.workload == "3":
         chain_workload(args)
+        return
+    if args.gpus == 1 and args.workload == "na":
+        na_sweep()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the scattering states of different energies are "

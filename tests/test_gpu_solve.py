@@ -168,3 +168,29 @@ def test_full_size_invariants(torch, cfg):
         neg = [pos[((g.ny - m // g.nx) % g.ny) * g.nx + (g.nx - m % g.nx) % g.nx] for m in ids]
         assert np.abs(TL - TR[np.ix_(neg, neg)].T).max() <= 1e-8
         assert abs(TL.sum() - TR.sum()) <= 1e-8
+
+
+def test_na_wire_preconditioner_ordering(torch):
+    """The paper's Table 2 trend on the shortest synthetic Na-like wire (36 x 36
+    x 80, hz != hx, 2nd order, jellium Fermi level): Eq. (17) cuts the COCG
+    iterations more as alpha decreases (3.0, 2.4, 1.8), the lateral-Fourier
+    preconditioner more still (by far less than on the smooth wide-wire
+    potential: these wells are as deep as E is large); every solve gives the
+    same transmissions."""
+    from paper_1009_5300_amd import iobm
+    from workloads import na_wire
+    w = na_wire(3)
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, (g.h, g.h, w.extra["hz"]), g.nf)
+    s.set_potential(w.V)
+    its, Ts = [], []
+    for pc, alpha in ((iobm.PC_NONE, 1.8), (iobm.PC_TRUNCATED_LAPLACIAN, 3.0), (iobm.PC_TRUNCATED_LAPLACIAN, 2.4),
+                      (iobm.PC_TRUNCATED_LAPLACIAN, 1.8), (iobm.PC_LATERAL_FFT, 1.8)):
+        out = s.solve(w.energies, opts=iobm.default_opts(precision=iobm.C128, precond=pc, alpha=alpha,
+                                                          check_every=1, max_iter=400000))
+        assert out["status"] == 0, out.get("error")
+        its.append(np.mean([st[0] for st in out["stats"]]))
+        Ts.append(out["T"])
+    assert its[0] > its[1] > its[2] > its[3] > its[4]
+    for T in Ts[1:]:
+        assert np.abs(T - Ts[0]).max() <= 1e-8

@@ -362,3 +362,23 @@ def test_workload_channel_counts():
     g4 = G_(48, 48, 4, 0.4, 2)
     n4 = [len(O.open_channels(g4, E)) for E in make(4, G_(48, 48, 4, 0.4, 2)).energies]
     assert min(n4) >= 40 and max(n4) <= 60 and sum(n4) == 768
+
+
+def test_na_wire_stand_in():
+    """The synthetic Na-like wires: the paper's cell (36 x 36 lateral points
+    over 25.66 bohr, nz = 60 + 10 (n_atom - 1), length (n_atom - 1) d + 42.12
+    with d = sqrt(3) a0 / 2), V = 0 in the electrodes, and the jellium Fermi
+    energy of r_s = 3.99 (3.15 eV)."""
+    from workloads import na_wire, jellium_fermi_energy
+    assert abs(jellium_fermi_energy() * 27.211386 - 3.148) < 2e-3
+    for n in (3, 8):
+        w = na_wire(n)
+        g = w.grid
+        assert (g.nx, g.ny, g.nz, g.nf) == (36, 36, 60 + 10 * (n - 1), 1)
+        assert abs(g.h * 36 - 25.66) < 1e-12
+        assert abs(w.extra["hz"] * g.nz - ((n - 1) * 8.11 * 3 ** 0.5 / 2 + 42.12)) < 1e-9
+        assert np.abs(w.V[:3]).max() < 1e-6 and np.abs(w.V[-3:]).max() < 1e-6
+        assert 0.19 < w.V.max() <= 0.2 and w.V.min() < -0.3
+        # the lateral dispersion gives 9 open channels at E_F (the paper quotes 13
+        # for its SCF wire; see the design notes)
+        assert len(O.open_channels(g, float(w.energies[0]))) == 9

@@ -202,6 +202,56 @@ def adjoint(grid: Grid | None = None, seed: int = 1005) -> Workload:
                     extra={"centres": centres, "fd_rng_seed": seed})
 
 
+NA_RS = 3.99              # Wigner-Seitz radius of the jellium electrodes (bohr)
+NA_A0 = 8.11              # Na bulk lattice constant (bohr)
+NA_D = 3.0 ** 0.5 * NA_A0 / 2.0   # interatomic distance of the [110] strand
+
+
+def jellium_fermi_energy(rs: float = NA_RS) -> float:
+    """Free-electron Fermi energy (Ha) of jellium of Wigner-Seitz radius rs,
+    measured from the band bottom: k_F = (9 pi / 4)^(1/3) / rs."""
+    kf = (9.0 * np.pi / 4.0) ** (1.0 / 3.0) / rs
+    return 0.5 * kf * kf
+
+
+def na_wire(n_atom: int, seed: int = 1006) -> Workload:
+    """Synthetic stand-in for the paper's single-row Na wires between jellium
+    electrodes (Sec. III): n_atom = 3..8 atoms NA_D apart on the axis of a
+    36 x 36 lateral cell of 25.66 bohr, nz = 60 + 10 (n_atom - 1) planes over
+    (n_atom - 1) NA_D + 42.12 bohr, 2nd-order FD, one energy at the jellium
+    Fermi level.  V is 0 inside the electrodes, which end 2.867 bohr
+    (sqrt(2) a0 / 4) beyond the edge atoms; between them V rises to 0.2 Ha
+    (logistic steps 0.5 bohr wide) and each atom is a Gaussian well of depth
+    0.6 Ha and width 3 bohr (positions jittered by U(+-0.1) bohr), which
+    overlap into one conducting channel along the axis.  The
+    grid spacing differs along z: extra["hz"]; grid.h is the lateral one."""
+    if not 1 <= n_atom <= 20:
+        raise ValueError("n_atom out of range")
+    nx = 36
+    hx = 25.66 / nx
+    nz = 60 + 10 * (n_atom - 1)
+    hz = ((n_atom - 1) * NA_D + 42.12) / nz
+    g = Grid(nx, nx, nz, hx, 1)
+    rng = np.random.default_rng(seed + n_atom)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(nx), np.arange(nx), indexing="ij")
+    X, Y, Z = i * hx, j * hx, k * hz
+    L = nx * hx
+    zc = (nz - 1) * hz / 2.0
+    za = [zc + NA_D * (a - (n_atom - 1) / 2.0) for a in range(n_atom)]
+    zl, zr = za[0] - 2.0 ** 0.5 * NA_A0 / 4.0, za[-1] + 2.0 ** 0.5 * NA_A0 / 4.0
+    w = 0.5
+    V = 0.2 / (1.0 + np.exp(-(Z - zl) / w)) / (1.0 + np.exp(-(zr - Z) / w))
+    centres = []
+    for z0 in za:
+        R = np.array([L / 2.0, L / 2.0, z0]) + rng.uniform(-0.1, 0.1, 3)
+        centres.append(R)
+        dx = _min_image(X - R[0], L)
+        dy = _min_image(Y - R[1], L)
+        V = V - 0.6 * np.exp(-(dx * dx + dy * dy + (Z - R[2]) ** 2) / (2.0 * 3.0 ** 2))
+    return Workload(f"na{n_atom}", g, V, np.array([jellium_fermi_energy()]),
+                    extra={"hz": hz, "centres": centres})
+
+
 CONFIGS = {1: flat, 2: barrier, 3: chain, 4: wide, 5: adjoint}
 
 
