@@ -299,7 +299,7 @@ def main():
     # stream around every launch of the profiled kernel classes; the library
     # reports each launch's algorithmic bytes
     classes = {"stencil": iobm.K_STENCIL, "fft_planes": iobm.K_FFT_PLANES, "fft_planes_dot": iobm.K_FFT_PLANES_DOT,
-               "update": iobm.K_UPDATE,
+               "fft_planes_update": iobm.K_FFT_PLANES_UPD, "update": iobm.K_UPDATE,
                "zfilter": iobm.K_ZFILTER, "stencil_c128": iobm.K_STENCIL_C128, "boundary": iobm.K_BOUNDARY,
                "accumulate": iobm.K_ACCUMULATE, "dot": iobm.K_DOT}
     s.profile_begin(list(classes.values()) + [iobm.K_PRECOND_FFT])

@@ -232,7 +232,8 @@ enum { IOBM_K_STENCIL = 1,      /* stencil in the iteration precision; with the
        IOBM_K_ZFILTER = 10,     /* the z recursion of the preconditioner */
        IOBM_K_ACCUMULATE = 11,  /* x += d, d = 0 (refinement) */
        IOBM_K_NONLOCAL_C128 = 12, /* as IOBM_K_NONLOCAL, complex128 (flops) */
-       IOBM_K_FFT_PLANES_DOT = 13 };/* inverse plane FFT with the r^T z partials */
+       IOBM_K_FFT_PLANES_DOT = 13, /* inverse plane FFT with the r^T z partials */
+       IOBM_K_FFT_PLANES_UPD = 14 };/* forward plane FFT with the fused d, r update */
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask);
 iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
                              double* alg_bytes);

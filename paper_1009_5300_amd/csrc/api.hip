@@ -89,7 +89,8 @@ iobm_status fail(iobm_ctx ctx, iobm_status s, const std::string& msg) {
 
 // ------------------------------------------------------------- scratch pool
 enum Slot {
-  S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_P2, S_Q, S_D, S_PF, S_PART, S_PARTA, S_PARTZ, S_PARTR, S_SCAL, S_IDX, S_AMP,
+  S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_P2, S_Q, S_D, S_PF, S_PART, S_PARTA, S_PARTZ, S_PARTR, S_PARTN, S_SCAL,
+  S_IDX, S_AMP,
   S_TR, S_KB, S_GRAD_U, S_GRAD_D, NSLOT
 };
 
@@ -325,6 +326,12 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
                          ? part
                          : (Partial*)scratch(ctx, S_PARTZ, (size_t)nb * nz_slots * sizeof(Partial));
   Partial* part_rn = (Partial*)scratch(ctx, S_PARTR, (size_t)nb * PQ_SLOTS * sizeof(Partial));
+  // with the lateral-Fourier preconditioner on square planes, the update
+  // d += alpha p, r -= alpha q runs inside its forward transform, which
+  // writes the |r|^2 partials per plane
+  const bool fuse_upd = o.precond == IOBM_PC_LATERAL_FFT && fft_reg_available(ctx);
+  Partial* part_n2 = fuse_upd ? (Partial*)scratch(ctx, S_PARTN, (size_t)nb * ctx->g.nz * sizeof(Partial)) : part;
+  const int n2_slots = fuse_upd ? ctx->g.nz : nblk;
   // per-rhs scalars; |r|^2 and the breakdown flags are adjacent so that one
   // copy brings both to the host at a convergence check
   const size_t nb8 = ((size_t)nb + 1) & ~(size_t)1;
@@ -419,6 +426,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   // One iteration is three passes over the batch:
   //   operator:  p_new = z + beta p_old, q = A p_new, partials of p_new^T q
   //   update:    d += alpha p_new, r -= alpha q, partials of |r|^2 (and r^T r)
+  //              (inside the preconditioner's forward transform when fused)
   //   precond:   z = P r, partials of r^T z
   // with the scalar steps (alpha; beta, rho, |r|^2) in between.
   cplx<T>* pold = pa;
@@ -428,9 +436,16 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       ApplyFuse<T> F{z, pold, beta, pnew, part_pq};
       HIPCHK(launch_apply<T>(ctx, nullptr, q, nact, E_d, e_d, modes, act_d, &F));
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_pq, PQ_SLOTS, nullptr, 0, FIN_ALPHA, nact, act_d));
-      HIPCHK((launch_update_xr<T, T>(ctx, d, pnew, r, q, alpha, nact, act_d, part)));
-      if (o.precond != IOBM_PC_NONE) precond(nact, act_d);  // P = I: r^T r came with the update
-      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, part, nblk, FIN_BETA, nact, act_d));
+      if (fuse_upd) {
+        FftUpd<T> U;
+        U.q = q; U.d = d; U.p = pnew; U.alpha = alpha; U.n2part = part_n2;
+        HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nact, e_d, modes, act_d, part_rz, &U));
+      } else {
+        HIPCHK((launch_update_xr<T, T>(ctx, d, pnew, r, q, alpha, nact, act_d, part)));
+        if (o.precond != IOBM_PC_NONE) precond(nact, act_d);  // P = I: r^T r came with the update
+      }
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, part_n2, n2_slots, FIN_BETA, nact,
+                            act_d));
       std::swap(pold, pnew);
     }
     HIPCHK(hipMemcpyAsync(rbh, rn2, check_bytes, hipMemcpyDeviceToHost, ctx->stream));
@@ -688,7 +703,7 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
 
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask) {
   if (!ctx) return IOBM_E_INVALID_ARG;
-  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_FFT_PLANES_DOT + 1)))
+  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_FFT_PLANES_UPD + 1)))
     return fail(ctx, IOBM_E_INVALID_ARG, "bad kernel class mask");
   ctx->prof_mask = class_mask;
   ctx->prof_used = 0;

@@ -154,10 +154,22 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z,
                                     int nrhs, const int* active, Partial* dpart = nullptr);
+// The COCG update d += alpha p, r -= alpha q fused into the preconditioner's
+// forward transform (square planes of the register FFT only, see
+// fft_reg_available); the per-plane partials of |r|^2 go to n2part[rhs][nz].
+template <typename T>
+struct FftUpd {
+  const cplx<T>* q = nullptr;
+  cplx<T>* d = nullptr;
+  const cplx<T>* p = nullptr;
+  const zd* alpha = nullptr;
+  Partial* n2part = nullptr;
+};
+bool fft_reg_available(iobm_ctx c);
 template <typename T>
 hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch,
                               int nrhs, const int* e_rhs, const ModeData* modes,
-                              const int* active, Partial* dpart = nullptr);
+                              const int* active, Partial* dpart = nullptr, const FftUpd<T>* upd = nullptr);
 int precond_slots(iobm_ctx c, int precond);
 template <typename T>
 hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, Partial* pq_part,

@@ -672,12 +672,20 @@ template <> struct Pair<double> { typedef double2 type; static constexpr int n =
 //   sum_x r(x) out(x) = scale * sum_k R(-k) in(k),   R = forward FFT of r = mvec,
 // from loads issued together with those of the input (a real-space dot
 // would read r after the transforms, with its latency exposed).
-template <typename T, int N, int PPB, bool DOT>
+// With MODE = FFT_UPDATE (the forward transform of the preconditioner), the
+// block first applies the COCG update to its planes, d += alpha p and
+// r -= alpha q (in = r, rewritten in place), writes the per-plane partials
+// of |r|^2 to dpart[rhs][z], and transforms the updated r: the update costs
+// no separate pass over r.
+enum { FFT_PLAIN = 0, FFT_DOT = 1, FFT_UPDATE = 2 };
+
+template <typename T, int N, int PPB, int MODE>
 __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes, const cplx<T>* in, cplx<T>* out,
                                                            const cplx<T>* __restrict__ tw, int sign, T scale,
                                                            const int* __restrict__ active,
                                                            const cplx<T>* __restrict__ mvec,
-                                                           Partial* __restrict__ dpart) {
+                                                           Partial* __restrict__ dpart, FftUpd<T> U) {
+  constexpr bool DOT = MODE == FFT_DOT;
   typedef typename Pair<T>::type VT;
   constexpr int PE = Pair<T>::n;          // elements per vector access
   constexpr int NN = N * N;
@@ -689,12 +697,14 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
   const int g0 = blockIdx.x * PPB;
   long long poff[PPB];
   bool pok[PPB];
+  int prhs[PPB];
 #pragma unroll
   for (int q = 0; q < PPB; ++q) {
     const int gp = g0 + q;
     pok[q] = gp < nplanes;
     const int slot = pok[q] ? gp / nz : 0, z = pok[q] ? gp - slot * nz : 0;
-    poff[q] = (long long)rhs_of(active, slot) * vol + (long long)z * NN;
+    prhs[q] = rhs_of(active, slot);
+    poff[q] = (long long)prhs[q] * vol + (long long)z * NN;
   }
   VT buf[EPT];
   double ds_re[PPB], ds_im[PPB];
@@ -758,6 +768,72 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
       }
     }
     __syncthreads();
+  } else if constexpr (MODE == FFT_UPDATE) {
+    cplx<T> al[PPB];
+#pragma unroll
+    for (int q = 0; q < PPB; ++q) al[q] = pok[q] ? cvt<T>(U.alpha[prhs[q]]) : mk<T>(0, 0);
+    // d += alpha p, in two batches of loads
+    constexpr int H = (EPT + 1) / 2;
+#pragma unroll
+    for (int b0 = 0; b0 < EPT; b0 += H) {
+      VT pv[H], dv[H];
+#pragma unroll
+      for (int e = 0; e < H; ++e) {
+        const int v = threadIdx.x + (b0 + e) * BLK;
+        const int q = v / (NN / PE), w = v - q * (NN / PE);
+        if (b0 + e < EPT && v < NV && pok[q]) {
+          pv[e] = reinterpret_cast<const VT*>(U.p + poff[q])[w];
+          dv[e] = reinterpret_cast<const VT*>(U.d + poff[q])[w];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < H; ++e) {
+        const int v = threadIdx.x + (b0 + e) * BLK;
+        const int q = v / (NN / PE), w = v - q * (NN / PE);
+        if (b0 + e < EPT && v < NV && pok[q]) {
+          cplx<T>* dc = reinterpret_cast<cplx<T>*>(&dv[e]);
+          const cplx<T>* pc = reinterpret_cast<const cplx<T>*>(&pv[e]);
+#pragma unroll
+          for (int k = 0; k < PE; ++k)
+#pragma unroll
+            for (int qq = 0; qq < PPB; ++qq)
+              if (qq == q) dc[k] = dc[k] + al[qq] * pc[k];
+          reinterpret_cast<VT*>(U.d + poff[q])[w] = dv[e];
+        }
+      }
+    }
+    // r -= alpha q into buf, written back, |r|^2 partials
+#pragma unroll
+    for (int b0 = 0; b0 < EPT; b0 += H) {
+      VT qv[H];
+#pragma unroll
+      for (int e = 0; e < H; ++e) {
+        const int v = threadIdx.x + (b0 + e) * BLK;
+        const int q = v / (NN / PE), w = v - q * (NN / PE);
+        if (b0 + e < EPT && v < NV && pok[q]) {
+          buf[b0 + e] = reinterpret_cast<const VT*>(in + poff[q])[w];
+          qv[e] = reinterpret_cast<const VT*>(U.q + poff[q])[w];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < H; ++e) {
+        const int v = threadIdx.x + (b0 + e) * BLK;
+        const int q = v / (NN / PE), w = v - q * (NN / PE);
+        if (b0 + e < EPT && v < NV && pok[q]) {
+          cplx<T>* rc = reinterpret_cast<cplx<T>*>(&buf[b0 + e]);
+          const cplx<T>* qc = reinterpret_cast<const cplx<T>*>(&qv[e]);
+#pragma unroll
+          for (int k = 0; k < PE; ++k)
+#pragma unroll
+            for (int qq = 0; qq < PPB; ++qq)
+              if (qq == q) {
+                rc[k] = rc[k] - al[qq] * qc[k];
+                ds_re[qq] += (double)rc[k].re * rc[k].re + (double)rc[k].im * rc[k].im;
+              }
+          reinterpret_cast<VT*>(const_cast<cplx<T>*>(in) + poff[q])[w] = buf[b0 + e];
+        }
+      }
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -809,16 +885,21 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
       reinterpret_cast<VT*>(out + poff[q])[w] = o;
     }
   }
-  if constexpr (DOT) {
+  if constexpr (MODE != FFT_PLAIN) {
 #pragma unroll
     for (int q = 0; q < PPB; ++q) {
-      double a = (double)scale * ds_re[q], b = (double)scale * ds_im[q];
+      double a = ds_re[q], b = ds_im[q];
       block_sum2<BLK>(a, b);
       if (threadIdx.x == 0 && pok[q]) {
         const int gp = g0 + q;
         const int slot = gp / nz, z = gp - slot * nz;
         Partial P;
-        P.re = a; P.im = b; P.n2 = 0; P.pad = 0;
+        if (DOT) {
+          P.re = (double)scale * a; P.im = (double)scale * b; P.n2 = 0;
+        } else {
+          P.re = 0; P.im = 0; P.n2 = a;  // |r|^2 of the updated r
+        }
+        P.pad = 0;
         dpart[(long long)rhs_of(active, slot) * nz + z] = P;
       }
     }
@@ -1557,30 +1638,42 @@ hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, 
 
 template <typename T, int N, int PPB>
 static void launch_fft_reg(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
-                           const int* active, const cplx<T>* mvec, Partial* dpart) {
+                           const int* active, const cplx<T>* mvec, Partial* dpart, const FftUpd<T>* upd) {
   const int nplanes = nrhs * c->g.nz;
-  if (dpart)
-    hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB, true>), dim3((nplanes + PPB - 1) / PPB), dim3(N * PPB), 0,
-                       c->stream, c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active, mvec, dpart);
+  const dim3 grid((nplanes + PPB - 1) / PPB), blk(N * PPB);
+  const FftUpd<T> U = upd ? *upd : FftUpd<T>();
+  if (upd)
+    hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB, FFT_UPDATE>), grid, blk, 0, c->stream, c->g.nz, nplanes, in, out,
+                       twx<T>(c), sign, (T)scale, active, mvec, dpart, U);
+  else if (dpart)
+    hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB, FFT_DOT>), grid, blk, 0, c->stream, c->g.nz, nplanes, in, out,
+                       twx<T>(c), sign, (T)scale, active, mvec, dpart, U);
   else
-    hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB, false>), dim3((nplanes + PPB - 1) / PPB), dim3(N * PPB), 0,
-                       c->stream, c->g.nz, nplanes, in, out, twx<T>(c), sign, (T)scale, active, mvec, dpart);
+    hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB, FFT_PLAIN>), grid, blk, 0, c->stream, c->g.nz, nplanes, in, out,
+                       twx<T>(c), sign, (T)scale, active, mvec, dpart, U);
 }
 
 // planes per block of the register FFT (measured: one plane per block is
 // fastest at 48 x 48)
-template <typename T>
-static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
-                             const int* active, const cplx<T>* mvec, Partial* dpart) {
+bool fft_reg_available(iobm_ctx c) {
   if (c->g.nx != c->g.ny || c->tune_fft_generic) return false;
   switch (c->g.nx) {
-    case 8: launch_fft_reg<T, 8, 16>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
-    case 12: launch_fft_reg<T, 12, 8>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
-    case 16: launch_fft_reg<T, 16, 8>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
-    case 24: launch_fft_reg<T, 24, 4>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
-    case 32: launch_fft_reg<T, 32, 4>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
-    case 48: launch_fft_reg<T, 48, 1>(c, in, out, sign, scale, nrhs, active, mvec, dpart); return true;
+    case 8: case 12: case 16: case 24: case 32: case 48: return true;
     default: return false;
+  }
+}
+
+template <typename T>
+static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
+                             const int* active, const cplx<T>* mvec, Partial* dpart, const FftUpd<T>* upd) {
+  if (!fft_reg_available(c)) return false;
+  switch (c->g.nx) {
+    case 8: launch_fft_reg<T, 8, 16>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd); return true;
+    case 12: launch_fft_reg<T, 12, 8>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd); return true;
+    case 16: launch_fft_reg<T, 16, 8>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd); return true;
+    case 24: launch_fft_reg<T, 24, 4>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd); return true;
+    case 32: launch_fft_reg<T, 32, 4>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd); return true;
+    default: launch_fft_reg<T, 48, 1>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd); return true;
   }
 }
 
@@ -1590,14 +1683,17 @@ static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int si
 template <typename T>
 hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                              const int* active, const cplx<T>* dvec = nullptr, const cplx<T>* mvec = nullptr,
-                             Partial* dpart = nullptr) {
-  const int rec = prof_start(c, dpart ? IOBM_K_FFT_PLANES_DOT : IOBM_K_FFT_PLANES);
-  if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, mvec, dpart)) {
+                             Partial* dpart = nullptr, const FftUpd<T>* upd = nullptr) {
+  if (upd && !fft_reg_available(c)) return hipErrorInvalidValue;
+  const int rec = prof_start(c, upd ? IOBM_K_FFT_PLANES_UPD : (dpart ? IOBM_K_FFT_PLANES_DOT : IOBM_K_FFT_PLANES));
+  if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd)) {
     size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
     hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
                        twx<T>(c), twy<T>(c), sign, (T)scale, active, dvec, dpart);
   }
-  prof_stop(c, rec, (dpart ? 3.0 : 2.0) * nrhs * c->g.npts * sizeof(cplx<T>));
+  // streams: plain 2; with the dot 3 (read Z, R; write z); with the update 7
+  // (read r, q, d, p; write r, d, R)
+  prof_stop(c, rec, (upd ? 7.0 : (dpart ? 3.0 : 2.0)) * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -1642,11 +1738,13 @@ static int zfilter_chunk(iobm_ctx c) {
 
 template <typename T>
 hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch, int nrhs,
-                              const int* e_rhs, const ModeData* modes, const int* active, Partial* dpart) {
+                              const int* e_rhs, const ModeData* modes, const int* active, Partial* dpart,
+                              const FftUpd<T>* upd) {
   const int L = zfilter_chunk<T>(c);
   if ((c->g.nz + L - 1) / L > 8) return hipErrorInvalidValue;
   const int rec = prof_start(c, IOBM_K_PRECOND_FFT);
-  hipError_t err = launch_fft_planes<T>(c, r, scratch, -1, 1.0, nrhs, active);
+  hipError_t err = launch_fft_planes<T>(c, r, scratch, -1, 1.0, nrhs, active, nullptr, nullptr,
+                                        upd ? upd->n2part : nullptr, upd);
   if (err == hipSuccess) err = launch_zfilter<T>(c, L, scratch, z, nrhs, e_rhs, modes, active);
   if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active, r, scratch, dpart);
   prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
@@ -1721,9 +1819,9 @@ template hipError_t launch_apply<float>(iobm_ctx, const zf*, zf*, int, const dou
 template hipError_t launch_precond_laplacian<double>(iobm_ctx, double, const zd*, zd*, int, const int*, Partial*);
 template hipError_t launch_precond_laplacian<float>(iobm_ctx, double, const zf*, zf*, int, const int*, Partial*);
 template hipError_t launch_precond_fft<double>(iobm_ctx, const zd*, zd*, zd*, int, const int*,
-                                               const ModeData*, const int*, Partial*);
+                                               const ModeData*, const int*, Partial*, const FftUpd<double>*);
 template hipError_t launch_precond_fft<float>(iobm_ctx, const zf*, zf*, zf*, int, const int*,
-                                              const ModeData*, const int*, Partial*);
+                                              const ModeData*, const int*, Partial*, const FftUpd<float>*);
 
 // partials of r^T z per rhs written by each preconditioner (P = I: the
 // update kernel's r^T r, one per reduction block)

@@ -20,7 +20,7 @@ LIBPATH = os.path.join(_HERE, "libiobm.so")
 C128, C64_REFINED = 0, 1
 PC_NONE, PC_TRUNCATED_LAPLACIAN, PC_LATERAL_FFT = 0, 1, 2
 (K_STENCIL, K_BOUNDARY, K_PRECOND_FFT, K_PRECOND_LAP, K_NONLOCAL, K_DOT, K_UPDATE, K_STENCIL_C128,
- K_FFT_PLANES, K_ZFILTER, K_ACCUMULATE, K_NONLOCAL_C128, K_FFT_PLANES_DOT) = range(1, 14)
+ K_FFT_PLANES, K_ZFILTER, K_ACCUMULATE, K_NONLOCAL_C128, K_FFT_PLANES_DOT, K_FFT_PLANES_UPD) = range(1, 15)
 STATUS = ["ok", "invalid argument", "bad state", "out of device memory", "device error",
           "not converged", "Krylov breakdown", "energy at a channel threshold", "unsupported"]
 
