@@ -173,9 +173,13 @@ iobm_status iobm_apply(iobm_ctx ctx, double E, int32_t nrhs, const void* x, void
 
 /* z = P r for nrhs vectors with the preconditioner `precond` (IOBM_PC_*) at
  * energy E (only IOBM_PC_LATERAL_FFT depends on E), same layout rules as
- * iobm_apply.  Asynchronous. */
+ * iobm_apply.  rz: NULL, or host complex128 [nrhs] that receives the bilinear
+ * form r^T z of each vector (no conjugation), from the same FP64-accumulated
+ * partials that the solver's COCG step takes (for IOBM_PC_LATERAL_FFT they
+ * come from the inverse plane FFT, in mode space).  Asynchronous when rz is
+ * NULL; synchronises the stream otherwise. */
 iobm_status iobm_precondition(iobm_ctx ctx, int32_t precond, double alpha, double E,
-                              int32_t nrhs, const void* r, void* z, int32_t precision);
+                              int32_t nrhs, const void* r, void* z, int32_t precision, double* rz);
 
 /* Right-hand side of Eq. (6) for incident channels: b[c] for energy E and
  * channel ids[c] (must be open), device complex128 [n][nz][ny][nx], zero

@@ -326,9 +326,11 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
                          ? part
                          : (Partial*)scratch(ctx, S_PARTZ, (size_t)nb * nz_slots * sizeof(Partial));
   Partial* part_rn = (Partial*)scratch(ctx, S_PARTR, (size_t)nb * PQ_SLOTS * sizeof(Partial));
-  // with the lateral-Fourier preconditioner on square planes, the update
-  // d += alpha p, r -= alpha q runs inside its forward transform, which
-  // writes the |r|^2 partials per plane
+  // with the lateral-Fourier preconditioner on square planes, the update runs
+  // inside its forward transform, which writes the |r|^2 partials per plane:
+  // between replacements the iterated residual lives only in lateral mode
+  // space (R = FFT(r) in pf, R -= alpha FFT(q)); the real-space r is formed
+  // only by a replacement, whose preconditioner pass transforms it into pf
   const bool fuse_upd = o.precond == IOBM_PC_LATERAL_FFT && fft_reg_available(ctx);
   Partial* part_n2 = fuse_upd ? (Partial*)scratch(ctx, S_PARTN, (size_t)nb * ctx->g.nz * sizeof(Partial)) : part;
   const int n2_slots = fuse_upd ? ctx->g.nz : nblk;
@@ -426,7 +428,8 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   // One iteration is three passes over the batch:
   //   operator:  p_new = z + beta p_old, q = A p_new, partials of p_new^T q
   //   update:    d += alpha p_new, r -= alpha q, partials of |r|^2 (and r^T r)
-  //              (inside the preconditioner's forward transform when fused)
+  //              (fused: inside the preconditioner's forward transform, on
+  //              R = FFT(r) from FFT(q))
   //   precond:   z = P r, partials of r^T z
   // with the scalar steps (alpha; beta, rho, |r|^2) in between.
   cplx<T>* pold = pa;
@@ -951,7 +954,7 @@ iobm_status iobm_apply(iobm_ctx ctx, double E, int32_t nrhs, const void* x, void
 }
 
 iobm_status iobm_precondition(iobm_ctx ctx, int32_t precond, double alpha, double E, int32_t nrhs,
-                              const void* r, void* z, int32_t precision) {
+                              const void* r, void* z, int32_t precision, double* rz) {
   if (!ctx) return IOBM_E_INVALID_ARG;
   if (nrhs < 0 || (nrhs > 0 && (!r || !z)) || !isfinite(E) || !(alpha > 0) ||
       (precision != IOBM_C128 && precision != IOBM_C64_REFINED) || precond < 0 || precond > 2)
@@ -960,24 +963,40 @@ iobm_status iobm_precondition(iobm_ctx ctx, int32_t precond, double alpha, doubl
   if (nrhs == 0) return IOBM_OK;
   try {
     const long long vol = ctx->g.npts;
+    const int slots = precond_slots(ctx, precond);
+    Partial* part = rz ? (Partial*)scratch(ctx, S_PARTZ, (size_t)nrhs * slots * sizeof(Partial)) : nullptr;
     if (precond == IOBM_PC_NONE) {
       size_t es = precision == IOBM_C128 ? sizeof(zd) : sizeof(zf);
       HIPCHK(hipMemcpyAsync(z, r, (size_t)nrhs * vol * es, hipMemcpyDeviceToDevice, ctx->stream));
+      if (part && precision == IOBM_C128) HIPCHK(launch_dot<double>(ctx, (const zd*)r, (const zd*)r, nrhs, nullptr, part));
+      if (part && precision != IOBM_C128) HIPCHK(launch_dot<float>(ctx, (const zf*)r, (const zf*)r, nrhs, nullptr, part));
     } else if (precond == IOBM_PC_TRUNCATED_LAPLACIAN) {
       if (precision == IOBM_C128)
-        HIPCHK(launch_precond_laplacian<double>(ctx, alpha, (const zd*)r, (zd*)z, nrhs, nullptr));
+        HIPCHK(launch_precond_laplacian<double>(ctx, alpha, (const zd*)r, (zd*)z, nrhs, nullptr, part));
       else
-        HIPCHK(launch_precond_laplacian<float>(ctx, alpha, (const zf*)r, (zf*)z, nrhs, nullptr));
+        HIPCHK(launch_precond_laplacian<float>(ctx, alpha, (const zf*)r, (zf*)z, nrhs, nullptr, part));
     } else {
       ensure_modes(ctx, std::vector<double>{E});
       std::vector<int> e(nrhs, 0);
       int* e_d = upload(ctx, S_IDX, e, 0);
       if (precision == IOBM_C128) {
         zd* pf = (zd*)scratch(ctx, S_PF, (size_t)nrhs * vol * sizeof(zd));
-        HIPCHK(launch_precond_fft<double>(ctx, (const zd*)r, (zd*)z, pf, nrhs, e_d, ctx->modes_d, nullptr));
+        HIPCHK(launch_precond_fft<double>(ctx, (const zd*)r, (zd*)z, pf, nrhs, e_d, ctx->modes_d, nullptr, part));
       } else {
         zf* pf = (zf*)scratch(ctx, S_PF, (size_t)nrhs * vol * sizeof(zf));
-        HIPCHK(launch_precond_fft<float>(ctx, (const zf*)r, (zf*)z, pf, nrhs, e_d, ctx->modes_d, nullptr));
+        HIPCHK(launch_precond_fft<float>(ctx, (const zf*)r, (zf*)z, pf, nrhs, e_d, ctx->modes_d, nullptr, part));
+      }
+    }
+    if (rz) {
+      // the partials, summed per vector in slot order as the solver does
+      std::vector<Partial> h((size_t)nrhs * slots);
+      HIPCHK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(Partial), hipMemcpyDeviceToHost, ctx->stream));
+      stream_sync(ctx);
+      for (int i = 0; i < nrhs; ++i) {
+        double re = 0, im = 0;
+        for (int k = 0; k < slots; ++k) { re += h[(size_t)i * slots + k].re; im += h[(size_t)i * slots + k].im; }
+        rz[2 * i] = re;
+        rz[2 * i + 1] = im;
       }
     }
   } catch (Fail& f) {

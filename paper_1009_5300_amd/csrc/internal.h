@@ -154,9 +154,11 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z,
                                     int nrhs, const int* active, Partial* dpart = nullptr);
-// The COCG update d += alpha p, r -= alpha q fused into the preconditioner's
-// forward transform (square planes of the register FFT only, see
-// fft_reg_available); the per-plane partials of |r|^2 go to n2part[rhs][nz].
+// The COCG update fused into the preconditioner's forward transform (square
+// planes of the register FFT only, see fft_reg_available): d += alpha p, and
+// the residual, kept in lateral mode space in the preconditioner's scratch
+// (R = FFT(r)), is updated from q: R -= alpha FFT(q).  The per-plane partials
+// of |r|^2 go to n2part[rhs][nz].
 template <typename T>
 struct FftUpd {
   const cplx<T>* q = nullptr;

@@ -672,11 +672,13 @@ template <> struct Pair<double> { typedef double2 type; static constexpr int n =
 //   sum_x r(x) out(x) = scale * sum_k R(-k) in(k),   R = forward FFT of r = mvec,
 // from loads issued together with those of the input (a real-space dot
 // would read r after the transforms, with its latency exposed).
-// With MODE = FFT_UPDATE (the forward transform of the preconditioner), the
-// block first applies the COCG update to its planes, d += alpha p and
-// r -= alpha q (in = r, rewritten in place), writes the per-plane partials
-// of |r|^2 to dpart[rhs][z], and transforms the updated r: the update costs
-// no separate pass over r.
+// With MODE = FFT_UPDATE (the forward transform of the preconditioner in the
+// COCG step), the residual is kept in lateral mode space, R = FFT(r): the
+// block applies d += alpha p to its planes, transforms in = q and updates
+// out = R in place, R -= alpha FFT(q), and writes the per-plane partials of
+// |r|^2 = |R|^2 / Nxy (Parseval) to dpart[rhs][z].  The real-space r is
+// neither read nor written, and the transform of the preconditioner comes
+// with the update.
 enum { FFT_PLAIN = 0, FFT_DOT = 1, FFT_UPDATE = 2 };
 
 template <typename T, int N, int PPB, int MODE>
@@ -707,6 +709,9 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
     poff[q] = (long long)prhs[q] * vol + (long long)z * NN;
   }
   VT buf[EPT];
+  cplx<T> al[PPB];  // alpha of each plane's rhs (FFT_UPDATE)
+#pragma unroll
+  for (int q = 0; q < PPB; ++q) al[q] = (MODE == FFT_UPDATE && pok[q]) ? cvt<T>(U.alpha[prhs[q]]) : mk<T>(0, 0);
   double ds_re[PPB], ds_im[PPB];
 #pragma unroll
   for (int q = 0; q < PPB; ++q) ds_re[q] = ds_im[q] = 0;
@@ -769,9 +774,6 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
     }
     __syncthreads();
   } else if constexpr (MODE == FFT_UPDATE) {
-    cplx<T> al[PPB];
-#pragma unroll
-    for (int q = 0; q < PPB; ++q) al[q] = pok[q] ? cvt<T>(U.alpha[prhs[q]]) : mk<T>(0, 0);
     // d += alpha p, in two batches of loads
     constexpr int H = (EPT + 1) / 2;
 #pragma unroll
@@ -802,37 +804,11 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
         }
       }
     }
-    // r -= alpha q into buf, written back, |r|^2 partials
 #pragma unroll
-    for (int b0 = 0; b0 < EPT; b0 += H) {
-      VT qv[H];
-#pragma unroll
-      for (int e = 0; e < H; ++e) {
-        const int v = threadIdx.x + (b0 + e) * BLK;
-        const int q = v / (NN / PE), w = v - q * (NN / PE);
-        if (b0 + e < EPT && v < NV && pok[q]) {
-          buf[b0 + e] = reinterpret_cast<const VT*>(in + poff[q])[w];
-          qv[e] = reinterpret_cast<const VT*>(U.q + poff[q])[w];
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < H; ++e) {
-        const int v = threadIdx.x + (b0 + e) * BLK;
-        const int q = v / (NN / PE), w = v - q * (NN / PE);
-        if (b0 + e < EPT && v < NV && pok[q]) {
-          cplx<T>* rc = reinterpret_cast<cplx<T>*>(&buf[b0 + e]);
-          const cplx<T>* qc = reinterpret_cast<const cplx<T>*>(&qv[e]);
-#pragma unroll
-          for (int k = 0; k < PE; ++k)
-#pragma unroll
-            for (int qq = 0; qq < PPB; ++qq)
-              if (qq == q) {
-                rc[k] = rc[k] - al[qq] * qc[k];
-                ds_re[qq] += (double)rc[k].re * rc[k].re + (double)rc[k].im * rc[k].im;
-              }
-          reinterpret_cast<VT*>(const_cast<cplx<T>*>(in) + poff[q])[w] = buf[b0 + e];
-        }
-      }
+    for (int e = 0; e < EPT; ++e) {
+      const int v = threadIdx.x + e * BLK;
+      const int q = v / (NN / PE), w = v - q * (NN / PE);
+      if (v < NV && pok[q]) buf[e] = reinterpret_cast<const VT*>(in + poff[q])[w];
     }
   } else {
 #pragma unroll
@@ -870,19 +846,53 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
 #pragma unroll
   for (int i = 0; i < N; ++i) sm[pl][i][li] = scale * v[i];
   __syncthreads();
+  if constexpr (MODE == FFT_UPDATE) {
+    // R -= alpha FFT(q), the old R loaded in two batches
+    constexpr int H = (EPT + 1) / 2;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int vv = threadIdx.x + e * BLK;
-    const int q = vv / (NN / PE), w = vv - q * (NN / PE);
-    if (vv < NV && pok[q]) {
-      VT o;
-      cplx<T>* c = reinterpret_cast<cplx<T>*>(&o);
+    for (int b0 = 0; b0 < EPT; b0 += H) {
+      VT ro[H];
 #pragma unroll
-      for (int k = 0; k < PE; ++k) {
-        const int el = w * PE + k;
-        c[k] = sm[q][el / N][el % N];
+      for (int e = 0; e < H; ++e) {
+        const int vv = threadIdx.x + (b0 + e) * BLK;
+        const int q = vv / (NN / PE), w = vv - q * (NN / PE);
+        if (b0 + e < EPT && vv < NV && pok[q]) ro[e] = reinterpret_cast<const VT*>(out + poff[q])[w];
       }
-      reinterpret_cast<VT*>(out + poff[q])[w] = o;
+#pragma unroll
+      for (int e = 0; e < H; ++e) {
+        const int vv = threadIdx.x + (b0 + e) * BLK;
+        const int q = vv / (NN / PE), w = vv - q * (NN / PE);
+        if (b0 + e < EPT && vv < NV && pok[q]) {
+          cplx<T>* c = reinterpret_cast<cplx<T>*>(&ro[e]);
+#pragma unroll
+          for (int k = 0; k < PE; ++k) {
+            const int el = w * PE + k;
+#pragma unroll
+            for (int qq = 0; qq < PPB; ++qq)
+              if (qq == q) {
+                c[k] = c[k] - al[qq] * sm[q][el / N][el % N];
+                ds_re[qq] += (double)c[k].re * c[k].re + (double)c[k].im * c[k].im;
+              }
+          }
+          reinterpret_cast<VT*>(out + poff[q])[w] = ro[e];
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int vv = threadIdx.x + e * BLK;
+      const int q = vv / (NN / PE), w = vv - q * (NN / PE);
+      if (vv < NV && pok[q]) {
+        VT o;
+        cplx<T>* c = reinterpret_cast<cplx<T>*>(&o);
+#pragma unroll
+        for (int k = 0; k < PE; ++k) {
+          const int el = w * PE + k;
+          c[k] = sm[q][el / N][el % N];
+        }
+        reinterpret_cast<VT*>(out + poff[q])[w] = o;
+      }
     }
   }
   if constexpr (MODE != FFT_PLAIN) {
@@ -897,7 +907,7 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
         if (DOT) {
           P.re = (double)scale * a; P.im = (double)scale * b; P.n2 = 0;
         } else {
-          P.re = 0; P.im = 0; P.n2 = a;  // |r|^2 of the updated r
+          P.re = 0; P.im = 0; P.n2 = a / NN;  // |r|^2 of the updated residual
         }
         P.pad = 0;
         dpart[(long long)rhs_of(active, slot) * nz + z] = P;
@@ -1691,9 +1701,9 @@ hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int si
     hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
                        twx<T>(c), twy<T>(c), sign, (T)scale, active, dvec, dpart);
   }
-  // streams: plain 2; with the dot 3 (read Z, R; write z); with the update 7
-  // (read r, q, d, p; write r, d, R)
-  prof_stop(c, rec, (upd ? 7.0 : (dpart ? 3.0 : 2.0)) * nrhs * c->g.npts * sizeof(cplx<T>));
+  // streams: plain 2; with the dot 3 (read Z, R; write z); with the update 6
+  // (read q, d, p, R; write d, R)
+  prof_stop(c, rec, (upd ? 6.0 : (dpart ? 3.0 : 2.0)) * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -1743,7 +1753,8 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
   const int L = zfilter_chunk<T>(c);
   if ((c->g.nz + L - 1) / L > 8) return hipErrorInvalidValue;
   const int rec = prof_start(c, IOBM_K_PRECOND_FFT);
-  hipError_t err = launch_fft_planes<T>(c, r, scratch, -1, 1.0, nrhs, active, nullptr, nullptr,
+  // with upd, scratch holds the residual in mode space and is updated from q
+  hipError_t err = launch_fft_planes<T>(c, upd ? upd->q : r, scratch, -1, 1.0, nrhs, active, nullptr, nullptr,
                                         upd ? upd->n2part : nullptr, upd);
   if (err == hipSuccess) err = launch_zfilter<T>(c, L, scratch, z, nrhs, e_rhs, modes, active);
   if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active, r, scratch, dpart);

@@ -58,7 +58,7 @@ EXPORTS = {
     "iobm_self_energy": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
     "iobm_apply": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     "iobm_precondition": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32,
-                                    C.c_void_p, C.c_void_p, C.c_int32]),
+                                    C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "iobm_rhs": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
     "iobm_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -218,13 +218,16 @@ class Solver:
         self._check(lib().iobm_apply(self._ctx, float(E), nrhs, _ptr(x), _ptr(y), precision))
         return y
 
-    def precondition(self, kind, r, alpha=1.8, E=0.0, precision=C128):
+    def precondition(self, kind, r, alpha=1.8, E=0.0, precision=C128, want_rz=False):
+        """z = P r; with want_rz, also (z, rz) with rz[i] = r_i^T z_i (complex128,
+        numpy) from the solver's own reduction."""
         r = r.contiguous()
         z = self.torch.empty_like(r)
         nrhs = r.numel() // self.npts
+        rz = np.zeros(nrhs, dtype=np.complex128) if want_rz else None
         self._check(lib().iobm_precondition(self._ctx, kind, float(alpha), float(E), nrhs, _ptr(r),
-                                            _ptr(z), precision))
-        return z
+                                            _ptr(z), precision, _ptr(rz)))
+        return (z, rz) if want_rz else z
 
     def rhs(self, E, ids, side=0):
         ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int32))

@@ -179,3 +179,30 @@ def test_lateral_fft_preconditioner_inverts_flat_operator(torch, n, nz):
     z32 = s.precondition(iobm.PC_LATERAL_FFT, torch.as_tensor(y, device="cuda").to(torch.complex64), E=E,
                          precision=iobm.C64_REFINED).cpu().numpy()
     assert np.abs(z32 - x).max() <= 1e-3 * np.abs(x).max()
+
+
+RZ_GRIDS = [GRIDS[0], GRIDS[2], Grid(16, 16, 20, 0.4, 2), Grid(12, 12, 40, 0.4, 2), Grid(9, 7, 20, 0.5, 2), Grid(7, 10, 33, 0.5, 3)]
+
+
+@pytest.mark.parametrize("g", RZ_GRIDS, ids=lambda g: f"{g.nx}x{g.ny}x{g.nz}nf{g.nf}")
+def test_preconditioner_rz_partials(torch, g):
+    """r^T z from the solver's own reductions (for the lateral-Fourier
+    preconditioner taken in mode space, sum_k R(-k) Z(k) / Nxy, which pairs
+    every lateral mode with its negative: odd plane sizes have one
+    self-paired mode, even ones four) against the bilinear form of the
+    oracle's z = P r."""
+    from paper_1009_5300_amd import iobm
+    s = _solver(g, np.zeros(g.shape))
+    E = 1.3
+    r = random_field((3,) + g.shape, 11)
+    rt = torch.as_tensor(r, device="cuda")
+    refs = {iobm.PC_LATERAL_FFT: O.precond.flat_wire_inverse(g, E, r),
+            iobm.PC_TRUNCATED_LAPLACIAN: O.precond.truncated_laplacian(g, r, 1.8),
+            iobm.PC_NONE: r}
+    for kind, ref in refs.items():
+        a, b = r.reshape(len(r), -1), ref.reshape(len(r), -1)
+        rz_ref = (a * b).sum(axis=1)  # no conjugation
+        scale = (np.abs(a) * np.abs(b)).sum(axis=1)
+        for prec, rr, tol in ((iobm.C128, rt, 1e-11), (iobm.C64_REFINED, rt.to(torch.complex64), 2e-5)):
+            _, rz = s.precondition(kind, rr, alpha=1.8, E=E, precision=prec, want_rz=True)
+            assert np.all(np.abs(rz - rz_ref) <= tol * scale), (kind, prec, rz, rz_ref)
