@@ -33,9 +33,9 @@ hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rh
 int dot_blocks(iobm_ctx c);
 template <typename T>
 hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active, void* part);
-template <typename T, typename TX>
-hipError_t launch_update_xr(iobm_ctx c, cplx<TX>* x, const cplx<T>* p, cplx<T>* r, const cplx<T>* q,
-                            const zd* alpha, int nact, const int* active, void* part);
+template <typename T>
+hipError_t launch_update_r(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* alpha, int nact, const int* active,
+                           void* part);
 enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3 };
 hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const Partial* pa,
                           int na, const Partial* pb, int nb, int mode, int nact, const int* active);
@@ -44,7 +44,8 @@ hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const 
 template <typename TD, typename TS>
 hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int nact, const int* active);
 template <typename T>
-hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, int nact, const int* active);
+hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, int nact,
+                             const int* active);
 template <typename TR>
 hipError_t launch_refresh(iobm_ctx c, const zd* x, const zd* b, zd* rface, cplx<TR>* r, int nrhs,
                           const double* E_rhs, const int* e_rhs, const ModeData* modes, const int* active,
@@ -283,10 +284,12 @@ struct SolveOut {
 // The Krylov recurrences run in type T (complex64 or complex128) on the
 // correction d of the FP64 solution x: q = A p, alpha = rho / p^T q,
 // d += alpha p, r -= alpha q, z = P r, beta = (r^T z) / rho, p = z + beta p,
-// with every inner product accumulated in FP64.  When the recursively
+// with every inner product accumulated in FP64.  The step d += alpha p is
+// deferred to the next operator pass, which reads p anyway (alpha then
+// holds the pending factor; a restart clears it).  When the recursively
 // updated residual of a right-hand side has fallen by the factor `delta`
 // (opts.inner_tol) since its last update, or below the target, the
-// correction is folded into x in FP64 (x += d, d = 0), the true residual
+// correction is folded into x in FP64 (x += d + alpha p, d = 0), the true residual
 // r_hi = b - A x is formed with the complex128 operator, the iterated
 // residual is replaced by it and the direction restarts (p = z).  Keeping
 // the old direction across the replacement is fragile once the
@@ -366,7 +369,9 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     else
       HIPCHK(launch_dot<T>(ctx, r, r, nact, ad, part_rz));
   };
-  // Refinement of the listed rhs: x += d, d = 0, r = b - A x in FP64 (stored
+  cplx<T>* pold = pa;  // the direction of the last step (its update pending)
+  cplx<T>* pnew = pb;
+  // Refinement of the listed rhs: x += d + alpha p, d = 0, r = b - A x in FP64 (stored
   // in the iteration precision; the FP64 face planes pass through r_hi), and
   // |r|^2 -> host.  With a nonlocal term the residual is formed in full in
   // r_hi first, since its back-projection comes after the stencil.
@@ -379,7 +384,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   auto refresh = [&](const std::vector<int>& lst, int region) {
     int* ld = upload(ctx, S_IDX, lst, (size_t)region * 8192);
     const int n = (int)lst.size();
-    HIPCHK(launch_accumulate<T>(ctx, x, d, n, ld));
+    HIPCHK(launch_accumulate<T>(ctx, x, d, pold, alpha, n, ld));
     if (ctx->kb.ncen == 0) {
       HIPCHK(launch_refresh<T>(ctx, x, b, rhi, r, n, E_d, e_d, modes, ld, part_rn));
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part_rn, PQ_SLOTS, nullptr, 0, FIN_NORM, n, ld));
@@ -418,7 +423,8 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     // nonzero beta (0x3F bytes: 4.8e-4), so that every stream is read
     HIPCHK(hipMemsetAsync(pa, 0, vb, ctx->stream));
     HIPCHK(hipMemsetAsync(beta, 0x3F, nb * sizeof(zd), ctx->stream));
-    ApplyFuse<T> TF{r, pa, beta, pb, part_pq};
+    HIPCHK(hipMemsetAsync(alpha, 0x3F, nb * sizeof(zd), ctx->stream));  // d += alpha * 0 leaves d = 0
+    ApplyFuse<T> TF{r, pa, beta, pb, part_pq, alpha, d};
     autotune<T>(ctx, r, q, pf, nact, E_d, e_d, modes, act_d, &TF);
     HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   }
@@ -432,19 +438,18 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   //              R = FFT(r) from FFT(q))
   //   precond:   z = P r, partials of r^T z
   // with the scalar steps (alpha; beta, rho, |r|^2) in between.
-  cplx<T>* pold = pa;
-  cplx<T>* pnew = pb;
+  int nfresh = nact;  // active rhs whose next step starts from a restart (byte count only)
   while (nact > 0) {
     for (int k = 0; k < check; ++k) {
-      ApplyFuse<T> F{z, pold, beta, pnew, part_pq};
+      ApplyFuse<T> F{z, pold, beta, pnew, part_pq, alpha, d, k == 0 ? nfresh : 0};
       HIPCHK(launch_apply<T>(ctx, nullptr, q, nact, E_d, e_d, modes, act_d, &F));
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_pq, PQ_SLOTS, nullptr, 0, FIN_ALPHA, nact, act_d));
       if (fuse_upd) {
         FftUpd<T> U;
-        U.q = q; U.d = d; U.p = pnew; U.alpha = alpha; U.n2part = part_n2;
+        U.q = q; U.alpha = alpha; U.n2part = part_n2;
         HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nact, e_d, modes, act_d, part_rz, &U));
       } else {
-        HIPCHK((launch_update_xr<T, T>(ctx, d, pnew, r, q, alpha, nact, act_d, part)));
+        HIPCHK(launch_update_r<T>(ctx, r, q, alpha, nact, act_d, part));
         if (o.precond != IOBM_PC_NONE) precond(nact, act_d);  // P = I: r^T r came with the update
       }
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, part_n2, n2_slots, FIN_BETA, nact,
@@ -462,6 +467,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       if (bad || r2 <= 0.25 * tol2 * bn2[i] || r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter) upd.push_back(i);
       else maxr2[i] = std::max(maxr2[i], r2);
     }
+    nfresh = 0;
     if (upd.empty()) continue;
     refresh(upd, 7);
     std::vector<int> cont;  // updated rhs that go on iterating, from a restart
@@ -494,6 +500,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     act.assign(lists.begin() + nc, lists.end());
     nact = (int)act.size();
     act_d = ld + nc;  // the old list's region was rewritten
+    nfresh = nc;  // every restarted rhs stays active
   }
   for (int i = 0; i < nb; ++i) {
     out.rel[i] = bn2[i] > 0 ? sqrt(tn2_h[i] / bn2[i]) : 0.0;

@@ -1,6 +1,7 @@
 // Internal declarations of libiobm (not part of the ABI).
 #pragma once
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -135,7 +136,10 @@ enum { PQ_STENCIL_MAX = 64, PQ_BOUNDARY = 64, PQ_KB = 66, PQ_SLOTS = 68 };
 
 // Fused COCG direction update for launch_apply: the operand is
 // pnew = z + beta p_old (beta per rhs; p_old is not read where beta = 0),
-// written to pnew, and the partials of pnew^T (A pnew) go to part.
+// written to pnew, and the partials of pnew^T (A pnew) go to part.  With
+// alpha and d set, the previous step's update d += alpha p_old is applied on
+// the way (per rhs; none where alpha = 0).  nfresh: how many of the rhs
+// restart here (beta = alpha = 0), for the byte count of the timing hook.
 template <typename T>
 struct ApplyFuse {
   const cplx<T>* z;
@@ -143,6 +147,9 @@ struct ApplyFuse {
   const zd* beta;
   cplx<T>* pnew;
   Partial* part;  // [rhs][PQ_SLOTS]
+  const zd* alpha = nullptr;
+  cplx<T>* d = nullptr;
+  int nfresh = 0;
 };
 
 template <typename T>
@@ -154,16 +161,14 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z,
                                     int nrhs, const int* active, Partial* dpart = nullptr);
-// The COCG update fused into the preconditioner's forward transform (square
-// planes of the register FFT only, see fft_reg_available): d += alpha p, and
-// the residual, kept in lateral mode space in the preconditioner's scratch
-// (R = FFT(r)), is updated from q: R -= alpha FFT(q).  The per-plane partials
+// The COCG residual update fused into the preconditioner's forward transform
+// (square planes of the register FFT only, see fft_reg_available): the
+// residual, kept in lateral mode space in the preconditioner's scratch
+// (R = FFT(r)), is updated from q, R -= alpha FFT(q).  The per-plane partials
 // of |r|^2 go to n2part[rhs][nz].
 template <typename T>
 struct FftUpd {
   const cplx<T>* q = nullptr;
-  cplx<T>* d = nullptr;
-  const cplx<T>* p = nullptr;
   const zd* alpha = nullptr;
   Partial* n2part = nullptr;
 };

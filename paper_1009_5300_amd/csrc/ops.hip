@@ -102,9 +102,11 @@ struct OpPlain {  // y = A_st x
   cplx<T>* y;
   __device__ __forceinline__ void bind(int rhs, long long vol) { x += rhs * vol; y += rhs * vol; }
   __device__ __forceinline__ cplx<T> load(long long o) const { return x[o]; }
-  __device__ __forceinline__ Raw load_raw(long long o) const { return x[o]; }
+  __device__ __forceinline__ Raw load_raw(long long o, bool) const { return x[o]; }
   __device__ __forceinline__ cplx<T> combine(Raw r, bool ok) const { return ok ? r : mk<T>(0, 0); }
+  __device__ __forceinline__ void side(const Raw&, long long, bool) {}
   __device__ __forceinline__ void center(long long, cplx<T>) {}
+  __device__ __forceinline__ void center_at(long long, cplx<T>) {}
   __device__ __forceinline__ void store(int, long long o, cplx<T>, cplx<T> acc) { y[o] = acc; }
   __device__ __forceinline__ void finish(int, int, int) {}
 };
@@ -120,13 +122,16 @@ __device__ __forceinline__ void clear_unused_slots(Partial* part, int rhs, int c
 }
 
 // COCG direction update fused into the operator: the operand is
-// p_new = z + beta p_old (p_old not read where beta = 0), written to pnew for
-// the block's own points; the block's partial of p_new^T y goes to
-// part[rhs][chunk] (PQ_SLOTS per rhs).
+// p_new = z + beta p_old (p_old not read where beta = 0 and no update is
+// pending), written to pnew for the block's own points; the block's partial
+// of p_new^T y goes to part[rhs][chunk] (PQ_SLOTS per rhs).  With alpha set,
+// the previous step's solution update d += alpha p_old is applied to the
+// block's own points from the same p_old loads (skipped where alpha = 0,
+// the first step after a restart).
 template <typename T>
 struct OpFuseP {
   struct Raw {
-    cplx<T> z, p;
+    cplx<T> z, p, d;
   };
   static constexpr int lookahead = sizeof(T) == 4 ? 2 : 1;
   const cplx<T>* z;
@@ -135,32 +140,52 @@ struct OpFuseP {
   cplx<T>* pnew;
   cplx<T>* y;
   Partial* part;
+  const zd* alpha;  // pending alpha per rhs, or nullptr
+  cplx<T>* d;
   const cplx<T>* psrc;
-  cplx<T> bt;
-  bool use_p;
+  const cplx<T>* dsrc;
+  cplx<T> bt, at;
+  bool use_b, use_p, use_d;
   double s_re, s_im;
   __device__ __forceinline__ void bind(int rhs, long long vol) {
     z += rhs * vol; pold += rhs * vol; pnew += rhs * vol; y += rhs * vol;
     bt = cvt<T>(beta[rhs]);
-    use_p = bt.re != (T)0 || bt.im != (T)0;
+    at = alpha ? cvt<T>(alpha[rhs]) : mk<T>(0, 0);
+    use_d = at.re != (T)0 || at.im != (T)0;
+    if (use_d) d += rhs * vol;
+    use_b = bt.re != (T)0 || bt.im != (T)0;
+    use_p = use_b || use_d;
+    // where a stream is not needed its loads read z again: cache hits, not
+    // another stream
     psrc = use_p ? pold : z;
+    dsrc = use_d ? d : z;
     s_re = s_im = 0;
   }
   __device__ __forceinline__ cplx<T> load(long long o) const {
     cplx<T> v = z[o];
-    if (use_p) v = v + bt * pold[o];
+    if (use_b) v = v + bt * pold[o];
     return v;
   }
-  __device__ __forceinline__ Raw load_raw(long long o) const {
+  __device__ __forceinline__ Raw load_raw(long long o, bool own) const {
     Raw r;
     r.z = z[o];
-    r.p = psrc[o];  // psrc = z where beta = 0: a cache hit, not a second stream
+    r.p = psrc[o];
+    r.d = (own ? dsrc : z)[o];
     return r;
   }
   __device__ __forceinline__ cplx<T> combine(const Raw& r, bool ok) const {
-    return ok ? (use_p ? r.z + bt * r.p : r.z) : mk<T>(0, 0);
+    return ok ? (use_b ? r.z + bt * r.p : r.z) : mk<T>(0, 0);
+  }
+  // a plane entering the window: the pending update of the block's own points
+  __device__ __forceinline__ void side(const Raw& r, long long o, bool own) {
+    if (use_d && own) d[o] = r.d + at * r.p;
   }
   __device__ __forceinline__ void center(long long o, cplx<T> v) { pnew[o] = v; }
+  // the cache-based kernel: the same at the centre point
+  __device__ __forceinline__ void center_at(long long o, cplx<T> v) {
+    pnew[o] = v;
+    if (use_d) d[o] = d[o] + at * pold[o];
+  }
   __device__ __forceinline__ void store(int, long long o, cplx<T> c, cplx<T> acc) {
     y[o] = acc;
     s_re += (double)c.re * acc.re - (double)c.im * acc.im;
@@ -200,9 +225,11 @@ struct OpRefresh {
     s_n2 = 0;
   }
   __device__ __forceinline__ zd load(long long o) const { return x[o]; }
-  __device__ __forceinline__ Raw load_raw(long long o) const { return x[o]; }
+  __device__ __forceinline__ Raw load_raw(long long o, bool) const { return x[o]; }
   __device__ __forceinline__ zd combine(Raw r, bool ok) const { return ok ? r : mk(0.0, 0.0); }
+  __device__ __forceinline__ void side(const Raw&, long long, bool) {}
   __device__ __forceinline__ void center(long long, zd) {}
+  __device__ __forceinline__ void center_at(long long, zd) {}
   __device__ __forceinline__ void store(int zz, long long o, zd, zd acc) {
     if (zz < nf || zz >= nz - nf) {
       rface[o] = b[o] - acc;
@@ -245,7 +272,7 @@ __global__ void __launch_bounds__(256) k_apply(StencilArgs S, Op op, const T* __
       const int j = p / S.nx;
       const int i = p - j * S.nx;
       const cplx<T> c0 = op.load(zo + p);
-      op.center(zo + p, c0);
+      op.center_at(zo + p, c0);
       const T d = diag0 - V[zo + p];
       cplx<T> acc = d * c0;
       for (int n = 1; n <= S.nf; ++n) {
@@ -320,14 +347,22 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
   auto valid = [&](int z, int u) -> bool {
     return (int)(threadIdx.x + u * blockDim.x) < nxy && z >= 0 && z < nz;
   };
+  // the block's own points (the operator may update them when they enter
+  // the window)
+  auto own = [&](int z, int u) -> bool { return valid(z, u) && z >= z0 && z < z1; };
 #pragma unroll
   for (int d = 0; d < W; ++d)
 #pragma unroll
-    for (int u = 0; u < MAXP; ++u) w[d][u] = op.combine(op.load_raw(off(z0 - NF + d, u)), valid(z0 - NF + d, u));
+    for (int u = 0; u < MAXP; ++u) {
+      const int zz = z0 - NF + d;
+      const Raw r = op.load_raw(off(zz, u), own(zz, u));
+      w[d][u] = op.combine(r, valid(zz, u));
+      op.side(r, off(zz, u), own(zz, u));
+    }
 #pragma unroll
   for (int k = 0; k < LA; ++k)
 #pragma unroll
-    for (int u = 0; u < MAXP; ++u) pre[k][u] = op.load_raw(off(z0 + NF + 1 + k, u));
+    for (int u = 0; u < MAXP; ++u) pre[k][u] = op.load_raw(off(z0 + NF + 1 + k, u), own(z0 + NF + 1 + k, u));
 #pragma unroll
   for (int u = 0; u < MAXP; ++u) vq[0][u] = V[off(z0, u)];
   for (int z = z0; z < z1; ++z) {
@@ -368,9 +403,10 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
 #pragma unroll
       for (int d = 0; d < W - 1; ++d) w[d][u] = w[d + 1][u];
       w[W - 1][u] = op.combine(pre[0][u], valid(z + NF + 1, u));
+      op.side(pre[0][u], off(z + NF + 1, u), own(z + NF + 1, u));
 #pragma unroll
       for (int k = 0; k < LA - 1; ++k) pre[k][u] = pre[k + 1][u];
-      pre[LA - 1][u] = op.load_raw(off(z + NF + 1 + LA, u));
+      pre[LA - 1][u] = op.load_raw(off(z + NF + 1 + LA, u), own(z + NF + 1 + LA, u));
       vq[0][u] = vq[1][u];
     }
   }
@@ -674,11 +710,10 @@ template <> struct Pair<double> { typedef double2 type; static constexpr int n =
 // would read r after the transforms, with its latency exposed).
 // With MODE = FFT_UPDATE (the forward transform of the preconditioner in the
 // COCG step), the residual is kept in lateral mode space, R = FFT(r): the
-// block applies d += alpha p to its planes, transforms in = q and updates
-// out = R in place, R -= alpha FFT(q), and writes the per-plane partials of
-// |r|^2 = |R|^2 / Nxy (Parseval) to dpart[rhs][z].  The real-space r is
-// neither read nor written, and the transform of the preconditioner comes
-// with the update.
+// block transforms in = q and updates out = R in place, R -= alpha FFT(q),
+// and writes the per-plane partials of |r|^2 = |R|^2 / Nxy (Parseval) to
+// dpart[rhs][z].  The real-space r is neither read nor written, and the
+// transform of the preconditioner comes with the update.
 enum { FFT_PLAIN = 0, FFT_DOT = 1, FFT_UPDATE = 2 };
 
 template <typename T, int N, int PPB, int MODE>
@@ -774,36 +809,6 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
     }
     __syncthreads();
   } else if constexpr (MODE == FFT_UPDATE) {
-    // d += alpha p, in two batches of loads
-    constexpr int H = (EPT + 1) / 2;
-#pragma unroll
-    for (int b0 = 0; b0 < EPT; b0 += H) {
-      VT pv[H], dv[H];
-#pragma unroll
-      for (int e = 0; e < H; ++e) {
-        const int v = threadIdx.x + (b0 + e) * BLK;
-        const int q = v / (NN / PE), w = v - q * (NN / PE);
-        if (b0 + e < EPT && v < NV && pok[q]) {
-          pv[e] = reinterpret_cast<const VT*>(U.p + poff[q])[w];
-          dv[e] = reinterpret_cast<const VT*>(U.d + poff[q])[w];
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < H; ++e) {
-        const int v = threadIdx.x + (b0 + e) * BLK;
-        const int q = v / (NN / PE), w = v - q * (NN / PE);
-        if (b0 + e < EPT && v < NV && pok[q]) {
-          cplx<T>* dc = reinterpret_cast<cplx<T>*>(&dv[e]);
-          const cplx<T>* pc = reinterpret_cast<const cplx<T>*>(&pv[e]);
-#pragma unroll
-          for (int k = 0; k < PE; ++k)
-#pragma unroll
-            for (int qq = 0; qq < PPB; ++qq)
-              if (qq == q) dc[k] = dc[k] + al[qq] * pc[k];
-          reinterpret_cast<VT*>(U.d + poff[q])[w] = dv[e];
-        }
-      }
-    }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int v = threadIdx.x + e * BLK;
@@ -1187,12 +1192,12 @@ __global__ void __launch_bounds__(256) k_dot(const cplx<T>* __restrict__ a, cons
 }
 
 // x += alpha p ; r -= alpha q ; partial |r|^2
-template <typename T, typename TX>
-__global__ void __launch_bounds__(256) k_update_xr(cplx<TX>* __restrict__ x, const cplx<T>* __restrict__ p,
-                                                   cplx<T>* __restrict__ r, const cplx<T>* __restrict__ q,
-                                                   const zd* __restrict__ alpha, long long vol, int nblk,
-                                                   Partial* __restrict__ part,
-                                                   const int* __restrict__ active) {
+// r -= alpha q with the partials of |r|^2 and r^T r (the solution update
+// d += alpha p is applied by the next operator pass).
+template <typename T>
+__global__ void __launch_bounds__(256) k_update_r(cplx<T>* __restrict__ r, const cplx<T>* __restrict__ q,
+                                                  const zd* __restrict__ alpha, long long vol, int nblk,
+                                                  Partial* __restrict__ part, const int* __restrict__ active) {
   const int slot = blockIdx.x / nblk;
   const int blk = blockIdx.x - slot * nblk;
   const int rhs = rhs_of(active, slot);
@@ -1202,10 +1207,6 @@ __global__ void __launch_bounds__(256) k_update_xr(cplx<TX>* __restrict__ x, con
   const long long off = rhs * vol;
   double sn = 0, d0 = 0, d1 = 0;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    cplx<T> pv = p[off + i];
-    cplx<TX> xv = x[off + i];
-    cplx<T> ap = a * pv;
-    x[off + i] = mk<TX>(xv.re + (TX)ap.re, xv.im + (TX)ap.im);
     cplx<T> rv = r[off + i] - a * q[off + i];
     r[off + i] = rv;
     sn += (double)rv.re * rv.re + (double)rv.im * rv.im;
@@ -1283,8 +1284,9 @@ __global__ void __launch_bounds__(256) k_finish2(Scal S, const Partial* __restri
     S.rn2[rhs] = n2;
   } else if (mode == FIN_NORM) {
     S.rn2[rhs] = n2;
-  } else {
+  } else {  // FIN_RESTART: p_new = z next, with no pending solution update
     S.rho[rhs] = mk(re, im);
+    S.alpha[rhs] = mk(0.0, 0.0);
     S.beta[rhs] = mk(0.0, 0.0);
     S.flag[rhs] = 0;
   }
@@ -1317,14 +1319,17 @@ __global__ void k_convert(const cplx<TS>* __restrict__ src, cplx<TD>* __restrict
 
 // x (complex128) += d (complex64 or complex128), then d = 0
 template <typename T>
-__global__ void k_accumulate(zd* __restrict__ x, cplx<T>* __restrict__ d, long long vol,
-                             const int* __restrict__ active) {
+__global__ void k_accumulate(zd* __restrict__ x, cplx<T>* __restrict__ d, const cplx<T>* __restrict__ p,
+                             const zd* __restrict__ alpha, long long vol, const int* __restrict__ active) {
   const int rhs = rhs_of(active, blockIdx.y);
   const long long off = rhs * vol;
+  const cplx<T> a = cvt<T>(alpha[rhs]);
+  const bool pend = a.re != (T)0 || a.im != (T)0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
        i += (long long)gridDim.x * blockDim.x) {
     zd xv = x[off + i];
     cplx<T> dv = d[off + i];
+    if (pend) dv = dv + a * p[off + i];
     x[off + i] = mk(xv.re + (double)dv.re, xv.im + (double)dv.im);
     d[off + i] = mk<T>(0, 0);
   }
@@ -1603,8 +1608,12 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
   hipError_t err;
   Partial* part = nullptr;
   if (fuse) {
-    OpFuseP<T> op{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part};
-    err = launch_stencil<T>(c, op, nrhs, E_rhs, active, 4.0 * sizeof(cplx<T>));
+    OpFuseP<T> op{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part, fuse->alpha, fuse->d};
+    // streams: read z, p_old (and d); write p_new, y (and d); the nfresh
+    // restarted rhs read z only
+    const int nf = std::min(std::max(fuse->nfresh, 0), nrhs);
+    const double full = fuse->alpha ? 6.0 : 4.0;
+    err = launch_stencil<T>(c, op, nrhs, E_rhs, active, (full * (nrhs - nf) + 3.0 * nf) / nrhs * sizeof(cplx<T>));
     x = fuse->pnew;  // the electrode and nonlocal terms read the assembled operand
     part = fuse->part;
   } else {
@@ -1701,9 +1710,9 @@ hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int si
     hipLaunchKernelGGL(k_fft_planes<T>, dim3(nrhs * c->g.nz), dim3(256), sh, c->stream, c->plan, c->g.nz, in, out,
                        twx<T>(c), twy<T>(c), sign, (T)scale, active, dvec, dpart);
   }
-  // streams: plain 2; with the dot 3 (read Z, R; write z); with the update 6
-  // (read q, d, p, R; write d, R)
-  prof_stop(c, rec, (upd ? 6.0 : (dpart ? 3.0 : 2.0)) * nrhs * c->g.npts * sizeof(cplx<T>));
+  // streams: plain 2; with the dot 3 (read Z, R; write z); with the update 3
+  // (read q, R; write R)
+  prof_stop(c, rec, (upd ? 3.0 : (dpart ? 3.0 : 2.0)) * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -1795,7 +1804,9 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
         if (zc > c->g.nz && zc != 16) continue;
         float t = timed([&] {
           if (fuse)
-            launch_apply25_shape<T>(c, ppt, zc, OpFuseP<T>{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part},
+            launch_apply25_shape<T>(c, ppt, zc,
+                                    OpFuseP<T>{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part,
+                                               fuse->alpha, fuse->d},
                                     nrhs, E_rhs, active);
           else
             launch_apply25_shape<T>(c, ppt, zc, OpPlain<T>{x, y}, nrhs, E_rhs, active);
@@ -1877,14 +1888,14 @@ hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, 
   return hipGetLastError();
 }
 
-template <typename T, typename TX>
-hipError_t launch_update_xr(iobm_ctx c, cplx<TX>* x, const cplx<T>* p, cplx<T>* r, const cplx<T>* q,
-                            const zd* alpha, int nact, const int* active, void* part) {
+template <typename T>
+hipError_t launch_update_r(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* alpha, int nact, const int* active,
+                           void* part) {
   int nblk = dot_blocks(c);
   const int rec = prof_start(c, IOBM_K_UPDATE);
-  hipLaunchKernelGGL((k_update_xr<T, TX>), dim3(nact * nblk), dim3(256), 0, c->stream, x, p, r, q, alpha,
-                     c->g.npts, nblk, (Partial*)part, active);
-  prof_stop(c, rec, 4.0 * nact * c->g.npts * sizeof(cplx<T>) + 2.0 * nact * c->g.npts * sizeof(cplx<TX>));
+  hipLaunchKernelGGL(k_update_r<T>, dim3(nact * nblk), dim3(256), 0, c->stream, r, q, alpha, c->g.npts, nblk,
+                     (Partial*)part, active);
+  prof_stop(c, rec, 3.0 * nact * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -1913,11 +1924,13 @@ hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int na
 }
 
 template <typename T>
-hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, int nact, const int* active) {
+hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, int nact,
+                             const int* active) {
   const int rec = prof_start(c, IOBM_K_ACCUMULATE);
-  hipLaunchKernelGGL(k_accumulate<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, x, d, c->g.npts,
-                     active);
-  prof_stop(c, rec, 2.0 * nact * c->g.npts * (sizeof(zd) + sizeof(cplx<T>)));
+  hipLaunchKernelGGL(k_accumulate<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, x, d, p, alpha,
+                     c->g.npts, active);
+  // read x, d, p; write x, d
+  prof_stop(c, rec, nact * c->g.npts * (2.0 * sizeof(zd) + 3.0 * sizeof(cplx<T>)));
   return hipGetLastError();
 }
 
@@ -1947,17 +1960,17 @@ hipError_t launch_combine_psi(iobm_ctx c, int nreq, const zd* x, cplx<TO>* psi, 
 
 template hipError_t launch_dot<double>(iobm_ctx, const zd*, const zd*, int, const int*, void*);
 template hipError_t launch_dot<float>(iobm_ctx, const zf*, const zf*, int, const int*, void*);
-template hipError_t launch_update_xr<double, double>(iobm_ctx, zd*, const zd*, zd*, const zd*, const zd*, int,
+template hipError_t launch_update_r<double>(iobm_ctx, zd*, const zd*, const zd*, int,
                                                      const int*, void*);
-template hipError_t launch_update_xr<float, float>(iobm_ctx, zf*, const zf*, zf*, const zf*, const zd*, int,
+template hipError_t launch_update_r<float>(iobm_ctx, zf*, const zf*, const zd*, int,
                                                    const int*, void*);
 template hipError_t launch_residual<double>(iobm_ctx, const zd*, zd*, int, const int*);
 template hipError_t launch_residual<float>(iobm_ctx, const zd*, zf*, int, const int*);
 template hipError_t launch_convert<float, double>(iobm_ctx, const zd*, zf*, int, const int*);
 template hipError_t launch_convert<double, double>(iobm_ctx, const zd*, zd*, int, const int*);
 template hipError_t launch_convert<float, float>(iobm_ctx, const zf*, zf*, int, const int*);
-template hipError_t launch_accumulate<float>(iobm_ctx, zd*, zf*, int, const int*);
-template hipError_t launch_accumulate<double>(iobm_ctx, zd*, zd*, int, const int*);
+template hipError_t launch_accumulate<float>(iobm_ctx, zd*, zf*, const zf*, const zd*, int, const int*);
+template hipError_t launch_accumulate<double>(iobm_ctx, zd*, zd*, const zd*, const zd*, int, const int*);
 template hipError_t launch_combine_psi<double>(iobm_ctx, int, const zd*, zd*, const int*, const int*,
                                                const int*);
 template hipError_t launch_combine_psi<float>(iobm_ctx, int, const zd*, zf*, const int*, const int*,
