@@ -324,7 +324,8 @@ def main():
     stencil = {"achieved": round(st["achieved_GBps"], 1), "unit": "GB/s",
                "frac": round(st["achieved_GBps"] / HBM_PEAK_GBPS, 4), "avg_launch_ms": round(st["avg_ms"], 4),
                "alg_bytes_per_launch": st["alg_bytes_per_launch"],
-               "note": "fused operator: reads z and p_old, writes p_new and A p_new (4 vector streams)"}
+               "note": "fused operator: reads z, p_old and d, writes p_new, A p_new and d += alpha p_old "
+                         "(6 vector streams; 3 right after a restart)"}
     tot_ms = sum(v["total_ms"] for v in kern.values() if v)
     tot_b = sum(v["alg_bytes_per_launch"] * v["launches"] for v in kern.values() if v)
     whole = {"achieved": round(tot_b / (tot_ms * 1e-3) / 1e9, 1), "unit": "GB/s",
