@@ -194,3 +194,29 @@ def test_na_wire_preconditioner_ordering(torch):
     assert its[0] > its[1] > its[2] > its[3] > its[4]
     for T in Ts[1:]:
         assert np.abs(T - Ts[0]).max() <= 1e-8
+
+
+@pytest.mark.parametrize("check_every,inner_tol", [(1, 1e-3), (3, 1e-3), (1, 0.3), (5, 1e-5)])
+@pytest.mark.parametrize("cfg,grid", [(2, None), (5, Grid(16, 12, 40, 0.4, 2))], ids=["square_fused", "rect"])
+def test_refinement_cadence(torch, cfg, grid, check_every, inner_tol):
+    """The complex64 solve with FP64 replacement at several check and
+    replacement cadences: a replacement right after a restart (check_every=1,
+    a pending step of one iteration), frequent replacements (inner_tol 0.3)
+    and long stretches between them; square planes run the fused mode-space
+    residual update, the rectangular ones the separate update kernel."""
+    from paper_1009_5300_amd import iobm
+    w = make(cfg) if grid is None else make(cfg, grid)
+    Es = list(w.energies[:3]) if grid is None else [0.2, 0.8]
+    s = _solver(w)
+    _, ref = _oracle(w, Es)
+    out = s.solve(Es, opts=iobm.default_opts(precision=iobm.C64_REFINED, check_every=check_every,
+                                             inner_tol=inner_tol), want_psi=True)
+    assert out["status"] == 0, out.get("error")
+    k = 0
+    for (modes, psi, TR) in ref:
+        for j, m in enumerate(modes):
+            assert abs(out["T"][k] - TR[j, 0]) <= DT
+            assert abs(out["R"][k] - TR[j, 1]) <= DT
+            got = out["psi"][k].cpu().numpy()
+            assert np.abs(got - psi[j]).max() <= 1e-6 * np.abs(psi[j]).max()
+            k += 1
