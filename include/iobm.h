@@ -221,8 +221,10 @@ iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, in
  * except IOBM_K_PRECOND_FFT, which spans the three launches of the
  * lateral-Fourier preconditioner (algorithmic bytes: read r, write z). */
 enum { IOBM_K_STENCIL = 1,      /* stencil in the iteration precision; with the
-                                   fused direction update: read z, p_old,
-                                   write p_new, y; else read x, write y */
+                                   fused direction update: read z, p_old, d,
+                                   write p_new, y, d (d += alpha p_old; z only,
+                                   p_new and y right after a restart); else
+                                   read x, write y */
        IOBM_K_BOUNDARY = 2,     /* electrode term on the 2 nf face planes */
        IOBM_K_PRECOND_FFT = 3,  /* the whole lateral-Fourier preconditioner */
        IOBM_K_PRECOND_LAP = 4,  /* Eq. (17) preconditioner */
@@ -230,14 +232,15 @@ enum { IOBM_K_STENCIL = 1,      /* stencil in the iteration precision; with the
                                    is algorithmic flops, 2 n_proj (2 n_rhs) n_support,
                                    not bytes */
        IOBM_K_DOT = 6,          /* bilinear / norm reductions */
-       IOBM_K_UPDATE = 7,       /* d += alpha p, r -= alpha q, |r|^2 partials */
+       IOBM_K_UPDATE = 7,       /* r -= alpha q, |r|^2 partials */
        IOBM_K_STENCIL_C128 = 8, /* stencil in complex128 (FP64 residuals) */
        IOBM_K_FFT_PLANES = 9,   /* forward batched 2D plane FFT of the preconditioner */
        IOBM_K_ZFILTER = 10,     /* the z recursion of the preconditioner */
-       IOBM_K_ACCUMULATE = 11,  /* x += d, d = 0 (refinement) */
+       IOBM_K_ACCUMULATE = 11,  /* x += d + alpha p, d = 0 (refinement) */
        IOBM_K_NONLOCAL_C128 = 12, /* as IOBM_K_NONLOCAL, complex128 (flops) */
        IOBM_K_FFT_PLANES_DOT = 13, /* inverse plane FFT with the r^T z partials */
-       IOBM_K_FFT_PLANES_UPD = 14 };/* forward plane FFT with the fused d, r update */
+       IOBM_K_FFT_PLANES_UPD = 14 };/* forward plane FFT of q with the mode-space
+                                   residual update R -= alpha FFT(q) */
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask);
 iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
                              double* alg_bytes);
