@@ -413,6 +413,24 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
   op.finish(rhs, chunk, S.nchunks);
 }
 
+// Vector type for pairs of elements in global accesses (16 bytes: two
+// complex64 or one complex128).
+template <typename T> struct Pair;
+template <> struct Pair<float> {
+  typedef float4 type;
+  static constexpr int n = 2;
+  static __device__ __forceinline__ zf get(const float4& v, int k) { return k ? mk(v.z, v.w) : mk(v.x, v.y); }
+  static __device__ __forceinline__ void set(float4& v, int k, zf c) {
+    if (k) { v.z = c.re; v.w = c.im; } else { v.x = c.re; v.y = c.im; }
+  }
+};
+template <> struct Pair<double> {
+  typedef double2 type;
+  static constexpr int n = 1;
+  static __device__ __forceinline__ zd get(const double2& v, int) { return mk(v.x, v.y); }
+  static __device__ __forceinline__ void set(double2& v, int, zd c) { v.x = c.re; v.y = c.im; }
+};
+
 // ----------------------------------------------------- electrode term ---
 // y[boundary planes] -= Sigma x[boundary planes], applied in lateral
 // momentum space (Eqs. (14)-(16)): FFT each of the nf planes, mix the planes
@@ -511,6 +529,16 @@ __global__ void __launch_bounds__(N * NF) k_boundary_reg(int nz, const cplx<T>* 
                                                         const int* __restrict__ active,
                                                         Partial* __restrict__ part, int np, int pslot) {
   constexpr int NN = N * N, BLK = N * NF;
+  typedef typename Pair<T>::type VT;
+  constexpr int PE = Pair<T>::n;              // elements per vector access
+  constexpr int NV = NF * NN / PE;            // vector accesses of the nf planes
+  constexpr int EPT = (NV + BLK - 1) / BLK;   // per thread
+  constexpr int MPT = (NN + BLK - 1) / BLK;   // modes per thread
+  // loads are issued in batches, each batch in flight at once: the kernel
+  // has one short block per state and side, so a load waited on one at a
+  // time would expose its latency once per element
+  constexpr int B1 = 12, B5 = 8;
+  constexpr int B3 = NF == 1 ? 24 : (NF == 2 ? 6 : 2);
   __shared__ cplx<T> sm[NF][N][N + 1];
   __shared__ double red[3][BLK];
   const int slot = blockIdx.x >> 1;
@@ -519,9 +547,25 @@ __global__ void __launch_bounds__(N * NF) k_boundary_reg(int nz, const cplx<T>* 
   const cplx<T>* sg = sig + (long long)e_rhs[rhs] * NF * NF * NN;  // [k][mode]
   const int pbase = side ? nz - NF : 0;
   const long long off = (long long)rhs * NN * nz + (long long)pbase * NN;  // NF consecutive planes
-  for (int i = threadIdx.x; i < NF * NN; i += BLK) {
-    const int k = i / NN, e = i - k * NN;
-    sm[k][e / N][e % N] = x[off + i];
+  auto at = [&](int el) -> cplx<T>& {
+    const int kk = el / NN, e = el - kk * NN;
+    return sm[kk][e / N][e % N];
+  };
+#pragma unroll
+  for (int b0 = 0; b0 < EPT; b0 += B1) {
+    VT buf[B1];
+#pragma unroll
+    for (int e = 0; e < B1; ++e) {
+      const int v = threadIdx.x + (b0 + e) * BLK;
+      if (b0 + e < EPT && v < NV) buf[e] = reinterpret_cast<const VT*>(x + off)[v];
+    }
+#pragma unroll
+    for (int e = 0; e < B1; ++e) {
+      const int v = threadIdx.x + (b0 + e) * BLK;
+      if (b0 + e < EPT && v < NV)
+#pragma unroll
+        for (int k = 0; k < PE; ++k) at(v * PE + k) = Pair<T>::get(buf[e], k);
+    }
   }
   __syncthreads();
   const int k = threadIdx.x / N, li = threadIdx.x - k * N;
@@ -544,40 +588,77 @@ __global__ void __launch_bounds__(N * NF) k_boundary_reg(int nz, const cplx<T>* 
   // mode mixing, mode m = ky N + kx at sm[.][ky][kx]; plane k <-> boundary
   // index i as in k_boundary
   const T inv = (T)(1.0 / NN);
-#pragma unroll 4
-  for (int m = threadIdx.x; m < NN; m += BLK) {
-    const int r = m / N, cc = m - r * N;
-    cplx<T> in[NF];
 #pragma unroll
-    for (int l = 0; l < NF; ++l) in[l] = sm[l][r][cc];
+  for (int j0 = 0; j0 < MPT; j0 += B3) {
+    cplx<T> sv[B3][NF * NF];
 #pragma unroll
-    for (int kk = 0; kk < NF; ++kk) {
-      const int ik = side ? kk : NF - 1 - kk;
-      cplx<T> acc = mk<T>(0, 0);
+    for (int jj = 0; jj < B3; ++jj) {
+      const int m = threadIdx.x + (j0 + jj) * BLK;
+      // entry (kk, l) of the block in plane order (the left side reverses
+      // the planes), so that the register array is indexed statically
+      if (j0 + jj < MPT && m < NN)
 #pragma unroll
-      for (int l = 0; l < NF; ++l) {
-        const int il = side ? l : NF - 1 - l;
-        acc = acc + sg[(ik * NF + il) * NN + m] * in[l];
+        for (int kk = 0; kk < NF; ++kk)
+#pragma unroll
+          for (int l = 0; l < NF; ++l) {
+            const int ik = side ? kk : NF - 1 - kk, il = side ? l : NF - 1 - l;
+            sv[jj][kk * NF + l] = sg[(ik * NF + il) * NN + m];
+          }
+    }
+#pragma unroll
+    for (int jj = 0; jj < B3; ++jj) {
+      const int m = threadIdx.x + (j0 + jj) * BLK;
+      if (j0 + jj < MPT && m < NN) {
+        const int r = m / N, cc = m - r * N;
+        cplx<T> in[NF];
+#pragma unroll
+        for (int l = 0; l < NF; ++l) in[l] = sm[l][r][cc];
+#pragma unroll
+        for (int kk = 0; kk < NF; ++kk) {
+          cplx<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int l = 0; l < NF; ++l) acc = acc + sv[jj][kk * NF + l] * in[l];
+          sm[kk][r][cc] = inv * acc;
+        }
       }
-      sm[kk][r][cc] = inv * acc;
     }
   }
   __syncthreads();
   rows_cols(+1);
   double s_re = 0, s_im = 0, s_n2 = 0;
-  for (int i = threadIdx.x; i < NF * NN; i += BLK) {
-    const int kk = i / NN, e = i - kk * NN;
-    const cplx<T> res = sm[kk][e / N][e % N];
-    if (rout) {
-      const cplx<T> val = y[off + i] + res;
-      rout[off + i] = cvt<TR>(val);
-      s_n2 += (double)val.re * val.re + (double)val.im * val.im;
-    } else {
-      y[off + i] = y[off + i] - res;
-      if (part) {
-        const cplx<T> c = x[off + i];
-        s_re -= (double)c.re * res.re - (double)c.im * res.im;
-        s_im -= (double)c.re * res.im + (double)c.im * res.re;
+#pragma unroll
+  for (int b0 = 0; b0 < EPT; b0 += B5) {
+    VT yv[B5], xv[B5];
+#pragma unroll
+    for (int e = 0; e < B5; ++e) {
+      const int vv = threadIdx.x + (b0 + e) * BLK;
+      if (b0 + e < EPT && vv < NV) {
+        yv[e] = reinterpret_cast<const VT*>(y + off)[vv];
+        if (part && !rout) xv[e] = reinterpret_cast<const VT*>(x + off)[vv];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < B5; ++e) {
+      const int vv = threadIdx.x + (b0 + e) * BLK;
+      if (b0 + e < EPT && vv < NV) {
+#pragma unroll
+        for (int kq = 0; kq < PE; ++kq) {
+          const cplx<T> res = at(vv * PE + kq);
+          const cplx<T> yc = Pair<T>::get(yv[e], kq);
+          if (rout) {
+            const cplx<T> val = yc + res;
+            rout[off + vv * PE + kq] = cvt<TR>(val);
+            s_n2 += (double)val.re * val.re + (double)val.im * val.im;
+          } else {
+            Pair<T>::set(yv[e], kq, yc - res);
+            if (part) {
+              const cplx<T> xc = Pair<T>::get(xv[e], kq);
+              s_re -= (double)xc.re * res.re - (double)xc.im * res.im;
+              s_im -= (double)xc.re * res.im + (double)xc.im * res.re;
+            }
+          }
+        }
+        if (!rout) reinterpret_cast<VT*>(y + off)[vv] = yv[e];
       }
     }
   }
@@ -698,9 +779,6 @@ __global__ void __launch_bounds__(256) k_fft_planes(FFTPlan2D plan, int nz, cons
 // global loads and stores move pairs of elements (16 bytes for complex64)
 // and every thread issues all of its loads before the first LDS store, so
 // that the few threads of a block keep many requests in flight.
-template <typename T> struct Pair;
-template <> struct Pair<float> { typedef float4 type; static constexpr int n = 2; };
-template <> struct Pair<double> { typedef double2 type; static constexpr int n = 1; };
 
 // With mvec and dpart set (the inverse transform of the preconditioner),
 // the block also writes, per plane, the partial of the bilinear form
