@@ -29,7 +29,10 @@
 
 // launchers from ops.hip
 hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs,
-                      int side, const ModeData* modes, zd* b);
+                      int side, const ModeData* modes, zd* b, bool faces_only);
+hipError_t launch_face_norm2(iobm_ctx c, const zd* b, int nact, const int* active, Partial* part);
+template <typename T>
+hipError_t launch_init_rd(iobm_ctx c, const zd* b, cplx<T>* r, cplx<T>* d, int nact, const int* active);
 int dot_blocks(iobm_ctx c);
 template <typename T>
 hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active, void* part);
@@ -403,8 +406,10 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   HIPCHK(hipMemsetAsync(flag, 0, nb * sizeof(int), ctx->stream));
   HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   HIPCHK(hipMemsetAsync(part_rn, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
-  HIPCHK(launch_dot<double>(ctx, b, b, nb, all_d, part));
-  HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, nb, all_d));
+  // b vanishes between the 2 nf face planes (the solver's right-hand sides
+  // are read there only)
+  HIPCHK(launch_face_norm2(ctx, b, nb, all_d, part));
+  HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, 1, nullptr, 0, FIN_NORM, nb, all_d));
   read_tn2(bn2);
   std::vector<int> act;
   for (int i = 0; i < nb; ++i)
@@ -416,8 +421,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   if (act.empty()) return;
   int nact = (int)act.size();
   int* act_d = upload(ctx, S_IDX, act, 64 * 1024);
-  HIPCHK((launch_convert<T, double>(ctx, b, r, nact, act_d)));
-  HIPCHK((launch_convert<T, double>(ctx, nullptr, d, nact, act_d)));
+  HIPCHK(launch_init_rd<T>(ctx, b, r, d, nact, act_d));
   if (!(lowp ? ctx->tuned_c64 : ctx->tuned_c128)) {
     // the shapes are timed on the fused operator with p_old = 0 and a
     // nonzero beta (0x3F bytes: 4.8e-4), so that every stream is read
@@ -1026,7 +1030,7 @@ iobm_status iobm_rhs(iobm_ctx ctx, double E, int32_t n, const int32_t* ids, int3
     int* e_d = upload(ctx, S_IDX, e, 0);
     int* m_d = upload(ctx, S_IDX, m, 16 * 1024);
     int* k_d = upload(ctx, S_IDX, kind, 32 * 1024);
-    HIPCHK(launch_rhs(ctx, n, e_d, m_d, k_d, side, ctx->modes_d, (zd*)b));
+    HIPCHK(launch_rhs(ctx, n, e_d, m_d, k_d, side, ctx->modes_d, (zd*)b, false));
   } catch (Fail& f) {
     return f.s;
   }
@@ -1062,7 +1066,7 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
       int* e_d = upload(ctx, S_IDX, B.e, 0);
       int* m_d = upload(ctx, S_IDX, B.mode, 16 * 1024);
       int* k_d = upload(ctx, S_IDX, B.kind, 32 * 1024);
-      HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b));
+      HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b, true));
     }
     SolveOut so;
     solve_batch(ctx, o, B, b, x, so);
@@ -1174,7 +1178,7 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
       int* e_d = upload(ctx, S_IDX, B.e, 0);
       int* m_d = upload(ctx, S_IDX, B.mode, 16 * 1024);
       int* k_d = upload(ctx, S_IDX, B.kind, 32 * 1024);
-      HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b));
+      HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b, true));
     }
     SolveOut so;
     solve_batch(ctx, o, B, b, u, so);

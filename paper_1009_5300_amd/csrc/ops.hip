@@ -1215,9 +1215,11 @@ __device__ __forceinline__ double lateral_phase(int m, int nx, int ny, int p) {
   return 2.0 * M_PI * ((double)a / nx + (double)b / ny);
 }
 
+// With faces_only the planes between the two faces are not written (the
+// solver reads b on the 2 nf face planes only).
 __global__ void k_rhs(int nx, int ny, int nz, int nf, const int* __restrict__ e_rhs,
                       const int* __restrict__ mode_rhs, const int* __restrict__ kind_rhs,
-                      int side, const ModeData* __restrict__ modes, zd* __restrict__ b) {
+                      int side, const ModeData* __restrict__ modes, zd* __restrict__ b, int faces_only) {
   const int rhs = blockIdx.y;
   const int nxy = nx * ny;
   const long long vol = (long long)nxy * nz;
@@ -1225,8 +1227,11 @@ __global__ void k_rhs(int nx, int ny, int nz, int nf, const int* __restrict__ e_
   const int kind = kind_rhs[rhs];
   if (m < 0 || m >= nxy) return;  // ids are validated on the host
   const ModeData& md = modes[(long long)e_rhs[rhs] * nxy + m];
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < vol;
-       idx += (long long)gridDim.x * blockDim.x) {
+  const long long n = faces_only ? 2LL * nf * nxy : vol;
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x) {
+    long long idx = j;
+    if (faces_only && j >= (long long)nf * nxy) idx += (long long)(nz - 2 * nf) * nxy;  // the far face
     const int z = (int)(idx / nxy);
     const int p = (int)(idx - (long long)z * nxy);
     const int i = side ? nz - 1 - z : z;
@@ -1372,13 +1377,15 @@ __global__ void __launch_bounds__(256) k_finish2(Scal S, const Partial* __restri
 
 // y = b - y  (b nonzero only where the rhs kernel wrote it; stored in full)
 template <typename T>
-__global__ void k_residual(const zd* __restrict__ b, cplx<T>* __restrict__ y, long long vol,
-                           const int* __restrict__ active) {
+// y = b - y, with b read on the 2 nf face planes only (it vanishes between
+// them)
+__global__ void k_residual(const zd* __restrict__ b, cplx<T>* __restrict__ y, long long vol, long long lo,
+                           long long hi, const int* __restrict__ active) {
   const int rhs = rhs_of(active, blockIdx.y);
   const long long off = rhs * vol;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
        i += (long long)gridDim.x * blockDim.x) {
-    zd bv = b[off + i];
+    const zd bv = (i < lo || i >= hi) ? b[off + i] : mk(0.0, 0.0);
     cplx<T> yv = y[off + i];
     y[off + i] = mk<T>((T)bv.re - yv.re, (T)bv.im - yv.im);
   }
@@ -1940,12 +1947,69 @@ static dim3 vol_grid(long long vol, int nrhs) {
 }
 
 hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs,
-                      int side, const ModeData* modes, zd* b) {
-  long long vol = c->g.npts;
-  hipLaunchKernelGGL(k_rhs, vol_grid(vol, nrhs), dim3(256), 0, c->stream, c->g.nx, c->g.ny, c->g.nz, c->g.nf,
-                     e_rhs, mode_rhs, kind_rhs, side, modes, b);
+                      int side, const ModeData* modes, zd* b, bool faces_only) {
+  const bool fo = faces_only && c->g.nz >= 2 * c->g.nf;
+  const long long n = fo ? 2LL * c->g.nf * c->g.nxy : c->g.npts;
+  hipLaunchKernelGGL(k_rhs, vol_grid(n, nrhs), dim3(256), 0, c->stream, c->g.nx, c->g.ny, c->g.nz, c->g.nf,
+                     e_rhs, mode_rhs, kind_rhs, side, modes, b, fo ? 1 : 0);
   return hipGetLastError();
 }
+
+// |b|^2 per rhs over the 2 nf face planes (b vanishes between them), one
+// partial per rhs
+__global__ void __launch_bounds__(256) k_face_norm2(const zd* __restrict__ b, long long vol, int nxy, int nz, int nf,
+                                                    Partial* __restrict__ part, const int* __restrict__ active) {
+  const int rhs = rhs_of(active, blockIdx.x);
+  const zd* br = b + rhs * vol;
+  const long long n = 2LL * nf * nxy, far = (long long)(nz - 2 * nf) * nxy;
+  double s = 0, d0 = 0, d1 = 0;
+  for (long long j = threadIdx.x; j < n; j += blockDim.x) {
+    const zd v = br[j < (long long)nf * nxy ? j : j + far];
+    s += v.re * v.re + v.im * v.im;
+  }
+  block_reduce3(s, d0, d1);
+  if (threadIdx.x == 0) {
+    Partial P;
+    P.re = P.im = P.pad = 0;
+    P.n2 = s;
+    part[rhs] = P;
+  }
+}
+
+hipError_t launch_face_norm2(iobm_ctx c, const zd* b, int nact, const int* active, Partial* part) {
+  if (c->g.nz < 2 * c->g.nf) return hipErrorInvalidValue;
+  const int rec = prof_start(c, IOBM_K_DOT);
+  hipLaunchKernelGGL(k_face_norm2, dim3(nact), dim3(256), 0, c->stream, b, c->g.npts, c->g.nxy, c->g.nz, c->g.nf,
+                     part, active);
+  prof_stop(c, rec, (double)nact * 2 * c->g.nf * c->g.nxy * sizeof(zd));
+  return hipGetLastError();
+}
+
+// The start of an iteration from x = 0: r = b (b read on the face planes
+// only), d = 0.
+template <typename T>
+__global__ void __launch_bounds__(256) k_init_rd(const zd* __restrict__ b, cplx<T>* __restrict__ r,
+                                                 cplx<T>* __restrict__ d, long long vol, int nxy, int nz, int nf,
+                                                 const int* __restrict__ active) {
+  const int rhs = rhs_of(active, blockIdx.y);
+  const long long off = rhs * vol, lo = (long long)nf * nxy, hi = (long long)(nz - nf) * nxy;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
+       i += (long long)gridDim.x * blockDim.x) {
+    cplx<T> v = mk<T>(0, 0);
+    if (i < lo || i >= hi) v = mk<T>((T)b[off + i].re, (T)b[off + i].im);
+    r[off + i] = v;
+    d[off + i] = mk<T>(0, 0);
+  }
+}
+
+template <typename T>
+hipError_t launch_init_rd(iobm_ctx c, const zd* b, cplx<T>* r, cplx<T>* d, int nact, const int* active) {
+  hipLaunchKernelGGL(k_init_rd<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, b, r, d, c->g.npts,
+                     c->g.nxy, c->g.nz, c->g.nf, active);
+  return hipGetLastError();
+}
+template hipError_t launch_init_rd<float>(iobm_ctx, const zd*, zf*, zf*, int, const int*);
+template hipError_t launch_init_rd<double>(iobm_ctx, const zd*, zd*, zd*, int, const int*);
 
 int dot_blocks(iobm_ctx c) {
   long long vol = c->g.npts;
@@ -1989,7 +2053,8 @@ hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2,
 
 template <typename T>
 hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const int* active) {
-  hipLaunchKernelGGL(k_residual<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, b, y, c->g.npts,
+  const long long lo = (long long)c->g.nf * c->g.nxy, hi = (long long)(c->g.nz - c->g.nf) * c->g.nxy;
+  hipLaunchKernelGGL(k_residual<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, b, y, c->g.npts, lo, hi,
                      active);
   return hipGetLastError();
 }
