@@ -41,14 +41,15 @@ hipError_t launch_update_r(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* a
                            void* part);
 enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3 };
 hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const Partial* pa,
-                          int na, const Partial* pb, int nb, int mode, int nact, const int* active);
+                          int na, const Partial* pb, int nb, int mode, int nact, const int* active,
+                          int* xset = nullptr);
 template <typename T>
 hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const int* active);
 template <typename TD, typename TS>
 hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int nact, const int* active);
 template <typename T>
-hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, int nact,
-                             const int* active);
+hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, const int* xset,
+                             int nact, const int* active, int nfirst);
 template <typename TR>
 hipError_t launch_refresh(iobm_ctx c, const zd* x, const zd* b, zd* rface, cplx<TR>* r, int nrhs,
                           const double* E_rhs, const int* e_rhs, const ModeData* modes, const int* active,
@@ -343,13 +344,14 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   // per-rhs scalars; |r|^2 and the breakdown flags are adjacent so that one
   // copy brings both to the host at a convergence check
   const size_t nb8 = ((size_t)nb + 1) & ~(size_t)1;
-  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + sizeof(int)) + 64);
+  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + 2 * sizeof(int)) + 64);
   zd* rho = (zd*)sc;
   zd* alpha = rho + nb;
   zd* beta = alpha + nb;
   double* rn2 = (double*)(beta + nb);
   int* flag = (int*)(rn2 + nb);
   double* tn2 = (double*)(flag + nb8);
+  int* xset = (int*)(tn2 + nb8);  // 1 once a refinement has written x (x is not cleared up front)
   const size_t check_bytes = (size_t)nb * sizeof(double) + (size_t)nb * sizeof(int);
   char* rbh = (char*)pinned_readback(ctx, check_bytes + nb8 * sizeof(int) + (size_t)nb * sizeof(double) + 64);
   const double* rn2_h = (const double*)rbh;
@@ -387,22 +389,26 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   auto refresh = [&](const std::vector<int>& lst, int region) {
     int* ld = upload(ctx, S_IDX, lst, (size_t)region * 8192);
     const int n = (int)lst.size();
-    HIPCHK(launch_accumulate<T>(ctx, x, d, pold, alpha, n, ld));
+    int nfirst = 0;  // first refinement: x = d + alpha p, x not read
+    for (int i : lst) nfirst += out.refin[i] == 0;
+    HIPCHK(launch_accumulate<T>(ctx, x, d, pold, alpha, xset, n, ld, nfirst));
     if (ctx->kb.ncen == 0) {
       HIPCHK(launch_refresh<T>(ctx, x, b, rhi, r, n, E_d, e_d, modes, ld, part_rn));
-      HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part_rn, PQ_SLOTS, nullptr, 0, FIN_NORM, n, ld));
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part_rn, PQ_SLOTS, nullptr, 0, FIN_NORM, n, ld,
+                            xset));
     } else {
       HIPCHK(launch_apply<double>(ctx, x, rhi, n, E_d, e_d, modes, ld));
       HIPCHK(launch_residual<double>(ctx, b, rhi, n, ld));
       HIPCHK(launch_dot<double>(ctx, rhi, rhi, n, ld, part));
-      HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld));
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld, xset));
       HIPCHK((launch_convert<T, double>(ctx, rhi, r, n, ld)));
     }
     read_tn2(tn2_h);
   };
 
-  // start: x = 0, r_hi = b, d = 0, r = r_hi, z = P r, rho = r^T z, beta = 0
-  HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * vol * sizeof(zd), ctx->stream));
+  // start: x = 0 (written by the first refinement), d = 0, r = b, z = P r,
+  // rho = r^T z, beta = 0
+  HIPCHK(hipMemsetAsync(xset, 0, nb * sizeof(int), ctx->stream));
   HIPCHK(hipMemsetAsync(flag, 0, nb * sizeof(int), ctx->stream));
   HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   HIPCHK(hipMemsetAsync(part_rn, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
@@ -411,9 +417,12 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   HIPCHK(launch_face_norm2(ctx, b, nb, all_d, part));
   HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, 1, nullptr, 0, FIN_NORM, nb, all_d));
   read_tn2(bn2);
-  std::vector<int> act;
+  std::vector<int> act, zero;
   for (int i = 0; i < nb; ++i)
-    if (bn2[i] > 0) act.push_back(i);
+    (bn2[i] > 0 ? act : zero).push_back(i);
+  // x = 0 for b = 0; every other rhs gets x from its first refinement
+  if (!zero.empty()) HIPCHK((launch_convert<double, double>(ctx, nullptr, x, (int)zero.size(),
+                                                             upload(ctx, S_IDX, zero, 48 * 1024))));
   std::vector<double> maxr2(nb), best(nb), last(nb);
   std::vector<int> stall(nb, 0);
   for (int i = 0; i < nb; ++i) maxr2[i] = best[i] = last[i] = bn2[i];

@@ -1311,6 +1311,7 @@ struct Scal {
   zd* beta;
   double* rn2;   // |r|^2 after the update
   int* flag;     // breakdown flags
+  int* xset;     // FIN_NORM after a refinement: marks x as written (or nullptr)
 };
 
 // Scalar steps of the fused iteration, one wavefront per active rhs: the
@@ -1367,6 +1368,7 @@ __global__ void __launch_bounds__(256) k_finish2(Scal S, const Partial* __restri
     S.rn2[rhs] = n2;
   } else if (mode == FIN_NORM) {
     S.rn2[rhs] = n2;
+    if (S.xset) S.xset[rhs] = 1;
   } else {  // FIN_RESTART: p_new = z next, with no pending solution update
     S.rho[rhs] = mk(re, im);
     S.alpha[rhs] = mk(0.0, 0.0);
@@ -1402,17 +1404,20 @@ __global__ void k_convert(const cplx<TS>* __restrict__ src, cplx<TD>* __restrict
     dst[off + i] = src ? mk<TD>((TD)src[off + i].re, (TD)src[off + i].im) : mk<TD>(0, 0);
 }
 
-// x (complex128) += d (complex64 or complex128), then d = 0
+// x (complex128) += d + alpha p (complex64 or complex128), then d = 0; x is
+// not read where xset[rhs] = 0 (its first refinement: x = d + alpha p)
 template <typename T>
 __global__ void k_accumulate(zd* __restrict__ x, cplx<T>* __restrict__ d, const cplx<T>* __restrict__ p,
-                             const zd* __restrict__ alpha, long long vol, const int* __restrict__ active) {
+                             const zd* __restrict__ alpha, const int* __restrict__ xset, long long vol,
+                             const int* __restrict__ active) {
   const int rhs = rhs_of(active, blockIdx.y);
   const long long off = rhs * vol;
   const cplx<T> a = cvt<T>(alpha[rhs]);
   const bool pend = a.re != (T)0 || a.im != (T)0;
+  const bool have_x = xset[rhs] != 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
        i += (long long)gridDim.x * blockDim.x) {
-    zd xv = x[off + i];
+    const zd xv = have_x ? x[off + i] : mk(0.0, 0.0);
     cplx<T> dv = d[off + i];
     if (pend) dv = dv + a * p[off + i];
     x[off + i] = mk(xv.re + (double)dv.re, xv.im + (double)dv.im);
@@ -2042,10 +2047,10 @@ hipError_t launch_update_r(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* a
 }
 
 hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const Partial* pa,
-                          int na, const Partial* pb, int nb, int mode, int nact, const int* active) {
+                          int na, const Partial* pb, int nb, int mode, int nact, const int* active, int* xset) {
   if (nact <= 0) return hipSuccess;
   Scal S;
-  S.rho = rho; S.alpha = alpha; S.beta = beta; S.rn2 = rn2; S.flag = flag;
+  S.rho = rho; S.alpha = alpha; S.beta = beta; S.rn2 = rn2; S.flag = flag; S.xset = xset;
   hipLaunchKernelGGL(k_finish2, dim3((nact + 3) / 4), dim3(256), 0, c->stream, S, pa, na, pb, nb, mode, active,
                      nact);
   return hipGetLastError();
@@ -2067,13 +2072,14 @@ hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int na
 }
 
 template <typename T>
-hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, int nact,
-                             const int* active) {
+hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, const int* xset,
+                             int nact, const int* active, int nfirst) {
   const int rec = prof_start(c, IOBM_K_ACCUMULATE);
-  hipLaunchKernelGGL(k_accumulate<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, x, d, p, alpha,
+  hipLaunchKernelGGL(k_accumulate<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, x, d, p, alpha, xset,
                      c->g.npts, active);
-  // read x, d, p; write x, d
-  prof_stop(c, rec, nact * c->g.npts * (2.0 * sizeof(zd) + 3.0 * sizeof(cplx<T>)));
+  // read x (not at the first refinement of the nfirst rhs), d, p; write x, d
+  prof_stop(c, rec, c->g.npts * ((double)nact * (sizeof(zd) + 3.0 * sizeof(cplx<T>)) +
+                                 (double)(nact - nfirst) * sizeof(zd)));
   return hipGetLastError();
 }
 
@@ -2112,8 +2118,10 @@ template hipError_t launch_residual<float>(iobm_ctx, const zd*, zf*, int, const 
 template hipError_t launch_convert<float, double>(iobm_ctx, const zd*, zf*, int, const int*);
 template hipError_t launch_convert<double, double>(iobm_ctx, const zd*, zd*, int, const int*);
 template hipError_t launch_convert<float, float>(iobm_ctx, const zf*, zf*, int, const int*);
-template hipError_t launch_accumulate<float>(iobm_ctx, zd*, zf*, const zf*, const zd*, int, const int*);
-template hipError_t launch_accumulate<double>(iobm_ctx, zd*, zd*, const zd*, const zd*, int, const int*);
+template hipError_t launch_accumulate<float>(iobm_ctx, zd*, zf*, const zf*, const zd*, const int*, int, const int*,
+                                            int);
+template hipError_t launch_accumulate<double>(iobm_ctx, zd*, zd*, const zd*, const zd*, const int*, int,
+                                             const int*, int);
 template hipError_t launch_combine_psi<double>(iobm_ctx, int, const zd*, zd*, const int*, const int*,
                                                const int*);
 template hipError_t launch_combine_psi<float>(iobm_ctx, int, const zd*, zf*, const int*, const int*,

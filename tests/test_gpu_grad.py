@@ -68,11 +68,18 @@ def test_autograd_function(torch):
     V = torch.tensor(w.V, dtype=torch.float64, device="cuda", requires_grad=True)
     T = transmission(V, s, [0.35])
     (2.0 * T).backward()
+    # the same context (same tuned launch shapes, so the same summation
+    # order): the wrapper returns exactly what the library computes
+    T1, g1 = s.grad_transmission([0.35])
+    assert abs(T.item() - T1) < 1e-12
+    assert torch.allclose(V.grad, 2.0 * g1, rtol=0, atol=1e-12 * float(g1.abs().max()))
+    # a fresh context tunes its launch shapes anew; its solves agree to the
+    # solver tolerance (residual 1e-10)
     s2 = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
     s2.set_potential(w.V)
     T2, g2 = s2.grad_transmission([0.35])
-    assert abs(T.item() - T2) < 1e-12
-    assert torch.allclose(V.grad, 2.0 * g2, rtol=0, atol=1e-12 * float(g2.abs().max()))
+    assert abs(T.item() - T2) < 1e-9
+    assert torch.allclose(V.grad, 2.0 * g2, rtol=0, atol=1e-8 * float(g2.abs().max()))
 
 
 def test_gradient_at_full_adjoint_workload(torch):
