@@ -32,7 +32,7 @@ hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rh
                       int side, const ModeData* modes, zd* b, bool faces_only);
 hipError_t launch_face_norm2(iobm_ctx c, const zd* b, int nact, const int* active, Partial* part);
 template <typename T>
-hipError_t launch_init_rd(iobm_ctx c, const zd* b, cplx<T>* r, cplx<T>* d, int nact, const int* active);
+hipError_t launch_init_r(iobm_ctx c, const zd* b, cplx<T>* r, int nact, const int* active);
 int dot_blocks(iobm_ctx c);
 template <typename T>
 hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active, void* part);
@@ -42,14 +42,14 @@ hipError_t launch_update_r(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* a
 enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3 };
 hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const Partial* pa,
                           int na, const Partial* pb, int nb, int mode, int nact, const int* active,
-                          int* xset = nullptr);
+                          int* xset = nullptr, int* dlive = nullptr);
 template <typename T>
 hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const int* active);
 template <typename TD, typename TS>
 hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int nact, const int* active);
 template <typename T>
-hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, const int* xset,
-                             int nact, const int* active, int nfirst);
+hipError_t launch_accumulate(iobm_ctx c, zd* x, const cplx<T>* d, const cplx<T>* p, const zd* alpha,
+                             const int* xset, const int* dlive, int nact, const int* active, int nfirst, int ndead);
 template <typename TR>
 hipError_t launch_refresh(iobm_ctx c, const zd* x, const zd* b, zd* rface, cplx<TR>* r, int nrhs,
                           const double* E_rhs, const int* e_rhs, const ModeData* modes, const int* active,
@@ -344,7 +344,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   // per-rhs scalars; |r|^2 and the breakdown flags are adjacent so that one
   // copy brings both to the host at a convergence check
   const size_t nb8 = ((size_t)nb + 1) & ~(size_t)1;
-  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + 2 * sizeof(int)) + 64);
+  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + 3 * sizeof(int)) + 64);
   zd* rho = (zd*)sc;
   zd* alpha = rho + nb;
   zd* beta = alpha + nb;
@@ -352,6 +352,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   int* flag = (int*)(rn2 + nb);
   double* tn2 = (double*)(flag + nb8);
   int* xset = (int*)(tn2 + nb8);  // 1 once a refinement has written x (x is not cleared up front)
+  int* dlive = xset + nb8;        // 1 while d holds steps not yet folded into x
   const size_t check_bytes = (size_t)nb * sizeof(double) + (size_t)nb * sizeof(int);
   char* rbh = (char*)pinned_readback(ctx, check_bytes + nb8 * sizeof(int) + (size_t)nb * sizeof(double) + 64);
   const double* rn2_h = (const double*)rbh;
@@ -374,6 +375,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     else
       HIPCHK(launch_dot<T>(ctx, r, r, nact, ad, part_rz));
   };
+  std::vector<int> since(nb, 0);  // steps since the last restart, per rhs (d holds data from 2 on)
   cplx<T>* pold = pa;  // the direction of the last step (its update pending)
   cplx<T>* pnew = pb;
   // Refinement of the listed rhs: x += d + alpha p, d = 0, r = b - A x in FP64 (stored
@@ -389,18 +391,19 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   auto refresh = [&](const std::vector<int>& lst, int region) {
     int* ld = upload(ctx, S_IDX, lst, (size_t)region * 8192);
     const int n = (int)lst.size();
-    int nfirst = 0;  // first refinement: x = d + alpha p, x not read
-    for (int i : lst) nfirst += out.refin[i] == 0;
-    HIPCHK(launch_accumulate<T>(ctx, x, d, pold, alpha, xset, n, ld, nfirst));
+    int nfirst = 0, ndead = 0;  // x not read (first refinement), d not read (no step since the last)
+    for (int i : lst) { nfirst += out.refin[i] == 0; ndead += since[i] < 2; }
+    HIPCHK(launch_accumulate<T>(ctx, x, d, pold, alpha, xset, dlive, n, ld, nfirst, ndead));
     if (ctx->kb.ncen == 0) {
       HIPCHK(launch_refresh<T>(ctx, x, b, rhi, r, n, E_d, e_d, modes, ld, part_rn));
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part_rn, PQ_SLOTS, nullptr, 0, FIN_NORM, n, ld,
-                            xset));
+                            xset, dlive));
     } else {
       HIPCHK(launch_apply<double>(ctx, x, rhi, n, E_d, e_d, modes, ld));
       HIPCHK(launch_residual<double>(ctx, b, rhi, n, ld));
       HIPCHK(launch_dot<double>(ctx, rhi, rhi, n, ld, part));
-      HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld, xset));
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld, xset,
+                            dlive));
       HIPCHK((launch_convert<T, double>(ctx, rhi, r, n, ld)));
     }
     read_tn2(tn2_h);
@@ -408,7 +411,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
 
   // start: x = 0 (written by the first refinement), d = 0, r = b, z = P r,
   // rho = r^T z, beta = 0
-  HIPCHK(hipMemsetAsync(xset, 0, nb * sizeof(int), ctx->stream));
+  HIPCHK(hipMemsetAsync(xset, 0, 2 * nb8 * sizeof(int), ctx->stream));  // xset and dlive
   HIPCHK(hipMemsetAsync(flag, 0, nb * sizeof(int), ctx->stream));
   HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   HIPCHK(hipMemsetAsync(part_rn, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
@@ -430,14 +433,14 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   if (act.empty()) return;
   int nact = (int)act.size();
   int* act_d = upload(ctx, S_IDX, act, 64 * 1024);
-  HIPCHK(launch_init_rd<T>(ctx, b, r, d, nact, act_d));
+  HIPCHK(launch_init_r<T>(ctx, b, r, nact, act_d));
   if (!(lowp ? ctx->tuned_c64 : ctx->tuned_c128)) {
     // the shapes are timed on the fused operator with p_old = 0 and a
     // nonzero beta (0x3F bytes: 4.8e-4), so that every stream is read
     HIPCHK(hipMemsetAsync(pa, 0, vb, ctx->stream));
     HIPCHK(hipMemsetAsync(beta, 0x3F, nb * sizeof(zd), ctx->stream));
     HIPCHK(hipMemsetAsync(alpha, 0x3F, nb * sizeof(zd), ctx->stream));  // d += alpha * 0 leaves d = 0
-    ApplyFuse<T> TF{r, pa, beta, pb, part_pq, alpha, d};
+    ApplyFuse<T> TF{r, pa, beta, pb, part_pq, alpha, d, dlive};
     autotune<T>(ctx, r, q, pf, nact, E_d, e_d, modes, act_d, &TF);
     HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   }
@@ -451,12 +454,15 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   //              R = FFT(r) from FFT(q))
   //   precond:   z = P r, partials of r^T z
   // with the scalar steps (alpha; beta, rho, |r|^2) in between.
-  int nfresh = nact;  // active rhs whose next step starts from a restart (byte count only)
   while (nact > 0) {
     for (int k = 0; k < check; ++k) {
-      ApplyFuse<T> F{z, pold, beta, pnew, part_pq, alpha, d, k == 0 ? nfresh : 0};
+      int nfresh = 0, nfirstd = 0;  // byte count only: steps since the restart 0 and 1
+      for (int i : act) { nfresh += since[i] == 0; nfirstd += since[i] == 1; }
+      ApplyFuse<T> F{z, pold, beta, pnew, part_pq, alpha, d, dlive, nfresh, nfirstd};
       HIPCHK(launch_apply<T>(ctx, nullptr, q, nact, E_d, e_d, modes, act_d, &F));
-      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_pq, PQ_SLOTS, nullptr, 0, FIN_ALPHA, nact, act_d));
+      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_pq, PQ_SLOTS, nullptr, 0, FIN_ALPHA, nact, act_d,
+                            nullptr, dlive));
+      for (int i : act) ++since[i];
       if (fuse_upd) {
         FftUpd<T> U;
         U.q = q; U.alpha = alpha; U.n2part = part_n2;
@@ -480,7 +486,6 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       if (bad || r2 <= 0.25 * tol2 * bn2[i] || r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter) upd.push_back(i);
       else maxr2[i] = std::max(maxr2[i], r2);
     }
-    nfresh = 0;
     if (upd.empty()) continue;
     refresh(upd, 7);
     std::vector<int> cont;  // updated rhs that go on iterating, from a restart
@@ -513,7 +518,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     act.assign(lists.begin() + nc, lists.end());
     nact = (int)act.size();
     act_d = ld + nc;  // the old list's region was rewritten
-    nfresh = nc;  // every restarted rhs stays active
+    for (int i : cont) since[i] = 0;
   }
   for (int i = 0; i < nb; ++i) {
     out.rel[i] = bn2[i] > 0 ? sqrt(tn2_h[i] / bn2[i]) : 0.0;

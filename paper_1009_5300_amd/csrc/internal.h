@@ -137,9 +137,11 @@ enum { PQ_STENCIL_MAX = 64, PQ_BOUNDARY = 64, PQ_KB = 66, PQ_SLOTS = 68 };
 // Fused COCG direction update for launch_apply: the operand is
 // pnew = z + beta p_old (beta per rhs; p_old is not read where beta = 0),
 // written to pnew, and the partials of pnew^T (A pnew) go to part.  With
-// alpha and d set, the previous step's update d += alpha p_old is applied on
-// the way (per rhs; none where alpha = 0).  nfresh: how many of the rhs
-// restart here (beta = alpha = 0), for the byte count of the timing hook.
+// alpha, d and dlive set, the previous step's update d += alpha p_old is
+// applied on the way (per rhs; none where alpha = 0; d is not read where
+// dlive = 0, the first step after a refinement).  For the byte count of the
+// timing hook: nfresh of the rhs restart here (beta = alpha = 0), nfirstd
+// make their first d update.
 template <typename T>
 struct ApplyFuse {
   const cplx<T>* z;
@@ -149,7 +151,9 @@ struct ApplyFuse {
   Partial* part;  // [rhs][PQ_SLOTS]
   const zd* alpha = nullptr;
   cplx<T>* d = nullptr;
+  const int* dlive = nullptr;
   int nfresh = 0;
+  int nfirstd = 0;
 };
 
 template <typename T>

@@ -142,23 +142,25 @@ struct OpFuseP {
   Partial* part;
   const zd* alpha;  // pending alpha per rhs, or nullptr
   cplx<T>* d;
+  const int* dlive;  // per rhs: d holds data (else it counts as zero and is not read)
   const cplx<T>* psrc;
   const cplx<T>* dsrc;
   cplx<T> bt, at;
-  bool use_b, use_p, use_d;
+  bool use_b, use_p, use_d, live;
   double s_re, s_im;
   __device__ __forceinline__ void bind(int rhs, long long vol) {
     z += rhs * vol; pold += rhs * vol; pnew += rhs * vol; y += rhs * vol;
     bt = cvt<T>(beta[rhs]);
     at = alpha ? cvt<T>(alpha[rhs]) : mk<T>(0, 0);
-    use_d = at.re != (T)0 || at.im != (T)0;
+    use_d = alpha && (alpha[rhs].re != 0 || alpha[rhs].im != 0);
+    live = use_d && dlive[rhs] != 0;
     if (use_d) d += rhs * vol;
     use_b = bt.re != (T)0 || bt.im != (T)0;
     use_p = use_b || use_d;
     // where a stream is not needed its loads read z again: cache hits, not
     // another stream
     psrc = use_p ? pold : z;
-    dsrc = use_d ? d : z;
+    dsrc = live ? d : z;
     s_re = s_im = 0;
   }
   __device__ __forceinline__ cplx<T> load(long long o) const {
@@ -178,13 +180,13 @@ struct OpFuseP {
   }
   // a plane entering the window: the pending update of the block's own points
   __device__ __forceinline__ void side(const Raw& r, long long o, bool own) {
-    if (use_d && own) d[o] = r.d + at * r.p;
+    if (use_d && own) d[o] = live ? r.d + at * r.p : at * r.p;
   }
   __device__ __forceinline__ void center(long long o, cplx<T> v) { pnew[o] = v; }
   // the cache-based kernel: the same at the centre point
   __device__ __forceinline__ void center_at(long long o, cplx<T> v) {
     pnew[o] = v;
-    if (use_d) d[o] = d[o] + at * pold[o];
+    if (use_d) d[o] = live ? d[o] + at * pold[o] : at * pold[o];
   }
   __device__ __forceinline__ void store(int, long long o, cplx<T> c, cplx<T> acc) {
     y[o] = acc;
@@ -1312,6 +1314,9 @@ struct Scal {
   double* rn2;   // |r|^2 after the update
   int* flag;     // breakdown flags
   int* xset;     // FIN_NORM after a refinement: marks x as written (or nullptr)
+  int* dlive;    // d holds data: set by FIN_ALPHA once the operator has applied a
+                 // pending step (the old alpha was nonzero), cleared by FIN_NORM
+                 // after a refinement has folded d into x (or nullptr)
 };
 
 // Scalar steps of the fused iteration, one wavefront per active rhs: the
@@ -1348,6 +1353,7 @@ __global__ void __launch_bounds__(256) k_finish2(Scal S, const Partial* __restri
   if (lane != 0) return;
   if (mode == FIN_ALPHA) {
     const zd rho = S.rho[rhs];
+    if (S.dlive && (S.alpha[rhs].re != 0 || S.alpha[rhs].im != 0)) S.dlive[rhs] = 1;
     const double d = re * re + im * im;
     if (!(d > 0) || !isfinite(d)) {
       S.alpha[rhs] = mk(0.0, 0.0);
@@ -1369,6 +1375,7 @@ __global__ void __launch_bounds__(256) k_finish2(Scal S, const Partial* __restri
   } else if (mode == FIN_NORM) {
     S.rn2[rhs] = n2;
     if (S.xset) S.xset[rhs] = 1;
+    if (S.dlive) S.dlive[rhs] = 0;
   } else {  // FIN_RESTART: p_new = z next, with no pending solution update
     S.rho[rhs] = mk(re, im);
     S.alpha[rhs] = mk(0.0, 0.0);
@@ -1404,24 +1411,25 @@ __global__ void k_convert(const cplx<TS>* __restrict__ src, cplx<TD>* __restrict
     dst[off + i] = src ? mk<TD>((TD)src[off + i].re, (TD)src[off + i].im) : mk<TD>(0, 0);
 }
 
-// x (complex128) += d + alpha p (complex64 or complex128), then d = 0; x is
-// not read where xset[rhs] = 0 (its first refinement: x = d + alpha p)
+// x (complex128) += d + alpha p (complex64 or complex128).  x is not read
+// where xset[rhs] = 0 (its first refinement), d not where dlive[rhs] = 0
+// (no step applied since the last refinement); d is left as it is, and the
+// refinement's norm step marks it dead.
 template <typename T>
-__global__ void k_accumulate(zd* __restrict__ x, cplx<T>* __restrict__ d, const cplx<T>* __restrict__ p,
-                             const zd* __restrict__ alpha, const int* __restrict__ xset, long long vol,
-                             const int* __restrict__ active) {
+__global__ void k_accumulate(zd* __restrict__ x, const cplx<T>* __restrict__ d, const cplx<T>* __restrict__ p,
+                             const zd* __restrict__ alpha, const int* __restrict__ xset,
+                             const int* __restrict__ dlive, long long vol, const int* __restrict__ active) {
   const int rhs = rhs_of(active, blockIdx.y);
   const long long off = rhs * vol;
   const cplx<T> a = cvt<T>(alpha[rhs]);
   const bool pend = a.re != (T)0 || a.im != (T)0;
-  const bool have_x = xset[rhs] != 0;
+  const bool have_x = xset[rhs] != 0, have_d = dlive[rhs] != 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
        i += (long long)gridDim.x * blockDim.x) {
     const zd xv = have_x ? x[off + i] : mk(0.0, 0.0);
-    cplx<T> dv = d[off + i];
+    cplx<T> dv = have_d ? d[off + i] : mk<T>(0, 0);
     if (pend) dv = dv + a * p[off + i];
     x[off + i] = mk(xv.re + (double)dv.re, xv.im + (double)dv.im);
-    d[off + i] = mk<T>(0, 0);
   }
 }
 
@@ -1698,12 +1706,14 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
   hipError_t err;
   Partial* part = nullptr;
   if (fuse) {
-    OpFuseP<T> op{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part, fuse->alpha, fuse->d};
+    OpFuseP<T> op{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part, fuse->alpha, fuse->d, fuse->dlive};
     // streams: read z, p_old (and d); write p_new, y (and d); the nfresh
-    // restarted rhs read z only
+    // restarted rhs read z only, the nfirst rhs after them do not read d
     const int nf = std::min(std::max(fuse->nfresh, 0), nrhs);
+    const int n1 = fuse->alpha ? std::min(std::max(fuse->nfirstd, 0), nrhs - nf) : 0;
     const double full = fuse->alpha ? 6.0 : 4.0;
-    err = launch_stencil<T>(c, op, nrhs, E_rhs, active, (full * (nrhs - nf) + 3.0 * nf) / nrhs * sizeof(cplx<T>));
+    err = launch_stencil<T>(c, op, nrhs, E_rhs, active,
+                            (full * (nrhs - nf - n1) + 5.0 * n1 + 3.0 * nf) / nrhs * sizeof(cplx<T>));
     x = fuse->pnew;  // the electrode and nonlocal terms read the assembled operand
     part = fuse->part;
   } else {
@@ -1896,7 +1906,7 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
           if (fuse)
             launch_apply25_shape<T>(c, ppt, zc,
                                     OpFuseP<T>{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part,
-                                               fuse->alpha, fuse->d},
+                                               fuse->alpha, fuse->d, fuse->dlive},
                                     nrhs, E_rhs, active);
           else
             launch_apply25_shape<T>(c, ppt, zc, OpPlain<T>{x, y}, nrhs, E_rhs, active);
@@ -1991,11 +2001,10 @@ hipError_t launch_face_norm2(iobm_ctx c, const zd* b, int nact, const int* activ
 }
 
 // The start of an iteration from x = 0: r = b (b read on the face planes
-// only), d = 0.
+// only).
 template <typename T>
-__global__ void __launch_bounds__(256) k_init_rd(const zd* __restrict__ b, cplx<T>* __restrict__ r,
-                                                 cplx<T>* __restrict__ d, long long vol, int nxy, int nz, int nf,
-                                                 const int* __restrict__ active) {
+__global__ void __launch_bounds__(256) k_init_r(const zd* __restrict__ b, cplx<T>* __restrict__ r, long long vol,
+                                                int nxy, int nz, int nf, const int* __restrict__ active) {
   const int rhs = rhs_of(active, blockIdx.y);
   const long long off = rhs * vol, lo = (long long)nf * nxy, hi = (long long)(nz - nf) * nxy;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < vol;
@@ -2003,18 +2012,17 @@ __global__ void __launch_bounds__(256) k_init_rd(const zd* __restrict__ b, cplx<
     cplx<T> v = mk<T>(0, 0);
     if (i < lo || i >= hi) v = mk<T>((T)b[off + i].re, (T)b[off + i].im);
     r[off + i] = v;
-    d[off + i] = mk<T>(0, 0);
   }
 }
 
 template <typename T>
-hipError_t launch_init_rd(iobm_ctx c, const zd* b, cplx<T>* r, cplx<T>* d, int nact, const int* active) {
-  hipLaunchKernelGGL(k_init_rd<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, b, r, d, c->g.npts,
-                     c->g.nxy, c->g.nz, c->g.nf, active);
+hipError_t launch_init_r(iobm_ctx c, const zd* b, cplx<T>* r, int nact, const int* active) {
+  hipLaunchKernelGGL(k_init_r<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, b, r, c->g.npts, c->g.nxy,
+                     c->g.nz, c->g.nf, active);
   return hipGetLastError();
 }
-template hipError_t launch_init_rd<float>(iobm_ctx, const zd*, zf*, zf*, int, const int*);
-template hipError_t launch_init_rd<double>(iobm_ctx, const zd*, zd*, zd*, int, const int*);
+template hipError_t launch_init_r<float>(iobm_ctx, const zd*, zf*, int, const int*);
+template hipError_t launch_init_r<double>(iobm_ctx, const zd*, zd*, int, const int*);
 
 int dot_blocks(iobm_ctx c) {
   long long vol = c->g.npts;
@@ -2047,10 +2055,11 @@ hipError_t launch_update_r(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* a
 }
 
 hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const Partial* pa,
-                          int na, const Partial* pb, int nb, int mode, int nact, const int* active, int* xset) {
+                          int na, const Partial* pb, int nb, int mode, int nact, const int* active, int* xset,
+                          int* dlive) {
   if (nact <= 0) return hipSuccess;
   Scal S;
-  S.rho = rho; S.alpha = alpha; S.beta = beta; S.rn2 = rn2; S.flag = flag; S.xset = xset;
+  S.rho = rho; S.alpha = alpha; S.beta = beta; S.rn2 = rn2; S.flag = flag; S.xset = xset; S.dlive = dlive;
   hipLaunchKernelGGL(k_finish2, dim3((nact + 3) / 4), dim3(256), 0, c->stream, S, pa, na, pb, nb, mode, active,
                      nact);
   return hipGetLastError();
@@ -2072,14 +2081,15 @@ hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int na
 }
 
 template <typename T>
-hipError_t launch_accumulate(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, const int* xset,
-                             int nact, const int* active, int nfirst) {
+hipError_t launch_accumulate(iobm_ctx c, zd* x, const cplx<T>* d, const cplx<T>* p, const zd* alpha,
+                             const int* xset, const int* dlive, int nact, const int* active, int nfirst, int ndead) {
   const int rec = prof_start(c, IOBM_K_ACCUMULATE);
   hipLaunchKernelGGL(k_accumulate<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, x, d, p, alpha, xset,
-                     c->g.npts, active);
-  // read x (not at the first refinement of the nfirst rhs), d, p; write x, d
-  prof_stop(c, rec, c->g.npts * ((double)nact * (sizeof(zd) + 3.0 * sizeof(cplx<T>)) +
-                                 (double)(nact - nfirst) * sizeof(zd)));
+                     dlive, c->g.npts, active);
+  // read x (not at the first refinement of the nfirst rhs), d (not for the
+  // ndead rhs), p; write x
+  prof_stop(c, rec, c->g.npts * ((double)nact * (sizeof(zd) + sizeof(cplx<T>)) + (double)(nact - nfirst) * sizeof(zd) +
+                                 (double)(nact - ndead) * sizeof(cplx<T>)));
   return hipGetLastError();
 }
 
@@ -2118,10 +2128,10 @@ template hipError_t launch_residual<float>(iobm_ctx, const zd*, zf*, int, const 
 template hipError_t launch_convert<float, double>(iobm_ctx, const zd*, zf*, int, const int*);
 template hipError_t launch_convert<double, double>(iobm_ctx, const zd*, zd*, int, const int*);
 template hipError_t launch_convert<float, float>(iobm_ctx, const zf*, zf*, int, const int*);
-template hipError_t launch_accumulate<float>(iobm_ctx, zd*, zf*, const zf*, const zd*, const int*, int, const int*,
-                                            int);
-template hipError_t launch_accumulate<double>(iobm_ctx, zd*, zd*, const zd*, const zd*, const int*, int,
-                                             const int*, int);
+template hipError_t launch_accumulate<float>(iobm_ctx, zd*, const zf*, const zf*, const zd*, const int*,
+                                            const int*, int, const int*, int, int);
+template hipError_t launch_accumulate<double>(iobm_ctx, zd*, const zd*, const zd*, const zd*, const int*,
+                                             const int*, int, const int*, int, int);
 template hipError_t launch_combine_psi<double>(iobm_ctx, int, const zd*, zd*, const int*, const int*,
                                                const int*);
 template hipError_t launch_combine_psi<float>(iobm_ctx, int, const zd*, zf*, const int*, const int*,
