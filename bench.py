@@ -182,6 +182,43 @@ def chain_workload(args):
     }), flush=True)
 
 
+def adjoint_workload(args):
+    """Workload 5 (32 x 32 x 96, h = 0.4, 4th-order FD, four wells, 4
+    energies, 28 scattering states): dT/dV by the adjoint method, i.e. the
+    forward solves, the readout, the adjoint solves and the gradient
+    contraction, per second."""
+    import numpy as np
+    import torch
+
+    from paper_1009_5300_amd import iobm
+    from workloads import make
+
+    torch.cuda.set_device(0)
+    w = make(5)
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s.set_potential(w.V)
+    T, grad = s.grad_transmission(w.energies)
+    for _ in range(args.warmup):
+        T, grad = s.grad_transmission(w.energies)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        T, grad = s.grad_transmission(w.energies)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nstates = sum(len(s.channels(E)[0]) for E in w.energies)
+    print(json.dumps({
+        "metric": "transmission gradients dT/dV per second (forward + adjoint solves)",
+        "value": round(args.steps / (t1 - t0), 3), "unit": "gradients/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * (t1 - t0) / args.steps, 3), "higher_is_better": True,
+        "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": "adjoint 32x32x96 h=0.4 4th-order FD, 4 wells, 4 energies",
+                   "forward_states": int(nstates), "adjoint_states": int(nstates)},
+        "T_total": float(T), "max_abs_grad": float(grad.abs().max()),
+    }), flush=True)
+
+
 def na_sweep(atoms=(3, 4, 5, 6, 7, 8)):
     """The paper's preconditioner experiment (Sec. III, Table 2) on the
     synthetic Na-like wires: average COCG iterations per incident wave at the
@@ -241,16 +278,19 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip plain-CG and Eq. (17) samples")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for the HBM counter calibration)")
-    ap.add_argument("--workload", default="4", choices=["3", "4", "na"],
+    ap.add_argument("--workload", default="4", choices=["3", "4", "5", "na"],
                     help="4: the headline wide-wire batch (default); 3: the atomic chain with the nonlocal "
-                         "term on MFMA (secondary measurement); na: iteration counts of the paper's "
-                         "preconditioner experiment on synthetic Na-like wires")
+                         "term on MFMA (secondary measurement); 5: the adjoint gradient dT/dV; na: iteration "
+                         "counts of the paper's preconditioner experiment on synthetic Na-like wires")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
     if args.gpus == 1 and args.workload == "3":
         chain_workload(args)
+        return
+    if args.gpus == 1 and args.workload == "5":
+        adjoint_workload(args)
         return
     if args.gpus == 1 and args.workload == "na":
         na_sweep()
