@@ -46,7 +46,8 @@
  *    tables and all solver workspaces; iobm_destroy frees them.
  *  - All device work is enqueued on the stream given to iobm_create (NULL =
  *    the null stream).  Calls that return host results synchronise that
- *    stream before returning; iobm_apply and iobm_precondition do not.
+ *    stream before returning (iobm_precondition when it returns r^T z);
+ *    iobm_apply and iobm_precondition otherwise do not.
  *  - A context is not thread-safe; separate contexts are independent.
  *
  * Errors
