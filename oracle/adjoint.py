@@ -9,7 +9,9 @@ consequence of its linear system (Eq. (6)):
   * T_mu = psi_B^H Gamma psi_B / J_mu, hence
     d T_mu / d V_i = 2 Re(lambda_i psi_i) with A^T lambda = conj(Gamma psi_B) / J_mu
     (adjoint vector placed on the far boundary planes);
-  * the transposed solve reuses the LU factors (trans='T').
+  * the transposed solve reuses the LU factors (trans='T'): SuperLU's, or
+    for wide cross-sections (dense self-energy blocks) a dense LAPACK LU of
+    the same matrix.
 With a nonlocal term the same holds for the bordered matrix; lambda is its
 first N_pts entries.
 """
@@ -20,7 +22,19 @@ import numpy as np
 from .lead import open_channels
 
 
-def total_transmission_and_gradient(prob, energies, side="L"):
+class _DenseLU:
+    """LAPACK LU of the dense matrix with SuperLU's solve(rhs, trans) call."""
+
+    def __init__(self, A):
+        import scipy.linalg as sla
+        self._sla = sla
+        self._f = sla.lu_factor(A.toarray(), check_finite=False)
+
+    def solve(self, rhs, trans="N"):
+        return self._sla.lu_solve(self._f, rhs, trans={"N": 0, "T": 1}[trans], check_finite=False)
+
+
+def total_transmission_and_gradient(prob, energies, side="L", dense=False):
     """(T_total, dT_total/dV as (nz, ny, nx)) summed over every open channel
     at every energy in `energies`."""
     g = prob.g
@@ -31,7 +45,7 @@ def total_transmission_and_gradient(prob, energies, side="L"):
     grad = np.zeros(g.npts)
     for E in energies:
         modes = open_channels(g, E)
-        lu = prob.factor(E)
+        lu = _DenseLU(prob.matrix(E)) if dense else prob.factor(E)
         psi = prob.solve(E, modes, side, lu=lu)
         G = prob.gamma(E, far)
         for m, p in zip(modes, psi):

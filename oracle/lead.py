@@ -48,21 +48,22 @@ def mode_numbers(n: int):
 
 def lateral_energy(g, mode):
     """eps_nu: lateral kinetic energy of the plane wave of mode id `mode` under
-    the lateral part of the FD Laplacian (Eq. (1))."""
+    the lateral part of the FD Laplacian (Eq. (1), spacing h_x along x and
+    h_y along y)."""
     c = fd_coefficients(g.nf)
     ix, iy = mode % g.nx, mode // g.nx
     e = 0.0
-    for nu, n_ in ((mode_numbers(g.nx)[ix], g.nx), (mode_numbers(g.ny)[iy], g.ny)):
-        th = 2.0 * np.pi * nu / n_  # G_nu * h
-        e += -(c[0] + 2.0 * sum(c[n] * np.cos(n * th) for n in range(1, g.nf + 1))) / (2.0 * g.h ** 2)
+    for nu, n_, h in ((mode_numbers(g.nx)[ix], g.nx, g.hx), (mode_numbers(g.ny)[iy], g.ny, g.hy)):
+        th = 2.0 * np.pi * nu / n_  # G_nu * h_mu
+        e += -(c[0] + 2.0 * sum(c[n] * np.cos(n * th) for n in range(1, g.nf + 1))) / (2.0 * h ** 2)
     return e
 
 
 def z_hopping(g):
     """a_n, n = 0..nf: the z part of H couples planes k and k+-n by
-    a_n = -chat_n / (2 h^2)."""
+    a_n = -chat_n / (2 h_z^2)."""
     c = fd_coefficients(g.nf)
-    return np.array([-c[n] / (2.0 * g.h ** 2) for n in range(g.nf + 1)])
+    return np.array([-c[n] / (2.0 * g.hz ** 2) for n in range(g.nf + 1)])
 
 
 def transfer_matrix(g, E, eps):

@@ -15,7 +15,9 @@ What is computed (Sec. II of the paper):
     left-lead planes that truncation dropped (B_z^dagger for N_f = 1), with
     the incident wave Phi_in a right-moving lateral plane wave x^k;
   * psi = A^-1 b by sparse direct LU (scipy SuperLU), one factorisation per
-    energy shared by every incident channel;
+    energy shared by every incident channel (or, for wide cross-sections
+    whose dense self-energy blocks defeat the sparse ordering, by a dense
+    LAPACK solve of the same matrix);
   * transmission and reflection from the probability current, as ratios of
     the current leaving through each lead to the incident current (the
     Landauer-Buttiker transmission quoted in Sec. III): the current into a
@@ -51,12 +53,12 @@ def _second_difference_1d(n, nf, periodic):
 
 
 def kinetic(g):
-    """-1/2 Laplacian (Eq. (1)) on the truncated grid, flat index
-    (k*ny + j)*nx + i: periodic in x and y, z couplings outside 0..nz-1
-    dropped (Eq. (4))."""
-    Dx = _second_difference_1d(g.nx, g.nf, True) / g.h ** 2
-    Dy = _second_difference_1d(g.ny, g.nf, True) / g.h ** 2
-    Dz = _second_difference_1d(g.nz, g.nf, False) / g.h ** 2
+    """-1/2 Laplacian (Eq. (1), c_{mu,n} = chat_n / h_mu^2 per direction) on
+    the truncated grid, flat index (k*ny + j)*nx + i: periodic in x and y,
+    z couplings outside 0..nz-1 dropped (Eq. (4))."""
+    Dx = _second_difference_1d(g.nx, g.nf, True) / g.hx ** 2
+    Dy = _second_difference_1d(g.ny, g.nf, True) / g.hy ** 2
+    Dz = _second_difference_1d(g.nz, g.nf, False) / g.hz ** 2
     Ix, Iy, Iz = (sp.identity(n, format="csr") for n in (g.nx, g.ny, g.nz))
     lap = sp.kron(Iz, sp.kron(Iy, Dx)) + sp.kron(Iz, sp.kron(Dy, Ix)) + sp.kron(Dz, sp.kron(Iy, Ix))
     return (-0.5 * lap).tocsr()
@@ -83,7 +85,7 @@ def lead_coupling(g, side):
 
 def kb_matrix(g, nl):
     """Sparse B (N_pts x nproj) and the per-projector coupling block
-    diag_a(h^3 D_a) (nproj x nproj)."""
+    diag_a(h^3 D_a) (nproj x nproj), h^3 = hx hy hz the volume element."""
     if nl is None:
         return None, None
     rows, cols, vals = [], [], []
@@ -95,7 +97,7 @@ def kb_matrix(g, nl):
             rows.append(idx)
             cols.append(np.full(idx.size, col + p))
             vals.append(beta[p])
-        blocks.append(g.h ** 3 * np.asarray(D, dtype=float))
+        blocks.append(g.hx * g.hy * g.hz * np.asarray(D, dtype=float))
         col += r
     B = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(g.npts, col))
@@ -211,15 +213,19 @@ class Problem:
     def factor(self, E):
         return spla.splu(self.matrix(E), permc_spec="COLAMD")
 
-    def solve(self, E, modes, side="L", lu=None, check=True):
-        """psi for every incident mode in `modes`: array (len(modes), nz, ny, nx)."""
+    def solve(self, E, modes, side="L", lu=None, check=True, dense=False):
+        """psi for every incident mode in `modes`: array (len(modes), nz, ny, nx).
+        dense=True solves with the dense matrix (numpy.linalg.solve)."""
         g = self.g
-        lu = lu or self.factor(E)
         nb = 0 if self.B is None else self.B.shape[1]
         Bm = np.zeros((g.npts + nb, len(modes)), dtype=complex)
         for c, m in enumerate(modes):
             Bm[:g.npts, c] = self.rhs(E, m, side)
-        X = lu.solve(Bm)
+        if dense:
+            X = np.linalg.solve(self.matrix(E).toarray(), Bm)
+        else:
+            lu = lu or self.factor(E)
+            X = lu.solve(Bm)
         psi = X[:g.npts].T.reshape((len(modes),) + g.shape)
         if check:
             res = self.apply(E, psi.reshape(len(modes), -1)) - Bm[:g.npts].T

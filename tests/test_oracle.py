@@ -49,12 +49,12 @@ def test_fd_order_of_accuracy(nf):
 
 # ------------------------------------- Eqs. (11)-(15) and the appendix
 def _chi(g, E, mode):
-    """Eq. (13) with kappa = 0 (N_f = 1)."""
+    """Eq. (13) with kappa = 0 (N_f = 1), spacings h_x, h_y, h_z."""
     nux = O.mode_numbers(g.nx)[mode % g.nx]
     nuy = O.mode_numbers(g.ny)[mode // g.nx]
-    h = g.h
-    return (h * h * E - (1 - math.cos(2 * math.pi * nux / g.nx))
-            - (1 - math.cos(2 * math.pi * nuy / g.ny)) - 1.0)
+    hz2 = g.hz * g.hz
+    return (hz2 * E - hz2 / g.hx ** 2 * (1 - math.cos(2 * math.pi * nux / g.nx))
+            - hz2 / g.hy ** 2 * (1 - math.cos(2 * math.pi * nuy / g.ny)) - 1.0)
 
 
 def _sigma_closed_form(g, E, mode):
@@ -63,7 +63,7 @@ def _sigma_closed_form(g, E, mode):
     discrete band top) the decaying root of x^2 + 2 chi x + 1 = 0 (the
     appendix's pole pair omega_1, omega_2 with omega_1 omega_2 = 1) is taken."""
     chi = _chi(g, E, mode)
-    h = g.h
+    h = g.hz
     if abs(chi) < 1:
         x = complex(math.cos(math.acos(-chi)), math.sin(math.acos(-chi)))
     elif chi < -1:
@@ -73,14 +73,17 @@ def _sigma_closed_form(g, E, mode):
     return -x / (2 * h * h)
 
 
+ANISO = Grid(8, 6, 10, 0.4, 1, hy_=0.55, hz_=0.3)
+
+
+@pytest.mark.parametrize("g", [Grid(8, 6, 10, 0.4, 1), ANISO], ids=["iso", "aniso"])
 @pytest.mark.parametrize("E", [0.05, 0.4, 2.0, 30.0])
-def test_sigma_nf1_equals_closed_form(E):
-    g = Grid(8, 6, 10, 0.4, 1)
+def test_sigma_nf1_equals_closed_form(g, E):
     for m in range(g.nx * g.ny):
         lm = O.LeadMode(g, E, m)
         s = lm.sigma_right()
         assert s.shape == (1, 1)
-        assert abs(s[0, 0] - _sigma_closed_form(g, E, m)) < 1e-12 * 2 / g.h ** 2
+        assert abs(s[0, 0] - _sigma_closed_form(g, E, m)) < 1e-12 * 2 / g.hz ** 2
         assert lm.open == (abs(_chi(g, E, m)) < 1)
 
 
@@ -91,7 +94,7 @@ def _sancho_rubio(g, E, mode, eta=1e-9, itmax=200):
     right-lead self-energy H01 g_s H10."""
     nf = g.nf
     c = O.fd_coefficients(nf)
-    a = [-c[n] / (2 * g.h ** 2) for n in range(nf + 1)]
+    a = [-c[n] / (2 * g.hz ** 2) for n in range(nf + 1)]
     eps = O.lateral_energy(g, mode)
     H00 = np.zeros((nf, nf))
     H01 = np.zeros((nf, nf))
@@ -116,10 +119,11 @@ def _sancho_rubio(g, E, mode, eta=1e-9, itmax=200):
     return H01 @ gs @ H01.T
 
 
+@pytest.mark.parametrize("aniso", [False, True])
 @pytest.mark.parametrize("nf", [2, 3])
 @pytest.mark.parametrize("E", [0.1, 0.9, 3.0])
-def test_sigma_matches_sancho_rubio(nf, E):
-    g = Grid(6, 4, 10, 0.4, nf)
+def test_sigma_matches_sancho_rubio(nf, E, aniso):
+    g = Grid(6, 4, 10, 0.4, nf, hy_=0.5, hz_=0.33) if aniso else Grid(6, 4, 10, 0.4, nf)
     for m in range(g.nx * g.ny):
         s = O.LeadMode(g, E, m).sigma_right()
         ref = _sancho_rubio(g, E, m)
@@ -163,10 +167,11 @@ def test_channel_count_of_ir_and_au_wires(row):
 
 
 # ------------------------------------------------------------ whole solve
+@pytest.mark.parametrize("aniso", [False, True])
 @pytest.mark.parametrize("nf", [1, 2, 3])
-def test_flat_wire_transmits_every_open_channel(nf):
+def test_flat_wire_transmits_every_open_channel(nf, aniso):
     # h = 0.9 on a 6x6 cell: several lateral channels open at E = 1.0
-    g = Grid(6, 6, 12, 0.9, nf)
+    g = Grid(6, 6, 12, 0.9, nf, hy_=0.8, hz_=0.6) if aniso else Grid(6, 6, 12, 0.9, nf)
     P = O.Problem(g, np.zeros(g.shape))
     E = 1.0
     modes = O.open_channels(g, E)
@@ -201,8 +206,90 @@ def test_lattice_square_barrier_closed_form(E, V0, n):
     P = O.Problem(g, V)
     psi = P.solve(E, [0])
     T, R = P.currents(E, 0, psi[0])
-    assert abs(T - _barrier_closed_form(E, V0, n, g.h)) < 1e-12
+    assert abs(T - _barrier_closed_form(E, V0, n, g.hz)) < 1e-12
     assert abs(T + R - 1) < 1e-12
+
+
+def _eps_nf1(g, mode):
+    """Lateral energy of a plane wave on the 3-point stencil (the textbook
+    tight-binding band of each lateral direction, spacing h_x or h_y)."""
+    nux = O.mode_numbers(g.nx)[mode % g.nx]
+    nuy = O.mode_numbers(g.ny)[mode // g.nx]
+    return ((1 - math.cos(2 * math.pi * nux / g.nx)) / g.hx ** 2
+            + (1 - math.cos(2 * math.pi * nuy / g.ny)) / g.hy ** 2)
+
+
+# h_x, h_y, h_z all different: a swapped spacing anywhere (kinetic operator,
+# lateral energy, lead hopping, incident current) changes every E_nu below
+UNIFORM = Grid(6, 4, 24, 0.9, 1, hy_=0.8, hz_=0.5)
+
+
+@pytest.mark.parametrize("E,V0,n", [(1.8, 0.5, 7), (2.4, -0.3, 5)])
+def test_uniform_barrier_eigenchannels_closed_form(E, V0, n):
+    """A laterally uniform barrier does not mix lateral modes, so t is
+    diagonal and the eigenvalues of t^dagger t (Sec. IV's eigenchannel
+    transmissions) are the lattice square-barrier transmissions of each open
+    mode at its longitudinal energy E - eps_nu (spacing h_z along z).  Pins
+    the per-channel flux normalisation of the eigenchannel matrix, and the
+    anisotropic grid."""
+    g = UNIFORM
+    V = np.zeros(g.shape)
+    V[8:8 + n] = V0
+    P = O.Problem(g, V)
+    modes = O.open_channels(g, E)
+    assert len(modes) >= 5
+    ref = sorted(_barrier_closed_form(E - _eps_nf1(g, m), V0, n, g.hz) for m in modes)
+    for side in ("L", "R"):
+        psi = P.solve(E, modes, side)
+        eig = np.sort(P.transmission_matrix_eigs(E, modes, psi, side))
+        assert np.abs(eig - ref).max() < 1e-11
+        for m, p in zip(modes, psi):
+            T, R = P.currents(E, m, p, side)
+            assert abs(T - _barrier_closed_form(E - _eps_nf1(g, m), V0, n, g.hz)) < 1e-11
+
+
+def test_eigenchannels_match_caroli_matrix():
+    """The nonzero eigenvalues of the Caroli matrix Gamma_L G_LR Gamma_R
+    G_LR^H (Green's function of the dense matrix, no wave functions) are the
+    eigenchannel transmissions: pins the off-diagonal (channel-mixing)
+    normalisation of the oracle's eigenchannel matrix on a random potential
+    with an anisotropic grid."""
+    g = Grid(4, 4, 10, 0.9, 2, hy_=0.85, hz_=0.7)
+    rng = np.random.default_rng(17)
+    V = 0.4 * rng.standard_normal(g.shape)
+    P = O.Problem(g, V)
+    E = 2.2
+    modes = O.open_channels(g, E)
+    assert len(modes) >= 5
+    G = np.linalg.inv(P.matrix(E).toarray())
+    sL, sR = P.boundary_slice("L"), P.boundary_slice("R")
+    M = P.gamma(E, "L") @ G[sL, sR] @ P.gamma(E, "R") @ G[sL, sR].conj().T
+    lam = np.sort(np.real(np.linalg.eigvals(M)))[::-1][:len(modes)]
+    psi = P.solve(E, modes)
+    eig = np.sort(P.transmission_matrix_eigs(E, modes, psi))[::-1]
+    assert np.abs(eig - lam).max() < 1e-10
+    assert eig.max() - eig.min() > 1e-3  # the eigenvalues are distinct: mixing is tested
+
+
+def test_truncated_laplacian_on_plane_waves():
+    """Eq. (17) on r(i, j, k) = exp(i(tx i + ty j)) f(k): the lateral
+    neighbours multiply the plane wave by 2 cos t, so interior planes give
+    [1 + 2 e^-alpha (cos tx + cos ty)] f(k) + e^-alpha (f(k-1) + f(k+1)) and
+    the first and last planes lose their missing z neighbour."""
+    g = Grid(6, 4, 9, 0.5, 2)
+    alpha = 1.8
+    c1 = math.exp(-alpha)
+    f = random_field(g.nz, 3)
+    for mx, my in ((0, 0), (1, 0), (2, 3), (5, 1)):
+        tx, ty = 2 * math.pi * mx / g.nx, 2 * math.pi * my / g.ny
+        jj, ii = np.meshgrid(np.arange(g.ny), np.arange(g.nx), indexing="ij")
+        lat = np.exp(1j * (tx * ii + ty * jj))
+        r = f[:, None, None] * lat[None]
+        z = O.precond.truncated_laplacian(g, r[None], alpha)[0]
+        fm = np.concatenate([[0], f[:-1]])  # f(k-1), zero below plane 0
+        fp = np.concatenate([f[1:], [0]])   # f(k+1), zero above plane nz-1
+        ref = ((1 + 2 * c1 * (math.cos(tx) + math.cos(ty))) * f + c1 * (fm + fp))[:, None, None] * lat[None]
+        assert np.abs(z - ref).max() < 1e-14 * np.abs(ref).max()
 
 
 def test_continuum_barrier_limit_is_second_order():
@@ -225,8 +312,8 @@ def test_continuum_barrier_limit_is_second_order():
     assert errs[1] < errs[0] / 2.5
 
 
-def _random_problem(nf, seed, kb=False, shape=(6, 6, 14), h=0.9):
-    g = Grid(shape[0], shape[1], shape[2], h, nf)
+def _random_problem(nf, seed, kb=False, shape=(6, 6, 14), h=0.9, hz=None):
+    g = Grid(shape[0], shape[1], shape[2], h, nf, hz_=hz)
     rng = np.random.default_rng(seed)
     V = 0.3 * rng.standard_normal(g.shape)
     nl = None
@@ -237,9 +324,10 @@ def _random_problem(nf, seed, kb=False, shape=(6, 6, 14), h=0.9):
     return O.Problem(g, V, nl)
 
 
-@pytest.mark.parametrize("nf,kb", [(1, False), (2, False), (3, False), (2, True)])
-def test_flux_conservation_and_reciprocity(nf, kb):
-    P = _random_problem(nf, 7 + nf, kb)
+@pytest.mark.parametrize("nf,kb,hz", [(1, False, None), (2, False, None), (3, False, None), (2, True, None),
+                                       (1, False, 0.7), (2, True, 0.75)])
+def test_flux_conservation_and_reciprocity(nf, kb, hz):
+    P = _random_problem(nf, 7 + nf, kb, hz=hz)
     E = 1.6
     modes = O.open_channels(P.g, E)
     assert len(modes) >= 5
@@ -282,6 +370,9 @@ def test_dense_solve_and_caroli_trace():
     assert abs(T - caroli) < 1e-10 * max(1, caroli)
     b = P.rhs(E, modes[0])
     assert np.abs(np.linalg.solve(A, b) - psi[0].ravel()).max() < 1e-10
+    # the dense path of the oracle's solve equals the sparse LU
+    psid = P.solve(E, modes, dense=True)
+    assert np.abs(psid - psi).max() < 1e-10 * np.abs(psi).max()
 
 
 def test_bordered_nonlocal_equals_dense_schur_complement():
@@ -329,6 +420,9 @@ def test_gradient_matches_central_differences():
     Es = [0.9, 1.4]
     T0, grad = O.total_transmission_and_gradient(P, Es)
     assert abs(T0 - O.total_transmission(P, Es)) < 1e-11
+    # the dense-LU path equals the sparse one
+    T1, grad1 = O.total_transmission_and_gradient(P, Es, dense=True)
+    assert abs(T1 - T0) < 1e-11 and np.abs(grad1 - grad).max() < 1e-10 * np.abs(grad).max()
     rng = np.random.default_rng(0)
     vox = rng.choice(g.npts, 12, replace=False)
     d = 1e-5
@@ -375,8 +469,9 @@ def test_na_wire_stand_in():
         w = na_wire(n)
         g = w.grid
         assert (g.nx, g.ny, g.nz, g.nf) == (36, 36, 60 + 10 * (n - 1), 1)
-        assert abs(g.h * 36 - 25.66) < 1e-12
-        assert abs(w.extra["hz"] * g.nz - ((n - 1) * 8.11 * 3 ** 0.5 / 2 + 42.12)) < 1e-9
+        assert abs(g.hx * 36 - 25.66) < 1e-12 and g.hy == g.hx
+        assert abs(g.hz * g.nz - ((n - 1) * 8.11 * 3 ** 0.5 / 2 + 42.12)) < 1e-9
+        assert g.hz == w.extra["hz"]
         assert np.abs(w.V[:3]).max() < 1e-6 and np.abs(w.V[-3:]).max() < 1e-6
         assert 0.19 < w.V.max() <= 0.2 and w.V.min() < -0.3
         # the lateral dispersion gives 9 open channels at E_F (the paper quotes 13

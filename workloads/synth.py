@@ -11,7 +11,8 @@ synthetic stand-in with the geometry class of the paper's wires: a periodic
 lateral cell, a transition region along z, jellium leads at V = 0.
 
 Conventions (Hartree atomic units):
-  * grid point (i, j, k) sits at r = (i*h, j*h, k*h), i < nx, j < ny, k < nz;
+  * grid point (i, j, k) sits at r = (i*hx, j*hy, k*hz), i < nx, j < ny,
+    k < nz (the spacings may differ per direction, as in Eq. (1));
   * arrays are indexed [k][j][i] (x fastest), float64;
   * the lateral cell is periodic with L = n*h; distances to atoms use the
     minimum image laterally and the plain difference along z.
@@ -25,11 +26,31 @@ import numpy as np
 
 @dataclass
 class Grid:
+    """Grid of the transition region.  `h` is the spacing along x; y and z
+    use it too unless `hy_` / `hz_` give their own."""
     nx: int
     ny: int
     nz: int
     h: float
     nf: int  # finite-difference half width: 1, 2 or 3 (2nd/4th/6th order)
+    hy_: float | None = None
+    hz_: float | None = None
+
+    @property
+    def hx(self):
+        return self.h
+
+    @property
+    def hy(self):
+        return self.h if self.hy_ is None else self.hy_
+
+    @property
+    def hz(self):
+        return self.h if self.hz_ is None else self.hz_
+
+    @property
+    def spacings(self):
+        return (self.hx, self.hy, self.hz)
 
     @property
     def shape(self):
@@ -73,7 +94,7 @@ class Workload:
 def _coords(g: Grid):
     k, j, i = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx),
                           indexing="ij")
-    return i * g.h, j * g.h, k * g.h
+    return i * g.hx, j * g.hy, k * g.hz
 
 
 def _min_image(d, L):
@@ -82,7 +103,7 @@ def _min_image(d, L):
 
 def _wells(g: Grid, centres, depth, sigma):
     X, Y, Z = _coords(g)
-    Lx, Ly = g.nx * g.h, g.ny * g.h
+    Lx, Ly = g.nx * g.hx, g.ny * g.hy
     V = np.zeros(g.shape)
     for R in centres:
         dx = _min_image(X - R[0], Lx)
@@ -93,8 +114,8 @@ def _wells(g: Grid, centres, depth, sigma):
 
 
 def _well_centres(g: Grid, n, spacing, jitter, rng):
-    zc = (g.nz - 1) * g.h / 2.0
-    base = [(g.nx * g.h / 2.0, g.ny * g.h / 2.0, zc + spacing * (a - (n - 1) / 2.0))
+    zc = (g.nz - 1) * g.hz / 2.0
+    base = [(g.nx * g.hx / 2.0, g.ny * g.hy / 2.0, zc + spacing * (a - (n - 1) / 2.0))
             for a in range(n)]
     return [np.array(b) + rng.uniform(-jitter, jitter, 3) for b in base]
 
@@ -112,9 +133,9 @@ def barrier(grid: Grid | None = None, seed: int = 1002) -> Workload:
     g = grid or Grid(16, 16, 48, 0.4, 2)
     rng = np.random.default_rng(seed)
     X, Y, Z = _coords(g)
-    zc = (g.nz - 1) * g.h / 2.0
+    zc = (g.nz - 1) * g.hz / 2.0
     V = 0.05 * np.exp(-(Z - zc) ** 2 / (2.0 * 3.0 ** 2))
-    L = (g.nx * g.h, g.ny * g.h, g.nz * g.h)
+    L = (g.nx * g.hx, g.ny * g.hy, g.nz * g.hz)
     dV = np.zeros(g.shape)
     for n in ((1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1)):
         a = rng.uniform(-1.0, 1.0)
@@ -130,7 +151,7 @@ def _kb_projectors(g: Grid, centres, sigma, rank, rng):
     phi_q in {1, x/s, y/s, z/s} * exp(-r^2/(2 s^2)), cut at r = 3 s, each
     normalised to h^3 sum beta^2 = 1; D = diag(U(0.05, 0.5)) Ha."""
     X, Y, Z = _coords(g)
-    Lx, Ly = g.nx * g.h, g.ny * g.h
+    Lx, Ly = g.nx * g.hx, g.ny * g.hy
     support, beta, D = [], [], []
     for R in centres:
         dx = _min_image(X - R[0], Lx)
@@ -146,7 +167,7 @@ def _kb_projectors(g: Grid, centres, sigma, rank, rng):
                         dz.ravel()[idx] / sigma * env])[:rank]
         M = rng.standard_normal((rank, phi.shape[0]))
         b = M @ phi
-        b /= np.sqrt(g.h ** 3 * np.sum(b * b, axis=1))[:, None]
+        b /= np.sqrt(g.hx * g.hy * g.hz * np.sum(b * b, axis=1))[:, None]
         support.append(idx)
         beta.append(np.ascontiguousarray(b))
         D.append(np.diag(rng.uniform(0.05, 0.5, rank)))
@@ -178,9 +199,9 @@ def wide(grid: Grid | None = None, seed: int = 1004) -> Workload:
     rng = np.random.default_rng(seed)
     F = rng.standard_normal(g.shape)
     d2 = 0.0
-    for ax, n in enumerate(g.shape):
+    for ax, (n, h) in enumerate(zip(g.shape, (g.hz, g.hy, g.hx))):
         m = np.arange(n)
-        m = np.minimum(m, n - m).astype(float) * g.h
+        m = np.minimum(m, n - m).astype(float) * h
         sh = [1, 1, 1]
         sh[ax] = n
         d2 = d2 + (m ** 2).reshape(sh)
@@ -214,7 +235,7 @@ def jellium_fermi_energy(rs: float = NA_RS) -> float:
     return 0.5 * kf * kf
 
 
-def na_wire(n_atom: int, seed: int = 1006) -> Workload:
+def na_wire(n_atom: int, seed: int = 1006, nx: int = 36, nz: int | None = None) -> Workload:
     """Synthetic stand-in for the paper's single-row Na wires between jellium
     electrodes (Sec. III): n_atom = 3..8 atoms NA_D apart on the axis of a
     36 x 36 lateral cell of 25.66 bohr, nz = 60 + 10 (n_atom - 1) planes over
@@ -223,18 +244,20 @@ def na_wire(n_atom: int, seed: int = 1006) -> Workload:
     (sqrt(2) a0 / 4) beyond the edge atoms; between them V rises to 0.2 Ha
     (logistic steps 0.5 bohr wide) and each atom is a Gaussian well of depth
     0.6 Ha and width 3 bohr (positions jittered by U(+-0.1) bohr), which
-    overlap into one conducting channel along the axis.  The
-    grid spacing differs along z: extra["hz"]; grid.h is the lateral one."""
+    overlap into one conducting channel along the axis.  The grid spacing
+    differs along z (grid.hz; also extra["hz"]).
+
+    nx < 36 keeps the lateral spacing and narrows the cell; nz sets another
+    plane count over the same length (both for oracle-sized parity cases)."""
     if not 1 <= n_atom <= 20:
         raise ValueError("n_atom out of range")
-    nx = 36
-    hx = 25.66 / nx
-    nz = 60 + 10 * (n_atom - 1)
+    hx = 25.66 / 36
+    if nz is None:
+        nz = 60 + 10 * (n_atom - 1)
     hz = ((n_atom - 1) * NA_D + 42.12) / nz
-    g = Grid(nx, nx, nz, hx, 1)
+    g = Grid(nx, nx, nz, hx, 1, hz_=hz)
     rng = np.random.default_rng(seed + n_atom)
-    k, j, i = np.meshgrid(np.arange(nz), np.arange(nx), np.arange(nx), indexing="ij")
-    X, Y, Z = i * hx, j * hx, k * hz
+    X, Y, Z = _coords(g)
     L = nx * hx
     zc = (nz - 1) * hz / 2.0
     za = [zc + NA_D * (a - (n_atom - 1) / 2.0) for a in range(n_atom)]
