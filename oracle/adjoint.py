@@ -44,7 +44,7 @@ def total_transmission_and_gradient(prob, energies, side="L", dense=False):
     T_total = 0.0
     grad = np.zeros(g.npts)
     for E in energies:
-        modes = open_channels(g, E)
+        modes = open_channels(g, E, prob.kappa)
         lu = _DenseLU(prob.matrix(E)) if dense else prob.factor(E)
         psi = prob.solve(E, modes, side, lu=lu)
         G = prob.gamma(E, far)
@@ -63,7 +63,7 @@ def total_transmission(prob, energies, side="L"):
     g = prob.g
     T = 0.0
     for E in energies:
-        modes = open_channels(g, E)
+        modes = open_channels(g, E, prob.kappa)
         psi = prob.solve(E, modes, side)
         for m, p in zip(modes, psi):
             T += prob.currents(E, m, p, side)[0]

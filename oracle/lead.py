@@ -26,6 +26,12 @@ Lateral mode numbering (interface convention shared with the library as
 data): mode id m = iy * nx + ix with ix, iy in FFT order, i.e.
 nu_x = ix for ix < nx/2 and ix - nx otherwise (same for y).
 
+Lateral Bloch vector kappa = (kappa_x, kappa_y) (Eqs. (2), (12)-(13) and
+(16) carry it; the workloads use kappa = 0): the wave functions obey
+psi(r + L_x e_x) = exp(i kappa_x L_x) psi(r), so the lateral plane waves
+are exp(i (G_nu + kappa) . r) and every lateral energy is taken at
+G_nu + kappa.
+
 Quantities are per unit lateral plane wave; the real-space matrices
 (Eq. (11) generalised) are built by explicit DFT sums, without an FFT.
 """
@@ -46,15 +52,16 @@ def mode_numbers(n: int):
     return np.array([i if i < n // 2 else i - n for i in range(n)])
 
 
-def lateral_energy(g, mode):
-    """eps_nu: lateral kinetic energy of the plane wave of mode id `mode` under
-    the lateral part of the FD Laplacian (Eq. (1), spacing h_x along x and
-    h_y along y)."""
+def lateral_energy(g, mode, kappa=(0.0, 0.0)):
+    """eps_nu: lateral kinetic energy of the plane wave exp(i (G_nu + kappa).r)
+    of mode id `mode` under the lateral part of the FD Laplacian (Eq. (1),
+    spacing h_x along x and h_y along y)."""
     c = fd_coefficients(g.nf)
     ix, iy = mode % g.nx, mode // g.nx
     e = 0.0
-    for nu, n_, h in ((mode_numbers(g.nx)[ix], g.nx, g.hx), (mode_numbers(g.ny)[iy], g.ny, g.hy)):
-        th = 2.0 * np.pi * nu / n_  # G_nu * h_mu
+    for nu, n_, h, k in ((mode_numbers(g.nx)[ix], g.nx, g.hx, kappa[0]),
+                         (mode_numbers(g.ny)[iy], g.ny, g.hy, kappa[1])):
+        th = 2.0 * np.pi * nu / n_ + k * h  # (G_nu + kappa) * h_mu
         e += -(c[0] + 2.0 * sum(c[n] * np.cos(n * th) for n in range(1, g.nf + 1))) / (2.0 * h ** 2)
     return e
 
@@ -125,9 +132,9 @@ def _polish(g, dE, x, steps=3):
 class LeadMode:
     """Generalized Bloch states and self-energies of one lateral mode."""
 
-    def __init__(self, g, E, mode, tol=1e-9):
+    def __init__(self, g, E, mode, tol=1e-9, kappa=(0.0, 0.0)):
         self.g, self.E, self.mode = g, E, mode
-        self.eps = lateral_energy(g, mode)
+        self.eps = lateral_energy(g, mode, kappa)
         roots = np.linalg.eigvals(transfer_matrix(g, E, self.eps))
         roots = np.array([_polish(g, E - self.eps, x) for x in roots])
         self.roots = roots
@@ -189,17 +196,17 @@ class LeadMode:
         return C @ Ql @ np.linalg.inv(Qb)
 
 
-def lead_modes(g, E):
-    return [LeadMode(g, E, m) for m in range(g.nx * g.ny)]
+def lead_modes(g, E, kappa=(0.0, 0.0)):
+    return [LeadMode(g, E, m, kappa=kappa) for m in range(g.nx * g.ny)]
 
 
-def open_channels(g, E):
+def open_channels(g, E, kappa=(0.0, 0.0)):
     """Mode ids of the propagating lateral modes at E (ascending)."""
-    return [m for m in range(g.nx * g.ny) if LeadMode(g, E, m).open]
+    return [m for m in range(g.nx * g.ny) if LeadMode(g, E, m, kappa=kappa).open]
 
 
-def plane_wave_matrix(g):
-    """F[l, m] = exp(i G_m . r_l) for lateral points l = j*nx + i."""
+def plane_wave_matrix(g, kappa=(0.0, 0.0)):
+    """F[l, m] = exp(i (G_m + kappa) . r_l) for lateral points l = j*nx + i."""
     jj, ii = np.meshgrid(np.arange(g.ny), np.arange(g.nx), indexing="ij")
     ii, jj = ii.ravel(), jj.ravel()
     mx = mode_numbers(g.nx)
@@ -207,19 +214,20 @@ def plane_wave_matrix(g):
     modes = np.arange(g.nx * g.ny)
     nux, nuy = mx[modes % g.nx], my[modes // g.nx]
     ph = 2.0 * np.pi * (np.outer(ii, nux) / g.nx + np.outer(jj, nuy) / g.ny)
+    ph = ph + (kappa[0] * g.hx * ii + kappa[1] * g.hy * jj)[:, None]
     return np.exp(1j * ph)
 
 
-def sigma_realspace(g, E, side):
+def sigma_realspace(g, E, side, kappa=(0.0, 0.0)):
     """Dense real-space self-energy on the N_f boundary planes (Eq. (11),
-    generalised): Sigma[(i,l),(j,l')] = 1/N_xy sum_nu e^{iG.(r_l - r_l')}
+    generalised): Sigma[(i,l),(j,l')] = 1/N_xy sum_nu e^{i(G+kappa).(r_l - r_l')}
     Sigma_nu[i, j], as explicit sums.  Shape (nf*Nxy, nf*Nxy); plane index i
     is the slow one.  side = 'L' (planes 0..nf-1) or 'R' (nz-nf..nz-1)."""
     nf, nxy = g.nf, g.nx * g.ny
-    F = plane_wave_matrix(g)
+    F = plane_wave_matrix(g, kappa)
     sig = np.zeros((nxy, nf, nf), dtype=complex)
     for m in range(nxy):
-        lm = LeadMode(g, E, m)
+        lm = LeadMode(g, E, m, kappa=kappa)
         sig[m] = lm.sigma_left() if side == "L" else lm.sigma_right()
     S = np.zeros((nf * nxy, nf * nxy), dtype=complex)
     for i in range(nf):

@@ -38,26 +38,30 @@ from .fd import fd_coefficients
 from .lead import LeadMode, mode_numbers, sigma_realspace, z_hopping
 
 
-def _second_difference_1d(n, nf, periodic):
-    """Matrix of sum_{m=-nf}^{nf} chat_|m| f(k+m) on n points (h = 1)."""
+def _second_difference_1d(n, nf, periodic, phase=1.0):
+    """Matrix of sum_{m=-nf}^{nf} chat_|m| f(k+m) on n points (h = 1).
+    periodic: f(k + n) = phase f(k) (a Bloch phase exp(i kappa L))."""
     c = fd_coefficients(nf)
-    D = sp.lil_matrix((n, n))
+    D = sp.lil_matrix((n, n), dtype=complex)
     for k in range(n):
         for m in range(-nf, nf + 1):
             q = k + m
             if periodic:
-                D[k, q % n] += c[abs(m)]
+                D[k, q % n] += c[abs(m)] * phase ** (q // n)
             elif 0 <= q < n:
                 D[k, q] += c[abs(m)]
     return D.tocsr()
 
 
-def kinetic(g):
+def kinetic(g, kappa=(0.0, 0.0)):
     """-1/2 Laplacian (Eq. (1), c_{mu,n} = chat_n / h_mu^2 per direction) on
-    the truncated grid, flat index (k*ny + j)*nx + i: periodic in x and y,
-    z couplings outside 0..nz-1 dropped (Eq. (4))."""
-    Dx = _second_difference_1d(g.nx, g.nf, True) / g.hx ** 2
-    Dy = _second_difference_1d(g.ny, g.nf, True) / g.hy ** 2
+    the truncated grid, flat index (k*ny + j)*nx + i: Bloch periodic in x and
+    y (phase exp(i kappa_mu L_mu) across the cell), z couplings outside
+    0..nz-1 dropped (Eq. (4))."""
+    px = np.exp(1j * kappa[0] * g.nx * g.hx)
+    py = np.exp(1j * kappa[1] * g.ny * g.hy)
+    Dx = _second_difference_1d(g.nx, g.nf, True, px) / g.hx ** 2
+    Dy = _second_difference_1d(g.ny, g.nf, True, py) / g.hy ** 2
     Dz = _second_difference_1d(g.nz, g.nf, False) / g.hz ** 2
     Ix, Iy, Iz = (sp.identity(n, format="csr") for n in (g.nx, g.ny, g.nz))
     lap = sp.kron(Iz, sp.kron(Iy, Dx)) + sp.kron(Iz, sp.kron(Dy, Ix)) + sp.kron(Dz, sp.kron(Iy, Ix))
@@ -106,13 +110,18 @@ def kb_matrix(g, nl):
 
 
 class Problem:
-    """One transition region: grid, local potential, optional nonlocal term."""
+    """One transition region: grid, local potential, optional nonlocal term,
+    lateral Bloch vector kappa (A(kappa)^T = A(-kappa); symmetric at 0)."""
 
-    def __init__(self, g, V, nl=None):
+    def __init__(self, g, V, nl=None, kappa=(0.0, 0.0)):
         self.g = g
         self.V = np.asarray(V, dtype=float).reshape(g.shape)
         self.nl = nl
-        self.H_loc = kinetic(g) + sp.diags(self.V.ravel())
+        self.kappa = (float(kappa[0]), float(kappa[1]))
+        H = kinetic(g, self.kappa)
+        if self.kappa == (0.0, 0.0):
+            H = H.real
+        self.H_loc = (H + sp.diags(self.V.ravel())).tocsr()
         self.B, self.hD = kb_matrix(g, nl)
         self._sig = {}
 
@@ -120,7 +129,7 @@ class Problem:
     def sigma(self, E, side):
         key = (float(E), side)
         if key not in self._sig:
-            self._sig[key] = sigma_realspace(self.g, E, side)
+            self._sig[key] = sigma_realspace(self.g, E, side, self.kappa)
         return self._sig[key]
 
     def boundary_slice(self, side):
@@ -164,7 +173,7 @@ class Problem:
         from the source lead, unit amplitude on the first transition plane
         it enters (plane 0 from the left, plane nz-1 from the right)."""
         g = self.g
-        lm = LeadMode(g, E, mode)
+        lm = LeadMode(g, E, mode, kappa=self.kappa)
         if not lm.open:
             raise ValueError(f"mode {mode} is closed at E={E}")
         x = lm.x_in if side == "L" else lm.x_back
@@ -174,7 +183,8 @@ class Problem:
         nux = mode_numbers(g.nx)[mode % g.nx]
         nuy = mode_numbers(g.ny)[mode // g.nx]
         jj, ii = np.meshgrid(np.arange(g.ny), np.arange(g.nx), indexing="ij")
-        lat = np.exp(2j * np.pi * (nux * ii / g.nx + nuy * jj / g.ny))
+        lat = np.exp(2j * np.pi * (nux * ii / g.nx + nuy * jj / g.ny)
+                     + 1j * (self.kappa[0] * g.hx * ii + self.kappa[1] * g.hy * jj))
         return zpart[:, None, None] * lat[None, :, :]
 
     def rhs(self, E, mode, side="L"):
@@ -251,6 +261,68 @@ class Problem:
         Jr = np.real(np.vdot(d, self.gamma(E, near) @ d))
         return Jt / J, Jr / J
 
+    def lateral_components(self, psi, planes):
+        """psi~_nu(plane) = (1/Nxy) sum_l exp(-i G_nu . r_l) psi(plane, l) for
+        every lateral mode nu (Eq. (16)), by explicit sums: (len(planes), Nxy)."""
+        from .lead import plane_wave_matrix
+        F = plane_wave_matrix(self.g, self.kappa)
+        P = np.stack([np.asarray(psi)[k].ravel() for k in planes])
+        return P @ F.conj() / (self.g.nx * self.g.ny)
+
+    def amplitudes(self, E, mode, psi, side="L"):
+        """Outgoing amplitudes of psi in every open channel (the scattering
+        condition, Eq. (7)): on the nf planes next to each lead, the lateral
+        component of every open channel nu is expanded in the nf Bloch states
+        that leave through that lead; the coefficient of the propagating one,
+        referred to the plane next to the lead (plane 0 or nz-1), is the
+        amplitude.  On the side of incidence the incident wave (unit amplitude
+        at that plane) is subtracted first.  Returns dicts {nu: amplitude} for
+        the left and right leads."""
+        from .lead import LeadMode, open_channels
+        g = self.g
+        nf, nz = g.nf, g.nz
+        lo, hi = list(range(nf)), list(range(nz - nf, nz))
+        cl, cr = self.lateral_components(psi, lo), self.lateral_components(psi, hi)
+        out = {"L": {}, "R": {}}
+        for nu in open_channels(g, E, self.kappa):
+            lm = LeadMode(g, E, nu, kappa=self.kappa)
+            # right lead: states leaving to the right, x^(k - (nz-1)) on planes nz-nf..nz-1
+            vals = cr[:, nu].copy()
+            if side == "R" and nu == mode:
+                vals -= lm.x_back ** (np.array(hi) - (nz - 1))
+            X = np.array([[x ** (k - (nz - 1)) for x in lm.right] for k in hi])
+            c = np.linalg.solve(X, vals)
+            out["R"][nu] = c[np.argmin(np.abs(np.abs(lm.right) - 1))]
+            # left lead: states leaving to the left, y^k on planes 0..nf-1
+            vals = cl[:, nu].copy()
+            if side == "L" and nu == mode:
+                vals -= lm.x_in ** np.array(lo)
+            Y = np.array([[y ** k for y in lm.left] for k in lo])
+            c = np.linalg.solve(Y, vals)
+            out["L"][nu] = c[np.argmin(np.abs(np.abs(lm.left) - 1))]
+        return out
+
+    def smatrix(self, E):
+        """Flux-normalised scattering matrix at E: rows and columns ordered
+        [left channels | right channels] (ascending ids), S[b nu, a mu] =
+        sqrt(J_nu / J_mu) x (amplitude of channel nu in lead b for unit
+        incidence in channel mu from lead a), every amplitude referred to the
+        plane next to its lead; J is the current of the unit Bloch wave."""
+        from .lead import LeadMode, open_channels
+        modes = open_channels(self.g, E, self.kappa)
+        n = len(modes)
+        J = np.array([LeadMode(self.g, E, m, kappa=self.kappa).J for m in modes])
+        S = np.zeros((2 * n, 2 * n), dtype=complex)
+        lu = self.factor(E)
+        for a, side in enumerate(("L", "R")):
+            psis = self.solve(E, modes, side, lu=lu)
+            for j, (mu, p) in enumerate(zip(modes, psis)):
+                amp = self.amplitudes(E, mu, p, side)
+                for b, lead in enumerate(("L", "R")):
+                    for i, nu in enumerate(modes):
+                        S[b * n + i, a * n + j] = np.sqrt(J[i] / J[j]) * amp[lead][nu]
+        return modes, S
+
     def transmission_matrix_eigs(self, E, modes, psis, side="L"):
         """Eigenvalues of t^dagger t for the incident channels `modes` at E:
         the flux-normalised matrix M[m, m'] = psi_m^H Gamma_far psi_m' /
@@ -270,7 +342,7 @@ def solve_workload(prob, energies, side="L", channels=None):
     from .lead import open_channels
     out = []
     for E in energies:
-        modes = open_channels(prob.g, E)
+        modes = open_channels(prob.g, E, prob.kappa)
         if channels == "lowest":
             modes = modes[:1]
         lu = prob.factor(E)

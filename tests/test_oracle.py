@@ -477,3 +477,182 @@ def test_na_wire_stand_in():
         # the lateral dispersion gives 9 open channels at E_F (the paper quotes 13
         # for its SCF wire; see the design notes)
         assert len(O.open_channels(g, float(w.energies[0]))) == 9
+
+
+@pytest.mark.parametrize("nf,kb,hz", [(1, False, None), (2, True, 0.75), (3, False, None)])
+def test_mode_amplitudes_and_scattering_matrix(nf, kb, hz):
+    """The amplitude readout (the nf boundary values of each open channel
+    expanded in the Bloch states leaving through that lead, Eq. (7)) against
+    the current-based readout: T_mu = sum_nu (J_nu / J_mu) |t_nu mu|^2 and
+    R_mu likewise, for incidence from both leads.  The assembled flux-
+    normalised S-matrix is unitary (current conservation) and obeys the
+    time-reversal relation S[b nu, a mu] = S[a -mu, b -nu] (real V,
+    kappa = 0: time reversal maps the lateral wave G to -G)."""
+    P = _random_problem(nf, 40 + nf, kb, hz=hz)
+    g = P.g
+    E = 1.6
+    modes, S = P.smatrix(E)
+    n = len(modes)
+    assert n >= 5
+    J = {m: O.LeadMode(g, E, m).J for m in modes}
+    for side in ("L", "R"):
+        psis = P.solve(E, modes, side)
+        far, near = ("R", "L") if side == "L" else ("L", "R")
+        for mu, p in zip(modes, psis):
+            amp = P.amplitudes(E, mu, p, side)
+            T = sum(J[nu] / J[mu] * abs(amp[far][nu]) ** 2 for nu in modes)
+            R = sum(J[nu] / J[mu] * abs(amp[near][nu]) ** 2 for nu in modes)
+            Tc, Rc = P.currents(E, mu, p, side)
+            assert abs(T - Tc) < 1e-10 and abs(R - Rc) < 1e-10
+    assert np.abs(S.conj().T @ S - np.eye(2 * n)).max() < 1e-10
+    neg = [modes.index(((g.ny - m // g.nx) % g.ny) * g.nx + (g.nx - m % g.nx) % g.nx) for m in modes]
+    perm = neg + [n + i for i in neg]
+    assert np.abs(S - S[np.ix_(perm, perm)].T).max() < 1e-10
+
+
+def test_scattering_matrix_of_the_flat_wire_is_pure_transmission():
+    """V = 0: every channel passes with amplitude 1 referred to the plane
+    next to each lead, i.e. S = [[0, D], [D, 0]] with D the phase of the free
+    propagation from plane 0 to plane nz-1, x_mu^(nz-1)."""
+    g = Grid(6, 6, 12, 0.9, 2, hy_=0.8, hz_=0.6)
+    P = O.Problem(g, np.zeros(g.shape))
+    E = 1.0
+    modes, S = P.smatrix(E)
+    n = len(modes)
+    D = np.diag([O.LeadMode(g, E, m).x_in ** (g.nz - 1) for m in modes])
+    assert np.abs(S[:n, :n]).max() < 1e-10 and np.abs(S[n:, n:]).max() < 1e-10
+    assert np.abs(S[n:, :n] - D).max() < 1e-10 and np.abs(S[:n, n:] - D).max() < 1e-10
+
+
+@pytest.mark.parametrize("nf,kb", [(1, False), (2, True), (3, False)])
+def test_jacobi_diagonal_is_the_operator_diagonal(nf, kb):
+    """Brute force on a small grid: the Jacobi diagonal equals e_i^T A e_i
+    for every voxel i, with A applied to unit vectors by the operator's
+    plain definition (Problem.apply)."""
+    P = _random_problem(nf, 60 + nf, kb, shape=(4, 3, 2 * nf + 3), hz=0.7)
+    g = P.g
+    E = 0.9
+    a = O.precond.jacobi_diagonal(P, E).ravel()
+    I = np.eye(g.npts, dtype=complex)
+    diag = np.array([P.apply(E, I[i])[i] for i in range(g.npts)])
+    assert np.abs(a - diag).max() < 1e-12 * np.abs(diag).max()
+    r = random_field((2,) + g.shape, 5)
+    z = O.precond.jacobi(P, E, r)
+    assert np.abs(z.reshape(2, -1) * diag[None] - r.reshape(2, -1)).max() < 1e-12 * np.abs(r).max()
+
+
+# ------------------------------------------------ lateral Bloch vector kappa
+KAPPAS = [(0.31, 0.0), (0.17, -0.42)]
+
+
+@pytest.mark.parametrize("kappa", KAPPAS)
+@pytest.mark.parametrize("nf", [1, 2, 3])
+def test_flat_wire_at_nonzero_kappa(nf, kappa):
+    """V = 0 at a lateral Bloch vector kappa: every open channel (counted at
+    G + kappa) passes with T = 1, R = 0 and psi = Phi_in."""
+    g = Grid(6, 5, 12, 0.9, nf, hz_=0.7)
+    P = O.Problem(g, np.zeros(g.shape), kappa=kappa)
+    E = 1.2
+    modes = O.open_channels(g, E, kappa)
+    assert len(modes) >= 3
+    psi = P.solve(E, modes)
+    for m, p in zip(modes, psi):
+        Phi = P.incident(E, m)[nf:nf + g.nz]
+        assert np.abs(p - Phi).max() < 1e-11
+        T, R = P.currents(E, m, p)
+        assert abs(T - 1) < 1e-11 and abs(R) < 1e-11
+
+
+@pytest.mark.parametrize("nf", [1, 2])
+def test_kappa_transpose_identity(nf):
+    """A(kappa)^T = A(-kappa) (the Bloch phases of the lateral wrap and of the
+    self-energies conjugate under transposition), and A(kappa) is not
+    complex symmetric for kappa != 0."""
+    P = _random_problem(nf, 70 + nf, kb=(nf == 2))
+    Pp = O.Problem(P.g, P.V, P.nl, kappa=(0.23, -0.11))
+    Pm = O.Problem(P.g, P.V, P.nl, kappa=(-0.23, 0.11))
+    A, Am = Pp.matrix(0.9), Pm.matrix(0.9)
+    assert abs(A - Am.T).max() < 1e-12
+    assert abs(A - A.T).max() > 1e-3
+
+
+def _eps_nf1_kappa(g, mode, kappa):
+    nux = O.mode_numbers(g.nx)[mode % g.nx]
+    nuy = O.mode_numbers(g.ny)[mode // g.nx]
+    return ((1 - math.cos(2 * math.pi * nux / g.nx + kappa[0] * g.hx)) / g.hx ** 2
+            + (1 - math.cos(2 * math.pi * nuy / g.ny + kappa[1] * g.hy)) / g.hy ** 2)
+
+
+@pytest.mark.parametrize("kappa", KAPPAS)
+def test_uniform_barrier_closed_form_at_nonzero_kappa(kappa):
+    """Laterally uniform barrier: the channels decouple, and each one follows
+    the lattice square-barrier closed form at E - eps(G + kappa)."""
+    g = UNIFORM
+    V = np.zeros(g.shape)
+    V[8:15] = 0.5
+    P = O.Problem(g, V, kappa=kappa)
+    E = 1.8
+    modes = O.open_channels(g, E, kappa)
+    assert len(modes) >= 4
+    psi = P.solve(E, modes)
+    for m, p in zip(modes, psi):
+        T, R = P.currents(E, m, p)
+        assert abs(T - _barrier_closed_form(E - _eps_nf1_kappa(g, m, kappa), 0.5, 7, g.hz)) < 1e-11
+        assert abs(T + R - 1) < 1e-11
+
+
+@pytest.mark.parametrize("nf", [1, 2])
+def test_flux_caroli_and_reciprocity_at_nonzero_kappa(nf):
+    """Random V at kappa != 0: T + R = 1 per channel, the total transmission
+    equals the Caroli trace and is the same from both leads, the S-matrix is
+    unitary, and time reversal maps (kappa, G) to (-kappa, -G):
+    S(kappa)[b nu, a mu] = S(-kappa)[a -mu, b -nu]."""
+    P0 = _random_problem(nf, 80 + nf, kb=(nf == 2))
+    kappa = (0.29, -0.13)
+    P = O.Problem(P0.g, P0.V, P0.nl, kappa=kappa)
+    Pm = O.Problem(P0.g, P0.V, P0.nl, kappa=(-kappa[0], -kappa[1]))
+    g = P.g
+    E = 1.6
+    modes = O.open_channels(g, E, kappa)
+    assert len(modes) >= 4
+    TL = 0.0
+    for m, p in zip(modes, P.solve(E, modes, "L")):
+        T, R = P.currents(E, m, p, "L")
+        assert abs(T + R - 1) < 1e-10
+        TL += T
+    TR = sum(P.currents(E, m, p, "R")[0] for m, p in zip(modes, P.solve(E, modes, "R")))
+    assert abs(TL - TR) < 1e-10
+    A = P.matrix(E).toarray()
+    G = np.linalg.inv(A)
+    sL, sR = P.boundary_slice("L"), P.boundary_slice("R")
+    n = g.npts
+    caroli = np.real(np.trace(P.gamma(E, "R") @ G[:n, :n][sR, sL] @ P.gamma(E, "L") @ G[:n, :n][sR, sL].conj().T))
+    assert abs(TL - caroli) < 1e-10 * max(1, caroli)
+    modes_p, S = P.smatrix(E)
+    modes_m, Sm = Pm.smatrix(E)
+    k = len(modes_p)
+    assert np.abs(S.conj().T @ S - np.eye(2 * k)).max() < 1e-10
+    neg = [modes_m.index(((g.ny - m // g.nx) % g.ny) * g.nx + (g.nx - m % g.nx) % g.nx) for m in modes_p]
+    perm = neg + [k + i for i in neg]
+    assert np.abs(S - Sm[np.ix_(perm, perm)].T).max() < 1e-10
+
+
+def test_truncated_laplacian_bloch_phases():
+    """Eq. (17) on a Bloch wave exp(i (G + kappa) . r) f(k): the lateral
+    neighbours multiply it by 2 cos((G_mu + kappa_mu) h_mu) across the cell."""
+    g = Grid(6, 4, 7, 0.5, 2, hy_=0.6)
+    kappa = (0.4, -0.7)
+    alpha = 2.4
+    c1 = math.exp(-alpha)
+    f = random_field(g.nz, 9)
+    jj, ii = np.meshgrid(np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    for mx, my in ((0, 0), (2, 1), (5, 3)):
+        tx = 2 * math.pi * mx / g.nx + kappa[0] * g.hx
+        ty = 2 * math.pi * my / g.ny + kappa[1] * g.hy
+        lat = np.exp(1j * (tx * ii + ty * jj))
+        r = f[:, None, None] * lat[None]
+        z = O.precond.truncated_laplacian(g, r[None], alpha, kappa)[0]
+        fm = np.concatenate([[0], f[:-1]])
+        fp = np.concatenate([f[1:], [0]])
+        ref = ((1 + 2 * c1 * (math.cos(tx) + math.cos(ty))) * f + c1 * (fm + fp))[:, None, None] * lat[None]
+        assert np.abs(z - ref).max() < 1e-13 * np.abs(ref).max()
