@@ -87,35 +87,56 @@ def _kernel_stats(s, cls):
             "achieved_GBps": alg / (ms * 1e-3) / 1e9}
 
 
-def cpu_baseline(seconds_hint=30.0):
-    """The oracle (sparse LU, FP64) on a bounded sample of the workload: the
-    same recipe (h, FD order, V statistics, first energy, every open channel)
-    on a 24 x 24 x 16 grid.  The full 48 x 48 cross-section is out of the
-    oracle's reach (its dense 4608 x 4608 electrode blocks alone take minutes
-    to factor per energy), so this rate overstates the oracle on the real
-    workload.  Returns solves/s."""
+def _cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    return model, ncpu
+
+
+def cpu_baseline():
+    """The oracle on a bounded sample of the workload: the same recipe
+    (48 x 48 cross-section, h = 0.4, 4th-order FD, V statistics, first
+    energy, all 45 open channels) on a z-shortened 48 x 48 x 4 grid (the two
+    electrode plane groups, nz = 2 nf, the fewest planes it takes), solved
+    with the oracle's dense path (its sparse LU does not finish on a 48 x 48
+    cross-section: the dense 4608 x 4608 self-energy blocks defeat the
+    ordering).  Times the assembly (self-energies by explicit sums), the
+    solve of every channel and the current readout.  The full 128-plane grid
+    is out of the oracle's reach, so this rate overstates the oracle on the
+    real workload.  Returns solves/s."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     import oracle as O
     from workloads import Grid, make
 
-    g = Grid(24, 24, 16, 0.4, 2)
+    g = Grid(48, 48, 4, 0.4, 2)
     w = make(4, g)
     E = float(w.energies[0])
     t0 = time.perf_counter()
     P = O.Problem(g, w.V)
     modes = O.open_channels(g, E)
-    lu = P.factor(E)
-    psi = P.solve(E, modes, lu=lu, check=False)
+    psi = P.solve(E, modes, dense=True, check=False)
     T = [P.currents(E, m, p)[0] for m, p in zip(modes, psi)]
     dt = time.perf_counter() - t0
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    model, ncpu = _cpu_info()
     assert np.all(np.isfinite(T))
     return {"value": len(modes) / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"24x24x16 grid (workload recipe on a reduced grid; the 48x48x128 grid is out of "
-                      f"reach of the sparse LU), E={E} Ha, "
-                      f"{len(modes)} channels, sparse LU + solves + readout in {dt:.1f} s"}
+            "host_cpus": ncpu, "cpu_model": model,
+            "sample": f"48x48x4 grid (the workload recipe on a z-shortened copy of its cross-section), "
+                      f"E={E} Ha, {len(modes)} channels, dense LU (LAPACK, {threads} BLAS threads) + "
+                      f"solves + current readout in {dt:.1f} s"}
 
 
 MFMA_F32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
@@ -136,7 +157,7 @@ def chain_workload(args):
     torch.cuda.set_device(0)
     w = make(3)
     g = w.grid
-    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
     s.set_potential(w.V)
     s.set_nonlocal(w.nonlocal_)
     opts = iobm.default_opts()
@@ -196,7 +217,7 @@ def adjoint_workload(args):
     torch.cuda.set_device(0)
     w = make(5)
     g = w.grid
-    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
     s.set_potential(w.V)
     T, grad = s.grad_transmission(w.energies)
     for _ in range(args.warmup):
@@ -241,7 +262,7 @@ def na_sweep(atoms=(3, 4, 5, 6, 7, 8)):
     for n in atoms:
         w = na_wire(n)
         g = w.grid
-        s = iobm.Solver(g.nx, g.ny, g.nz, (g.h, g.h, w.extra["hz"]), g.nf)
+        s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
         s.set_potential(w.V)
         row = {"n_atom": n, "nz": g.nz}
         Tref = None
@@ -252,9 +273,8 @@ def na_sweep(atoms=(3, 4, 5, 6, 7, 8)):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             ids = [int(m) for m in out["modes"][0]]
-            wgt = [1.0 if ((g.ny - m // g.nx) % g.ny) * g.nx + (g.nx - m % g.nx) % g.nx == m else 0.5 for m in ids]
-            iters = sum(st[0] * c for st, c in zip(out["stats"], wgt)) / len(ids)
-            row[name] = {"iters_per_wave": round(iters, 1), "status": int(out["status"]), "s": round(dt, 3)}
+            row[name] = {"iters_per_wave": round(_iters_per_wave(out, g), 1), "status": int(out["status"]),
+                         "s": round(dt, 3)}
             if Tref is None:
                 Tref = out["T"]
                 row["channels"] = len(ids)
@@ -269,6 +289,108 @@ def na_sweep(atoms=(3, 4, 5, 6, 7, 8)):
                       "speedup_vs_none": {k: round(mean["none"] / v, 2) for k, v in mean.items()}}), flush=True)
 
 
+def _iters_per_wave(out, g):
+    """Mean COCG iterations per standing-wave solve.  The channels of a +-G
+    pair are solved as one cos and one sin standing wave, and each of the two
+    channels reports both solves summed; a self-paired channel is one solve.
+    So the solves number the channels, and weighting the pair's reports by
+    1/2 counts every solve once."""
+    ids = [int(m) for e in range(len(out["modes"])) for m in out["modes"][e]]
+    wgt = [1.0 if ((g.ny - m // g.nx) % g.ny) * g.nx + (g.nx - m % g.nx) % g.nx == m else 0.5 for m in ids]
+    return sum(st[0] * c for st, c in zip(out["stats"], wgt)) / len(ids)
+
+
+def precision_sweep():
+    """Iterations of the preconditioned COCG per standing-wave solve, and its
+    wall time, for each preconditioner (none, the paper's Eq. (17) at
+    alpha = 1.8, Jacobi, lateral-Fourier) in complex128 and in complex64 with
+    FP64 residual replacement (search direction restarted at a replacement,
+    or kept), on the wide wire's first energy (48 x 48 x 128, 45
+    channels) and on the shortest synthetic Na-like wire (36 x 36 x 80, 9
+    channels).  Transmissions of every variant against the first."""
+    import numpy as np
+    import torch
+
+    from paper_1009_5300_amd import iobm
+    from workloads import make, na_wire
+
+    torch.cuda.set_device(0)
+    cases = [("wide_48x48x128_E0.71", make(4), [0.71]), ("na3_36x36x80_EF", na_wire(3), None)]
+    pcs = [("none", iobm.PC_NONE), ("eq17_alpha1.8", iobm.PC_TRUNCATED_LAPLACIAN), ("jacobi", iobm.PC_JACOBI),
+           ("lateral_fft", iobm.PC_LATERAL_FFT)]
+    precs = [("c128", iobm.C128, 0), ("c64_restart", iobm.C64_REFINED, 0), ("c64_keep", iobm.C64_REFINED, 1)]
+    res = {}
+    for name, w, Es in cases:
+        g = w.grid
+        Es = list(w.energies) if Es is None else Es
+        s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
+        s.set_potential(w.V)
+        s.solve(Es, opts=iobm.default_opts(precond=iobm.PC_LATERAL_FFT))  # tune, allocate
+        s.solve(Es, opts=iobm.default_opts(precision=iobm.C128, precond=iobm.PC_LATERAL_FFT))
+        Tref = None
+        rows = {}
+        for pname, pc in pcs:
+            for qname, prec, rep in precs:
+                o = iobm.default_opts(precision=prec, precond=pc, keep_direction=rep, max_iter=400000, check_every=4)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = s.solve(Es, opts=o)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if Tref is None:
+                    Tref = out["T"]
+                rows[f"{pname}/{qname}"] = {"iters_per_wave": round(_iters_per_wave(out, g), 1),
+                                            "s": round(dt, 3), "status": int(out["status"]),
+                                            "max_dT": float(np.abs(out["T"] - Tref).max())}
+                print(json.dumps({"case": name, "variant": f"{pname}/{qname}", **rows[f"{pname}/{qname}"]}),
+                      flush=True)
+        res[name] = rows
+    print(json.dumps({"experiment": "preconditioner x precision sweep", "rows": res}), flush=True)
+
+
+def block_sweep():
+    """Block COCG per energy against per-state COCG, both in complex128, on
+    the wide wire (48 x 48 x 128): the lateral-Fourier preconditioner over
+    all 16 energies (768 states), the paper's Eq. (17) (alpha = 1.8) and no
+    preconditioner on the first energy (45 states).  Iterations per
+    standing-wave solve, solves/s, and |Delta T| against the per-state run;
+    one line per variant as it finishes."""
+    import numpy as np
+    import torch
+
+    from paper_1009_5300_amd import iobm
+    from workloads import make
+
+    torch.cuda.set_device(0)
+    w = make(4)
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
+    s.set_potential(w.V)
+    s.solve(w.energies, opts=iobm.default_opts(precision=iobm.C128))  # tune, allocate
+    rows = {}
+    for pname, pc, Es in (("lateral_fft", iobm.PC_LATERAL_FFT, list(w.energies)),
+                          ("eq17_alpha1.8", iobm.PC_TRUNCATED_LAPLACIAN, [w.energies[0]]),
+                          ("none", iobm.PC_NONE, [w.energies[0]])):
+        Tref = None
+        for mode, blk in (("per_state", 0), ("block", 1)):
+            print(json.dumps({"starting": f"{pname}/{mode}"}), flush=True)
+            o = iobm.default_opts(precision=iobm.C128, precond=pc, block=blk, max_iter=100000,
+                                  check_every=4 if pc != iobm.PC_LATERAL_FFT else 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = s.solve(Es, opts=o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            Tref = out["T"] if Tref is None else Tref
+            rows[f"{pname}/{mode}"] = {"states": len(out["T"]), "iters_per_wave": round(_iters_per_wave(out, g), 1),
+                                       "solves_per_s": round(len(out["T"]) / dt, 2), "s": round(dt, 3),
+                                       "status": int(out["status"]),
+                                       "max_dT_vs_per_state": float(np.abs(out["T"] - Tref).max())}
+            print(json.dumps({"variant": f"{pname}/{mode}", **rows[f"{pname}/{mode}"]}), flush=True)
+    print(json.dumps({"experiment": "block COCG vs per-state COCG (complex128), wide wire 48x48x128",
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,7 +400,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip plain-CG and Eq. (17) samples")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for the HBM counter calibration)")
-    ap.add_argument("--workload", default="4", choices=["3", "4", "5", "na"],
+    ap.add_argument("--workload", default="4", choices=["3", "4", "5", "na", "precision", "block"],
                     help="4: the headline wide-wire batch (default); 3: the atomic chain with the nonlocal "
                          "term on MFMA (secondary measurement); 5: the adjoint gradient dT/dV; na: iteration "
                          "counts of the paper's preconditioner experiment on synthetic Na-like wires")
@@ -295,6 +417,12 @@ def main():
     if args.gpus == 1 and args.workload == "na":
         na_sweep()
         return
+    if args.gpus == 1 and args.workload == "precision":
+        precision_sweep()
+        return
+    if args.gpus == 1 and args.workload == "block":
+        block_sweep()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the scattering states of different energies are "
               "independent, and multi-GPU runs are not part of this build (use --gpus 1).",
@@ -310,7 +438,7 @@ def main():
     torch.cuda.set_device(0)
     w = make(4)
     g = w.grid
-    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
     s.set_potential(w.V)
     opts = iobm.default_opts()
     # one-time setup (not a step): allocation of the batch workspaces and the
@@ -342,7 +470,7 @@ def main():
                "fft_planes_update": iobm.K_FFT_PLANES_UPD, "update": iobm.K_UPDATE,
                "zfilter": iobm.K_ZFILTER, "stencil_c128": iobm.K_STENCIL_C128, "boundary": iobm.K_BOUNDARY,
                "accumulate": iobm.K_ACCUMULATE, "dot": iobm.K_DOT}
-    s.profile_begin(list(classes.values()) + [iobm.K_PRECOND_FFT])
+    s.profile_begin(list(classes.values()))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(args.steps):
@@ -350,7 +478,6 @@ def main():
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     kern = {k: _kernel_stats(s, c) for k, c in classes.items()}
-    precond = _kernel_stats(s, iobm.K_PRECOND_FFT)
     s.profile_begin([])
     # the dominant single kernel by summed time
     dom_name = max((k for k in kern if kern[k]), key=lambda k: kern[k]["total_ms"])
@@ -387,7 +514,7 @@ def main():
         "all_kernels": whole,
         "setup_s": round(t_setup, 3),
         "kernels": {k: ({kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()} if v else None)
-                    for k, v in list(kern.items()) + [("precond_fft_whole", precond)]},
+                    for k, v in kern.items()},
         "solve_stats": {"per": "channel (cos + sin standing-wave solves of a +-G pair summed)",
                         "iters_mean": float(stats[:, 0].mean()), "iters_max": int(stats[:, 0].max()),
                         "refinements_mean": float(stats[:, 1].mean()),
@@ -422,22 +549,26 @@ def main():
                                              f"last energy), one complex128 COCG solve each, no preconditioner",
                                    "iters": iters, "speedup_of_value": round(value / (len(sample) / sum(dts)), 1)}
         result["max_dT_vs_plain_fp64_cg"] = float(max(dT))
-        # the paper's Eq. (17) preconditioner, batched complex64 + refinement, one energy
-        # some states need well over 50,000 iterations with this preconditioner
-        e17 = iobm.default_opts(precond=iobm.PC_TRUNCATED_LAPLACIAN, check_every=32, max_iter=400000)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        o2 = s.solve([w.energies[0]], opts=e17)
-        torch.cuda.synchronize()
-        b = time.perf_counter() - a
-        n_ok = int(sum(x[2] == 0 for x in o2["stats"]))
-        result["paper_pcg_eq17"] = {"value": round(n_ok / b, 3), "unit": "solves/s (converged channels only)",
-                                    "sample": f"first energy, {len(o2['T'])} channels, alpha=1.8",
-                                    "iters_mean": float(np.mean([x[0] for x in o2["stats"]])),
-                                    "status": int(o2["status"]),
-                                    "not_converged": int(sum(x[2] != 0 for x in o2["stats"])),
-                                    "max_rel_residual": float(max(x[3] for x in o2["stats"])),
-                                    "max_dT_vs_value": float(np.abs(o2["T"] - out["T"][:len(o2["T"])]).max())}
+        # the paper's Eq. (17) preconditioner against no preconditioner, both
+        # in complex128 (weak preconditioners converge faster in complex128 than
+        # in complex64 with replacement), batched over the first energy; the
+        # paper's Table 2 reports 1.27 / 1.67 / 2.24x fewer iterations at
+        # alpha = 3.0 / 2.4 / 1.8
+        pcg = {}
+        for name, pc in (("none", iobm.PC_NONE), ("eq17_alpha1.8", iobm.PC_TRUNCATED_LAPLACIAN)):
+            o = iobm.default_opts(precision=iobm.C128, precond=pc, alpha=1.8, check_every=32, max_iter=400000)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            o2 = s.solve([w.energies[0]], opts=o)
+            torch.cuda.synchronize()
+            b = time.perf_counter() - a
+            pcg[name] = {"solves_per_s": round(len(o2["T"]) / b, 3), "iters_per_wave": round(_iters_per_wave(o2, g), 1),
+                         "status": int(o2["status"]),
+                         "max_dT_vs_value": float(np.abs(o2["T"] - out["T"][:len(o2["T"])]).max())}
+        pcg["iteration_ratio_none_over_eq17"] = round(pcg["none"]["iters_per_wave"] /
+                                                      pcg["eq17_alpha1.8"]["iters_per_wave"], 2)
+        pcg["sample"] = f"first energy, {len(o2['T'])} channels, complex128, batched"
+        result["paper_pcg"] = pcg
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline()

@@ -94,8 +94,12 @@ enum { IOBM_C128 = 0,          /* complex128 throughout */
 enum { IOBM_PC_NONE = 0,
        IOBM_PC_TRUNCATED_LAPLACIAN = 1, /* Eq. (17): C0 g + C1 sum over the 6 face
                                            neighbours, C0 = 1, C1 = exp(-alpha) */
-       IOBM_PC_LATERAL_FFT = 2 };       /* exact inverse of the V = 0 operator: lateral
+       IOBM_PC_LATERAL_FFT = 2,         /* exact inverse of the V = 0 operator: lateral
                                            FFT + per-mode z Green's function */
+       IOBM_PC_JACOBI = 3 };            /* diagonal scaling (Sec. II): z = r / diag A(E),
+                                           diag A = E - V - kinetic diagonal - nonlocal
+                                           diagonal - real-space Sigma diagonal on the
+                                           face planes */
 
 typedef struct {
   int32_t precision;   /* IOBM_C128 or IOBM_C64_REFINED */
@@ -109,6 +113,30 @@ typedef struct {
   int32_t max_iter;    /* total COCG iterations per RHS; default 50000 */
   int32_t side;        /* 0: incidence from the left electrode, 1: from the right */
   int32_t check_every; /* iterations between host convergence checks; default 2 */
+  int32_t keep_direction; /* at a residual replacement: 0 = restart the search
+                          direction (p = z; default), 1 = keep it (the
+                          recurrence continues from the replaced residual; it
+                          still restarts after a breakdown, a diverging
+                          residual or a replacement that did not lower the true
+                          residual).  Ignored with IOBM_PC_LATERAL_FFT, where
+                          keeping it was measured to diverge */
+  int32_t graph;       /* 1: the iterations between two convergence checks are
+                          captured once into a HIP graph (on a stream of the
+                          library, ordered after the caller's stream by events)
+                          and replayed while the set of unconverged right-hand
+                          sides stays the same; 0: launched one by one.  Same
+                          kernels in the same order either way (bit-identical
+                          results).  Ignored while the timing hook is on.
+                          Default 0 */
+  int32_t block;       /* 0: every state iterates on its own (per-state COCG
+                          scalars); 1: block COCG per energy: the states of one
+                          energy (at most 64) share one Krylov space, with the
+                          s x s Grams P^T A P and R^T Z (FP64, matrix cores)
+                          and s x s solves in place of the scalars.  Complex128
+                          only (UNSUPPORTED with IOBM_C64_REFINED: the complex64
+                          block recurrence diverges once the columns become
+                          nearly dependent).  Default 0 */
+  int32_t pad_;
 } iobm_solve_opts;
 
 /* Per (energy, incident channel) statistics (the paper's Table 2 counts
@@ -202,6 +230,63 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
                        const int32_t* ninc, const int32_t* inc, void* psi, double* t,
                        double* T, double* R, iobm_solve_stat* st);
 
+/* Scattering matrix of each energy (the scattering condition, Eq. (7), with
+ * incidence from both electrodes; the transmission block is the T matrix of
+ * Sec. IV).  For energy e with n = nopen(E[e]) open channels (ascending ids,
+ * as iobm_channels), S[e] is 2n x 2n, rows and columns ordered [left-lead
+ * channels | right-lead channels]:
+ *     S[b nu][a mu] = sqrt(v_nu / v_mu) * amplitude of the outgoing wave in
+ *                     channel nu of lead b for a unit incident wave in
+ *                     channel mu from lead a,
+ * every amplitude (incident and outgoing) referred to the transition-region
+ * plane next to its lead (plane 0 for the left lead, nz-1 for the right).
+ * Flux conservation makes S unitary; with real V and kappa = 0 time
+ * reversal gives S[b nu][a mu] = S[a -mu][b -nu], -mu being the channel of
+ * the opposite lateral wave vector.  Runs every open channel from both
+ * sides (2 sum_e n_e scattering states).
+ *  S:  host complex128 interleaved, row-major, concatenated over energies
+ *      (sum_e 4 n_e^2 entries).
+ *  st: host [2 sum_e n_e] (left incidence first, then right), or NULL.
+ * Synchronises the stream.  Returns NOT_CONVERGED if any state missed tol. */
+iobm_status iobm_smatrix(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, const double* E, double* S,
+                         iobm_solve_stat* st);
+
+/* Lateral Bloch vector kappa = (kx, ky) (1/bohr): wave functions obey
+ * psi(r + L_mu e_mu) = exp(i kappa_mu L_mu) psi(r) across the lateral cell
+ * (Eq. (2)); the lateral waves are exp(i (G + kappa).r) (Eq. (16)) and every
+ * lateral energy, Bloch root and self-energy is taken at G + kappa (Eqs.
+ * (12)-(15)).  Channel ids are those of G, as for kappa = 0.
+ *
+ * Open channels at E and kappa: as iobm_channels. */
+iobm_status iobm_channels_bloch(iobm_ctx ctx, double E, double kx, double ky, int32_t* nopen, int32_t* ids,
+                                double* kz, double* v);
+
+/* Scattering matrices at kappa and at -kappa, for each energy (Eq. (7) with
+ * incidence from both electrodes, as iobm_smatrix, which is the case
+ * kappa = 0).  With kappa != 0 the operator is not complex symmetric
+ * (A(kappa)^T = A(-kappa)), so every state at kappa (channel mu) is solved
+ * together with its time-reversal partner at -kappa (channel -mu, the
+ * opposite lateral wave vector, same incident side) by biconjugate gradients
+ * with the bilinear form; the pair shares its iteration.
+ *  kx, ky: the Bloch vector (finite; any value, also 0 or the zone edge).
+ *  S_plus, S_minus: host complex128 interleaved, concatenated over energies;
+ *      energy e has n_e open channels (the same number at kappa and -kappa)
+ *      and its matrix is 2n_e x 2n_e, ordered [left | right], channels in
+ *      ascending ids of iobm_channels_bloch at kappa (S_plus) and at -kappa
+ *      (S_minus), flux normalised and referred to the planes next to the
+ *      leads as in iobm_smatrix.  Reciprocity gives
+ *      S_plus[b nu][a mu] = S_minus[a -mu][b -nu].
+ *  st: host [2 sum_e n_e] per pair (left incidence first), or NULL;
+ *      flux_error is that of the state at kappa.
+ *  opts: precision must be IOBM_C128 and block 0 (UNSUPPORTED otherwise);
+ *      precond, alpha, tol, max_iter and check_every apply; inner_tol,
+ *      keep_direction and graph are ignored.
+ * Errors: UNSUPPORTED with a nonlocal term set (iobm_set_nonlocal);
+ * AT_THRESHOLD; NOT_CONVERGED / BREAKDOWN if a pair missed tol (the
+ * matrices are still written).  Synchronises the stream. */
+iobm_status iobm_smatrix_bloch(iobm_ctx ctx, const iobm_solve_opts* opts, double kx, double ky, int32_t nE,
+                               const double* E, double* S_plus, double* S_minus, iobm_solve_stat* st);
+
 /* Total transmission T_tot = sum over energies and every open incident
  * channel of T_mu, and its gradient with respect to the local potential,
  * dT_tot/dV(r), by one adjoint solve per channel with the same (complex
@@ -209,6 +294,45 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
  * [nz][ny][nx] (overwritten).  Synchronises the stream. */
 iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE,
                                    const double* E, double* T_total, void* dT_dV);
+
+/* Launch shapes of the volume kernels: a tuning knob, not part of the
+ * method.  By default the first solve of a context in each precision times
+ * the admissible stencil shapes and z-filter chunk lengths on its own batch
+ * and keeps the fastest (the autotuner).  Shapes change the order in which
+ * the FP64 partial sums of the COCG inner products are combined, so two
+ * contexts tuned on their own may differ in the last bits (|Delta T| at the
+ * solver tolerance).  Pinning the same shape in both makes them run the same
+ * kernels in the same order: bit-identical results for identical input.
+ * A zero field means "the default rule".
+ *   stencil:           1 = 2.5D register-window stencil, 2 = cache-based stencil
+ *   points_per_thread: 2.5D stencil, 1..4 (4 only for nf = 1); the block is
+ *                      ceil(nx*ny / ppt) threads, which must fit the variant's
+ *                      bound (1024, 1024, 768 and 640 threads)
+ *   planes_per_block:  2.5D stencil, 8, 16, 32 or 64: the longest z chunk of a
+ *                      block (small batches get shorter chunks, so that every
+ *                      compute unit has blocks)
+ *   zfilter_chunk:     lateral-Fourier preconditioner, 8, 16 or 32 planes per
+ *                      chunk of the z recursion (at most 8 chunks)
+ *   plane_fft:         1 = in-register plane FFT (square planes of 8, 12, 16,
+ *                      24, 32 or 48 points), 2 = LDS Stockham plane FFT
+ * Shapes are kept per kernel arithmetic: IOBM_C64_REFINED selects the
+ * complex64 kernels of the inner iteration, IOBM_C128 the complex128 ones
+ * (including the FP64 residual refresh of a IOBM_C64_REFINED solve).
+ * iobm_get_launch_shape returns the shape in effect for `precision` with
+ * every field resolved.
+ * iobm_set_launch_shape pins `shape` for that precision (the autotuner no
+ * longer runs for it); shape = NULL unpins, and the next solve tunes again.
+ * Errors: INVALID_ARG (field out of range), UNSUPPORTED (the shape does not
+ * fit this grid). */
+typedef struct {
+  int32_t stencil;
+  int32_t points_per_thread;
+  int32_t planes_per_block;
+  int32_t zfilter_chunk;
+  int32_t plane_fft;
+} iobm_launch_shape;
+iobm_status iobm_get_launch_shape(iobm_ctx ctx, int32_t precision, iobm_launch_shape* shape);
+iobm_status iobm_set_launch_shape(iobm_ctx ctx, int32_t precision, const iobm_launch_shape* shape);
 
 /* Benchmark hook (not part of the method): time the launches of selected
  * kernel classes with HIP events recorded on the context stream around each
@@ -240,8 +364,14 @@ enum { IOBM_K_STENCIL = 1,      /* stencil in the iteration precision; with the
        IOBM_K_ACCUMULATE = 11,  /* x += d + alpha p, d = 0 (refinement) */
        IOBM_K_NONLOCAL_C128 = 12, /* as IOBM_K_NONLOCAL, complex128 (flops) */
        IOBM_K_FFT_PLANES_DOT = 13, /* inverse plane FFT with the r^T z partials */
-       IOBM_K_FFT_PLANES_UPD = 14 };/* forward plane FFT of q with the mode-space
+       IOBM_K_FFT_PLANES_UPD = 14, /* forward plane FFT of q with the mode-space
                                    residual update R -= alpha FFT(q) */
+       IOBM_K_PRECOND_JACOBI = 15,  /* Jacobi preconditioner: read r, write z */
+       IOBM_K_BLOCK_GRAM = 16,      /* block COCG: s x s Grams of a group (MFMA f64) + their
+                                       fixed-order sum; bytes: read both blocks once */
+       IOBM_K_BLOCK_UPDATE = 17,    /* block COCG: Y (+/-)= X C or Y = Z + X C */
+       IOBM_K_BLOCH_STENCIL = 18,   /* stencil with lateral bond phases (kappa != 0), complex128 */
+       IOBM_K_BLOCH_VECTOR = 19 };  /* kappa != 0: pair inner products, updates, residuals, directions */
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask);
 iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,
                              double* alg_bytes);

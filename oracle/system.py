@@ -245,8 +245,11 @@ class Problem:
         return psi
 
     def gamma(self, E, side):
-        S = self.sigma(E, side)
-        return 1j * (S - S.conj().T)
+        key = (float(E), side, "gamma")
+        if key not in self._sig:
+            S = self.sigma(E, side)
+            self._sig[key] = 1j * (S - S.conj().T)
+        return self._sig[key]
 
     def currents(self, E, mode, psi, side="L"):
         """(T, R): current leaving through the far / near lead divided by the

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libiobm.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["modes.hip", "ops.hip", "kb.hip", "api.hip", "grad.hip"]
+SOURCES = ["modes.hip", "ops.hip", "kb.hip", "api.hip", "grad.hip", "block.hip", "bloch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("IOBM_OFFLOAD_ARCH", "gfx950")

@@ -23,23 +23,21 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
 
 // launchers from ops.hip
-hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs,
-                      int side, const ModeData* modes, zd* b, bool faces_only);
 hipError_t launch_face_norm2(iobm_ctx c, const zd* b, int nact, const int* active, Partial* part);
 template <typename T>
 hipError_t launch_init_r(iobm_ctx c, const zd* b, cplx<T>* r, int nact, const int* active);
-int dot_blocks(iobm_ctx c);
 template <typename T>
 hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active, void* part);
 template <typename T>
 hipError_t launch_update_r(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* alpha, int nact, const int* active,
                            void* part);
-enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3 };
+enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3, FIN_KEEP = 4 };
 hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag, const Partial* pa,
                           int na, const Partial* pb, int nb, int mode, int nact, const int* active,
                           int* xset = nullptr, int* dlive = nullptr);
@@ -54,8 +52,6 @@ template <typename TR>
 hipError_t launch_refresh(iobm_ctx c, const zd* x, const zd* b, zd* rface, cplx<TR>* r, int nrhs,
                           const double* E_rhs, const int* e_rhs, const ModeData* modes, const int* active,
                           Partial* part);
-hipError_t launch_readout(iobm_ctx c, int nrhs, int side, const zd* x, const ModeData* modes,
-                          const int* e_rhs, zd* amp_near, zd* amp_far);
 hipError_t launch_combine(iobm_ctx c, int nreq, const int* req_e, const int* req_mode, const int* req_c,
                           const int* req_s, const int* req_sgn, const ModeData* modes, const zd* amp_near,
                           const zd* amp_far, zd* t_out, zd* r_out, double* T, double* R);
@@ -70,6 +66,34 @@ hipError_t launch_grad_D(iobm_ctx c, int nE, int nmax, const int* base, const in
                          const zd* tamp, zd* D, const long long* dbase);
 hipError_t launch_grad(iobm_ctx c, int nE, const int* base, const long long* dbase, const zd* D, const zd* u,
                        const zd* w, double* g);
+
+// block.hip
+template <typename T>
+hipError_t launch_gram(iobm_ctx c, const cplx<T>* U, const cplx<T>* W, int ngroups, const int* cols,
+                       const int* goff, const int* gsize, const int* gid, double* part, int nblk, zd* G, int ncols);
+hipError_t launch_small_solve(iobm_ctx c, int ngroups, const int* gsize, const int* gid, const zd* G, const zd* Y,
+                              zd* Gw, zd* X, int* flag);
+template <typename T, typename TY>
+hipError_t launch_block_update(iobm_ctx c, cplx<TY>* Y, const cplx<T>* X, const cplx<T>* Z, const zd* C, int ngroups,
+                               const int* cols, const int* goff, const int* gsize, const int* gid, int nchunk,
+                               int mode, Partial* n2part, int ncols);
+
+// bloch.hip
+struct BlochPhase;
+hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const zd* x, zd* y, int nrhs, const double* E_rhs,
+                              const int* e_rhs, const int* sgn, const int* active);
+hipError_t launch_bloch_laplacian(iobm_ctx c, const BlochPhase& ph, double alpha, const zd* r, zd* z, int nrhs,
+                                  const int* sgn, const int* active);
+hipError_t launch_bloch_dot(iobm_ctx c, const zd* u, const zd* v, int npairs, const int* pairs, Partial* part,
+                            int nblk);
+hipError_t launch_bloch_scalars(iobm_ctx c, int mode, int npairs, const int* pairs, const Partial* pd, const Partial* pn,
+                                int nblk, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag);
+hipError_t launch_bloch_update(iobm_ctx c, zd* x, zd* r, const zd* p, const zd* q, const zd* alpha, int nslots,
+                               const int* active, Partial* pn, int nblk);
+hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, zd* r, const zd* y, int nslots, const int* active, Partial* pn,
+                              int nblk);
+hipError_t launch_bloch_direction(iobm_ctx c, zd* p, const zd* z, const zd* beta, int nslots, const int* active,
+                                  int nblk);
 
 namespace {
 
@@ -96,10 +120,10 @@ iobm_status fail(iobm_ctx ctx, iobm_status s, const std::string& msg) {
 enum Slot {
   S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_P2, S_Q, S_D, S_PF, S_PART, S_PARTA, S_PARTZ, S_PARTR, S_PARTN, S_SCAL,
   S_IDX, S_AMP,
-  S_TR, S_KB, S_GRAD_U, S_GRAD_D, NSLOT
+  S_TR, S_KB, S_GRAD_U, S_GRAD_D, S_BLK_PART, S_BLK_G, S_BLK_N2, NSLOT
 };
 
-void* scratch(iobm_ctx ctx, int slot, size_t bytes) {
+void* workspace(iobm_ctx ctx, int slot, size_t bytes) {
   if ((int)ctx->pool.size() < NSLOT) ctx->pool.resize(NSLOT, {nullptr, 0});
   auto& e = ctx->pool[slot];
   if (e.second < bytes) {
@@ -192,11 +216,14 @@ bool plan_ok(const FFTPlan1D& p) {
 }
 
 // --------------------------------------------------------------- modes
-// Ensure the device mode table holds exactly the energies `E` (in order).
-// Only the mode flags come back to the host; the full records are copied on
-// demand (host_modes) by the calls that report them.
-void ensure_modes(iobm_ctx ctx, const std::vector<double>& E, bool force = false) {
-  if (!force && E == ctx->modeE && ctx->modes_d) return;
+// Ensure the device mode table holds exactly the energies `E` (in order),
+// entry e at the lateral Bloch vector given by K[2e], K[2e+1] (phases per
+// lattice step; K empty: kappa = 0 throughout).  Only the mode flags come
+// back to the host; the full records are copied on demand (host_modes) by
+// the calls that report them.
+void ensure_modes(iobm_ctx ctx, const std::vector<double>& E, bool force = false,
+                  const std::vector<double>& K = std::vector<double>()) {
+  if (!force && E == ctx->modeE && K == ctx->modeK && ctx->modes_d) return;
   const size_t n = (size_t)E.size() * ctx->g.nxy;
   if (ctx->modes_cap < n) {
     if (ctx->modes_d) (void)hipFree(ctx->modes_d);
@@ -210,20 +237,26 @@ void ensure_modes(iobm_ctx ctx, const std::vector<double>& E, bool force = false
     if (ctx->sig_d) (void)hipFree(ctx->sig_d);
     if (ctx->sig_f) (void)hipFree(ctx->sig_f);
     if (ctx->mode_flags_d) (void)hipFree(ctx->mode_flags_d);
+    if (ctx->sdiag_d) (void)hipFree(ctx->sdiag_d);
     ctx->sig_d = nullptr;
     ctx->sig_f = nullptr;
     ctx->mode_flags_d = nullptr;
+    ctx->sdiag_d = nullptr;
     ctx->sig_cap = 0;
     HIPCHK(hipMalloc(&ctx->sig_d, ns * sizeof(zd)));
     HIPCHK(hipMalloc(&ctx->sig_f, ns * sizeof(zf)));
     HIPCHK(hipMalloc(&ctx->mode_flags_d, n * sizeof(int)));
+    HIPCHK(hipMalloc(&ctx->sdiag_d, (size_t)E.size() * ctx->g.nxy * ctx->g.nf * sizeof(zd)));
     ctx->sig_cap = ns;
   }
   ctx->modeE.clear();
+  ctx->modeK.clear();
   ctx->modes_h_valid = false;
   double* Ed = upload(ctx, S_IDX, E);
-  HIPCHK(launch_modes(ctx, Ed, (int)E.size(), ctx->modes_d));
+  double* Kd = K.empty() ? nullptr : upload(ctx, S_IDX, K, 64 * 1024);
+  HIPCHK(launch_modes(ctx, Ed, (int)E.size(), ctx->modes_d, Kd));
   HIPCHK(launch_sigma_tables(ctx, (int)E.size(), ctx->modes_d, ctx->sig_d, ctx->sig_f, ctx->mode_flags_d));
+  HIPCHK(launch_sigma_diag(ctx, (int)E.size()));
   int* fh = (int*)pinned_readback(ctx, n * sizeof(int));
   HIPCHK(hipMemcpyAsync(fh, ctx->mode_flags_d, n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   stream_sync(ctx);
@@ -245,6 +278,7 @@ void ensure_modes(iobm_ctx ctx, const std::vector<double>& E, bool force = false
       }
     }
   ctx->modeE = E;
+  ctx->modeK = K;
 }
 
 // The full mode records of the current table on the host.
@@ -283,6 +317,21 @@ struct SolveOut {
   std::vector<double> rel;
 };
 
+// Executable graph of one check's iterations, valid for one active list
+// (count and device pointer) and one parity of the direction buffers.
+struct CheckGraph {
+  hipGraphExec_t exec = nullptr;
+  int nact = -1;
+  const int* act = nullptr;
+  const void* pold = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    nact = -1;
+  }
+  ~CheckGraph() { reset(); }
+};
+
 // Batched preconditioned COCG with FP64 residual replacement (mixed precision).
 //
 // The Krylov recurrences run in type T (complex64 or complex128) on the
@@ -290,18 +339,17 @@ struct SolveOut {
 // d += alpha p, r -= alpha q, z = P r, beta = (r^T z) / rho, p = z + beta p,
 // with every inner product accumulated in FP64.  The step d += alpha p is
 // deferred to the next operator pass, which reads p anyway (alpha then
-// holds the pending factor; a restart clears it).  When the recursively
-// updated residual of a right-hand side has fallen by the factor `delta`
-// (opts.inner_tol) since its last update, or below the target, the
-// correction is folded into x in FP64 (x += d + alpha p, d = 0), the true residual
-// r_hi = b - A x is formed with the complex128 operator, the iterated
-// residual is replaced by it and the direction restarts (p = z).  Keeping
-// the old direction across the replacement is fragile once the
-// preconditioner itself runs in complex64 (some states diverged), and with
-// a strong preconditioner the restarts cost no extra iterations.  A
-// right-hand side is done when its true residual is <= tol ||b||; a
-// breakdown (vanishing rho or p^T q) or a diverging iterated residual
-// forces an early replacement.
+// holds the pending factor).  When the recursively updated residual of a
+// right-hand side has fallen by the factor `delta` (opts.inner_tol) since
+// its last update, or below the target, the correction is folded into x in
+// FP64 (x += d + alpha p, d = 0), the true residual r = b - A x is formed
+// with the complex128 operator and the iterated residual is replaced by it
+// (a reliable update in the sense of van der Vorst and Ye).  The search
+// direction then restarts (p = z), or, with opts.keep_direction, is kept
+// across the replacement (beta from the replaced residual, p = z + beta p)
+// unless the state broke down (vanishing rho or p^T q), diverged, or its true
+// residual did not improve.  A right-hand side is done when its true
+// residual is <= tol ||b||.
 template <typename T>
 void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const zd* b, zd* x, SolveOut& out) {
   const int nb = B.n;
@@ -317,34 +365,34 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   std::vector<int> all(nb);
   for (int i = 0; i < nb; ++i) all[i] = i;
   int* all_d = upload(ctx, S_IDX, all, 32 * 1024);
-  zd* rhi = (zd*)scratch(ctx, S_RHI, (size_t)nb * vol * sizeof(zd));
-  cplx<T>* d = (cplx<T>*)scratch(ctx, S_D, vb);
-  cplx<T>* r = (cplx<T>*)scratch(ctx, S_R, vb);
-  cplx<T>* pa = (cplx<T>*)scratch(ctx, S_P, vb);   // direction, two buffers used in turn
-  cplx<T>* pb = (cplx<T>*)scratch(ctx, S_P2, vb);
-  cplx<T>* q = (cplx<T>*)scratch(ctx, S_Q, vb);
-  cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)scratch(ctx, S_Z, vb);
-  cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)scratch(ctx, S_PF, vb) : nullptr;
+  zd* rhi = (zd*)workspace(ctx, S_RHI, (size_t)nb * vol * sizeof(zd));
+  cplx<T>* d = (cplx<T>*)workspace(ctx, S_D, vb);
+  cplx<T>* r = (cplx<T>*)workspace(ctx, S_R, vb);
+  cplx<T>* pa = (cplx<T>*)workspace(ctx, S_P, vb);   // direction, two buffers used in turn
+  cplx<T>* pb = (cplx<T>*)workspace(ctx, S_P2, vb);
+  cplx<T>* q = (cplx<T>*)workspace(ctx, S_Q, vb);
+  cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)workspace(ctx, S_Z, vb);
+  cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)workspace(ctx, S_PF, vb) : nullptr;
   const int nblk = dot_blocks(ctx);
   const int nz_slots = precond_slots(ctx, o.precond);
-  Partial* part = (Partial*)scratch(ctx, S_PART, (size_t)nb * nblk * sizeof(Partial));
-  Partial* part_pq = (Partial*)scratch(ctx, S_PARTA, (size_t)nb * PQ_SLOTS * sizeof(Partial));
+  Partial* part = (Partial*)workspace(ctx, S_PART, (size_t)nb * nblk * sizeof(Partial));
+  Partial* part_pq = (Partial*)workspace(ctx, S_PARTA, (size_t)nb * PQ_SLOTS * sizeof(Partial));
   Partial* part_rz = o.precond == IOBM_PC_NONE
                          ? part
-                         : (Partial*)scratch(ctx, S_PARTZ, (size_t)nb * nz_slots * sizeof(Partial));
-  Partial* part_rn = (Partial*)scratch(ctx, S_PARTR, (size_t)nb * PQ_SLOTS * sizeof(Partial));
+                         : (Partial*)workspace(ctx, S_PARTZ, (size_t)nb * nz_slots * sizeof(Partial));
+  Partial* part_rn = (Partial*)workspace(ctx, S_PARTR, (size_t)nb * PQ_SLOTS * sizeof(Partial));
   // with the lateral-Fourier preconditioner on square planes, the update runs
   // inside its forward transform, which writes the |r|^2 partials per plane:
   // between replacements the iterated residual lives only in lateral mode
   // space (R = FFT(r) in pf, R -= alpha FFT(q)); the real-space r is formed
   // only by a replacement, whose preconditioner pass transforms it into pf
-  const bool fuse_upd = o.precond == IOBM_PC_LATERAL_FFT && fft_reg_available(ctx);
-  Partial* part_n2 = fuse_upd ? (Partial*)scratch(ctx, S_PARTN, (size_t)nb * ctx->g.nz * sizeof(Partial)) : part;
+  const bool fuse_upd = o.precond == IOBM_PC_LATERAL_FFT && fft_reg_available<T>(ctx);
+  Partial* part_n2 = fuse_upd ? (Partial*)workspace(ctx, S_PARTN, (size_t)nb * ctx->g.nz * sizeof(Partial)) : part;
   const int n2_slots = fuse_upd ? ctx->g.nz : nblk;
   // per-rhs scalars; |r|^2 and the breakdown flags are adjacent so that one
   // copy brings both to the host at a convergence check
   const size_t nb8 = ((size_t)nb + 1) & ~(size_t)1;
-  char* sc = (char*)scratch(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + 3 * sizeof(int)) + 64);
+  char* sc = (char*)workspace(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + 3 * sizeof(int)) + 64);
   zd* rho = (zd*)sc;
   zd* alpha = rho + nb;
   zd* beta = alpha + nb;
@@ -364,6 +412,9 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   const double tol2 = o.tol * o.tol;
   const double delta2 = lowp ? o.inner_tol * o.inner_tol : 0.0;
   const int check = std::max(1, o.check_every);
+  // keeping the direction across replacements diverged with the
+  // lateral-Fourier preconditioner (measured): it always restarts there
+  const bool keep_dir = o.keep_direction != 0 && o.precond != IOBM_PC_LATERAL_FFT;
 
   // z = P r for the listed rhs, with the partials of r^T z in part_rz (for
   // P = I they come from a separate reduction)
@@ -372,10 +423,14 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       HIPCHK(launch_precond_laplacian<T>(ctx, o.alpha, r, z, nact, ad, part_rz));
     else if (o.precond == IOBM_PC_LATERAL_FFT)
       HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nact, e_d, modes, ad, part_rz));
+    else if (o.precond == IOBM_PC_JACOBI)
+      HIPCHK(launch_precond_jacobi<T>(ctx, r, z, nact, e_d, E_d, ad, part_rz));
     else
       HIPCHK(launch_dot<T>(ctx, r, r, nact, ad, part_rz));
   };
-  std::vector<int> since(nb, 0);  // steps since the last restart, per rhs (d holds data from 2 on)
+  std::vector<int> since(nb, 0);  // steps since the last replacement, per rhs (d holds data from 2 on)
+  std::vector<char> kept(nb, 0);  // the last replacement kept the direction (p_old is read at its first step)
+  std::vector<char> badv(nb, 0);  // breakdown or divergence seen at the last check
   cplx<T>* pold = pa;  // the direction of the last step (its update pending)
   cplx<T>* pnew = pb;
   // Refinement of the listed rhs: x += d + alpha p, d = 0, r = b - A x in FP64 (stored
@@ -434,7 +489,7 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   int nact = (int)act.size();
   int* act_d = upload(ctx, S_IDX, act, 64 * 1024);
   HIPCHK(launch_init_r<T>(ctx, b, r, nact, act_d));
-  if (!(lowp ? ctx->tuned_c64 : ctx->tuned_c128)) {
+  if (!ctx->tuned[prec_index<T>()]) {
     // the shapes are timed on the fused operator with p_old = 0 and a
     // nonzero beta (0x3F bytes: 4.8e-4), so that every stream is read
     HIPCHK(hipMemsetAsync(pa, 0, vb, ctx->stream));
@@ -454,15 +509,21 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   //              R = FFT(r) from FFT(q))
   //   precond:   z = P r, partials of r^T z
   // with the scalar steps (alpha; beta, rho, |r|^2) in between.
-  while (nact > 0) {
+  // one check's iterations, launched one by one or captured into a graph
+  const bool graphs = o.graph != 0 && ctx->prof_mask == 0;
+  CheckGraph cg;
+  auto enqueue_check = [&]() {
     for (int k = 0; k < check; ++k) {
-      int nfresh = 0, nfirstd = 0;  // byte count only: steps since the restart 0 and 1
-      for (int i : act) { nfresh += since[i] == 0; nfirstd += since[i] == 1; }
-      ApplyFuse<T> F{z, pold, beta, pnew, part_pq, alpha, d, dlive, nfresh, nfirstd};
+      int nfresh = 0, nfirstd = 0, nkept = 0;  // byte count only: steps since the replacement 0 and 1
+      for (int i : act) {
+        nfresh += since[i] + k == 0 && !kept[i];
+        nkept += since[i] + k == 0 && kept[i];
+        nfirstd += since[i] + k == 1;
+      }
+      ApplyFuse<T> F{z, pold, beta, pnew, part_pq, alpha, d, dlive, nfresh, nfirstd, nkept};
       HIPCHK(launch_apply<T>(ctx, nullptr, q, nact, E_d, e_d, modes, act_d, &F));
       HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_pq, PQ_SLOTS, nullptr, 0, FIN_ALPHA, nact, act_d,
                             nullptr, dlive));
-      for (int i : act) ++since[i];
       if (fuse_upd) {
         FftUpd<T> U;
         U.q = q; U.alpha = alpha; U.n2part = part_n2;
@@ -475,6 +536,51 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
                             act_d));
       std::swap(pold, pnew);
     }
+  };
+  auto run_check = [&]() {
+    if (!graphs) {
+      enqueue_check();
+      return;
+    }
+    if (!ctx->cap_stream) {
+      HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      for (hipEvent_t& ev : ctx->cap_ev) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    if (!cg.exec || cg.nact != nact || cg.act != act_d || cg.pold != (const void*)pold) {
+      cg.reset();
+      const void* p0 = pold;
+      hipStream_t caller = ctx->stream;
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+      ctx->stream = ctx->cap_stream;  // every launcher enqueues on ctx->stream
+      try {
+        enqueue_check();
+      } catch (Fail&) {
+        ctx->stream = caller;
+        (void)hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      ctx->stream = caller;
+      HIPCHK(hipStreamEndCapture(ctx->cap_stream, &graph));
+      const hipError_t ie = hipGraphInstantiate(&cg.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(ie);
+      cg.nact = nact;
+      cg.act = act_d;
+      cg.pold = p0;
+      if (check % 2) std::swap(pold, pnew);  // capture swapped them on the host: back to the launch state
+    }
+    HIPCHK(hipEventRecord(ctx->cap_ev[0], ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->cap_stream, ctx->cap_ev[0], 0));
+    HIPCHK(hipGraphLaunch(cg.exec, ctx->cap_stream));
+    HIPCHK(hipEventRecord(ctx->cap_ev[1], ctx->cap_stream));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->cap_ev[1], 0));
+    if (check % 2) std::swap(pold, pnew);
+  };
+  while (nact > 0) {
+    run_check();
+    for (int i : act) since[i] += check;
     HIPCHK(hipMemcpyAsync(rbh, rn2, check_bytes, hipMemcpyDeviceToHost, ctx->stream));
     stream_sync(ctx);
     // which rhs fold their correction into x and refresh the residual
@@ -483,42 +589,50 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
       out.iters[i] += check;
       const double r2 = rn2_h[i];
       const bool bad = flag_h[i] || !(r2 == r2) || r2 > 1e4 * maxr2[i];  // breakdown or divergence
-      if (bad || r2 <= 0.25 * tol2 * bn2[i] || r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter) upd.push_back(i);
+      badv[i] = bad;
+      if (bad || r2 <= 0.25 * tol2 * bn2[i] || r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter)
+        upd.push_back(i);
       else maxr2[i] = std::max(maxr2[i], r2);
     }
     if (upd.empty()) continue;
     refresh(upd, 7);
-    std::vector<int> cont;  // updated rhs that go on iterating, from a restart
+    std::vector<int> rst, keep;  // updated rhs that go on iterating: from a restart / with the old direction
     for (int i : upd) {
       out.refin[i] += 1;
       const double t2 = tn2_h[i];
       if (t2 <= tol2 * bn2[i]) continue;  // converged
       if (out.iters[i] >= o.max_iter) { out.status[i] = IOBM_E_NOT_CONVERGED; continue; }
+      const bool improved = t2 < best[i];
       if (t2 < 0.25 * best[i]) { best[i] = t2; stall[i] = 0; }
       else if (++stall[i] >= 6) {
         out.status[i] = flag_h[i] ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
         continue;
       }
-      cont.push_back(i);
+      (keep_dir && !badv[i] && improved && since[i] > 0 ? keep : rst).push_back(i);
       maxr2[i] = t2;
     }
     std::vector<char> gone(nb, 0);
     for (int i : upd) gone[i] = 1;
-    for (int i : cont) gone[i] = 0;
-    std::vector<int> lists(cont);  // one upload: [restarted rhs | new active list]
+    for (int i : rst) gone[i] = 0;
+    for (int i : keep) gone[i] = 0;
+    std::vector<int> lists(rst);  // one upload: [restarted rhs | kept rhs | new active list]
+    lists.insert(lists.end(), keep.begin(), keep.end());
     for (int i : act)
       if (!gone[i]) lists.push_back(i);
-    const int nc = (int)cont.size();
+    const int nr = (int)rst.size(), nk = (int)keep.size(), nc = nr + nk;
     int* ld = upload(ctx, S_IDX, lists, 64 * 1024);
     if (nc > 0) {
-      // z = P r, rho = r^T z, beta = 0 (p_new = z next)
+      // z = P r of the replaced residual, rho = r^T z; a restart sets beta = 0
+      // (p_new = z next), a kept direction beta = rho' / rho (p_new = z + beta p)
       precond(nc, ld);
-      HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nc, ld));
+      if (nr) HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nr, ld));
+      if (nk) HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_KEEP, nk, ld + nr));
     }
     act.assign(lists.begin() + nc, lists.end());
     nact = (int)act.size();
     act_d = ld + nc;  // the old list's region was rewritten
-    for (int i : cont) since[i] = 0;
+    for (int i : rst) { since[i] = 0; kept[i] = 0; }
+    for (int i : keep) { since[i] = 0; kept[i] = 1; }
   }
   for (int i = 0; i < nb; ++i) {
     out.rel[i] = bn2[i] > 0 ? sqrt(tn2_h[i] / bn2[i]) : 0.0;
@@ -526,7 +640,275 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   }
 }
 
+// Block COCG per energy (opts.block = 1).  The states of one energy form a
+// group of s <= 64 columns that share the Krylov space: with R, Z, P, Q the
+// blocks of the group's residuals, preconditioned residuals, directions and
+// operator images,
+//   alpha = (P^T Q)^-1 (R^T Z),  D += P alpha,  R -= Q alpha,  Z = M R,
+//   beta = (R^T Z)_old^-1 (R^T Z)_new,  P = Z + P beta,
+// with the s x s Grams accumulated in FP64 on the matrix cores and solved
+// in FP64.  The recurrences run in complex128 on the correction D of the
+// solution x (the driver is written for either iteration precision, but
+// solve_batch admits complex128 only).  A group is refreshed (x += D, the
+// true residual r = b - A x, converged columns leave, the recursion
+// restarts with P = Z) when a column's iterated residual reaches the
+// target, falls by opts.inner_tol (complex64), diverges, or a Gram solve
+// breaks down (the block has become rank deficient).
+template <typename T>
+void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const zd* b, zd* x, SolveOut& out) {
+  const int nb = B.n;
+  const long long vol = ctx->g.npts;
+  out.iters.assign(nb, 0);
+  out.refin.assign(nb, 0);
+  out.status.assign(nb, IOBM_OK);
+  out.rel.assign(nb, 0.0);
+  if (nb == 0) return;
+  // groups: the consecutive states of one energy
+  std::vector<int> gfirst, gsz;
+  for (int i = 0; i < nb; ++i) {
+    if (i == 0 || B.e[i] != B.e[i - 1]) {
+      gfirst.push_back(i);
+      gsz.push_back(0);
+    }
+    gsz.back()++;
+  }
+  const int ng = (int)gfirst.size();
+  for (int g = 0; g < ng; ++g)
+    if (gsz[g] > 64) {
+      ctx->err = "block COCG takes at most 64 states per energy";
+      throw Fail{IOBM_E_UNSUPPORTED};
+    }
+  const size_t vb = (size_t)nb * vol * sizeof(cplx<T>);
+  int* e_d = upload(ctx, S_IDX, B.e, 0);
+  double* E_d = upload(ctx, S_IDX, B.E, 16 * 1024);
+  std::vector<int> all(nb);
+  for (int i = 0; i < nb; ++i) all[i] = i;
+  int* all_d = upload(ctx, S_IDX, all, 32 * 1024);
+  zd* rhi = (zd*)workspace(ctx, S_RHI, (size_t)nb * vol * sizeof(zd));
+  cplx<T>* d = (cplx<T>*)workspace(ctx, S_D, vb);
+  cplx<T>* r = (cplx<T>*)workspace(ctx, S_R, vb);
+  cplx<T>* pa = (cplx<T>*)workspace(ctx, S_P, vb);
+  cplx<T>* pb = (cplx<T>*)workspace(ctx, S_P2, vb);
+  cplx<T>* q = (cplx<T>*)workspace(ctx, S_Q, vb);
+  cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)workspace(ctx, S_Z, vb);
+  cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)workspace(ctx, S_PF, vb) : nullptr;
+  const int nblk_g = std::min(128, std::max(16, 512 / ng));
+  double* gpart = (double*)workspace(ctx, S_BLK_PART, (size_t)ng * nblk_g * 64 * 64 * 4 * sizeof(double));
+  const size_t gmat = (size_t)64 * 64;
+  zd* gm = (zd*)workspace(ctx, S_BLK_G, 6 * (size_t)ng * gmat * sizeof(zd));
+  zd* G1 = gm;
+  zd* G2 = gm + (size_t)ng * gmat;
+  zd* G2n = gm + 2 * (size_t)ng * gmat;
+  zd* AL = gm + 3 * (size_t)ng * gmat;
+  zd* BE = gm + 4 * (size_t)ng * gmat;
+  zd* GW = gm + 5 * (size_t)ng * gmat;
+  const int nchunk = (int)std::min<long long>(256, (vol + 63) / 64);
+  Partial* n2p = (Partial*)workspace(ctx, S_BLK_N2, (size_t)nb * nchunk * sizeof(Partial));
+  const int nblk = dot_blocks(ctx);
+  Partial* part = (Partial*)workspace(ctx, S_PART, (size_t)nb * nblk * sizeof(Partial));
+  Partial* part_rn = (Partial*)workspace(ctx, S_PARTR, (size_t)nb * PQ_SLOTS * sizeof(Partial));
+  const size_t nb8 = ((size_t)nb + 1) & ~(size_t)1, ng8 = ((size_t)ng + 1) & ~(size_t)1;
+  char* sc = (char*)workspace(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + 3 * sizeof(int)) +
+                                             2 * ng8 * sizeof(int) + 64);
+  zd* rho = (zd*)sc;
+  zd* alpha = rho + nb;  // zero: x += d + 0 p at a refresh
+  zd* beta = alpha + nb;
+  double* rn2 = (double*)(beta + nb);
+  int* flag = (int*)(rn2 + nb);
+  double* tn2 = (double*)(flag + nb8);
+  int* xset = (int*)(tn2 + nb8);
+  int* dlive = xset + nb8;
+  int* gflag = dlive + nb8;  // [2][ng]: breakdown of the alpha and the beta solve
+  const size_t chk = (size_t)nb * sizeof(double);
+  char* rbh = (char*)pinned_readback(ctx, chk + nb8 * sizeof(int) + (size_t)nb * sizeof(double) + 2 * ng8 * sizeof(int) + 64);
+  const double* rn2_h = (const double*)rbh;
+  int* gflag_h = (int*)(rbh + chk);
+  double* tn2_pin = (double*)(rbh + chk + 2 * ng8 * sizeof(int));
+  if (ctx->kb.ncen > 0) (void)kb_scratch(ctx, kb_proj_bytes(ctx, nb));
+  const ModeData* modes = ctx->modes_d;
+  const bool lowp = sizeof(T) == sizeof(float);
+  const double tol2 = o.tol * o.tol;
+  const double delta2 = lowp ? o.inner_tol * o.inner_tol : 0.0;
+  const int check = std::max(1, o.check_every);
+
+  auto precond = [&](int n, const int* ld) {
+    if (o.precond == IOBM_PC_TRUNCATED_LAPLACIAN) HIPCHK(launch_precond_laplacian<T>(ctx, o.alpha, r, z, n, ld));
+    else if (o.precond == IOBM_PC_LATERAL_FFT) HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, n, e_d, modes, ld));
+    else if (o.precond == IOBM_PC_JACOBI) HIPCHK(launch_precond_jacobi<T>(ctx, r, z, n, e_d, E_d, ld));
+  };
+  auto read_tn2 = [&](std::vector<double>& dst) {
+    HIPCHK(hipMemcpyAsync(tn2_pin, tn2, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    memcpy(dst.data(), tn2_pin, nb * sizeof(double));
+  };
+  // group lists on the device: [gid | goff | gsize | cols] in one upload
+  struct Groups {
+    int n = 0, ncols = 0;
+    const int *gid = nullptr, *goff = nullptr, *gsize = nullptr, *cols = nullptr;
+  };
+  auto make_groups = [&](const std::vector<int>& gl, const std::vector<std::vector<int>>& gc, int region) {
+    Groups G;
+    G.n = (int)gl.size();
+    std::vector<int> buf(3 * G.n);
+    for (int k = 0; k < G.n; ++k) {
+      buf[k] = gl[k];
+      buf[G.n + k] = G.ncols;
+      buf[2 * G.n + k] = (int)gc[gl[k]].size();
+      G.ncols += (int)gc[gl[k]].size();
+    }
+    for (int k = 0; k < G.n; ++k) buf.insert(buf.end(), gc[gl[k]].begin(), gc[gl[k]].end());
+    const int* dptr = upload(ctx, S_IDX, buf, (size_t)region * 8192);
+    G.gid = dptr;
+    G.goff = dptr + G.n;
+    G.gsize = dptr + 2 * G.n;
+    G.cols = dptr + 3 * G.n;
+    return G;
+  };
+  // (re)start the block recursion of the listed groups: Z = M R, G2 = R^T Z, P = Z
+  auto start_groups = [&](const Groups& S) {
+    if (S.n == 0) return;
+    precond(S.ncols, S.cols);
+    HIPCHK(launch_gram<T>(ctx, r, z, S.n, S.cols, S.goff, S.gsize, S.gid, gpart, nblk_g, G2, S.ncols));
+    HIPCHK((launch_convert<T, T>(ctx, z, pa, S.ncols, S.cols)));
+  };
+
+  // start: x = 0, d = 0, r = b; the refresh's partial slots start at zero
+  // (slots past the stencil chunks and the electrode faces are never written)
+  HIPCHK(hipMemsetAsync(part_rn, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
+  HIPCHK((launch_convert<double, double>(ctx, nullptr, x, nb, all_d)));
+  HIPCHK((launch_convert<T, T>(ctx, nullptr, d, nb, all_d)));
+  HIPCHK(hipMemsetAsync(alpha, 0, nb * sizeof(zd), ctx->stream));
+  HIPCHK(hipMemsetD32Async((hipDeviceptr_t)xset, 1, 2 * nb8, ctx->stream));  // xset and dlive: x and d hold data
+  HIPCHK(launch_face_norm2(ctx, b, nb, all_d, part));
+  HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, 1, nullptr, 0, FIN_NORM, nb, all_d));
+  std::vector<double> bn2(nb), tn2_h(nb);
+  read_tn2(bn2);
+  tn2_h = bn2;
+  HIPCHK(launch_init_r<T>(ctx, b, r, nb, all_d));
+  std::vector<std::vector<int>> gc(ng);
+  std::vector<int> glist;
+  for (int g = 0; g < ng; ++g) {
+    for (int i = gfirst[g]; i < gfirst[g] + gsz[g]; ++i)
+      if (bn2[i] > 0) gc[g].push_back(i);
+    if (!gc[g].empty()) glist.push_back(g);
+  }
+  std::vector<double> maxr2(bn2), best(bn2);
+  std::vector<int> stall(nb, 0);
+  std::vector<char> want(nb, 0);  // the column itself asked for the group's refresh
+  Groups A = make_groups(glist, gc, 8);
+  start_groups(A);
+  int it = 0;
+  while (A.n > 0) {
+    for (int k = 0; k < check; ++k) {
+      HIPCHK(launch_apply<T>(ctx, pa, q, A.ncols, E_d, e_d, modes, A.cols));
+      HIPCHK(launch_gram<T>(ctx, pa, q, A.n, A.cols, A.goff, A.gsize, A.gid, gpart, nblk_g, G1, A.ncols));
+      HIPCHK(launch_small_solve(ctx, A.n, A.gsize, A.gid, G1, G2, GW, AL, gflag));
+      HIPCHK((launch_block_update<T, T>(ctx, d, pa, nullptr, AL, A.n, A.cols, A.goff, A.gsize, A.gid, nchunk, 0,
+                                        nullptr, A.ncols)));
+      HIPCHK((launch_block_update<T, T>(ctx, r, q, nullptr, AL, A.n, A.cols, A.goff, A.gsize, A.gid, nchunk, 1, n2p,
+                                        A.ncols)));
+      precond(A.ncols, A.cols);
+      HIPCHK(launch_gram<T>(ctx, r, z, A.n, A.cols, A.goff, A.gsize, A.gid, gpart, nblk_g, G2n, A.ncols));
+      HIPCHK(launch_small_solve(ctx, A.n, A.gsize, A.gid, G2, G2n, GW, BE, gflag + ng8));
+      std::swap(G2, G2n);
+      HIPCHK((launch_block_update<T, T>(ctx, pb, pa, z, BE, A.n, A.cols, A.goff, A.gsize, A.gid, nchunk, 2, nullptr,
+                                        A.ncols)));
+      std::swap(pa, pb);
+    }
+    it += check;
+    HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, n2p, nchunk, nullptr, 0, FIN_NORM, A.ncols, A.cols));
+    HIPCHK(hipMemcpyAsync(rbh, rn2, chk, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(gflag_h, gflag, 2 * ng8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    // groups to refresh: a group goes when any of its columns asks for it
+    // (its own target, replacement factor, divergence) or a Gram solve broke
+    // down; maxr2 tracks each column's largest iterated residual since its
+    // last refresh
+    std::vector<int> upd_g, upd_c;
+    for (int g : glist) {
+      const bool brk = gflag_h[g] || gflag_h[ng8 + g];
+      bool go = brk;
+      for (int i : gc[g]) {
+        out.iters[i] += check;
+        const double r2 = rn2_h[i];
+        const bool w = !(r2 == r2) || r2 > 1e4 * maxr2[i] || r2 <= 0.25 * tol2 * bn2[i] ||
+                       r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter;
+        want[i] = w || brk;
+        if (!w) maxr2[i] = std::max(maxr2[i], r2);
+        go = go || w;
+      }
+      if (go) {
+        upd_g.push_back(g);
+        upd_c.insert(upd_c.end(), gc[g].begin(), gc[g].end());
+      }
+    }
+    if (upd_g.empty()) continue;
+    // refresh: x += d, d = 0, r = b - A x in FP64 (stored in the iteration precision)
+    {
+      int* ld = upload(ctx, S_IDX, upd_c, 7 * 8192);
+      const int n = (int)upd_c.size();
+      HIPCHK(launch_accumulate<T>(ctx, x, d, pa, alpha, xset, dlive, n, ld, 0, 0));
+      HIPCHK((launch_convert<T, T>(ctx, nullptr, d, n, ld)));
+      if (ctx->kb.ncen == 0) {
+        HIPCHK(launch_refresh<T>(ctx, x, b, rhi, r, n, E_d, e_d, modes, ld, part_rn));
+        HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part_rn, PQ_SLOTS, nullptr, 0, FIN_NORM, n, ld));
+      } else {
+        HIPCHK(launch_apply<double>(ctx, x, rhi, n, E_d, e_d, modes, ld));
+        HIPCHK(launch_residual<double>(ctx, b, rhi, n, ld));
+        HIPCHK(launch_dot<double>(ctx, rhi, rhi, n, ld, part));
+        HIPCHK(launch_finish2(ctx, rho, alpha, beta, tn2, flag, part, nblk, nullptr, 0, FIN_NORM, n, ld));
+        HIPCHK((launch_convert<T, double>(ctx, rhi, r, n, ld)));
+      }
+      read_tn2(tn2_h);
+    }
+    std::vector<int> restart_g;
+    for (int g : upd_g) {
+      std::vector<int> keep;
+      for (int i : gc[g]) {
+        out.refin[i] += 1;
+        const double t2 = tn2_h[i];
+        if (t2 <= tol2 * bn2[i]) continue;
+        if (out.iters[i] >= o.max_iter) { out.status[i] = IOBM_E_NOT_CONVERGED; continue; }
+        // a refresh the column asked for must improve its true residual
+        // (six in a row without a fourfold gain end it); one triggered by
+        // another column of the group does not count against it
+        if (t2 < 0.25 * best[i]) { best[i] = t2; stall[i] = 0; }
+        else if (want[i] && ++stall[i] >= 6) {
+          out.status[i] = (gflag_h[g] || gflag_h[ng8 + g]) ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
+          continue;
+        }
+        maxr2[i] = t2;
+        keep.push_back(i);
+      }
+      gc[g] = keep;
+      if (!keep.empty()) restart_g.push_back(g);
+    }
+    std::vector<int> nl;
+    for (int g : glist)
+      if (!gc[g].empty()) nl.push_back(g);
+    glist = nl;
+    A = make_groups(glist, gc, 8);
+    start_groups(make_groups(restart_g, gc, 16));
+  }
+  (void)it;
+  for (int i = 0; i < nb; ++i) {
+    out.rel[i] = bn2[i] > 0 ? sqrt(tn2_h[i] / bn2[i]) : 0.0;
+    if (out.status[i] == IOBM_OK && bn2[i] > 0 && tn2_h[i] > tol2 * bn2[i]) out.status[i] = IOBM_E_NOT_CONVERGED;
+  }
+}
+
 void solve_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const zd* b, zd* x, SolveOut& out) {
+  if (o.block) {
+    // the complex64 block recurrence loses the small differences between
+    // the nearly dependent residual columns of a group and diverges after a
+    // few replacements: block COCG runs in complex128
+    if (o.precision != IOBM_C128) {
+      ctx->err = "block COCG runs in complex128 only (opts.precision = IOBM_C128)";
+      throw Fail{IOBM_E_UNSUPPORTED};
+    }
+    solve_block_batch<double>(ctx, o, B, b, x, out);
+    return;
+  }
   if (o.precision == IOBM_C64_REFINED) solve_rhs_batch<float>(ctx, o, B, b, x, out);
   else solve_rhs_batch<double>(ctx, o, B, b, x, out);
 }
@@ -536,13 +918,14 @@ void validate_opts(iobm_ctx ctx, const iobm_solve_opts* o) {
   if (o->precision != IOBM_C128 && o->precision != IOBM_C64_REFINED) {
     ctx->err = "unknown precision"; throw Fail{IOBM_E_INVALID_ARG};
   }
-  if (o->precond < IOBM_PC_NONE || o->precond > IOBM_PC_LATERAL_FFT) {
+  if (o->precond < IOBM_PC_NONE || o->precond > IOBM_PC_JACOBI) {
     ctx->err = "unknown preconditioner"; throw Fail{IOBM_E_INVALID_ARG};
   }
   if (!(o->tol > 0 && o->tol < 1) || !(o->inner_tol > 0 && o->inner_tol < 1) || o->max_iter < 1 ||
-      o->check_every < 1 ||
+      o->check_every < 1 || (o->keep_direction != 0 && o->keep_direction != 1) || (o->graph != 0 && o->graph != 1) || (o->block != 0 && o->block != 1) ||
       (o->side != 0 && o->side != 1) || !(o->alpha > 0) || !isfinite(o->alpha)) {
-    ctx->err = "invalid solver option (tol, inner_tol in (0,1), max_iter >= 1, side 0/1, alpha > 0)";
+    ctx->err = "invalid solver option (tol, inner_tol in (0,1), max_iter >= 1, side 0/1, keep_direction 0/1, graph 0/1, "
+               "block 0/1, alpha > 0)";
     throw Fail{IOBM_E_INVALID_ARG};
   }
 }
@@ -601,6 +984,252 @@ void plan_requests(iobm_ctx ctx, int nE, const double* E, const int* ninc, const
   }
 }
 
+// One batched solve of every requested (energy, channel) pair and its
+// readout.  The device results (solutions x, per-request amplitudes t_out
+// and r_out [nreq][nxy], T and R in TR [2 nreq]) live in the workspace pool
+// until the next call; the request lists are on the device (qc, qs, qg).
+struct SolveRun {
+  Batch B;
+  Request Q;
+  SolveOut so;
+  zd* x = nullptr;
+  zd* t_out = nullptr;
+  zd* r_out = nullptr;
+  double* TR = nullptr;
+  int *qc = nullptr, *qs = nullptr, *qg = nullptr;
+};
+
+void run_solve(iobm_ctx ctx, const iobm_solve_opts& o, int nE, const double* E, const int* ninc, const int* inc,
+               SolveRun& run) {
+  plan_requests(ctx, nE, E, ninc, inc, run.B, run.Q);
+  const int nb = run.B.n, nreq = (int)run.Q.e.size();
+  const long long vol = ctx->g.npts;
+  const int nxy = ctx->g.nxy;
+  zd* b = (zd*)workspace(ctx, S_B, (size_t)nb * vol * sizeof(zd));
+  run.x = (zd*)workspace(ctx, S_XHI, (size_t)nb * vol * sizeof(zd));
+  {
+    int* e_d = upload(ctx, S_IDX, run.B.e, 0);
+    int* m_d = upload(ctx, S_IDX, run.B.mode, 16 * 1024);
+    int* k_d = upload(ctx, S_IDX, run.B.kind, 32 * 1024);
+    HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b, true));
+  }
+  solve_batch(ctx, o, run.B, b, run.x, run.so);
+  // readout of every basis solution, then combination into channels
+  zd* amp = (zd*)workspace(ctx, S_AMP, (size_t)(2 * nb + 2 * nreq) * nxy * sizeof(zd));
+  zd* amp_near = amp;
+  zd* amp_far = amp + (size_t)nb * nxy;
+  run.t_out = amp + (size_t)2 * nb * nxy;
+  run.r_out = run.t_out + (size_t)nreq * nxy;
+  run.TR = (double*)workspace(ctx, S_TR, (size_t)2 * nreq * sizeof(double) + 64);
+  int* e_d = upload(ctx, S_IDX, run.B.e, 0);
+  HIPCHK(launch_readout(ctx, nb, o.side, run.x, ctx->modes_d, e_d, amp_near, amp_far));
+  int* qe = upload(ctx, S_IDX, run.Q.e, 16 * 1024);
+  int* qm = upload(ctx, S_IDX, run.Q.mode, 24 * 1024);
+  run.qc = upload(ctx, S_IDX, run.Q.c, 32 * 1024);
+  run.qs = upload(ctx, S_IDX, run.Q.s, 40 * 1024);
+  run.qg = upload(ctx, S_IDX, run.Q.sgn, 48 * 1024);
+  HIPCHK(launch_combine(ctx, nreq, qe, qm, run.qc, run.qs, run.qg, ctx->modes_d, amp_near, amp_far, run.t_out,
+                        run.r_out, run.TR, run.TR + nreq));
+}
+
+// Per-request statistics (cos + sin solves of a +-G pair summed) and the
+// worst status.
+iobm_status request_stats(const SolveRun& run, const std::vector<double>& TRh, iobm_solve_stat* st) {
+  const int nreq = (int)run.Q.e.size();
+  iobm_status worst = IOBM_OK;
+  const SolveOut& so = run.so;
+  for (int c = 0; c < nreq; ++c) {
+    int ic = run.Q.c[c], is = run.Q.s[c];
+    int status = so.status[ic];
+    if (is >= 0 && so.status[is] != IOBM_OK) status = so.status[is];
+    if (status != IOBM_OK) worst = (iobm_status)status;
+    if (st) {
+      st[c].iters = so.iters[ic] + (is >= 0 ? so.iters[is] : 0);
+      st[c].refinements = so.refin[ic] + (is >= 0 ? so.refin[is] : 0);
+      st[c].status = status;
+      st[c].pad_ = 0;
+      st[c].rel_residual = std::max(so.rel[ic], is >= 0 ? so.rel[is] : 0.0);
+      st[c].flux_error = TRh[c] + TRh[nreq + c] - 1.0;
+    }
+  }
+  return worst;
+}
+
+// ------------------------------------------- lateral Bloch vector kappa
+// States of a solve at kappa != 0, in pairs: slot 2k at +kappa (mode-table
+// entry e, incident channel mu), slot 2k+1 its partner at -kappa (entry
+// nE + e, channel -mu), both incident from the same side.
+struct PairBatch {
+  int n = 0;               // slots (two per pair)
+  std::vector<int> e;      // mode-table entry per slot
+  std::vector<double> E;   // energy per slot
+  std::vector<int> mode;   // incident channel per slot
+  std::vector<int> sgn;    // +1 at +kappa, -1 at -kappa
+};
+
+enum { BL_ALPHA = 0, BL_BETA = 1, BL_RESTART = 2 };
+
+// Preconditioned biconjugate gradients with the bilinear form, complex128,
+// on pairs (the primary solves A(kappa) x = b, the shadow A(kappa)^T y = c
+// with A(kappa)^T = A(-kappa) and the preconditioner P(kappa)^T = P(-kappa)):
+//   q = A p, q~ = A^T p~;  alpha = rho / (p~^T q);
+//   x += alpha p, y += alpha p~;  r -= alpha q, r~ -= alpha q~;
+//   z = P r, z~ = P^T r~;  rho' = r~^T z;  beta = rho' / rho;
+//   p = z + beta p, p~ = z~ + beta p~.
+// Every inner product is summed in FP64 in a fixed order.  A pair whose
+// recursive residuals both reach tol ||b||, or that broke down (vanishing
+// rho or p~^T q) or diverged, is restarted from its true residual
+// r = b - A x (p = z); it is done when both true residuals are below
+// tol ||b||.  The operators run in the gauge u = exp(-i kappa.r) psi.
+void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& ph, const PairBatch& B, const zd* b,
+                      zd* x, SolveOut& out) {
+  const int ns = B.n, np = ns / 2;
+  const long long vol = ctx->g.npts;
+  out.iters.assign(ns, 0);
+  out.refin.assign(ns, 0);
+  out.status.assign(ns, IOBM_OK);
+  out.rel.assign(ns, 0.0);
+  if (np == 0) return;
+  const size_t vb = (size_t)ns * vol * sizeof(zd);
+  int* e_d = upload(ctx, S_IDX, B.e, 0);
+  double* E_d = upload(ctx, S_IDX, B.E, 16 * 1024);
+  int* sg_d = upload(ctx, S_IDX, B.sgn, 32 * 1024);
+  zd* r = (zd*)workspace(ctx, S_R, vb);
+  zd* p = (zd*)workspace(ctx, S_P, vb);
+  zd* q = (zd*)workspace(ctx, S_Q, vb);
+  zd* z = o.precond == IOBM_PC_NONE ? r : (zd*)workspace(ctx, S_Z, vb);
+  zd* pf = o.precond == IOBM_PC_LATERAL_FFT ? (zd*)workspace(ctx, S_PF, vb) : nullptr;
+  const int nblk = dot_blocks(ctx);
+  Partial* pd = (Partial*)workspace(ctx, S_PART, (size_t)np * nblk * sizeof(Partial));
+  Partial* pn = (Partial*)workspace(ctx, S_PARTR, (size_t)ns * nblk * sizeof(Partial));
+  char* sc = (char*)workspace(ctx, S_SCAL, (size_t)np * 3 * sizeof(zd) + (size_t)ns * sizeof(double) +
+                                                  (size_t)np * sizeof(int) + 64);
+  zd* rho = (zd*)sc;
+  zd* alpha = rho + np;
+  zd* beta = alpha + np;
+  double* rn2 = (double*)(beta + np);
+  int* flag = (int*)(rn2 + ns);
+  const size_t rb_bytes = (size_t)ns * sizeof(double) + (size_t)np * sizeof(int);
+  char* rbh = (char*)pinned_readback(ctx, rb_bytes + 64);
+  const double* rn2_h = (const double*)rbh;
+  const int* flag_h = (const int*)(rbh + (size_t)ns * sizeof(double));
+  const double tol2 = o.tol * o.tol;
+  const int check = std::max(1, o.check_every);
+  HIPCHK(hipMemsetAsync(x, 0, vb, ctx->stream));
+
+  // device lists of the pairs in `pairs_h` (pair ids): their slots (2k,
+  // 2k+1 in pair order) and their primary slots
+  int *sl_d = nullptr, *pl_d = nullptr;
+  auto set_lists = [&](const std::vector<int>& pairs_h) {
+    std::vector<int> sl, pl;
+    for (int k : pairs_h) {
+      sl.push_back(2 * k);
+      sl.push_back(2 * k + 1);
+      pl.push_back(2 * k);
+    }
+    sl_d = upload(ctx, S_IDX, sl, 40 * 1024);
+    pl_d = upload(ctx, S_IDX, pl, 48 * 1024);
+  };
+  auto precond = [&](int nsl) {
+    if (o.precond == IOBM_PC_TRUNCATED_LAPLACIAN)
+      HIPCHK(launch_bloch_laplacian(ctx, ph, o.alpha, r, z, nsl, sg_d, sl_d));
+    else if (o.precond == IOBM_PC_LATERAL_FFT)
+      HIPCHK(launch_precond_fft<double>(ctx, r, z, pf, nsl, e_d, ctx->modes_d, sl_d, nullptr));
+    else if (o.precond == IOBM_PC_JACOBI)
+      HIPCHK(launch_precond_jacobi<double>(ctx, r, z, nsl, e_d, E_d, sl_d, nullptr));
+  };
+  // r = b - A x, z = P r, rho = r~^T z, p = z for the listed pairs
+  auto restart = [&](int npr) {
+    HIPCHK(launch_bloch_apply(ctx, ph, x, q, 2 * npr, E_d, e_d, sg_d, sl_d));
+    HIPCHK(launch_bloch_resid(ctx, b, r, q, 2 * npr, sl_d, pn, nblk));
+    precond(2 * npr);
+    HIPCHK(launch_bloch_dot(ctx, r, z, npr, pl_d, pd, nblk));
+    HIPCHK(launch_bloch_scalars(ctx, BL_RESTART, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
+    HIPCHK(launch_bloch_direction(ctx, p, z, beta, 2 * npr, sl_d, nblk));
+  };
+  auto iterate = [&](int npr) {
+    HIPCHK(launch_bloch_apply(ctx, ph, p, q, 2 * npr, E_d, e_d, sg_d, sl_d));
+    HIPCHK(launch_bloch_dot(ctx, p, q, npr, pl_d, pd, nblk));
+    HIPCHK(launch_bloch_scalars(ctx, BL_ALPHA, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
+    HIPCHK(launch_bloch_update(ctx, x, r, p, q, alpha, 2 * npr, sl_d, pn, nblk));
+    precond(2 * npr);
+    HIPCHK(launch_bloch_dot(ctx, r, z, npr, pl_d, pd, nblk));
+    HIPCHK(launch_bloch_scalars(ctx, BL_BETA, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
+    HIPCHK(launch_bloch_direction(ctx, p, z, beta, 2 * npr, sl_d, nblk));
+  };
+  auto read_back = [&]() {
+    HIPCHK(hipMemcpyAsync(rbh, rn2, (size_t)ns * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(rbh + (size_t)ns * sizeof(double), flag, (size_t)np * sizeof(int), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    stream_sync(ctx);
+  };
+
+  std::vector<int> act(np);
+  for (int k = 0; k < np; ++k) act[k] = k;
+  set_lists(act);
+  restart(np);  // x = 0: r = b
+  read_back();
+  std::vector<double> bn2(rn2_h, rn2_h + ns);
+  std::vector<int> it(np, 0), rs(np, 0);
+  auto finish = [&](int k, int status) {
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int sl = 2 * k + s2;
+      out.iters[sl] = it[k];
+      out.refin[sl] = rs[k];
+      out.status[sl] = status;
+      out.rel[sl] = bn2[sl] > 0 ? sqrt(rn2_h[sl] / bn2[sl]) : 0.0;
+    }
+  };
+  auto pair_conv = [&](int k) {
+    return rn2_h[2 * k] <= tol2 * bn2[2 * k] && rn2_h[2 * k + 1] <= tol2 * bn2[2 * k + 1];
+  };
+  {  // right-hand sides that vanish, or a first rho that vanishes
+    std::vector<int> keep;
+    for (int k : act) {
+      if (pair_conv(k)) finish(k, IOBM_OK);
+      else if (flag_h[k]) finish(k, IOBM_E_BREAKDOWN);
+      else keep.push_back(k);
+    }
+    if (keep.size() != act.size()) {
+      act = keep;
+      if (!act.empty()) set_lists(act);
+    }
+  }
+  const int max_restarts = 1000;
+  while (!act.empty()) {
+    const int npr = (int)act.size();
+    for (int c2 = 0; c2 < check; ++c2) iterate(npr);
+    for (int k : act) it[k] += check;
+    read_back();
+    std::vector<int> keep, redo;
+    for (int k : act) {
+      const double a = rn2_h[2 * k], c3 = rn2_h[2 * k + 1];
+      const bool bad = flag_h[k] || !std::isfinite(a) || !std::isfinite(c3) || a > 1e20 * bn2[2 * k] ||
+                       c3 > 1e20 * bn2[2 * k + 1];
+      if (bad || pair_conv(k)) redo.push_back(k);
+      else if (it[k] >= o.max_iter) finish(k, IOBM_E_NOT_CONVERGED);
+      else keep.push_back(k);
+    }
+    if (!redo.empty()) {
+      set_lists(redo);
+      restart((int)redo.size());
+      read_back();
+      for (int k : redo) {
+        ++rs[k];
+        if (pair_conv(k)) finish(k, IOBM_OK);
+        else if (flag_h[k] || rs[k] >= max_restarts) finish(k, IOBM_E_BREAKDOWN);
+        else if (it[k] >= o.max_iter) finish(k, IOBM_E_NOT_CONVERGED);
+        else keep.push_back(k);
+      }
+    }
+    std::sort(keep.begin(), keep.end());
+    if (keep != act || !redo.empty()) {
+      act = keep;
+      if (!act.empty()) set_lists(act);
+    }
+  }
+}
+
 }  // namespace
 
 int prof_start(iobm_ctx c, int cls) {
@@ -631,7 +1260,7 @@ void prof_stop(iobm_ctx c, int rec, double alg_bytes) {
 
 double* kb_scratch(iobm_ctx c, size_t bytes) {
   try {
-    return (double*)scratch(c, S_KB, bytes);
+    return (double*)workspace(c, S_KB, bytes);
   } catch (Fail&) {
     return nullptr;
   }
@@ -650,6 +1279,10 @@ void iobm_default_opts(iobm_solve_opts* o) {
   o->max_iter = 50000;
   o->side = 0;
   o->check_every = 2;
+  o->keep_direction = 0;
+  o->graph = 0;
+  o->block = 0;
+  o->pad_ = 0;
 }
 
 const char* iobm_status_str(iobm_status s) {
@@ -731,7 +1364,7 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
 
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask) {
   if (!ctx) return IOBM_E_INVALID_ARG;
-  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_FFT_PLANES_UPD + 1)))
+  if (class_mask < 0 || class_mask >= (1 << (IOBM_K_BLOCH_VECTOR + 1)))
     return fail(ctx, IOBM_E_INVALID_ARG, "bad kernel class mask");
   ctx->prof_mask = class_mask;
   ctx->prof_used = 0;
@@ -758,16 +1391,46 @@ iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launch
   return IOBM_OK;
 }
 
+iobm_status iobm_get_launch_shape(iobm_ctx ctx, int32_t precision, iobm_launch_shape* shape) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (!shape || (precision != IOBM_C128 && precision != IOBM_C64_REFINED))
+    return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+  *shape = launch_shape_in_effect(ctx, precision == IOBM_C128 ? 0 : 1);
+  return IOBM_OK;
+}
+
+iobm_status iobm_set_launch_shape(iobm_ctx ctx, int32_t precision, const iobm_launch_shape* shape) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (precision != IOBM_C128 && precision != IOBM_C64_REFINED) return fail(ctx, IOBM_E_INVALID_ARG, "bad precision");
+  const int p = precision == IOBM_C128 ? 0 : 1;
+  if (!shape) {  // unpin: the next solve in this precision tunes again
+    ctx->shape[p] = iobm_launch_shape{};
+    ctx->tuned[p] = ctx->pinned[p] = false;
+    return IOBM_OK;
+  }
+  std::string why;
+  if (shape->stencil < 0 || shape->stencil > 2 || shape->plane_fft < 0 || shape->plane_fft > 2 ||
+      shape->points_per_thread < 0 || shape->planes_per_block < 0 || shape->zfilter_chunk < 0)
+    return fail(ctx, IOBM_E_INVALID_ARG, "launch shape field out of range");
+  if (!launch_shape_valid(ctx, p, *shape, why)) return fail(ctx, IOBM_E_UNSUPPORTED, why);
+  ctx->shape[p] = *shape;
+  ctx->tuned[p] = ctx->pinned[p] = true;
+  return IOBM_OK;
+}
+
 iobm_status iobm_destroy(iobm_ctx ctx) {
   if (!ctx) return IOBM_E_INVALID_ARG;
   for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : ctx->cap_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   for (auto& e : ctx->pool)
     if (e.first) (void)hipFree(e.first);
   void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->V_d, ctx->V_f, ctx->modes_d, ctx->sig_d,
-                  ctx->sig_f, ctx->mode_flags_d,
-                  ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.hD, ctx->arena_d};
+                  ctx->sig_f, ctx->mode_flags_d, ctx->sdiag_d,
+                  ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.hD, ctx->kb.diag_d, ctx->arena_d};
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->arena_h) (void)hipHostFree(ctx->arena_h);
   if (ctx->rb_h) (void)hipHostFree(ctx->rb_h);
   for (void* p : ptrs)
@@ -889,9 +1552,17 @@ iobm_status iobm_set_nonlocal(iobm_ctx ctx, int32_t ncen, int32_t rank, const in
       for (int q = 0; q < rank; ++q)
         hD[(size_t)(a * rank + p) * nproj + a * rank + q] = h3 * D[(a * rank + p) * rank + q];
   std::vector<float> Bf(Bm.begin(), Bm.end());
+  // diagonal of B h^3 D B^T per voxel (zero off the supports)
+  std::vector<double> kdiag(nu > 0 ? (size_t)ctx->g.npts : 0, 0.0);
+  for (int u = 0; u < nu; ++u) {
+    double acc = 0;
+    for (int p = 0; p < nproj; ++p)
+      for (int q = 0; q < nproj; ++q) acc += Bm[(size_t)u * npad + p] * hD[(size_t)p * nproj + q] * Bm[(size_t)u * npad + q];
+    kdiag[uvox[u]] = acc;
+  }
   try {
     stream_sync(ctx);
-    void* old[] = {kb.uvox, kb.Bd, kb.Bf, kb.hD};
+    void* old[] = {kb.uvox, kb.Bd, kb.Bf, kb.hD, kb.diag_d};
     for (void* p : old)
       if (p) (void)hipFree(p);
     kb = KBData();
@@ -904,6 +1575,8 @@ iobm_status iobm_set_nonlocal(iobm_ctx ctx, int32_t ncen, int32_t rank, const in
     HIPCHK(hipMemcpy(kb.Bd, Bm.data(), Bm.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(kb.Bf, Bf.data(), Bf.size() * sizeof(float), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(kb.hD, hD.data(), hD.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&kb.diag_d, kdiag.size() * sizeof(double)));
+    HIPCHK(hipMemcpy(kb.diag_d, kdiag.data(), kdiag.size() * sizeof(double), hipMemcpyHostToDevice));
     kb.ncen = ncen;
     kb.rank = rank;
     kb.nproj = nproj;
@@ -982,14 +1655,14 @@ iobm_status iobm_precondition(iobm_ctx ctx, int32_t precond, double alpha, doubl
                               const void* r, void* z, int32_t precision, double* rz) {
   if (!ctx) return IOBM_E_INVALID_ARG;
   if (nrhs < 0 || (nrhs > 0 && (!r || !z)) || !isfinite(E) || !(alpha > 0) ||
-      (precision != IOBM_C128 && precision != IOBM_C64_REFINED) || precond < 0 || precond > 2)
+      (precision != IOBM_C128 && precision != IOBM_C64_REFINED) || precond < 0 || precond > IOBM_PC_JACOBI)
     return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
   if (r == z) return fail(ctx, IOBM_E_INVALID_ARG, "r and z must not overlap");
   if (nrhs == 0) return IOBM_OK;
   try {
     const long long vol = ctx->g.npts;
     const int slots = precond_slots(ctx, precond);
-    Partial* part = rz ? (Partial*)scratch(ctx, S_PARTZ, (size_t)nrhs * slots * sizeof(Partial)) : nullptr;
+    Partial* part = rz ? (Partial*)workspace(ctx, S_PARTZ, (size_t)nrhs * slots * sizeof(Partial)) : nullptr;
     if (precond == IOBM_PC_NONE) {
       size_t es = precision == IOBM_C128 ? sizeof(zd) : sizeof(zf);
       HIPCHK(hipMemcpyAsync(z, r, (size_t)nrhs * vol * es, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1000,15 +1673,25 @@ iobm_status iobm_precondition(iobm_ctx ctx, int32_t precond, double alpha, doubl
         HIPCHK(launch_precond_laplacian<double>(ctx, alpha, (const zd*)r, (zd*)z, nrhs, nullptr, part));
       else
         HIPCHK(launch_precond_laplacian<float>(ctx, alpha, (const zf*)r, (zf*)z, nrhs, nullptr, part));
+    } else if (precond == IOBM_PC_JACOBI) {
+      ensure_modes(ctx, std::vector<double>{E});
+      std::vector<int> e(nrhs, 0);
+      std::vector<double> Ev(nrhs, E);
+      int* e_d = upload(ctx, S_IDX, e, 0);
+      double* E_d = upload(ctx, S_IDX, Ev, 32 * 1024);
+      if (precision == IOBM_C128)
+        HIPCHK(launch_precond_jacobi<double>(ctx, (const zd*)r, (zd*)z, nrhs, e_d, E_d, nullptr, part));
+      else
+        HIPCHK(launch_precond_jacobi<float>(ctx, (const zf*)r, (zf*)z, nrhs, e_d, E_d, nullptr, part));
     } else {
       ensure_modes(ctx, std::vector<double>{E});
       std::vector<int> e(nrhs, 0);
       int* e_d = upload(ctx, S_IDX, e, 0);
       if (precision == IOBM_C128) {
-        zd* pf = (zd*)scratch(ctx, S_PF, (size_t)nrhs * vol * sizeof(zd));
+        zd* pf = (zd*)workspace(ctx, S_PF, (size_t)nrhs * vol * sizeof(zd));
         HIPCHK(launch_precond_fft<double>(ctx, (const zd*)r, (zd*)z, pf, nrhs, e_d, ctx->modes_d, nullptr, part));
       } else {
-        zf* pf = (zf*)scratch(ctx, S_PF, (size_t)nrhs * vol * sizeof(zf));
+        zf* pf = (zf*)workspace(ctx, S_PF, (size_t)nrhs * vol * sizeof(zf));
         HIPCHK(launch_precond_fft<float>(ctx, (const zf*)r, (zf*)z, pf, nrhs, e_d, ctx->modes_d, nullptr, part));
       }
     }
@@ -1068,45 +1751,17 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
     if (nE == 0) return IOBM_OK;
     const iobm_solve_opts& o = *opts;
     ensure_modes(ctx, std::vector<double>(E, E + nE), true);
-    Batch B;
-    Request Q;
-    plan_requests(ctx, nE, E, ninc, inc, B, Q);
-    const int nb = B.n, nreq = (int)Q.e.size();
-    const long long vol = ctx->g.npts;
+    SolveRun run;
+    run_solve(ctx, o, nE, E, ninc, inc, run);
+    const int nreq = (int)run.Q.e.size();
     const int nxy = ctx->g.nxy;
-    zd* b = (zd*)scratch(ctx, S_B, (size_t)nb * vol * sizeof(zd));
-    zd* x = (zd*)scratch(ctx, S_XHI, (size_t)nb * vol * sizeof(zd));
-    {
-      int* e_d = upload(ctx, S_IDX, B.e, 0);
-      int* m_d = upload(ctx, S_IDX, B.mode, 16 * 1024);
-      int* k_d = upload(ctx, S_IDX, B.kind, 32 * 1024);
-      HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b, true));
-    }
-    SolveOut so;
-    solve_batch(ctx, o, B, b, x, so);
-    // readout of every basis solution, then combination into channels
-    zd* amp = (zd*)scratch(ctx, S_AMP, (size_t)(2 * nb + 2 * nreq) * nxy * sizeof(zd));
-    zd* amp_near = amp;
-    zd* amp_far = amp + (size_t)nb * nxy;
-    zd* t_out = amp + (size_t)2 * nb * nxy;
-    zd* r_out = t_out + (size_t)nreq * nxy;
-    double* TR = (double*)scratch(ctx, S_TR, (size_t)2 * nreq * sizeof(double) + 64);
-    int* e_d = upload(ctx, S_IDX, B.e, 0);
-    HIPCHK(launch_readout(ctx, nb, o.side, x, ctx->modes_d, e_d, amp_near, amp_far));
-    int* qe = upload(ctx, S_IDX, Q.e, 16 * 1024);
-    int* qm = upload(ctx, S_IDX, Q.mode, 24 * 1024);
-    int* qc = upload(ctx, S_IDX, Q.c, 32 * 1024);
-    int* qs = upload(ctx, S_IDX, Q.s, 40 * 1024);
-    int* qg = upload(ctx, S_IDX, Q.sgn, 48 * 1024);
-    HIPCHK(launch_combine(ctx, nreq, qe, qm, qc, qs, qg, ctx->modes_d, amp_near, amp_far, t_out, r_out, TR,
-                          TR + nreq));
-    if (psi) HIPCHK(launch_combine_psi<double>(ctx, nreq, x, (zd*)psi, qc, qs, qg));
+    if (psi) HIPCHK(launch_combine_psi<double>(ctx, nreq, run.x, (zd*)psi, run.qc, run.qs, run.qg));
     std::vector<double> TRh(2 * nreq);
-    HIPCHK(hipMemcpyAsync(TRh.data(), TR, 2 * nreq * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(TRh.data(), run.TR, 2 * nreq * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     std::vector<zd> th;
     if (t) {
       th.resize((size_t)nreq * nxy);
-      HIPCHK(hipMemcpyAsync(th.data(), t_out, th.size() * sizeof(zd), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipMemcpyAsync(th.data(), run.t_out, th.size() * sizeof(zd), hipMemcpyDeviceToHost, ctx->stream));
     }
     stream_sync(ctx);
     if (T) for (int c = 0; c < nreq; ++c) T[c] = TRh[c];
@@ -1117,7 +1772,7 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
       int c0 = 0;
       for (int e = 0; e < nE; ++e) {
         int c1 = c0;
-        while (c1 < nreq && Q.e[c1] == e) ++c1;
+        while (c1 < nreq && run.Q.e[c1] == e) ++c1;
         const int* fl = &ctx->mode_flags_h[(size_t)e * nxy];
         int row = 0;
         for (int nu = 0; nu < nxy; ++nu) {
@@ -1133,23 +1788,256 @@ iobm_status iobm_solve(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, co
         c0 = c1;
       }
     }
+    const iobm_status worst = request_stats(run, TRh, st);
+    if (worst != IOBM_OK) {
+      ctx->err = "some right-hand sides did not converge";
+      return worst;
+    }
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_smatrix(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE, const double* E, double* S,
+                         iobm_solve_stat* st) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  try {
+    validate_opts(ctx, opts);
+    if (nE < 0 || (nE > 0 && (!E || !S))) return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+    if (!ctx->have_V) return fail(ctx, IOBM_E_BAD_STATE, "iobm_set_potential has not been called");
+    for (int e = 0; e < nE; ++e)
+      if (!isfinite(E[e])) return fail(ctx, IOBM_E_INVALID_ARG, "non-finite energy");
+    if (nE == 0) return IOBM_OK;
+    ensure_modes(ctx, std::vector<double>(E, E + nE), true);
+    const int nxy = ctx->g.nxy, nf = ctx->g.nf;
+    const ModeData* md = host_modes(ctx);
+    // open channels per energy (ascending ids) and the offsets of S
+    std::vector<std::vector<int>> open(nE);
+    std::vector<size_t> soff(nE + 1, 0);
+    int nstates = 0;
+    for (int e = 0; e < nE; ++e) {
+      for (int m = 0; m < nxy; ++m)
+        if (ctx->mode_flags_h[(size_t)e * nxy + m] & MODE_OPEN) open[e].push_back(m);
+      const size_t n = open[e].size();
+      soff[e + 1] = soff[e] + 4 * n * n;
+      nstates += (int)n;
+    }
+    std::vector<int> ninc(nE, -1);
     iobm_status worst = IOBM_OK;
-    for (int c = 0; c < nreq; ++c) {
-      int ic = Q.c[c], is = Q.s[c];
-      int status = so.status[ic];
-      if (is >= 0 && so.status[is] != IOBM_OK) status = so.status[is];
-      if (status != IOBM_OK) worst = (iobm_status)status;
-      if (st) {
-        st[c].iters = so.iters[ic] + (is >= 0 ? so.iters[is] : 0);
-        st[c].refinements = so.refin[ic] + (is >= 0 ? so.refin[is] : 0);
-        st[c].status = status;
-        st[c].pad_ = 0;
-        st[c].rel_residual = std::max(so.rel[ic], is >= 0 ? so.rel[is] : 0.0);
-        st[c].flux_error = TRh[c] + TRh[nreq + c] - 1.0;
+    for (int side = 0; side < 2; ++side) {
+      iobm_solve_opts o = *opts;
+      o.side = side;
+      SolveRun run;
+      run_solve(ctx, o, nE, E, ninc.data(), nullptr, run);
+      const int nreq = (int)run.Q.e.size();
+      std::vector<zd> th((size_t)nreq * nxy), rh((size_t)nreq * nxy);
+      std::vector<double> TRh(2 * nreq);
+      HIPCHK(hipMemcpyAsync(th.data(), run.t_out, th.size() * sizeof(zd), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipMemcpyAsync(rh.data(), run.r_out, rh.size() * sizeof(zd), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipMemcpyAsync(TRh.data(), run.TR, 2 * nreq * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      stream_sync(ctx);
+      const iobm_status w = request_stats(run, TRh, st ? st + (size_t)side * nstates : nullptr);
+      if (w != IOBM_OK) worst = w;
+      // column block a = side; row block b = the lead of the outgoing wave.
+      // Transmitted amplitudes come referred to the nf-th plane from the far
+      // lead; the propagating wave gains x^(nf-1) up to the plane next to it.
+      for (int c = 0; c < nreq; ++c) {
+        const int e = run.Q.e[c], mu = run.Q.mode[c];
+        const std::vector<int>& ids = open[e];
+        const int n = (int)ids.size();
+        const int j = (int)(std::lower_bound(ids.begin(), ids.end(), mu) - ids.begin());
+        const ModeData* me = md + (size_t)e * nxy;
+        for (int i = 0; i < n; ++i) {
+          const int nu = ids[i];
+          const double w_ = sqrt(me[nu].v / me[mu].v);
+          zd tr = th[(size_t)c * nxy + nu];
+          for (int k = 0; k < nf - 1; ++k) tr = tr * me[nu].xp;
+          const zd rf = rh[(size_t)c * nxy + nu];
+          const int col = side * n + j;
+          const int row_r = side * n + i, row_t = (1 - side) * n + i;
+          double* Se = S + 2 * soff[e];
+          Se[2 * ((size_t)row_r * 2 * n + col)] = w_ * rf.re;
+          Se[2 * ((size_t)row_r * 2 * n + col) + 1] = w_ * rf.im;
+          Se[2 * ((size_t)row_t * 2 * n + col)] = w_ * tr.re;
+          Se[2 * ((size_t)row_t * 2 * n + col) + 1] = w_ * tr.im;
+        }
       }
     }
     if (worst != IOBM_OK) {
       ctx->err = "some right-hand sides did not converge";
+      return worst;
+    }
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_channels_bloch(iobm_ctx ctx, double E, double kx, double ky, int32_t* nopen, int32_t* ids,
+                                double* kz, double* v) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (!nopen || !isfinite(E) || !isfinite(kx) || !isfinite(ky)) return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+  try {
+    ensure_modes(ctx, std::vector<double>{E}, false, std::vector<double>{kx * ctx->g.hx, ky * ctx->g.hy});
+    int n = 0;
+    for (int m = 0; m < ctx->g.nxy; ++m) {
+      const ModeData& md = host_modes(ctx)[m];
+      if (!(md.flags & MODE_OPEN)) continue;
+      if (ids) ids[n] = m;
+      if (kz) kz[n] = atan2(md.xp.im, md.xp.re) / ctx->g.hz;
+      if (v) v[n] = md.v;
+      ++n;
+    }
+    *nopen = n;
+  } catch (Fail& f) {
+    return f.s;
+  }
+  return IOBM_OK;
+}
+
+iobm_status iobm_smatrix_bloch(iobm_ctx ctx, const iobm_solve_opts* opts, double kx, double ky, int32_t nE,
+                               const double* E, double* S_plus, double* S_minus, iobm_solve_stat* st) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  try {
+    validate_opts(ctx, opts);
+    if (nE < 0 || (nE > 0 && (!E || !S_plus || !S_minus)) || !isfinite(kx) || !isfinite(ky))
+      return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+    if (opts->precision != IOBM_C128 || opts->block != 0)
+      return fail(ctx, IOBM_E_UNSUPPORTED, "the lateral-Bloch-vector solve runs in complex128 without block COCG");
+    if (ctx->kb.ncen > 0)
+      return fail(ctx, IOBM_E_UNSUPPORTED, "the lateral-Bloch-vector solve does not take a nonlocal term");
+    if (!ctx->have_V) return fail(ctx, IOBM_E_BAD_STATE, "iobm_set_potential has not been called");
+    for (int e = 0; e < nE; ++e)
+      if (!isfinite(E[e])) return fail(ctx, IOBM_E_INVALID_ARG, "non-finite energy");
+    if (nE == 0) return IOBM_OK;
+    const GridDev& g = ctx->g;
+    const int nxy = g.nxy, nf = g.nf;
+    // mode table: entries 0..nE-1 at +kappa, nE..2nE-1 at -kappa
+    std::vector<double> E2(E, E + nE), K2;
+    E2.insert(E2.end(), E, E + nE);
+    for (int e = 0; e < nE; ++e) { K2.push_back(kx * g.hx); K2.push_back(ky * g.hy); }
+    for (int e = 0; e < nE; ++e) { K2.push_back(-kx * g.hx); K2.push_back(-ky * g.hy); }
+    ensure_modes(ctx, E2, true, K2);
+    const ModeData* md = host_modes(ctx);
+    std::vector<std::vector<int>> openp(nE), openm(nE);
+    std::vector<size_t> soff(nE + 1, 0);
+    int nstates = 0;
+    for (int e = 0; e < nE; ++e) {
+      for (int m = 0; m < nxy; ++m) {
+        if (ctx->mode_flags_h[(size_t)e * nxy + m] & MODE_OPEN) openp[e].push_back(m);
+        if (ctx->mode_flags_h[(size_t)(nE + e) * nxy + m] & MODE_OPEN) openm[e].push_back(m);
+      }
+      if (openp[e].size() != openm[e].size()) {
+        ctx->err = "open channels at +kappa and -kappa differ";
+        throw Fail{IOBM_E_DEVICE};
+      }
+      const size_t n = openp[e].size();
+      soff[e + 1] = soff[e] + 4 * n * n;
+      nstates += (int)n;
+    }
+    BlochPhase ph;
+    for (int n = 0; n < 4; ++n) {
+      ph.x[n] = mk(cos(n * kx * g.hx), sin(n * kx * g.hx));
+      ph.y[n] = mk(cos(n * ky * g.hy), sin(n * ky * g.hy));
+    }
+    const long long vol = g.npts;
+    iobm_status worst = IOBM_OK;
+    for (int side = 0; side < 2; ++side) {
+      PairBatch B;
+      for (int e = 0; e < nE; ++e)
+        for (int mu : openp[e]) {
+          const int mneg = neg_mode(g, mu);
+          if (!std::binary_search(openm[e].begin(), openm[e].end(), mneg)) {
+            ctx->err = "the partner channel at -kappa is closed";
+            throw Fail{IOBM_E_DEVICE};
+          }
+          B.e.push_back(e); B.E.push_back(E[e]); B.mode.push_back(mu); B.sgn.push_back(1);
+          B.e.push_back(nE + e); B.E.push_back(E[e]); B.mode.push_back(mneg); B.sgn.push_back(-1);
+        }
+      B.n = (int)B.e.size();
+      if (B.n == 0) continue;
+      zd* b = (zd*)workspace(ctx, S_B, (size_t)B.n * vol * sizeof(zd));
+      zd* x = (zd*)workspace(ctx, S_XHI, (size_t)B.n * vol * sizeof(zd));
+      {  // plane-wave right-hand sides in the gauge u (Eq. (6) at G + kappa)
+        int* e_d = upload(ctx, S_IDX, B.e, 0);
+        int* m_d = upload(ctx, S_IDX, B.mode, 16 * 1024);
+        std::vector<int> kind(B.n, 0);
+        int* k_d = upload(ctx, S_IDX, kind, 32 * 1024);
+        HIPCHK(launch_rhs(ctx, B.n, e_d, m_d, k_d, side, ctx->modes_d, b, false));
+      }
+      SolveOut so;
+      solve_pair_batch(ctx, *opts, ph, B, b, x, so);
+      zd* amp = (zd*)workspace(ctx, S_AMP, (size_t)2 * B.n * nxy * sizeof(zd));
+      int* e_d = upload(ctx, S_IDX, B.e, 0);
+      HIPCHK(launch_readout(ctx, B.n, side, x, ctx->modes_d, e_d, amp, amp + (size_t)B.n * nxy));
+      std::vector<zd> ah((size_t)2 * B.n * nxy);
+      HIPCHK(hipMemcpyAsync(ah.data(), amp, ah.size() * sizeof(zd), hipMemcpyDeviceToHost, ctx->stream));
+      stream_sync(ctx);
+      const zd* an = ah.data();
+      const zd* af = ah.data() + (size_t)B.n * nxy;
+      // column a = side of the incident channel; row blocks: the lead of the
+      // outgoing wave.  Amplitudes are referred to the plane next to their
+      // lead (the transmitted wave gains x^(nf-1) from the nf-th plane).
+      int pos = 0;
+      for (int e = 0; e < nE; ++e) {
+        const int n = (int)openp[e].size();
+        for (int jj = 0; jj < n; ++jj, pos += 2) {
+          for (int h = 0; h < 2; ++h) {
+            const int slot = pos + h;
+            const std::vector<int>& ids = h ? openm[e] : openp[e];
+            const int mu = B.mode[slot];
+            const int j = (int)(std::lower_bound(ids.begin(), ids.end(), mu) - ids.begin());
+            const ModeData* me = md + (size_t)B.e[slot] * nxy;
+            double* Se = (h ? S_minus : S_plus) + 2 * soff[e];
+            for (int i = 0; i < n; ++i) {
+              const int nu = ids[i];
+              const double w_ = sqrt(me[nu].v / me[mu].v);
+              zd tr = af[(size_t)slot * nxy + nu];
+              for (int k = 0; k < nf - 1; ++k) tr = tr * me[nu].xp;
+              zd rf = an[(size_t)slot * nxy + nu];
+              if (nu == mu) rf = rf - me[mu].kin;
+              const int col = side * n + j;
+              const int row_r = side * n + i, row_t = (1 - side) * n + i;
+              Se[2 * ((size_t)row_r * 2 * n + col)] = w_ * rf.re;
+              Se[2 * ((size_t)row_r * 2 * n + col) + 1] = w_ * rf.im;
+              Se[2 * ((size_t)row_t * 2 * n + col)] = w_ * tr.re;
+              Se[2 * ((size_t)row_t * 2 * n + col) + 1] = w_ * tr.im;
+            }
+            if (so.status[slot] != IOBM_OK) worst = (iobm_status)so.status[slot];
+          }
+          if (st) {  // per pair: [side][sum_e n_e]
+            iobm_solve_stat& q = st[(size_t)side * nstates + pos / 2];
+            q.iters = so.iters[pos];
+            q.refinements = so.refin[pos];
+            q.status = so.status[pos] != IOBM_OK ? so.status[pos] : so.status[pos + 1];
+            q.pad_ = 0;
+            q.rel_residual = std::max(so.rel[pos], so.rel[pos + 1]);
+            q.flux_error = 0.0;
+          }
+        }
+      }
+    }
+    if (st) {  // flux error of the +kappa column: sum_b |S[b nu][a mu]|^2 - 1
+      int pos = 0;
+      for (int e = 0; e < nE; ++e) {
+        const int n = (int)openp[e].size();
+        const double* Se = S_plus + 2 * soff[e];
+        for (int side = 0; side < 2; ++side)
+          for (int j = 0; j < n; ++j) {
+            double f = 0;
+            for (int i = 0; i < 2 * n; ++i) {
+              const double re = Se[2 * ((size_t)i * 2 * n + side * n + j)];
+              const double im = Se[2 * ((size_t)i * 2 * n + side * n + j) + 1];
+              f += re * re + im * im;
+            }
+            st[(size_t)side * nstates + pos + j].flux_error = f - 1.0;
+          }
+        pos += n;
+      }
+    }
+    if (worst != IOBM_OK) {
+      ctx->err = "some scattering states did not converge";
       return worst;
     }
   } catch (Fail& f) {
@@ -1184,9 +2072,9 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
       stream_sync(ctx);
       return IOBM_OK;
     }
-    zd* b = (zd*)scratch(ctx, S_B, (size_t)nb * vol * sizeof(zd));
-    zd* u = (zd*)scratch(ctx, S_XHI, (size_t)nb * vol * sizeof(zd));
-    zd* w = (zd*)scratch(ctx, S_GRAD_U, (size_t)nb * vol * sizeof(zd));
+    zd* b = (zd*)workspace(ctx, S_B, (size_t)nb * vol * sizeof(zd));
+    zd* u = (zd*)workspace(ctx, S_XHI, (size_t)nb * vol * sizeof(zd));
+    zd* w = (zd*)workspace(ctx, S_GRAD_U, (size_t)nb * vol * sizeof(zd));
     // forward solves
     {
       int* e_d = upload(ctx, S_IDX, B.e, 0);
@@ -1196,12 +2084,12 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
     }
     SolveOut so;
     solve_batch(ctx, o, B, b, u, so);
-    zd* amp = (zd*)scratch(ctx, S_AMP, (size_t)(2 * nb + 2 * nreq) * nxy * sizeof(zd));
+    zd* amp = (zd*)workspace(ctx, S_AMP, (size_t)(2 * nb + 2 * nreq) * nxy * sizeof(zd));
     zd* amp_near = amp;
     zd* amp_far = amp + (size_t)nb * nxy;
     zd* t_out = amp + (size_t)2 * nb * nxy;
     zd* r_out = t_out + (size_t)nreq * nxy;
-    double* TR = (double*)scratch(ctx, S_TR, (size_t)2 * nreq * sizeof(double) + 64);
+    double* TR = (double*)workspace(ctx, S_TR, (size_t)2 * nreq * sizeof(double) + 64);
     int* e_d = upload(ctx, S_IDX, B.e, 0);
     HIPCHK(launch_readout(ctx, nb, o.side, u, ctx->modes_d, e_d, amp_near, amp_far));
     int* qe = upload(ctx, S_IDX, Q.e, 16 * 1024);
@@ -1253,7 +2141,7 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
         add(Q.s[c], c, mk(0.0, sg), mk(0.0, -sg));
       }
     }
-    zd* Dd = (zd*)scratch(ctx, S_GRAD_D, (size_t)std::max<long long>(1, dtot) * sizeof(zd));
+    zd* Dd = (zd*)workspace(ctx, S_GRAD_D, (size_t)std::max<long long>(1, dtot) * sizeof(zd));
     int* base_d = upload(ctx, S_IDX, base, 64 * 1024);
     long long* dbase_d = upload(ctx, S_IDX, dbase, 72 * 1024);
     int* chan_d = upload(ctx, S_IDX, chan, 80 * 1024);

@@ -35,6 +35,9 @@ struct ModeArgs {
   int nx, ny, nf, nE;
   double hx, hy, hz;
   double c[4];
+  // lateral Bloch vector of the entry as phases per lattice step,
+  // kappa_x h_x and kappa_y h_y (Eqs. (12)-(13) at G + kappa); 0 by default
+  double tx = 0, ty = 0;
 };
 __host__ __device__ void compute_mode(const ModeArgs& A, double E, int m, ModeData* out);
 
@@ -45,6 +48,7 @@ struct KBData {
   double* Bd = nullptr;   // [nu][nproj_pad] projector values, zero where off-support
   float* Bf = nullptr;
   double* hD = nullptr;   // [nproj][nproj] block-diagonal h^3 D (device)
+  double* diag_d = nullptr;  // [npts] diagonal of B h^3 D B^T (device; Jacobi preconditioner)
   int nproj_pad = 0;      // nproj rounded up to the MFMA tile (multiple of 16)
 };
 
@@ -71,6 +75,7 @@ struct iobm_ctx_s {
   KBData kb;
   // cached mode tables for the most recent energy list
   std::vector<double> modeE;
+  std::vector<double> modeK;  // per entry (kappa_x h_x, kappa_y h_y); empty when every kappa is 0
   ModeData* modes_d = nullptr;
   std::vector<ModeData> modes_h;
   size_t modes_cap = 0;
@@ -80,6 +85,7 @@ struct iobm_ctx_s {
   zf* sig_f = nullptr;
   size_t sig_cap = 0;
   int* mode_flags_d = nullptr;       // ModeData::flags of the same table, [energy][mode]
+  zd* sdiag_d = nullptr;             // [energy][nf] real-space diagonal of Sigma_R per face plane
   std::vector<int> mode_flags_h;     // host copy (the solve path needs only these)
   bool modes_h_valid = false;        // modes_h is copied from the device on demand
   void* arena_d = nullptr;  // small index arrays (device) and their pinned host mirror
@@ -87,13 +93,13 @@ struct iobm_ctx_s {
   void* rb_h = nullptr;     // pinned host buffer for the solver's per-rhs read-backs
   size_t rb_cap = 0;
   unsigned char region_pending[64] = {0};
-  // tuned launch shapes (0 = default rule)
-  int tune_zf_c64 = 0, tune_zf_c128 = 0;
-  int tune_fft_generic = 0;  // 1: always use the LDS Stockham plane FFT
-  int tune_stencil_simple = 0;  // 1: cache-based stencil instead of the 2.5D one
-  int tune_ppt_c64 = 0, tune_ppt_c128 = 0;  // 2.5D stencil points per thread (0 = default)
-  int tune_zc_c64 = 0, tune_zc_c128 = 0;    // 2.5D stencil planes per block (0 = 32)
-  bool tuned_c64 = false, tuned_c128 = false;
+  // launch shapes per iteration precision (index prec_index<T>(): 0
+  // complex128, 1 complex64); fields 0 = the default rule.  `tuned` is set
+  // once the autotuner has run or a shape was pinned (the autotuner then
+  // leaves the shape alone).
+  iobm_launch_shape shape[2] = {};
+  bool tuned[2] = {false, false};
+  bool pinned[2] = {false, false};
   // kernel timing hook
   int prof_mask = 0;
   std::vector<hipEvent_t> prof_ev;  // start/stop pairs
@@ -102,7 +108,34 @@ struct iobm_ctx_s {
   size_t prof_used = 0;             // pairs recorded
   // pooled device scratch
   std::vector<std::pair<void*, size_t>> pool;
+  // the library's own stream and events for graph-captured iterations
+  // (created on first use; the caller's stream may be the null stream,
+  // which cannot be captured)
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t cap_ev[2] = {nullptr, nullptr};
   std::string err;
+};
+
+template <typename T> constexpr int prec_index() { return sizeof(T) == sizeof(float) ? 1 : 0; }
+
+// FD stencil of the operator A_st = E - V - T (Eq. (1) with the central
+// weights chat_n / h_mu^2): e0 = the diagonal kinetic term, w*[n] the
+// coupling to the neighbours at distance n per direction; the volume
+// kernels run over chunks of zchunk planes per right-hand side.
+struct StencilArgs {
+  int nx, ny, nz, nf, nxy;
+  int zchunk, nchunks;
+  double e0;
+  double wx[4], wy[4], wz[4];
+};
+StencilArgs stencil_args(iobm_ctx c, int zchunk);
+
+// Bond phases of the lateral couplings in the gauge u = exp(-i kappa.r) psi
+// of a lateral Bloch vector kappa: x[n] = exp(i n kappa_x h_x),
+// y[n] = exp(i n kappa_y h_y), n = 1..3 (index 0 unused); the rhs at -kappa
+// take the conjugates.
+struct BlochPhase {
+  zd x[4], y[4];
 };
 
 // ---- kernel timing hook (api.hip) -------------------------------------------
@@ -119,7 +152,8 @@ struct RhsMap {        // device arrays describing a batch of right-hand sides
   const double* E;     // [nrhs] energy
 };
 
-hipError_t launch_modes(iobm_ctx c, const double* E_d, int nE, ModeData* out);
+// kap_d: per entry (kappa_x h_x, kappa_y h_y), or nullptr for kappa = 0
+hipError_t launch_modes(iobm_ctx c, const double* E_d, int nE, ModeData* out, const double* kap_d = nullptr);
 hipError_t launch_sigma_tables(iobm_ctx c, int nE, const ModeData* modes, zd* sig_d, zf* sig_f, int* flags);
 
 // Per-rhs FP64 partial sums of a bilinear form u^T v (re, im) and of |u|^2
@@ -140,8 +174,9 @@ enum { PQ_STENCIL_MAX = 64, PQ_BOUNDARY = 64, PQ_KB = 66, PQ_SLOTS = 68 };
 // alpha, d and dlive set, the previous step's update d += alpha p_old is
 // applied on the way (per rhs; none where alpha = 0; d is not read where
 // dlive = 0, the first step after a refinement).  For the byte count of the
-// timing hook: nfresh of the rhs restart here (beta = alpha = 0), nfirstd
-// make their first d update.
+// timing hook: nfresh of the rhs restart here (beta = alpha = 0), nkept
+// continue their direction right after a replacement (alpha = 0, beta != 0),
+// nfirstd make their first d update.
 template <typename T>
 struct ApplyFuse {
   const cplx<T>* z;
@@ -154,6 +189,7 @@ struct ApplyFuse {
   const int* dlive = nullptr;
   int nfresh = 0;
   int nfirstd = 0;
+  int nkept = 0;
 };
 
 template <typename T>
@@ -165,6 +201,17 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z,
                                     int nrhs, const int* active, Partial* dpart = nullptr);
+template <typename T>
+hipError_t launch_precond_jacobi(iobm_ctx c, const cplx<T>* r, cplx<T>* z, int nrhs, const int* e_rhs,
+                                 const double* E_rhs, const int* active, Partial* dpart = nullptr);
+hipError_t launch_sigma_diag(iobm_ctx c, int nE);  // sdiag_d from sig_d for the current table
+// y -= Sigma x on the 2 nf face planes (complex128), for the listed rhs
+hipError_t launch_face_sigma(iobm_ctx c, const zd* x, zd* y, int nrhs, const int* e_rhs, const int* active);
+hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs, int side,
+                      const ModeData* modes, zd* b, bool faces_only);
+hipError_t launch_readout(iobm_ctx c, int nrhs, int side, const zd* x, const ModeData* modes, const int* e_rhs,
+                          zd* amp_near, zd* amp_far);
+int dot_blocks(iobm_ctx c);
 // The COCG residual update fused into the preconditioner's forward transform
 // (square planes of the register FFT only, see fft_reg_available): the
 // residual, kept in lateral mode space in the preconditioner's scratch
@@ -176,6 +223,7 @@ struct FftUpd {
   const zd* alpha = nullptr;
   Partial* n2part = nullptr;
 };
+template <typename T>
 bool fft_reg_available(iobm_ctx c);
 template <typename T>
 hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch,
@@ -187,9 +235,13 @@ hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, P
                            const int* active);
 // Times the admissible stencil shapes (on the fused operator when `fuse` is
 // given; its buffers are overwritten) and z-filter chunk lengths once per
-// context and precision.
+// context and precision, unless a shape is pinned.
 template <typename T>
 void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
               const int* e_rhs, const ModeData* modes, const int* active, const ApplyFuse<T>* fuse = nullptr);
 size_t kb_proj_bytes(iobm_ctx c, int nrhs);
+// Launch-shape rules (ops.hip): whether a pinned shape is admissible for
+// this grid, and the shape in effect (pinned, tuned or the default rule).
+bool launch_shape_valid(iobm_ctx c, int prec, const iobm_launch_shape& s, std::string& why);
+iobm_launch_shape launch_shape_in_effect(iobm_ctx c, int prec);
 double* kb_scratch(iobm_ctx c, size_t bytes);  // context-owned scratch for the projector sums

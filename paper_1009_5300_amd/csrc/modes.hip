@@ -200,7 +200,8 @@ __host__ __device__ void compute_mode(const ModeArgs& A, double E, int m, ModeDa
   const int ix = m % A.nx, iy = m / A.nx;
   const int nux = ix < A.nx / 2 ? ix : ix - A.nx;
   const int nuy = iy < A.ny / 2 ? iy : iy - A.ny;
-  const double thx = 2.0 * M_PI * nux / A.nx, thy = 2.0 * M_PI * nuy / A.ny;
+  // (G_nu + kappa) h per direction
+  const double thx = 2.0 * M_PI * nux / A.nx + A.tx, thy = 2.0 * M_PI * nuy / A.ny + A.ty;
   double ex = c[0], ey = c[0];
   for (int n = 1; n <= nf; ++n) {
     ex += 2.0 * c[n] * cos(n * thx);
@@ -346,17 +347,22 @@ __host__ __device__ void compute_mode(const ModeArgs& A, double E, int m, ModeDa
 }
 
 namespace {
-__global__ void k_modes(ModeArgs A, const double* __restrict__ Elist, ModeData* __restrict__ out) {
+__global__ void k_modes(ModeArgs A, const double* __restrict__ Elist, const double* __restrict__ kap,
+                        ModeData* __restrict__ out) {
   const int nxy = A.nx * A.ny;
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long long)nxy * A.nE) return;
   const int e = (int)(gid / nxy);
   const int m = (int)(gid - (long long)e * nxy);
+  if (kap) {
+    A.tx = kap[2 * e];
+    A.ty = kap[2 * e + 1];
+  }
   compute_mode(A, Elist[e], m, &out[gid]);
 }
 }  // namespace
 
-hipError_t launch_modes(iobm_ctx ctx, const double* E_d, int nE, ModeData* out) {
+hipError_t launch_modes(iobm_ctx ctx, const double* E_d, int nE, ModeData* out, const double* kap_d) {
   ModeArgs A;
   A.nx = ctx->g.nx;
   A.ny = ctx->g.ny;
@@ -369,7 +375,7 @@ hipError_t launch_modes(iobm_ctx ctx, const double* E_d, int nE, ModeData* out) 
   long long n = (long long)ctx->g.nxy * nE;
   int threads = 128;
   long long blocks = (n + threads - 1) / threads;
-  hipLaunchKernelGGL(k_modes, dim3((unsigned)blocks), dim3(threads), 0, ctx->stream, A, E_d, out);
+  hipLaunchKernelGGL(k_modes, dim3((unsigned)blocks), dim3(threads), 0, ctx->stream, A, E_d, kap_d, out);
   return hipGetLastError();
 }
 

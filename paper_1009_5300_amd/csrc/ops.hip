@@ -80,13 +80,6 @@ template <> __device__ __forceinline__ const float* potential<float>(const doubl
 //   e0 = (chat_0/2) sum_mu 1/h_mu^2,  w_{mu,n} = chat_n / (2 h_mu^2),
 // lateral neighbours wrap (kappa = 0), z neighbours outside 0..nz-1 dropped.
 // One block owns full lateral planes of one rhs over a chunk of planes.
-struct StencilArgs {
-  int nx, ny, nz, nf, nxy;
-  int zchunk, nchunks;
-  double e0;
-  double wx[4], wy[4], wz[4];
-};
-
 // Operand and epilogue policies of the stencil kernels.  bind() selects the
 // rhs, load(o) returns the operand at flat offset o of that rhs (load_raw and
 // combine split it into the memory reads and the arithmetic, for prefetching
@@ -308,7 +301,7 @@ __global__ void __launch_bounds__(256) k_apply(StencilArgs S, Op op, const T* __
 // admissible variant); the bound sets the compiler's register budget.
 template <int MAXP>
 struct A25 {
-  static constexpr int max_threads = MAXP == 3 ? 768 : (MAXP == 4 ? 640 : (MAXP == 9 ? 512 : 1024));
+  static constexpr int max_threads = MAXP == 3 ? 768 : (MAXP == 4 ? 640 : 1024);
 };
 
 template <typename T, int NF, int MAXP, class Op>
@@ -722,6 +715,66 @@ __global__ void __launch_bounds__(256) k_precond_lap(StencilArgs S, T c1, const 
       dpart[(long long)rhs * S.nchunks + chunk] = P;
     }
   }
+}
+
+// ------------------------------------------------- Jacobi preconditioner ---
+// z = r / a, a = diag A(E) = E - V + e0 - (nonlocal diagonal) - (diagonal of
+// the real-space self-energy on the 2 nf face planes: the mean over the
+// lateral modes of the nf x nf blocks' diagonal, Eq. (11)).  Per-rhs
+// partials of r^T z, one per block of a contiguous chunk.
+template <typename T>
+__global__ void __launch_bounds__(256) k_precond_jacobi(const cplx<T>* __restrict__ r, cplx<T>* __restrict__ z,
+                                                        const double* __restrict__ V, const double* __restrict__ kbd,
+                                                        const zd* __restrict__ sdiag, const int* __restrict__ e_rhs,
+                                                        const double* __restrict__ E_rhs, double e0, int nz, int nf,
+                                                        int nxy, int nblk, const int* __restrict__ active,
+                                                        Partial* __restrict__ dpart) {
+  const int slot = blockIdx.x / nblk;
+  const int blk = blockIdx.x - slot * nblk;
+  const int rhs = rhs_of(active, slot);
+  const long long vol = (long long)nxy * nz;
+  const long long per = (vol + nblk - 1) / nblk;
+  const long long i0 = blk * per, i1 = min(vol, i0 + per);
+  const double d0 = E_rhs[rhs] + e0;
+  const zd* sd = sdiag + (long long)e_rhs[rhs] * nf;
+  double s_re = 0, s_im = 0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const int k = (int)(i / nxy);
+    zd a = mk(d0 - V[i] - (kbd ? kbd[i] : 0.0), 0.0);
+    if (k < nf) a = a - sd[nf - 1 - k];               // left face: reversed plane order
+    else if (k >= nz - nf) a = a - sd[k - (nz - nf)];  // right face
+    const double n = a.re * a.re + a.im * a.im;
+    const zd inv = mk(a.re / n, -a.im / n);
+    const cplx<T> c = r[rhs * vol + i];
+    const cplx<T> v = cvt<T>(inv) * c;
+    z[rhs * vol + i] = v;
+    s_re += (double)c.re * v.re - (double)c.im * v.im;
+    s_im += (double)c.re * v.im + (double)c.im * v.re;
+  }
+  if (dpart) {
+    double dummy = 0;
+    block_reduce3(s_re, s_im, dummy);
+    if (threadIdx.x == 0) {
+      Partial P;
+      P.re = s_re; P.im = s_im; P.n2 = 0; P.pad = 0;
+      dpart[(long long)rhs * nblk + blk] = P;
+    }
+  }
+}
+
+// Diagonal of the right self-energy in real space per energy and face plane
+// i: (1/Nxy) sum over the lateral modes of Sigma~_nu[i][i], summed in a fixed
+// order (one block per entry).
+__global__ void __launch_bounds__(256) k_sigma_diag(const zd* __restrict__ sig, int nxy, int nf, zd* __restrict__ sdiag) {
+  const int e = blockIdx.x / nf, i = blockIdx.x - e * nf;
+  const zd* row = sig + ((long long)e * nf * nf + i * nf + i) * nxy;
+  double re = 0, im = 0, dummy = 0;
+  for (int m = threadIdx.x; m < nxy; m += blockDim.x) {
+    re += row[m].re;
+    im += row[m].im;
+  }
+  block_reduce3(re, im, dummy);
+  if (threadIdx.x == 0) sdiag[blockIdx.x] = mk(re / nxy, im / nxy);
 }
 
 // ------------------------------------------ lateral-Fourier preconditioner ---
@@ -1327,7 +1380,14 @@ struct Scal {
 //                rn2 = sum pb.n2 (|r|^2 written by the update)
 //   FIN_RESTART  rho = sum pa (r^T z); beta = 0; flag cleared
 //   FIN_NORM     rn2 = sum pa.n2
-enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3 };
+//   FIN_KEEP     after a residual replacement that keeps the direction:
+//                rho' = sum pa (r^T z) of the replaced residual.  The last
+//                FIN_BETA left beta = rho_{k+1} / rho_k and rho = rho_{k+1}
+//                from the recursive residual; the direction update takes
+//                the replaced one instead: beta = rho_k^-1 rho' =
+//                beta rho' / rho; rho = rho'; alpha = 0 (the pending step is
+//                already folded into x); flag cleared
+enum { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RESTART = 2, FIN_NORM = 3, FIN_KEEP = 4 };
 
 __global__ void __launch_bounds__(256) k_finish2(Scal S, const Partial* __restrict__ pa, int na,
                                                  const Partial* __restrict__ pb, int nb, int mode,
@@ -1376,6 +1436,18 @@ __global__ void __launch_bounds__(256) k_finish2(Scal S, const Partial* __restri
     S.rn2[rhs] = n2;
     if (S.xset) S.xset[rhs] = 1;
     if (S.dlive) S.dlive[rhs] = 0;
+  } else if (mode == FIN_KEEP) {  // p_new = z + beta p_old next, no pending solution update
+    const zd rho = S.rho[rhs];
+    const double d = rho.re * rho.re + rho.im * rho.im;
+    if (!(d > 0) || !isfinite(re * re + im * im)) {
+      S.beta[rhs] = mk(0.0, 0.0);  // cannot continue the recurrence: restart instead
+    } else {
+      const zd q = mk((re * rho.re + im * rho.im) / d, (im * rho.re - re * rho.im) / d);  // rho' / rho
+      S.beta[rhs] = S.beta[rhs] * q;
+    }
+    S.rho[rhs] = mk(re, im);
+    S.alpha[rhs] = mk(0.0, 0.0);
+    S.flag[rhs] = 0;
   } else {  // FIN_RESTART: p_new = z next, with no pending solution update
     S.rho[rhs] = mk(re, im);
     S.alpha[rhs] = mk(0.0, 0.0);
@@ -1541,7 +1613,8 @@ __global__ void k_combine_psi(const zd* __restrict__ x, cplx<TO>* __restrict__ p
 }  // namespace
 
 // =================================================================== host ===
-static StencilArgs stencil_args(iobm_ctx c, int zchunk) {
+int dot_blocks(iobm_ctx c);
+StencilArgs stencil_args(iobm_ctx c, int zchunk) {
   StencilArgs S;
   S.nx = c->g.nx; S.ny = c->g.ny; S.nz = c->g.nz; S.nf = c->g.nf; S.nxy = c->g.nxy;
   S.zchunk = zchunk;
@@ -1581,21 +1654,29 @@ static int a25_max_threads(int ppt) {
   switch (ppt) {
     case 3: return A25<3>::max_threads;
     case 4: return A25<4>::max_threads;
-    case 9: return A25<9>::max_threads;
     default: return A25<1>::max_threads;
   }
 }
 
-// 2.5D stencil launch shape: points per thread (1, 2, 3, 4 or 9; the block is
+// Points-per-thread variants offered to the autotuner and to pinned shapes:
+// 1..3, and 4 only for nf = 1 (with wider stencils its register window
+// spills; 9 points per thread spilled at every order and is not built).
+static bool a25_ppt_ok(iobm_ctx c, int ppt) {
+  if (ppt < 1 || ppt > 4 || (ppt == 4 && c->g.nf > 1)) return false;
+  const int threads = ((c->g.nxy + ppt - 1) / ppt + 63) / 64 * 64;
+  return threads <= a25_max_threads(ppt);
+}
+
+// 2.5D stencil launch shape: points per thread (1, 2, 3 or 4; the block is
 // ceil(nxy / ppt) threads rounded to a wavefront, at most the variant's
-// bound) and planes per block.  Chosen by the autotuner below, else a
-// default rule.
+// bound) and planes per block.  Chosen by the autotuner below, pinned by
+// the caller, else a default rule.
 template <typename T, class Op>
 static bool launch_apply25_shape(iobm_ctx c, int ppt, int zc, const Op& op, int nrhs, const double* E_rhs,
                                  const int* active) {
   const int nxy = c->g.nxy;
+  if (!a25_ppt_ok(c, ppt)) return false;
   const int threads = ((nxy + ppt - 1) / ppt + 63) / 64 * 64;
-  if (threads > a25_max_threads(ppt) || ppt * threads < nxy) return false;
   StencilArgs S = stencil_args(c, zc);
   if (S.nchunks > PQ_STENCIL_MAX) return false;
   size_t sh = 2 * (size_t)nxy * sizeof(cplx<T>);
@@ -1605,11 +1686,12 @@ static bool launch_apply25_shape(iobm_ctx c, int ppt, int zc, const Op& op, int 
 #define IOBM_A25P(NF)                     \
   if (ppt == 1) { IOBM_A25(NF, 1); }      \
   else if (ppt == 2) { IOBM_A25(NF, 2); } \
-  else if (ppt == 3) { IOBM_A25(NF, 3); } \
-  else if (ppt == 4) { IOBM_A25(NF, 4); } \
-  else { IOBM_A25(NF, 9); }
+  else { IOBM_A25(NF, 3); }
   switch (c->g.nf) {
-    case 1: IOBM_A25P(1); break;
+    case 1:
+      if (ppt == 4) { IOBM_A25(1, 4); }
+      else { IOBM_A25P(1); }
+      break;
     case 2: IOBM_A25P(2); break;
     default: IOBM_A25P(3); break;
   }
@@ -1618,15 +1700,10 @@ static bool launch_apply25_shape(iobm_ctx c, int ppt, int zc, const Op& op, int 
   return true;
 }
 
-template <typename T> static int& tuned_ppt(iobm_ctx c) { return sizeof(T) == 4 ? c->tune_ppt_c64 : c->tune_ppt_c128; }
-template <typename T> static int& tuned_zc(iobm_ctx c) { return sizeof(T) == 4 ? c->tune_zc_c64 : c->tune_zc_c128; }
-
-static int default_ppt(int nxy, bool f32) {
-  // small enough a register queue for several waves per SIMD
-  for (int ppt : {f32 ? 4 : 2, 3, 4, 9}) {
-    const int threads = ((nxy + ppt - 1) / ppt + 63) / 64 * 64;
-    if (threads <= a25_max_threads(ppt)) return ppt;
-  }
+static int default_ppt(iobm_ctx c) {
+  // the fewest points per thread that fit: the smallest register window
+  for (int ppt : {1, 2, 3, 4})
+    if (a25_ppt_ok(c, ppt)) return ppt;
   return 0;
 }
 
@@ -1637,9 +1714,10 @@ static hipError_t launch_stencil(iobm_ctx c, const Op& op, int nrhs, const doubl
                                  double bytes_per_point) {
   const int rec = prof_start(c, sizeof(T) == 4 ? IOBM_K_STENCIL : IOBM_K_STENCIL_C128);
   bool done = false;
-  if (!c->tune_stencil_simple) {
-    int ppt = tuned_ppt<T>(c), zc = tuned_zc<T>(c);
-    if (ppt <= 0) ppt = default_ppt(c->g.nxy, sizeof(T) == 4);
+  const iobm_launch_shape& sh = c->shape[prec_index<T>()];
+  if (sh.stencil != 2) {
+    int ppt = sh.points_per_thread, zc = sh.planes_per_block;
+    if (ppt <= 0) ppt = default_ppt(c);
     if (zc <= 0) zc = 32;
     // a small batch (the tail of a solve, a small refinement subset) gets
     // shorter chunks, so that there are blocks for every compute unit and no
@@ -1678,7 +1756,7 @@ static hipError_t launch_boundary(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx
                                   const int* e_rhs, const ModeData* modes, const int* active, Partial* part) {
   size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(cplx<T>);
   const int rec = prof_start(c, IOBM_K_BOUNDARY);
-  bool reg = c->g.nx == c->g.ny && !c->tune_fft_generic;
+  bool reg = c->g.nx == c->g.ny && c->shape[prec_index<T>()].plane_fft != 2;
   if (reg) {
     switch (c->g.nx) {
       case 8: launch_boundary_reg<T, TR, 8>(c, x, y, rout, nrhs, e_rhs, modes, active, part); break;
@@ -1698,6 +1776,11 @@ static hipError_t launch_boundary(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx
   return hipGetLastError();
 }
 
+hipError_t launch_face_sigma(iobm_ctx c, const zd* x, zd* y, int nrhs, const int* e_rhs, const int* active) {
+  if (nrhs <= 0) return hipSuccess;
+  return launch_boundary<double, double>(c, x, y, nullptr, nrhs, e_rhs, c->modes_d, active, nullptr);
+}
+
 template <typename T>
 hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
                         const int* e_rhs, const ModeData* modes, const int* active,
@@ -1708,12 +1791,16 @@ hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, cons
   if (fuse) {
     OpFuseP<T> op{fuse->z, fuse->pold, fuse->beta, fuse->pnew, y, fuse->part, fuse->alpha, fuse->d, fuse->dlive};
     // streams: read z, p_old (and d); write p_new, y (and d); the nfresh
-    // restarted rhs read z only, the nfirst rhs after them do not read d
+    // restarted rhs read z only, the nkept rhs right after a replacement
+    // that kept the direction read z and p_old, the nfirst rhs after either
+    // do not read d
     const int nf = std::min(std::max(fuse->nfresh, 0), nrhs);
-    const int n1 = fuse->alpha ? std::min(std::max(fuse->nfirstd, 0), nrhs - nf) : 0;
+    const int nk = std::min(std::max(fuse->nkept, 0), nrhs - nf);
+    const int n1 = fuse->alpha ? std::min(std::max(fuse->nfirstd, 0), nrhs - nf - nk) : 0;
     const double full = fuse->alpha ? 6.0 : 4.0;
     err = launch_stencil<T>(c, op, nrhs, E_rhs, active,
-                            (full * (nrhs - nf - n1) + 5.0 * n1 + 3.0 * nf) / nrhs * sizeof(cplx<T>));
+                            (full * (nrhs - nf - nk - n1) + 5.0 * n1 + 4.0 * nk + 3.0 * nf) / nrhs *
+                                sizeof(cplx<T>));
     x = fuse->pnew;  // the electrode and nonlocal terms read the assembled operand
     part = fuse->part;
   } else {
@@ -1755,6 +1842,29 @@ hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_precond_jacobi(iobm_ctx c, const cplx<T>* r, cplx<T>* z, int nrhs, const int* e_rhs,
+                                 const double* E_rhs, const int* active, Partial* dpart) {
+  const int nblk = dot_blocks(c);
+  const StencilArgs S = stencil_args(c, 16);
+  const int rec = prof_start(c, IOBM_K_PRECOND_JACOBI);
+  hipLaunchKernelGGL(k_precond_jacobi<T>, dim3(nrhs * nblk), dim3(256), 0, c->stream, r, z, c->V_d, c->kb.diag_d,
+                     c->sdiag_d, e_rhs, E_rhs, S.e0, c->g.nz, c->g.nf, c->g.nxy, nblk, active, dpart);
+  prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
+  return hipGetLastError();
+}
+template hipError_t launch_precond_jacobi<float>(iobm_ctx, const zf*, zf*, int, const int*, const double*, const int*,
+                                                 Partial*);
+template hipError_t launch_precond_jacobi<double>(iobm_ctx, const zd*, zd*, int, const int*, const double*,
+                                                  const int*, Partial*);
+
+hipError_t launch_sigma_diag(iobm_ctx c, int nE) {
+  if (nE <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sigma_diag, dim3(nE * c->g.nf), dim3(256), 0, c->stream, c->sig_d, c->g.nxy, c->g.nf,
+                     c->sdiag_d);
+  return hipGetLastError();
+}
+
 template <typename T, int N, int PPB>
 static void launch_fft_reg(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                            const int* active, const cplx<T>* mvec, Partial* dpart, const FftUpd<T>* upd) {
@@ -1772,20 +1882,27 @@ static void launch_fft_reg(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign
                        twx<T>(c), sign, (T)scale, active, mvec, dpart, U);
 }
 
-// planes per block of the register FFT (measured: one plane per block is
-// fastest at 48 x 48)
-bool fft_reg_available(iobm_ctx c) {
-  if (c->g.nx != c->g.ny || c->tune_fft_generic) return false;
+static bool square_reg_size(iobm_ctx c) {
+  if (c->g.nx != c->g.ny) return false;
   switch (c->g.nx) {
     case 8: case 12: case 16: case 24: case 32: case 48: return true;
     default: return false;
   }
 }
 
+// planes per block of the register FFT (measured: one plane per block is
+// fastest at 48 x 48)
+template <typename T>
+bool fft_reg_available(iobm_ctx c) {
+  return square_reg_size(c) && c->shape[prec_index<T>()].plane_fft != 2;
+}
+template bool fft_reg_available<float>(iobm_ctx);
+template bool fft_reg_available<double>(iobm_ctx);
+
 template <typename T>
 static bool fft_reg_dispatch(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                              const int* active, const cplx<T>* mvec, Partial* dpart, const FftUpd<T>* upd) {
-  if (!fft_reg_available(c)) return false;
+  if (!fft_reg_available<T>(c)) return false;
   switch (c->g.nx) {
     case 8: launch_fft_reg<T, 8, 16>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd); return true;
     case 12: launch_fft_reg<T, 12, 8>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd); return true;
@@ -1803,7 +1920,7 @@ template <typename T>
 hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                              const int* active, const cplx<T>* dvec = nullptr, const cplx<T>* mvec = nullptr,
                              Partial* dpart = nullptr, const FftUpd<T>* upd = nullptr) {
-  if (upd && !fft_reg_available(c)) return hipErrorInvalidValue;
+  if (upd && !fft_reg_available<T>(c)) return hipErrorInvalidValue;
   const int rec = prof_start(c, upd ? IOBM_K_FFT_PLANES_UPD : (dpart ? IOBM_K_FFT_PLANES_DOT : IOBM_K_FFT_PLANES));
   if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd)) {
     size_t sh = 2 * (size_t)c->g.nxy * sizeof(cplx<T>);
@@ -1845,14 +1962,17 @@ static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* 
   return hipGetLastError();
 }
 
-template <typename T>
-static int zfilter_chunk(iobm_ctx c) {
-  const int tuned = sizeof(T) == 8 ? c->tune_zf_c128 : c->tune_zf_c64;
-  if (tuned > 0) return tuned;
+static int default_zfilter_chunk(iobm_ctx c) {
   // at most 8 chunks (512 threads per block)
   int L = 16;
   if ((c->g.nz + L - 1) / L > 8) L = 32;
   return L;
+}
+
+template <typename T>
+static int zfilter_chunk(iobm_ctx c) {
+  const int tuned = c->shape[prec_index<T>()].zfilter_chunk;
+  return tuned > 0 ? tuned : default_zfilter_chunk(c);
 }
 
 template <typename T>
@@ -1877,9 +1997,10 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
 template <typename T>
 void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
               const int* e_rhs, const ModeData* modes, const int* active, const ApplyFuse<T>* fuse) {
-  bool& done = sizeof(T) == 4 ? c->tuned_c64 : c->tuned_c128;
+  bool& done = c->tuned[prec_index<T>()];
   if (done || nrhs <= 0) return;
   done = true;
+  iobm_launch_shape& sh = c->shape[prec_index<T>()];
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return;
   if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
@@ -1893,14 +2014,13 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
     if (hipEventSynchronize(b) == hipSuccess && hipGetLastError() == hipSuccess) (void)hipEventElapsedTime(&ms, a, b);
     return ms;
   };
-  if (!c->tune_stencil_simple) {
+  if (sh.stencil != 2) {
     // the shape is timed on the operator as the iteration runs it
     float best = 1e30f;
     int bp = 0, bz = 0;
-    for (int ppt : {1, 2, 3, 4, 9})
+    for (int ppt : {1, 2, 3, 4})
       for (int zc : {16, 32, 64}) {
-        const int threads = ((c->g.nxy + ppt - 1) / ppt + 63) / 64 * 64;
-        if (threads > a25_max_threads(ppt) || (sizeof(T) == 8 && ppt == 9)) continue;
+        if (!a25_ppt_ok(c, ppt)) continue;
         if (zc > c->g.nz && zc != 16) continue;
         float t = timed([&] {
           if (fuse)
@@ -1913,7 +2033,7 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
         });
         if (t < best) { best = t; bp = ppt; bz = zc; }
       }
-    if (bp > 0) { tuned_ppt<T>(c) = bp; tuned_zc<T>(c) = bz; }
+    if (bp > 0) { sh.stencil = 1; sh.points_per_thread = bp; sh.planes_per_block = bz; }
   }
   if (scratch) {
     float best = 1e30f;
@@ -1923,7 +2043,7 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
       float t = timed([&] { (void)launch_zfilter<T>(c, L, scratch, y, nrhs, e_rhs, modes, active); });
       if (t < best) { best = t; bl = L; }
     }
-    if (bl > 0) (sizeof(T) == 4 ? c->tune_zf_c64 : c->tune_zf_c128) = bl;
+    if (bl > 0) sh.zfilter_chunk = bl;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -1945,11 +2065,55 @@ template hipError_t launch_precond_fft<double>(iobm_ctx, const zd*, zd*, zd*, in
 template hipError_t launch_precond_fft<float>(iobm_ctx, const zf*, zf*, zf*, int, const int*,
                                               const ModeData*, const int*, Partial*, const FftUpd<float>*);
 
+bool launch_shape_valid(iobm_ctx c, int prec, const iobm_launch_shape& s, std::string& why) {
+  (void)prec;
+  if (s.stencil < 0 || s.stencil > 2 || s.plane_fft < 0 || s.plane_fft > 2) {
+    why = "stencil and plane_fft must be 0, 1 or 2";
+    return false;
+  }
+  if (s.points_per_thread != 0 && !a25_ppt_ok(c, s.points_per_thread)) {
+    why = "points_per_thread does not fit this plane size / FD order";
+    return false;
+  }
+  if (s.stencil == 1 && s.points_per_thread == 0 && default_ppt(c) == 0) {
+    why = "no 2.5D stencil variant fits this plane size";
+    return false;
+  }
+  const int zc = s.planes_per_block;
+  if (zc != 0 && zc != 8 && zc != 16 && zc != 32 && zc != 64) {
+    why = "planes_per_block must be 8, 16, 32 or 64";
+    return false;
+  }
+  const int L = s.zfilter_chunk;
+  if (L != 0 && ((L != 8 && L != 16 && L != 32) || (c->g.nz + L - 1) / L > 8)) {
+    why = "zfilter_chunk must be 8, 16 or 32 with at most 8 chunks along z";
+    return false;
+  }
+  if (s.plane_fft == 1 && !square_reg_size(c)) {
+    why = "the in-register plane FFT needs square planes of 8, 12, 16, 24, 32 or 48 points";
+    return false;
+  }
+  return true;
+}
+
+iobm_launch_shape launch_shape_in_effect(iobm_ctx c, int prec) {
+  const iobm_launch_shape& s = c->shape[prec];
+  iobm_launch_shape r;
+  const int ppt = s.points_per_thread > 0 ? s.points_per_thread : default_ppt(c);
+  r.stencil = (s.stencil == 2 || ppt == 0) ? 2 : 1;
+  r.points_per_thread = r.stencil == 1 ? ppt : 0;
+  r.planes_per_block = r.stencil == 1 ? (s.planes_per_block > 0 ? s.planes_per_block : 32) : 16;
+  r.zfilter_chunk = s.zfilter_chunk > 0 ? s.zfilter_chunk : default_zfilter_chunk(c);
+  r.plane_fft = (square_reg_size(c) && s.plane_fft != 2) ? 1 : 2;
+  return r;
+}
+
 // partials of r^T z per rhs written by each preconditioner (P = I: the
 // update kernel's r^T r, one per reduction block)
 int dot_blocks(iobm_ctx c);
 int precond_slots(iobm_ctx c, int precond) {
   if (precond == IOBM_PC_LATERAL_FFT) return c->g.nz;
+  if (precond == IOBM_PC_JACOBI) return dot_blocks(c);
   if (precond == IOBM_PC_TRUNCATED_LAPLACIAN) return (c->g.nz + 15) / 16;
   return dot_blocks(c);
 }

@@ -18,9 +18,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libiobm.so")
 
 C128, C64_REFINED = 0, 1
-PC_NONE, PC_TRUNCATED_LAPLACIAN, PC_LATERAL_FFT = 0, 1, 2
+PC_NONE, PC_TRUNCATED_LAPLACIAN, PC_LATERAL_FFT, PC_JACOBI = 0, 1, 2, 3
 (K_STENCIL, K_BOUNDARY, K_PRECOND_FFT, K_PRECOND_LAP, K_NONLOCAL, K_DOT, K_UPDATE, K_STENCIL_C128,
- K_FFT_PLANES, K_ZFILTER, K_ACCUMULATE, K_NONLOCAL_C128, K_FFT_PLANES_DOT, K_FFT_PLANES_UPD) = range(1, 15)
+ K_FFT_PLANES, K_ZFILTER, K_ACCUMULATE, K_NONLOCAL_C128, K_FFT_PLANES_DOT, K_FFT_PLANES_UPD,
+ K_PRECOND_JACOBI, K_BLOCK_GRAM, K_BLOCK_UPDATE, K_BLOCH_STENCIL, K_BLOCH_VECTOR) = range(1, 20)
 STATUS = ["ok", "invalid argument", "bad state", "out of device memory", "device error",
           "not converged", "Krylov breakdown", "energy at a channel threshold", "unsupported"]
 
@@ -39,13 +40,21 @@ class Grid(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("alpha", C.c_double),
                 ("tol", C.c_double), ("inner_tol", C.c_double), ("max_iter", C.c_int32),
-                ("side", C.c_int32), ("check_every", C.c_int32)]
+                ("side", C.c_int32), ("check_every", C.c_int32), ("keep_direction", C.c_int32), ("graph", C.c_int32),
+                ("block", C.c_int32), ("pad_", C.c_int32)]
 
 
 class SolveStat(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("status", C.c_int32),
                 ("pad_", C.c_int32), ("rel_residual", C.c_double), ("flux_error", C.c_double)]
 
+
+class LaunchShape(C.Structure):
+    _fields_ = [("stencil", C.c_int32), ("points_per_thread", C.c_int32), ("planes_per_block", C.c_int32),
+                ("zfilter_chunk", C.c_int32), ("plane_fft", C.c_int32)]
+
+
+SHAPE_FIELDS = [f for f, _ in LaunchShape._fields_]
 
 EXPORTS = {
     "iobm_default_opts": (None, [C.POINTER(SolveOpts)]),
@@ -63,8 +72,15 @@ EXPORTS = {
     "iobm_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p]),
+    "iobm_smatrix": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "iobm_channels_bloch": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int32),
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+    "iobm_smatrix_bloch": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_double, C.c_double, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "iobm_grad_transmission": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p,
                                          C.POINTER(C.c_double), C.c_void_p]),
+    "iobm_get_launch_shape": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(LaunchShape)]),
+    "iobm_set_launch_shape": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(LaunchShape)]),
     "iobm_profile_begin": (C.c_int, [C.c_void_p, C.c_int32]),
     "iobm_profile_end": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -173,6 +189,21 @@ class Solver:
         self._check(lib().iobm_set_nonlocal(self._ctx, len(nl.support), rank, _ptr(nsup), _ptr(idx),
                                             _ptr(beta), _ptr(D)))
 
+    def get_launch_shape(self, precision):
+        """The launch shape in effect for `precision` (dict of iobm_launch_shape)."""
+        sh = LaunchShape()
+        self._check(lib().iobm_get_launch_shape(self._ctx, precision, C.byref(sh)))
+        return {f: getattr(sh, f) for f in SHAPE_FIELDS}
+
+    def set_launch_shape(self, precision, shape):
+        """Pin a launch shape (dict; missing fields 0 = default rule), or
+        unpin with None."""
+        if shape is None:
+            self._check(lib().iobm_set_launch_shape(self._ctx, precision, None))
+            return
+        sh = LaunchShape(*[int(shape.get(f, 0)) for f in SHAPE_FIELDS])
+        self._check(lib().iobm_set_launch_shape(self._ctx, precision, C.byref(sh)))
+
     def profile_begin(self, classes):
         mask = 0
         for k in classes:
@@ -278,6 +309,63 @@ class Solver:
             if status not in (5, 6):
                 raise IobmError(status, out["error"])
         return out
+
+    def smatrix(self, energies, opts=None):
+        """Per energy the flux-normalised scattering matrix (2n x 2n complex
+        numpy array, [left | right] channels); returns (list of S, stats)."""
+        energies = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+        n = [len(self.channels(E)[0]) for E in energies]
+        tot = sum(4 * k * k for k in n)
+        S = np.zeros((max(1, tot), 2))
+        st = (SolveStat * max(1, 2 * sum(n)))()
+        o = opts or default_opts()
+        status = lib().iobm_smatrix(self._ctx, C.byref(o), len(energies), _ptr(energies), _ptr(S), st)
+        if status not in (0, 5, 6):
+            self._check(status)
+        Sc = S[:, 0] + 1j * S[:, 1]
+        out, off = [], 0
+        for k in n:
+            out.append(Sc[off:off + 4 * k * k].reshape(2 * k, 2 * k))
+            off += 4 * k * k
+        stats = [(x.iters, x.refinements, x.status, x.rel_residual, x.flux_error) for x in st[:2 * sum(n)]]
+        return out, stats, status
+
+    def channels_bloch(self, E, kappa):
+        """(ids, kz, v) of the open channels at E and lateral Bloch vector kappa."""
+        n = C.c_int32()
+        cap = self.shape[1] * self.shape[2]
+        ids = np.zeros(cap, np.int32)
+        kz = np.zeros(cap)
+        v = np.zeros(cap)
+        self._check(lib().iobm_channels_bloch(self._ctx, float(E), float(kappa[0]), float(kappa[1]), C.byref(n),
+                                              _ptr(ids), _ptr(kz), _ptr(v)))
+        k = n.value
+        return ids[:k].copy(), kz[:k].copy(), v[:k].copy()
+
+    def smatrix_bloch(self, energies, kappa, opts=None):
+        """Scattering matrices at kappa and -kappa per energy: returns
+        (list of S(kappa), list of S(-kappa), stats, status)."""
+        energies = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+        n = [len(self.channels_bloch(E, kappa)[0]) for E in energies]
+        tot = sum(4 * k * k for k in n)
+        Sp = np.zeros((max(1, tot), 2))
+        Sm = np.zeros((max(1, tot), 2))
+        st = (SolveStat * max(1, 2 * sum(n)))()
+        o = opts or default_opts()
+        status = lib().iobm_smatrix_bloch(self._ctx, C.byref(o), float(kappa[0]), float(kappa[1]), len(energies),
+                                          _ptr(energies), _ptr(Sp), _ptr(Sm), st)
+        if status not in (0, 5, 6):
+            self._check(status)
+        outs = []
+        for S in (Sp, Sm):
+            Sc = S[:, 0] + 1j * S[:, 1]
+            out, off = [], 0
+            for k in n:
+                out.append(Sc[off:off + 4 * k * k].reshape(2 * k, 2 * k))
+                off += 4 * k * k
+            outs.append(out)
+        stats = [(x.iters, x.refinements, x.status, x.rel_residual, x.flux_error) for x in st[:2 * sum(n)]]
+        return outs[0], outs[1], stats, status
 
     def grad_transmission(self, energies, opts=None):
         energies = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))

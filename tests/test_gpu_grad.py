@@ -31,7 +31,7 @@ def test_gradient_matches_oracle_adjoint_and_fd(torch, precision):
     w = make(5, Grid(12, 12, 32, 0.4, 2))
     g = w.grid
     Es = [0.2, 0.55]
-    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
     s.set_potential(w.V)
     opts = iobm.default_opts(precision=precision, tol=1e-11)
     T, dT = s.grad_transmission(Es, opts)
@@ -64,7 +64,7 @@ def test_autograd_function(torch):
     from paper_1009_5300_amd.autograd import transmission
     w = make(5, Grid(10, 10, 24, 0.4, 2))
     g = w.grid
-    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
     V = torch.tensor(w.V, dtype=torch.float64, device="cuda", requires_grad=True)
     T = transmission(V, s, [0.35])
     (2.0 * T).backward()
@@ -75,28 +75,47 @@ def test_autograd_function(torch):
     assert torch.allclose(V.grad, 2.0 * g1, rtol=0, atol=1e-12 * float(g1.abs().max()))
     # a fresh context tunes its launch shapes anew; its solves agree to the
     # solver tolerance (residual 1e-10)
-    s2 = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s2 = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
     s2.set_potential(w.V)
     T2, g2 = s2.grad_transmission([0.35])
     assert abs(T.item() - T2) < 1e-9
     assert torch.allclose(V.grad, 2.0 * g2, rtol=0, atol=1e-8 * float(g2.abs().max()))
 
 
+def _wire_voxels(w, n, seed, radius=3.0):
+    """n voxels drawn with `seed` from those within `radius` bohr of the wire
+    axis (where the wells sit and the wave functions are large), chosen
+    without looking at any computed gradient."""
+    g = w.grid
+    k, j, i = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    dx = i * g.hx - g.nx * g.hx / 2
+    dy = j * g.hy - g.ny * g.hy / 2
+    cand = np.flatnonzero((dx * dx + dy * dy).ravel() <= radius * radius)
+    rng = np.random.default_rng(seed)
+    return rng.choice(cand, n, replace=False)
+
+
 def test_gradient_at_full_adjoint_workload(torch):
-    """Workload 5 at its full size (32x32x96, 4 energies, 28 channels): the
-    adjoint gradient against central differences of the GPU forward solve on
-    a sample of the 64 seeded voxels, and the oracle's total transmission."""
+    """Workload 5 at its full size (32 x 32 x 96, 4 energies, 28 channels):
+    the adjoint gradient (complex64 + FP64 refinement) against central
+    differences (delta = 1e-4 Ha) of complex128 forward solves on the 64
+    voxels drawn with the workload's seed (1005) near the wire axis.  The
+    oracle's LU adjoint of this grid is out of reach (its factorisation takes
+    many minutes); the oracle comparison of the same recipe on a z-shortened
+    32 x 32 grid is the next test."""
     from paper_1009_5300_amd import iobm
     w = make(5)
     g = w.grid
-    s = iobm.Solver(g.nx, g.ny, g.nz, g.h, g.nf)
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
     s.set_potential(w.V)
     opts = iobm.default_opts(tol=1e-11)
     fd_opts = iobm.default_opts(precision=iobm.C128, tol=1e-13)
     T, dT = s.grad_transmission(w.energies, opts)
     dT = dT.cpu().numpy()
-    vox = _fd_voxels(g, dT, 64, 1005)[:6]
+    vox = _wire_voxels(w, 64, w.extra["fd_rng_seed"])
+    gmax = np.abs(dT).max()
     d = 1e-4
+    big = 0
     for v in vox:
         Vp, Vm = w.V.copy(), w.V.copy()
         Vp.flat[v] += d
@@ -106,4 +125,33 @@ def test_gradient_at_full_adjoint_workload(torch):
         s.set_potential(Vm)
         Tm = s.solve(w.energies, opts=fd_opts)["T"].sum()
         fd = (Tp - Tm) / (2 * d)
-        assert abs(fd - dT.flat[v]) <= 1e-4 * abs(dT.flat[v]) + 1e-6 * np.abs(dT).max()
+        assert abs(fd - dT.flat[v]) <= 1e-4 * abs(dT.flat[v]) + 1e-6 * gmax, (v, fd, dT.flat[v])
+        big += abs(dT.flat[v]) >= 1e-2 * gmax
+    assert big >= 32  # most sampled voxels carry a gradient well above the absolute floor
+    s.set_potential(w.V)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gradient_z_shortened_32x32_against_oracle(torch, precision):
+    """The adjoint-workload recipe at its 32 x 32 cross-section on a
+    z-shortened 32 x 32 x 12 grid (the oracle's LU of the full 96 planes is
+    out of reach), energies 0.2 and 0.55 Ha (5 and 13 channels): T_total and
+    dT/dV against the oracle's LU adjoint, every voxel to 1e-4 of max |g|
+    and the voxels with |g| >= 1e-2 max |g| to 1e-4 relative."""
+    from paper_1009_5300_amd import iobm
+    w = make(5, Grid(32, 32, 12, 0.4, 2))
+    g = w.grid
+    Es = [0.2, 0.55]
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
+    s.set_potential(w.V)
+    T, dT = s.grad_transmission(Es, iobm.default_opts(precision=precision, tol=1e-11))
+    dT = dT.cpu().numpy()
+    T_ref, g_ref = O.total_transmission_and_gradient(O.Problem(g, w.V), Es, dense=True)
+    gmax = np.abs(g_ref).max()
+    assert abs(T - T_ref) <= 1e-6
+    assert np.abs(dT - g_ref).max() <= 1e-4 * gmax
+    big = np.abs(g_ref) >= 1e-2 * gmax
+    assert big.sum() > 100
+    assert np.abs(dT[big] - g_ref[big]).max() <= 1e-4 * np.abs(g_ref[big]).max()
+    assert np.all(np.abs(dT[big] - g_ref[big]) <= 1e-4 * np.abs(g_ref[big]) + 1e-6 * gmax)
