@@ -210,6 +210,30 @@ iobm_status iobm_apply(iobm_ctx ctx, double E, int32_t nrhs, const void* x, void
 iobm_status iobm_precondition(iobm_ctx ctx, int32_t precond, double alpha, double E,
                               int32_t nrhs, const void* r, void* z, int32_t precision, double* rz);
 
+/* iobm_precondition for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same operation, arguments, layouts, results and errors as
+ * iobm_precondition for IOBM_PC_NONE, IOBM_PC_TRUNCATED_LAPLACIAN and
+ * IOBM_PC_LATERAL_FFT (IOBM_PC_JACOBI returns INVALID_ARG here), and it
+ * calls no hipMalloc, hipFree or other allocating routine.  Every device workspace it needs (the energy's mode table and
+ * the plane-FFT scratch of IOBM_PC_LATERAL_FFT, the partial sums of r^T z)
+ * lives in a static workspace of IOBM_STATIC_WORKSPACE_BYTES that the
+ * library holds on every device it runs on until the process ends.  Needed:
+ * IOBM_PC_LATERAL_FFT nrhs * nx*ny*nz * (16 bytes complex128, 8 complex64)
+ * + 488 * nx*ny bytes; with rz, nrhs * (32 * slots + 16) bytes, slots = nz
+ * (lateral-Fourier), ceil(nz / 16) (Eq. (17)) or up to 64 (none).  A request
+ * beyond the workspace returns IOBM_E_UNSUPPORTED before any launch.
+ * Every call on one device shares that device's workspace and leaves its
+ * contents behind: calls that overlap on one GPU (several contexts, threads
+ * or streams) race and must be serialised by the caller.  The context's
+ * cached mode tables are not touched.  Synchronises the stream for
+ * IOBM_PC_LATERAL_FFT (the threshold check of E) and when rz is requested;
+ * otherwise asynchronous. */
+#define IOBM_STATIC_WORKSPACE_BYTES (64ull << 20)
+iobm_status iobm_precondition_noalloc(iobm_ctx ctx, int32_t precond, double alpha, double E,
+                                      int32_t nrhs, const void* r, void* z, int32_t precision,
+                                      double* rz);
+
 /* Right-hand side of Eq. (6) for incident channels: b[c] for energy E and
  * channel ids[c] (must be open), device complex128 [n][nz][ny][nx], zero
  * outside the first (side 0) or last (side 1) nf planes. */

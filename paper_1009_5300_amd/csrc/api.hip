@@ -28,6 +28,14 @@
 
 #include "internal.h"
 
+// Static device workspace of iobm_precondition_noalloc: a file-scope array
+// that every GPU the library runs on holds until the process ends.  Its name
+// is a host-side stand-in in host code, never a device address: iobm_create
+// looks up this device's address once per device (hipGetSymbolAddress, with
+// that device current) and host code uses only that address.
+#define IOBM_STATIC_WS_BYTES (64ull << 20)
+static __device__ __align__(256) unsigned char scratch[IOBM_STATIC_WS_BYTES];
+
 // launchers from ops.hip
 hipError_t launch_face_norm2(iobm_ctx c, const zd* b, int nact, const int* active, Partial* part);
 template <typename T>
@@ -100,6 +108,10 @@ namespace {
 struct Fail {
   iobm_status s;
 };
+
+const int kMaxDevices = 64;
+std::mutex static_ws_mu;
+void* static_ws_ptr[kMaxDevices] = {};
 
 #define HIPCHK(expr)                                                                        \
   do {                                                                                      \
@@ -1330,6 +1342,19 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
   try {
     HIPCHK(hipGetDevice(&ctx->device));
     HIPCHK(hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    {
+      std::lock_guard<std::mutex> lock(static_ws_mu);
+      if (ctx->device < 0 || ctx->device >= kMaxDevices) {
+        ctx->err = "device index beyond the static workspace table";
+        throw Fail{IOBM_E_UNSUPPORTED};
+      }
+      if (!static_ws_ptr[ctx->device]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        static_ws_ptr[ctx->device] = p;
+      }
+      ctx->static_ws = static_ws_ptr[ctx->device];
+    }
     std::vector<zd> tx(g->nx), ty(g->ny);
     std::vector<zf> fx(g->nx), fy(g->ny);
     for (int k = 0; k < g->nx; ++k) {
@@ -2162,4 +2187,160 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
     return f.s;
   }
   return IOBM_OK;
+}
+
+// ============================================== allocation-free preconditioner
+namespace {
+
+// OR of the mode flags of one energy's table (one block, fixed order).
+__global__ void __launch_bounds__(256) k_mode_flags_or(const ModeData* __restrict__ modes, int n, int* out) {
+  __shared__ int sh[256];
+  int f = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) f |= modes[i].flags;
+  sh[threadIdx.x] = f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0;
+    for (int i = 0; i < (int)blockDim.x; ++i) a |= sh[i];
+    out[0] = a;
+  }
+}
+
+// Sum of each vector's partials of r^T z in slot order (the order the host
+// sum of iobm_precondition takes), one thread per vector.
+__global__ void k_sum_partials(const Partial* __restrict__ part, int nrhs, int slots, double* __restrict__ rz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrhs) return;
+  double re = 0, im = 0;
+  for (int k = 0; k < slots; ++k) {
+    re += part[(long long)i * slots + k].re;
+    im += part[(long long)i * slots + k].im;
+  }
+  rz[2 * i] = re;
+  rz[2 * i + 1] = im;
+}
+
+// Zero fill (a kernel rather than a memset node, for callers that capture).
+__global__ void k_fill_zero(unsigned long long* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Host-to-device copy of a small array through the pinned arena (region r),
+// without building a host vector.
+void* upload_bytes(iobm_ctx ctx, int region, const void* src, size_t bytes) {
+  if (ctx->region_pending[region]) stream_sync(ctx);
+  char* h = (char*)ctx->arena_h + (size_t)region * kRegion;
+  char* d = (char*)ctx->arena_d + (size_t)region * kRegion;
+  memcpy(h, src, bytes);
+  HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
+  ctx->region_pending[region] = 1;
+  return d;
+}
+
+template <typename T>
+void precondition_static(iobm_ctx ctx, int precond, double alpha, double E, int nrhs, const void* r, void* z,
+                         double* rz) {
+  const long long vol = ctx->g.npts;
+  const int nxy = ctx->g.nxy;
+  const int slots = precond_slots(ctx, precond);
+  // layout of the static workspace: mode table and flag word (lateral-Fourier
+  // preconditioner), plane-FFT scratch, partials, per-vector r^T z
+  size_t off = 0;
+  const size_t o_modes = off;
+  if (precond == IOBM_PC_LATERAL_FFT) off += align256((size_t)nxy * sizeof(ModeData)) + 256;
+  const size_t o_pf = off;
+  if (precond == IOBM_PC_LATERAL_FFT) off += align256((size_t)nrhs * vol * sizeof(cplx<T>));
+  const size_t o_part = off;
+  if (rz) off += align256((size_t)nrhs * slots * sizeof(Partial)) + align256((size_t)nrhs * 2 * sizeof(double));
+  if (off > IOBM_STATIC_WS_BYTES || (rz && (size_t)nrhs * 2 * sizeof(double) > kRegion) ||
+      (size_t)nrhs * sizeof(int) > kRegion) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "iobm_precondition_noalloc needs %zu bytes of workspace for %d vectors; the static workspace holds %llu",
+             off, nrhs, (unsigned long long)IOBM_STATIC_WS_BYTES);
+    ctx->err = buf;
+    throw Fail{IOBM_E_UNSUPPORTED};
+  }
+  char* ws = (char*)ctx->static_ws;
+  Partial* part = rz ? (Partial*)(ws + o_part) : nullptr;
+  double* rz_d = rz ? (double*)(ws + o_part + align256((size_t)nrhs * slots * sizeof(Partial))) : nullptr;
+  if (part) {  // every slot is written by its block; cleared so that no stale value can survive
+    const long long n8 = (long long)nrhs * slots * sizeof(Partial) / 8;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<long long>(1024, (n8 + 255) / 256)), dim3(256), 0,
+                       ctx->stream, (unsigned long long*)part, n8);
+    HIPCHK(hipGetLastError());
+  }
+  if (precond == IOBM_PC_NONE) {
+    HIPCHK(hipMemcpyAsync(z, r, (size_t)nrhs * vol * sizeof(cplx<T>), hipMemcpyDeviceToDevice, ctx->stream));
+    if (part) HIPCHK(launch_dot<T>(ctx, (const cplx<T>*)r, (const cplx<T>*)r, nrhs, nullptr, part));
+  } else if (precond == IOBM_PC_TRUNCATED_LAPLACIAN) {
+    HIPCHK(launch_precond_laplacian<T>(ctx, alpha, (const cplx<T>*)r, (cplx<T>*)z, nrhs, nullptr, part));
+  } else {
+    // this energy's mode table in the workspace (the context's cached tables
+    // are left alone), checked for thresholds on the host
+    ModeData* modes = (ModeData*)(ws + o_modes);
+    int* flag = (int*)(ws + o_modes + align256((size_t)nxy * sizeof(ModeData)));
+    const double* E_d = (const double*)upload_bytes(ctx, 60, &E, sizeof(double));
+    HIPCHK(launch_modes(ctx, E_d, 1, modes));
+    hipLaunchKernelGGL(k_mode_flags_or, dim3(1), dim3(256), 0, ctx->stream, modes, nxy, flag);
+    HIPCHK(hipGetLastError());
+    int* flag_h = (int*)((char*)ctx->arena_h + 61 * kRegion);
+    HIPCHK(hipMemcpyAsync(flag_h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    if (flag_h[0] & MODE_THRESHOLD) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "energy %.12g is at a lateral channel threshold", E);
+      ctx->err = buf;
+      throw Fail{IOBM_E_AT_THRESHOLD};
+    }
+    if (flag_h[0] & MODE_FAIL) {
+      ctx->err = "mode setup failed";
+      throw Fail{IOBM_E_DEVICE};
+    }
+    // every vector uses mode table entry 0: an array of nrhs zeros in region 59
+    int* e_h = (int*)((char*)ctx->arena_h + 59 * kRegion);
+    if (ctx->region_pending[59]) stream_sync(ctx);
+    memset(e_h, 0, (size_t)nrhs * sizeof(int));
+    int* e_d = (int*)((char*)ctx->arena_d + 59 * kRegion);
+    HIPCHK(hipMemcpyAsync(e_d, e_h, (size_t)nrhs * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    ctx->region_pending[59] = 1;
+    HIPCHK(launch_precond_fft<T>(ctx, (const cplx<T>*)r, (cplx<T>*)z, (cplx<T>*)(ws + o_pf), nrhs, e_d, modes,
+                                 nullptr, part));
+  }
+  if (rz) {
+    hipLaunchKernelGGL(k_sum_partials, dim3((nrhs + 63) / 64), dim3(64), 0, ctx->stream, part, nrhs, slots, rz_d);
+    HIPCHK(hipGetLastError());
+    double* rz_h = (double*)((char*)ctx->arena_h + 62 * kRegion);
+    HIPCHK(hipMemcpyAsync(rz_h, rz_d, (size_t)nrhs * 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    stream_sync(ctx);
+    memcpy(rz, rz_h, (size_t)nrhs * 2 * sizeof(double));
+  }
+}
+
+}  // namespace
+
+extern "C" iobm_status iobm_precondition_noalloc(iobm_ctx ctx, int32_t precond, double alpha, double E,
+                                                 int32_t nrhs, const void* r, void* z, int32_t precision,
+                                                 double* rz) {
+  if (!ctx) return IOBM_E_INVALID_ARG;
+  if (nrhs < 0 || (nrhs > 0 && (!r || !z)) || !isfinite(E) || !(alpha > 0) ||
+      (precision != IOBM_C128 && precision != IOBM_C64_REFINED) || precond < 0 || precond > 2)
+    return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
+  if (r == z) return fail(ctx, IOBM_E_INVALID_ARG, "r and z must not overlap");
+  if (!ctx->static_ws) return fail(ctx, IOBM_E_BAD_STATE, "no static workspace on this device");
+  if (nrhs == 0) return IOBM_OK;
+  const int prof = ctx->prof_mask;  // the timing hook records events: off for this call
+  ctx->prof_mask = 0;
+  iobm_status st = IOBM_OK;
+  try {
+    if (precision == IOBM_C128) precondition_static<double>(ctx, precond, alpha, E, nrhs, r, z, rz);
+    else precondition_static<float>(ctx, precond, alpha, E, nrhs, r, z, rz);
+  } catch (Fail& f) {
+    st = f.s;
+  }
+  ctx->prof_mask = prof;
+  return st;
 }

@@ -113,6 +113,9 @@ struct iobm_ctx_s {
   // which cannot be captured)
   hipStream_t cap_stream = nullptr;
   hipEvent_t cap_ev[2] = {nullptr, nullptr};
+  // device address of this device's copy of the library's static workspace
+  // (iobm_precondition_noalloc), looked up once per device
+  void* static_ws = nullptr;
   std::string err;
 };
 

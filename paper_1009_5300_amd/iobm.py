@@ -68,6 +68,8 @@ EXPORTS = {
     "iobm_apply": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     "iobm_precondition": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "iobm_precondition_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                            C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "iobm_rhs": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
     "iobm_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -259,6 +261,16 @@ class Solver:
         self._check(lib().iobm_precondition(self._ctx, kind, float(alpha), float(E), nrhs, _ptr(r),
                                             _ptr(z), precision, _ptr(rz)))
         return (z, rz) if want_rz else z
+
+    def precondition_noalloc(self, kind, r, z, alpha=1.8, E=0.0, precision=C128, want_rz=False):
+        """z = P r into the caller's z through the allocation-free entry
+        point (the library's static workspace); returns rz as precondition."""
+        nrhs = r.numel() // self.npts
+        assert r.is_contiguous() and z.is_contiguous() and z.numel() == r.numel()
+        rz = np.zeros(nrhs, dtype=np.complex128) if want_rz else None
+        self._check(lib().iobm_precondition_noalloc(self._ctx, kind, float(alpha), float(E), nrhs, _ptr(r),
+                                                    _ptr(z), precision, _ptr(rz)))
+        return rz
 
     def rhs(self, E, ids, side=0):
         ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int32))
