@@ -33,7 +33,8 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy kernel), kept with
 # the git blob ids of the sources it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
-KERNEL_SOURCES = ["paper_1009_5300_amd/csrc/ops.hip", "paper_1009_5300_amd/csrc/common.h"]
+KERNEL_SOURCES = ["paper_1009_5300_amd/csrc/ops.hip", "paper_1009_5300_amd/csrc/common.h",
+                  "paper_1009_5300_amd/csrc/internal.h"]
 
 
 def _blob_id(path):
@@ -348,7 +349,7 @@ def precision_sweep():
     print(json.dumps({"experiment": "preconditioner x precision sweep", "rows": res}), flush=True)
 
 
-def block_sweep():
+def block_sweep(only=None):
     """Block COCG per energy against per-state COCG, both in complex128, on
     the wide wire (48 x 48 x 128): the lateral-Fourier preconditioner over
     all 16 energies (768 states), the paper's Eq. (17) (alpha = 1.8) and no
@@ -371,6 +372,8 @@ def block_sweep():
     for pname, pc, Es in (("lateral_fft", iobm.PC_LATERAL_FFT, list(w.energies)),
                           ("eq17_alpha1.8", iobm.PC_TRUNCATED_LAPLACIAN, [w.energies[0]]),
                           ("none", iobm.PC_NONE, [w.energies[0]])):
+        if only and pname != only:
+            continue
         Tref = None
         for mode, blk in (("per_state", 0), ("block", 1)):
             print(json.dumps({"starting": f"{pname}/{mode}"}), flush=True)
@@ -391,6 +394,71 @@ def block_sweep():
                       "rows": rows}), flush=True)
 
 
+def bloch_workload(args):
+    """The wide wire (48 x 48 x 128, 4th-order FD) at a general lateral Bloch
+    vector kappa = (0.37 pi / L_x, 0.61 pi / L_y), the first 4 energies of
+    the headline workload: the scattering matrices at kappa and -kappa
+    (every open channel from both leads, each state paired with its partner
+    at -kappa), complex128 biconjugate gradients with the lateral-Fourier
+    preconditioner.  Scattering states per second (both members of a pair
+    count) and the achieved HBM bandwidth of the phased stencil."""
+    import numpy as np
+    import torch
+
+    from paper_1009_5300_amd import iobm
+    from workloads import make
+
+    torch.cuda.set_device(0)
+    w = make(4)
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
+    s.set_potential(w.V)
+    kap = (0.37 * np.pi / (g.nx * g.hx), 0.61 * np.pi / (g.ny * g.hy))
+    Es = list(w.energies[:4])
+    opts = iobm.default_opts(precision=iobm.C128)
+    nst = 2 * 2 * sum(len(s.channels_bloch(E, kap)[0]) for E in Es)
+    for _ in range(max(1, args.warmup)):
+        Sp, Sm, stats, status = s.smatrix_bloch(Es, kap, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Sp, Sm, stats, status = s.smatrix_bloch(Es, kap, opts=opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert status == 0
+    s.profile_begin([iobm.K_BLOCH_STENCIL, iobm.K_BLOCH_VECTOR, iobm.K_PRECOND_FFT, iobm.K_BOUNDARY])
+    s.smatrix_bloch(Es, kap, opts=opts)
+    kern = {}
+    for name, cls in (("stencil_bloch", iobm.K_BLOCH_STENCIL), ("vector_bloch", iobm.K_BLOCH_VECTOR),
+                      ("precond_fft", iobm.K_PRECOND_FFT), ("boundary", iobm.K_BOUNDARY)):
+        n, ms, b = s.profile_end(cls)
+        if n:
+            kern[name] = {"launches": n, "avg_ms": round(ms / n, 4), "total_ms": round(ms, 3),
+                          "alg_bytes_per_launch": b / n, "achieved_GBps": round(b / (ms * 1e-3) / 1e9, 1)}
+    s.profile_begin([])
+    unit = 0.0
+    for Sa in Sp:
+        n = Sa.shape[0] // 2
+        unit = max(unit, float(np.abs(Sa.conj().T @ Sa - np.eye(2 * n)).max()))
+    st = np.array(stats, dtype=float)
+    sb = kern.get("stencil_bloch")
+    print(json.dumps({
+        "metric": "scattering states/sec at a lateral Bloch vector (S(kappa) and S(-kappa))",
+        "value": round(args.steps * nst / (t1 - t0), 2), "unit": "states/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * (t1 - t0) / args.steps, 3), "higher_is_better": True,
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "wide 48x48x128 h=0.4 4th-order FD at kappa = (0.37 pi/Lx, 0.61 pi/Ly), 4 energies, "
+                               "both leads", "states": int(nst), "precision": "complex128 biconjugate gradients, "
+                               "FP64 reductions", "preconditioner": "lateral-Fourier at G + kappa"},
+        "roofline": None if not sb else {"bound": "hbm", "achieved": sb["achieved_GBps"], "peak": 8000.0,
+                                         "unit": "GB/s", "frac": round(sb["achieved_GBps"] / 8000.0, 4),
+                                         "traffic": None, "kernel": "stencil_bloch"},
+        "kernels": kern,
+        "pair_iters_mean": float(st[:, 0].mean()), "max_rel_residual": float(st[:, 3].max()),
+        "max_unitarity_error": unit,
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,10 +468,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip plain-CG and Eq. (17) samples")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for the HBM counter calibration)")
-    ap.add_argument("--workload", default="4", choices=["3", "4", "5", "na", "precision", "block"],
+    ap.add_argument("--workload", default="4", choices=["3", "4", "5", "na", "precision", "block", "bloch"],
                     help="4: the headline wide-wire batch (default); 3: the atomic chain with the nonlocal "
                          "term on MFMA (secondary measurement); 5: the adjoint gradient dT/dV; na: iteration "
                          "counts of the paper's preconditioner experiment on synthetic Na-like wires")
+    ap.add_argument("--preconditioner", default=None, choices=["lateral_fft", "eq17_alpha1.8", "none"],
+                    help="--workload block: run this preconditioner only")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -421,11 +491,14 @@ def main():
         precision_sweep()
         return
     if args.gpus == 1 and args.workload == "block":
-        block_sweep()
+        block_sweep(args.preconditioner)
+        return
+    if args.gpus == 1 and args.workload == "bloch":
+        bloch_workload(args)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: the scattering states of different energies are "
-              "independent, and multi-GPU runs are not part of this build (use --gpus 1).",
+        print("bench.py measures one GPU (use --gpus 1): the scattering states of different energies are "
+              "independent, and runs across several GPUs are not supported.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -78,7 +78,8 @@ hipError_t launch_grad(iobm_ctx c, int nE, const int* base, const long long* dba
 // block.hip
 template <typename T>
 hipError_t launch_gram(iobm_ctx c, const cplx<T>* U, const cplx<T>* W, int ngroups, const int* cols,
-                       const int* goff, const int* gsize, const int* gid, double* part, int nblk, zd* G, int ncols);
+                       const int* goff, const int* gsize, const int* gid, const int* poff, double* part, int nblk,
+                       zd* G, int ncols);
 hipError_t launch_small_solve(iobm_ctx c, int ngroups, const int* gsize, const int* gid, const zd* G, const zd* Y,
                               zd* Gw, zd* X, int* flag);
 template <typename T, typename TY>
@@ -663,9 +664,17 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
 // solution x (the driver is written for either iteration precision, but
 // solve_batch admits complex128 only).  A group is refreshed (x += D, the
 // true residual r = b - A x, converged columns leave, the recursion
-// restarts with P = Z) when a column's iterated residual reaches the
-// target, falls by opts.inner_tol (complex64), diverges, or a Gram solve
-// breaks down (the block has become rank deficient).
+// restarts with P = Z) when the iterated residuals of all its columns have
+// reached the target, or a column's has fallen by opts.inner_tol
+// (complex64) or diverged, or a Gram solve broke down (the block has become
+// rank deficient).  Columns that reach the target early stay in the block
+// until the group is refreshed: a refresh restarts the block Krylov space of
+// every column of the group, and restarts at every converged column cost
+// far more than the extra iterations (measured in a NumPy model of this
+// driver: 135x the iterations of the plain recurrence on a Helmholtz test
+// problem).  A group whose Gram solve broke down is split into single
+// columns after its refresh; they keep their progress and continue as plain
+// COCG.
 template <typename T>
 void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, const zd* b, zd* x, SolveOut& out) {
   const int nb = B.n;
@@ -704,22 +713,31 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
   cplx<T>* q = (cplx<T>*)workspace(ctx, S_Q, vb);
   cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)workspace(ctx, S_Z, vb);
   cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)workspace(ctx, S_PF, vb) : nullptr;
-  const int nblk_g = std::min(128, std::max(16, 512 / ng));
-  double* gpart = (double*)workspace(ctx, S_BLK_PART, (size_t)ng * nblk_g * 64 * 64 * 4 * sizeof(double));
+  // point blocks per group of a Gram launch: about 512 blocks in all
+  auto gram_blocks = [](int ngroups) { return std::min(128, std::max(16, 512 / std::max(1, ngroups))); };
+  // group ids: the energies' groups, then the halves of split groups (one
+  // new id per split, at most nb groups at any time)
+  const int gcap = std::max(ng, nb);
+  // packed Gram partials: nblk * 4 * sum s^2 doubles.  With G groups in a
+  // launch, sum s^2 <= min(64^2 G, 64 nb): for G <= 32, nblk <= 512 / G or
+  // 128, so nblk sum s^2 <= min(512 * 64^2, 128 * 64 nb); beyond, nblk = 16
+  // and nblk sum s^2 <= 16 * 64 nb
+  const size_t gpart_n = std::max(std::min<size_t>((size_t)512 * 64 * 64, (size_t)128 * 64 * nb), (size_t)16 * 64 * nb);
+  double* gpart = (double*)workspace(ctx, S_BLK_PART, gpart_n * 4 * sizeof(double));
   const size_t gmat = (size_t)64 * 64;
-  zd* gm = (zd*)workspace(ctx, S_BLK_G, 6 * (size_t)ng * gmat * sizeof(zd));
+  zd* gm = (zd*)workspace(ctx, S_BLK_G, 6 * (size_t)gcap * gmat * sizeof(zd));
   zd* G1 = gm;
-  zd* G2 = gm + (size_t)ng * gmat;
-  zd* G2n = gm + 2 * (size_t)ng * gmat;
-  zd* AL = gm + 3 * (size_t)ng * gmat;
-  zd* BE = gm + 4 * (size_t)ng * gmat;
-  zd* GW = gm + 5 * (size_t)ng * gmat;
+  zd* G2 = gm + (size_t)gcap * gmat;
+  zd* G2n = gm + 2 * (size_t)gcap * gmat;
+  zd* AL = gm + 3 * (size_t)gcap * gmat;
+  zd* BE = gm + 4 * (size_t)gcap * gmat;
+  zd* GW = gm + 5 * (size_t)gcap * gmat;
   const int nchunk = (int)std::min<long long>(256, (vol + 63) / 64);
   Partial* n2p = (Partial*)workspace(ctx, S_BLK_N2, (size_t)nb * nchunk * sizeof(Partial));
   const int nblk = dot_blocks(ctx);
   Partial* part = (Partial*)workspace(ctx, S_PART, (size_t)nb * nblk * sizeof(Partial));
   Partial* part_rn = (Partial*)workspace(ctx, S_PARTR, (size_t)nb * PQ_SLOTS * sizeof(Partial));
-  const size_t nb8 = ((size_t)nb + 1) & ~(size_t)1, ng8 = ((size_t)ng + 1) & ~(size_t)1;
+  const size_t nb8 = ((size_t)nb + 1) & ~(size_t)1, ng8 = ((size_t)gcap + 1) & ~(size_t)1;
   char* sc = (char*)workspace(ctx, S_SCAL, (size_t)nb * 3 * sizeof(zd) + nb8 * (2 * sizeof(double) + 3 * sizeof(int)) +
                                              2 * ng8 * sizeof(int) + 64);
   zd* rho = (zd*)sc;
@@ -730,7 +748,7 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
   double* tn2 = (double*)(flag + nb8);
   int* xset = (int*)(tn2 + nb8);
   int* dlive = xset + nb8;
-  int* gflag = dlive + nb8;  // [2][ng]: breakdown of the alpha and the beta solve
+  int* gflag = dlive + nb8;  // [2][gcap]: breakdown of the alpha and the beta solve
   const size_t chk = (size_t)nb * sizeof(double);
   char* rbh = (char*)pinned_readback(ctx, chk + nb8 * sizeof(int) + (size_t)nb * sizeof(double) + 2 * ng8 * sizeof(int) + 64);
   const double* rn2_h = (const double*)rbh;
@@ -753,34 +771,40 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
     stream_sync(ctx);
     memcpy(dst.data(), tn2_pin, nb * sizeof(double));
   };
-  // group lists on the device: [gid | goff | gsize | cols] in one upload
+  // group lists on the device: [gid | goff | gsize | poff | cols] in one upload
   struct Groups {
     int n = 0, ncols = 0;
-    const int *gid = nullptr, *goff = nullptr, *gsize = nullptr, *cols = nullptr;
+    const int *gid = nullptr, *goff = nullptr, *gsize = nullptr, *poff = nullptr, *cols = nullptr;
   };
   auto make_groups = [&](const std::vector<int>& gl, const std::vector<std::vector<int>>& gc, int region) {
     Groups G;
     G.n = (int)gl.size();
-    std::vector<int> buf(3 * G.n);
+    std::vector<int> buf(4 * G.n);
+    int sq = 0;
     for (int k = 0; k < G.n; ++k) {
+      const int sz = (int)gc[gl[k]].size();
       buf[k] = gl[k];
       buf[G.n + k] = G.ncols;
-      buf[2 * G.n + k] = (int)gc[gl[k]].size();
-      G.ncols += (int)gc[gl[k]].size();
+      buf[2 * G.n + k] = sz;
+      buf[3 * G.n + k] = sq;
+      G.ncols += sz;
+      sq += sz * sz;
     }
     for (int k = 0; k < G.n; ++k) buf.insert(buf.end(), gc[gl[k]].begin(), gc[gl[k]].end());
     const int* dptr = upload(ctx, S_IDX, buf, (size_t)region * 8192);
     G.gid = dptr;
     G.goff = dptr + G.n;
     G.gsize = dptr + 2 * G.n;
-    G.cols = dptr + 3 * G.n;
+    G.poff = dptr + 3 * G.n;
+    G.cols = dptr + 4 * G.n;
     return G;
   };
   // (re)start the block recursion of the listed groups: Z = M R, G2 = R^T Z, P = Z
   auto start_groups = [&](const Groups& S) {
     if (S.n == 0) return;
     precond(S.ncols, S.cols);
-    HIPCHK(launch_gram<T>(ctx, r, z, S.n, S.cols, S.goff, S.gsize, S.gid, gpart, nblk_g, G2, S.ncols));
+    HIPCHK(launch_gram<T>(ctx, r, z, S.n, S.cols, S.goff, S.gsize, S.gid, S.poff, gpart, gram_blocks(S.n), G2,
+                          S.ncols));
     HIPCHK((launch_convert<T, T>(ctx, z, pa, S.ncols, S.cols)));
   };
 
@@ -797,8 +821,9 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
   read_tn2(bn2);
   tn2_h = bn2;
   HIPCHK(launch_init_r<T>(ctx, b, r, nb, all_d));
-  std::vector<std::vector<int>> gc(ng);
+  std::vector<std::vector<int>> gc(gcap);
   std::vector<int> glist;
+  int next_gid = ng;
   for (int g = 0; g < ng; ++g) {
     for (int i = gfirst[g]; i < gfirst[g] + gsz[g]; ++i)
       if (bn2[i] > 0) gc[g].push_back(i);
@@ -813,14 +838,16 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
   while (A.n > 0) {
     for (int k = 0; k < check; ++k) {
       HIPCHK(launch_apply<T>(ctx, pa, q, A.ncols, E_d, e_d, modes, A.cols));
-      HIPCHK(launch_gram<T>(ctx, pa, q, A.n, A.cols, A.goff, A.gsize, A.gid, gpart, nblk_g, G1, A.ncols));
+      HIPCHK(launch_gram<T>(ctx, pa, q, A.n, A.cols, A.goff, A.gsize, A.gid, A.poff, gpart, gram_blocks(A.n), G1,
+                            A.ncols));
       HIPCHK(launch_small_solve(ctx, A.n, A.gsize, A.gid, G1, G2, GW, AL, gflag));
       HIPCHK((launch_block_update<T, T>(ctx, d, pa, nullptr, AL, A.n, A.cols, A.goff, A.gsize, A.gid, nchunk, 0,
                                         nullptr, A.ncols)));
       HIPCHK((launch_block_update<T, T>(ctx, r, q, nullptr, AL, A.n, A.cols, A.goff, A.gsize, A.gid, nchunk, 1, n2p,
                                         A.ncols)));
       precond(A.ncols, A.cols);
-      HIPCHK(launch_gram<T>(ctx, r, z, A.n, A.cols, A.goff, A.gsize, A.gid, gpart, nblk_g, G2n, A.ncols));
+      HIPCHK(launch_gram<T>(ctx, r, z, A.n, A.cols, A.goff, A.gsize, A.gid, A.poff, gpart, gram_blocks(A.n), G2n,
+                            A.ncols));
       HIPCHK(launch_small_solve(ctx, A.n, A.gsize, A.gid, G2, G2n, GW, BE, gflag + ng8));
       std::swap(G2, G2n);
       HIPCHK((launch_block_update<T, T>(ctx, pb, pa, z, BE, A.n, A.cols, A.goff, A.gsize, A.gid, nchunk, 2, nullptr,
@@ -839,16 +866,18 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
     std::vector<int> upd_g, upd_c;
     for (int g : glist) {
       const bool brk = gflag_h[g] || gflag_h[ng8 + g];
-      bool go = brk;
+      bool go = brk, all_conv = true;
       for (int i : gc[g]) {
         out.iters[i] += check;
         const double r2 = rn2_h[i];
-        const bool w = !(r2 == r2) || r2 > 1e4 * maxr2[i] || r2 <= 0.25 * tol2 * bn2[i] ||
-                       r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter;
-        want[i] = w || brk;
+        const bool conv = r2 <= 0.25 * tol2 * bn2[i];
+        const bool w = !(r2 == r2) || r2 > 1e4 * maxr2[i] || r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter;
+        all_conv = all_conv && conv;
+        want[i] = w || brk || conv;
         if (!w) maxr2[i] = std::max(maxr2[i], r2);
         go = go || w;
       }
+      go = go || all_conv;
       if (go) {
         upd_g.push_back(g);
         upd_c.insert(upd_c.end(), gc[g].begin(), gc[g].end());
@@ -875,6 +904,8 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
     }
     std::vector<int> restart_g;
     for (int g : upd_g) {
+      const bool brk = gflag_h[g] || gflag_h[ng8 + g];
+      const bool split = brk && gc[g].size() > 1;
       std::vector<int> keep;
       for (int i : gc[g]) {
         out.refin[i] += 1;
@@ -883,21 +914,37 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
         if (out.iters[i] >= o.max_iter) { out.status[i] = IOBM_E_NOT_CONVERGED; continue; }
         // a refresh the column asked for must improve its true residual
         // (six in a row without a fourfold gain end it); one triggered by
-        // another column of the group does not count against it
-        if (t2 < 0.25 * best[i]) { best[i] = t2; stall[i] = 0; }
+        // another column of the group does not count against it, and a
+        // split gives the columns a fresh start
+        if (t2 < 0.25 * best[i] || split) { best[i] = std::min(best[i], t2); stall[i] = 0; }
         else if (want[i] && ++stall[i] >= 6) {
-          out.status[i] = (gflag_h[g] || gflag_h[ng8 + g]) ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
+          out.status[i] = brk ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
           continue;
         }
         maxr2[i] = t2;
         keep.push_back(i);
       }
+      if (split && keep.size() > 1) {
+        // every column but the first moves to a group of its own (new ids
+        // never run out: each split adds at most its columns - 1 groups)
+        std::vector<int> stay(1, keep[0]);
+        for (size_t k = 1; k < keep.size(); ++k) {
+          if (next_gid >= gcap) { stay.push_back(keep[k]); continue; }
+          const int ng2 = next_gid++;
+          gc[ng2].assign(1, keep[k]);
+          restart_g.push_back(ng2);
+        }
+        keep = stay;
+      }
       gc[g] = keep;
       if (!keep.empty()) restart_g.push_back(g);
     }
+    // groups in the order of their first column (deterministic launch order)
     std::vector<int> nl;
-    for (int g : glist)
+    for (int g = 0; g < next_gid; ++g)
       if (!gc[g].empty()) nl.push_back(g);
+    std::sort(nl.begin(), nl.end(), [&](int a, int b) { return gc[a][0] < gc[b][0]; });
+    std::sort(restart_g.begin(), restart_g.end(), [&](int a, int b) { return gc[a][0] < gc[b][0]; });
     glist = nl;
     A = make_groups(glist, gc, 8);
     start_groups(make_groups(restart_g, gc, 16));

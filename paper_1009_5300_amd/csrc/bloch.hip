@@ -9,8 +9,9 @@
 // condition psi(r + L) = exp(i kappa L) psi(r) turns into a periodic u whose
 // lateral couplings carry a bond phase: the neighbour at +n along x enters
 // with exp(i n kappa_x h_x), the one at -n with its conjugate.  Only the
-// stencil and Eq. (17) change (this file); the diagonal (and so the Jacobi
-// preconditioner) does not.
+// stencil (the 2.5D kernel with the OpBloch policy, ops.hip) and Eq. (17)
+// (this file) change; the diagonal (and so the Jacobi preconditioner) does
+// not.
 //
 // Transpose.  A(kappa)^T = A(-kappa): the operator is not complex symmetric
 // for one kappa, so each state at +kappa is solved together with a partner
@@ -40,60 +41,6 @@ __device__ __forceinline__ void bl_reduce3(double& a, double& b, double& c) {
     double ra = 0, rb = 0, rc = 0;
     for (int i = 0; i < nw; ++i) { ra += sh[0][i]; rb += sh[1][i]; rc += sh[2][i]; }
     a = ra; b = rb; c = rc;
-  }
-}
-
-// y = A_st x in the gauge u: (E - V + e0) x + sum_n w_n (phase_n x(+n) +
-// conj(phase_n) x(-n)) laterally, plain couplings along z (zero outside the
-// transition region).  The rhs at -kappa (sgn < 0) take the conjugate phases.
-// One thread per point of a chunk of planes, neighbours read from memory.
-template <int NF>
-__global__ void __launch_bounds__(256) k_bl_stencil(StencilArgs S, BlochPhase ph, const zd* __restrict__ x,
-                                                    zd* __restrict__ y, const double* __restrict__ V,
-                                                    const double* __restrict__ E_rhs, const int* __restrict__ sgn,
-                                                    const int* __restrict__ active) {
-  const int slot = blockIdx.x / S.nchunks;
-  const int chunk = blockIdx.x - slot * S.nchunks;
-  const int rhs = bl_rhs(active, slot);
-  const long long vol = (long long)S.nxy * S.nz;
-  const zd* xr = x + rhs * vol;
-  zd* yr = y + rhs * vol;
-  const double diag0 = E_rhs[rhs] + S.e0;
-  const bool neg = sgn[rhs] < 0;
-  zd fx[NF + 1], fy[NF + 1];
-  double wz[NF + 1];
-#pragma unroll
-  for (int n = 1; n <= NF; ++n) {
-    fx[n] = S.wx[n] * (neg ? conj(ph.x[n]) : ph.x[n]);
-    fy[n] = S.wy[n] * (neg ? conj(ph.y[n]) : ph.y[n]);
-    wz[n] = S.wz[n];
-  }
-  const int z0 = chunk * S.zchunk;
-  const int z1 = min(S.nz, z0 + S.zchunk);
-  for (int z = z0; z < z1; ++z) {
-    const long long zo = (long long)z * S.nxy;
-    for (int p = threadIdx.x; p < S.nxy; p += blockDim.x) {
-      const int j = p / S.nx;
-      const int i = p - j * S.nx;
-      const zd c0 = xr[zo + p];
-      zd acc = (diag0 - V[zo + p]) * c0;
-#pragma unroll
-      for (int n = 1; n <= NF; ++n) {
-        int ip = i + n; if (ip >= S.nx) ip -= S.nx;
-        int im = i - n; if (im < 0) im += S.nx;
-        int jp = j + n; if (jp >= S.ny) jp -= S.ny;
-        int jm = j - n; if (jm < 0) jm += S.ny;
-        acc = cfma(fx[n], xr[zo + j * S.nx + ip], acc);
-        acc = cfma(conj(fx[n]), xr[zo + j * S.nx + im], acc);
-        acc = cfma(fy[n], xr[zo + jp * S.nx + i], acc);
-        acc = cfma(conj(fy[n]), xr[zo + jm * S.nx + i], acc);
-        zd sz = mk(0.0, 0.0);
-        if (z + n < S.nz) sz = sz + xr[zo + (long long)n * S.nxy + p];
-        if (z - n >= 0) sz = sz + xr[zo - (long long)n * S.nxy + p];
-        acc = acc + wz[n] * sz;
-      }
-      yr[zo + p] = acc;
-    }
   }
 }
 
@@ -288,25 +235,7 @@ __global__ void __launch_bounds__(256) k_bl_direction(zd* __restrict__ p, const 
 hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const zd* x, zd* y, int nrhs, const double* E_rhs,
                               const int* e_rhs, const int* sgn, const int* active) {
   if (nrhs <= 0) return hipSuccess;
-  const StencilArgs S = stencil_args(c, 8);
-  const int rec = prof_start(c, IOBM_K_BLOCH_STENCIL);
-  switch (c->g.nf) {
-    case 1:
-      hipLaunchKernelGGL(k_bl_stencil<1>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, ph, x, y, c->V_d,
-                         E_rhs, sgn, active);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_bl_stencil<2>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, ph, x, y, c->V_d,
-                         E_rhs, sgn, active);
-      break;
-    default:
-      hipLaunchKernelGGL(k_bl_stencil<3>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, ph, x, y, c->V_d,
-                         E_rhs, sgn, active);
-      break;
-  }
-  // read x, write y (V is shared by every rhs)
-  prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(zd));
-  hipError_t err = hipGetLastError();
+  hipError_t err = launch_bloch_stencil(c, ph, x, y, nrhs, E_rhs, sgn, active);
   if (err != hipSuccess) return err;
   return launch_face_sigma(c, x, y, nrhs, e_rhs, active);
 }

@@ -21,8 +21,9 @@ constexpr int GRAM_PTS = 32;   // points per LDS chunk of the Gram kernel
 constexpr int GRAM_WAVES = 4;  // wavefronts per Gram block
 
 // G = U^T W for one group over the points of one block (a contiguous range),
-// written as partials [group][block][a][b][4]: the four real products
-// (re re, re im, im re, im im) of columns a, b.  Tiles of 8 complex columns
+// written as partials [group][block][a][b][4] packed per group (group g
+// starts at poff[g] * nblk * 4 doubles, its s x s entries per block): the
+// four real products (re re, re im, im re, im im) of columns a, b.  Tiles of 8 complex columns
 // are 16 real rows: row 2a + c holds component c of column a.  MFMA
 // 16x16x4 f64 operands (wave64): lane l holds A[row l % 16][k l / 16] and
 // B[k l / 16][col l % 16]; accumulator entry v of lane l is D[row (l >> 4) +
@@ -31,7 +32,8 @@ template <typename T>
 __global__ void __launch_bounds__(64 * GRAM_WAVES) k_gram(const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ W,
                                                           long long vol, const int* __restrict__ cols,
                                                           const int* __restrict__ goff, const int* __restrict__ gsize,
-                                                          int nblk, double* __restrict__ part) {
+                                                          const int* __restrict__ poff, int nblk,
+                                                          double* __restrict__ part) {
   __shared__ double su[64][GRAM_PTS][2];
   __shared__ double sw[64][GRAM_PTS][2];
   const int g = blockIdx.x / nblk;
@@ -47,9 +49,10 @@ __global__ void __launch_bounds__(64 * GRAM_WAVES) k_gram(const cplx<T>* __restr
   acc4 acc[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) acc[t] = acc4{0, 0, 0, 0};
+  const int nrow = nt * 8;  // rows the tiles read (columns s..nrow-1 are zero)
   for (long long xc = x0; xc < x1; xc += GRAM_PTS) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * GRAM_PTS; e += blockDim.x) {
+    for (int e = threadIdx.x; e < nrow * GRAM_PTS; e += blockDim.x) {
       const int c = e / GRAM_PTS, p = e - c * GRAM_PTS;
       const long long x = xc + p;
       cplx<T> u = mk<T>(0, 0), w = mk<T>(0, 0);
@@ -79,7 +82,7 @@ __global__ void __launch_bounds__(64 * GRAM_WAVES) k_gram(const cplx<T>* __restr
       }
     }
   }
-  double* out = part + ((long long)g * nblk + blk) * 64 * 64 * 4;
+  double* out = part + ((long long)poff[g] * nblk + (long long)blk * s * s) * 4;
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
     const int pr = wave + GRAM_WAVES * t;
@@ -93,7 +96,7 @@ __global__ void __launch_bounds__(64 * GRAM_WAVES) k_gram(const cplx<T>* __restr
       const int row = (lane >> 4) + 4 * v;
       const int a = ta * 8 + (row >> 1), ca = row & 1;
       const int b = tb * 8 + (col >> 1), cb = col & 1;
-      if (a < s && b < s) out[((long long)a * 64 + b) * 4 + ca * 2 + cb] = acc[t][v];
+      if (a < s && b < s) out[((long long)a * s + b) * 4 + ca * 2 + cb] = acc[t][v];
     }
   }
 }
@@ -102,7 +105,8 @@ __global__ void __launch_bounds__(64 * GRAM_WAVES) k_gram(const cplx<T>* __restr
 // leading dimension 64): G = (re re - im im, re im + im re), formed from the
 // pair with a <= b (the Grams U^T W of this solver are complex symmetric).
 __global__ void __launch_bounds__(256) k_gram_reduce(const int* __restrict__ gsize, const int* __restrict__ gid,
-                                                     int nblk, const double* __restrict__ part, zd* __restrict__ G) {
+                                                     const int* __restrict__ poff, int nblk,
+                                                     const double* __restrict__ part, zd* __restrict__ G) {
   const int g = blockIdx.x;
   const int s = gsize[g];
   for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
@@ -110,7 +114,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const int* __restrict__ gsi
     const int aa = min(a, b), bb = max(a, b);  // tile of aa is on or above the tile of bb
     double d[4] = {0, 0, 0, 0};
     for (int k = 0; k < nblk; ++k) {
-      const double* p = part + (((long long)g * nblk + k) * 64 * 64 + (long long)aa * 64 + bb) * 4;
+      const double* p = part + ((long long)poff[g] * nblk + (long long)k * s * s + (long long)aa * s + bb) * 4;
       d[0] += p[0]; d[1] += p[1]; d[2] += p[2]; d[3] += p[3];
     }
     // u_aa^T w_bb = (re re - im im, re im + im re); entries below the diagonal
@@ -224,9 +228,9 @@ __global__ void __launch_bounds__(256) k_block_update(cplx<TY>* __restrict__ Y, 
   const int p = threadIdx.x & 63, jw = threadIdx.x >> 6;
   for (long long x0 = (long long)ch * 64; x0 < vol; x0 += (long long)nchunk * 64) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+    for (int e = threadIdx.x; e < s * 64; e += blockDim.x) {
       const int c = e >> 6, q = e & 63;
-      sx[c][q] = (c < s && x0 + q < vol) ? X[(long long)cg[c] * vol + x0 + q] : mk<T>(0, 0);
+      sx[c][q] = x0 + q < vol ? X[(long long)cg[c] * vol + x0 + q] : mk<T>(0, 0);
     }
     __syncthreads();
     const long long x = x0 + p;
@@ -273,17 +277,19 @@ __global__ void __launch_bounds__(256) k_block_update(cplx<TY>* __restrict__ Y, 
 
 }  // namespace
 
-// Gram matrices of the listed groups: G[g] = U^T W (FP64, leading dimension 64).
-// (ncols = the listed columns in all groups, for the timing hook's byte count:
-// read U and W once)
+// Gram matrices of the listed groups: G[gid[g]] = U^T W (FP64, leading
+// dimension 64).  poff[g] = sum of s^2 over the groups listed before g (the
+// packed partials take nblk * 4 * sum s^2 doubles).  (ncols = the listed
+// columns in all groups, for the timing hook's byte count: read U and W once)
 template <typename T>
 hipError_t launch_gram(iobm_ctx c, const cplx<T>* U, const cplx<T>* W, int ngroups, const int* cols,
-                       const int* goff, const int* gsize, const int* gid, double* part, int nblk, zd* G, int ncols) {
+                       const int* goff, const int* gsize, const int* gid, const int* poff, double* part, int nblk,
+                       zd* G, int ncols) {
   if (ngroups <= 0) return hipSuccess;
   const int rec = prof_start(c, IOBM_K_BLOCK_GRAM);
   hipLaunchKernelGGL(k_gram<T>, dim3(ngroups * nblk), dim3(64 * GRAM_WAVES), 0, c->stream, U, W, c->g.npts, cols,
-                     goff, gsize, nblk, part);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(ngroups), dim3(256), 0, c->stream, gsize, gid, nblk, part, G);
+                     goff, gsize, poff, nblk, part);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ngroups), dim3(256), 0, c->stream, gsize, gid, poff, nblk, part, G);
   prof_stop(c, rec, 2.0 * ncols * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
@@ -312,9 +318,9 @@ hipError_t launch_block_update(iobm_ctx c, cplx<TY>* Y, const cplx<T>* X, const 
 }
 
 template hipError_t launch_gram<float>(iobm_ctx, const zf*, const zf*, int, const int*, const int*, const int*,
-                                       const int*, double*, int, zd*, int);
+                                       const int*, const int*, double*, int, zd*, int);
 template hipError_t launch_gram<double>(iobm_ctx, const zd*, const zd*, int, const int*, const int*, const int*,
-                                        const int*, double*, int, zd*, int);
+                                        const int*, const int*, double*, int, zd*, int);
 template hipError_t launch_block_update<float, float>(iobm_ctx, zf*, const zf*, const zf*, const zd*, int,
                                                       const int*, const int*, const int*, const int*, int, int,
                                                       Partial*, int);

@@ -91,6 +91,7 @@ template <typename T>
 struct OpPlain {  // y = A_st x
   typedef cplx<T> Raw;
   static constexpr int lookahead = 2;
+  static constexpr bool bloch = false;  // lateral couplings without bond phases
   const cplx<T>* x;
   cplx<T>* y;
   __device__ __forceinline__ void bind(int rhs, long long vol) { x += rhs * vol; y += rhs * vol; }
@@ -102,6 +103,42 @@ struct OpPlain {  // y = A_st x
   __device__ __forceinline__ void center_at(long long, cplx<T>) {}
   __device__ __forceinline__ void store(int, long long o, cplx<T>, cplx<T> acc) { y[o] = acc; }
   __device__ __forceinline__ void finish(int, int, int) {}
+};
+
+// y = A_st x in the gauge u = exp(-i kappa.r) psi of a lateral Bloch vector
+// (complex128): the lateral neighbour at +n along a direction enters with
+// the weight times exp(i n kappa h), the one at -n with its conjugate;
+// f[dir][n] holds weight x phase for the rhs at +kappa, and the rhs at
+// -kappa (sgn < 0) take the conjugates.
+struct OpBloch {
+  typedef zd Raw;
+  static constexpr int lookahead = 2;
+  static constexpr bool bloch = true;
+  const zd* x;
+  zd* y;
+  const int* sgn;
+  zd f[2][4];
+  __device__ __forceinline__ void bind(int rhs, long long vol) {
+    x += rhs * vol;
+    y += rhs * vol;
+    if (sgn[rhs] < 0)
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int n = 1; n < 4; ++n) f[d][n] = conj(f[d][n]);
+  }
+  __device__ __forceinline__ zd load(long long o) const { return x[o]; }
+  __device__ __forceinline__ Raw load_raw(long long o, bool) const { return x[o]; }
+  __device__ __forceinline__ zd combine(Raw r, bool ok) const { return ok ? r : mk(0.0, 0.0); }
+  __device__ __forceinline__ void side(const Raw&, long long, bool) {}
+  __device__ __forceinline__ void center(long long, zd) {}
+  __device__ __forceinline__ void center_at(long long, zd) {}
+  __device__ __forceinline__ void store(int, long long o, zd, zd acc) { y[o] = acc; }
+  __device__ __forceinline__ void finish(int, int, int) {}
+  // coupling to the neighbours at +n and -n along direction dir (0 x, 1 y)
+  __device__ __forceinline__ zd lat(int dir, int n, zd ap, zd am) const {
+    return cfma(conj(f[dir][n]), am, f[dir][n] * ap);
+  }
 };
 
 // The number of z chunks of a launch depends on the batch size, so the
@@ -127,6 +164,7 @@ struct OpFuseP {
     cplx<T> z, p, d;
   };
   static constexpr int lookahead = sizeof(T) == 4 ? 2 : 1;
+  static constexpr bool bloch = false;
   const cplx<T>* z;
   const cplx<T>* pold;
   const zd* beta;
@@ -208,6 +246,7 @@ template <typename TR>
 struct OpRefresh {
   typedef zd Raw;
   static constexpr int lookahead = 1;
+  static constexpr bool bloch = false;
   const zd* x;
   const zd* b;
   zd* rface;
@@ -275,9 +314,14 @@ __global__ void __launch_bounds__(256) k_apply(StencilArgs S, Op op, const T* __
         int im = i - n; if (im < 0) im += S.nx;
         int jp = j + n; if (jp >= S.ny) jp -= S.ny;
         int jm = j - n; if (jm < 0) jm += S.ny;
-        cplx<T> sx = op.load(zo + j * S.nx + ip) + op.load(zo + j * S.nx + im);
-        cplx<T> sy = op.load(zo + jp * S.nx + i) + op.load(zo + jm * S.nx + i);
-        acc = acc + wx[n] * sx + wy[n] * sy;
+        if constexpr (Op::bloch) {
+          acc = acc + op.lat(0, n, op.load(zo + j * S.nx + ip), op.load(zo + j * S.nx + im)) +
+                op.lat(1, n, op.load(zo + jp * S.nx + i), op.load(zo + jm * S.nx + i));
+        } else {
+          cplx<T> sx = op.load(zo + j * S.nx + ip) + op.load(zo + j * S.nx + im);
+          cplx<T> sy = op.load(zo + jp * S.nx + i) + op.load(zo + jm * S.nx + i);
+          acc = acc + wx[n] * sx + wy[n] * sy;
+        }
         cplx<T> sz = mk<T>(0, 0);
         if (z + n < S.nz) sz = sz + op.load(zo + (long long)n * S.nxy + p);
         if (z - n >= 0) sz = sz + op.load(zo - (long long)n * S.nxy + p);
@@ -386,8 +430,12 @@ __global__ void __launch_bounds__(A25<MAXP>::max_threads) k_apply25(StencilArgs 
           int im = i - n; if (im < 0) im += S.nx;
           int jp = j + n; if (jp >= S.ny) jp -= S.ny;
           int jm = j - n; if (jm < 0) jm += S.ny;
-          acc = acc + wx[n] * (pl[j * S.nx + ip] + pl[j * S.nx + im]) + wy[n] * (pl[jp * S.nx + i] + pl[jm * S.nx + i]) +
-                wz[n] * (w[NF + n][u] + w[NF - n][u]);
+          if constexpr (Op::bloch)
+            acc = acc + op.lat(0, n, pl[j * S.nx + ip], pl[j * S.nx + im]) +
+                  op.lat(1, n, pl[jp * S.nx + i], pl[jm * S.nx + i]) + wz[n] * (w[NF + n][u] + w[NF - n][u]);
+          else
+            acc = acc + wx[n] * (pl[j * S.nx + ip] + pl[j * S.nx + im]) +
+                  wy[n] * (pl[jp * S.nx + i] + pl[jm * S.nx + i]) + wz[n] * (w[NF + n][u] + w[NF - n][u]);
         }
         op.store(z, (long long)z * nxy + p, w[NF][u], acc);
       }
@@ -1711,8 +1759,8 @@ static int default_ppt(iobm_ctx c) {
 // shape, else the cache-based one.
 template <typename T, class Op>
 static hipError_t launch_stencil(iobm_ctx c, const Op& op, int nrhs, const double* E_rhs, const int* active,
-                                 double bytes_per_point) {
-  const int rec = prof_start(c, sizeof(T) == 4 ? IOBM_K_STENCIL : IOBM_K_STENCIL_C128);
+                                 double bytes_per_point, int cls = 0) {
+  const int rec = prof_start(c, cls ? cls : (sizeof(T) == 4 ? IOBM_K_STENCIL : IOBM_K_STENCIL_C128));
   bool done = false;
   const iobm_launch_shape& sh = c->shape[prec_index<T>()];
   if (sh.stencil != 2) {
@@ -1774,6 +1822,22 @@ static hipError_t launch_boundary(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx
                        (int)PQ_SLOTS, (int)PQ_BOUNDARY);
   prof_stop(c, rec, (double)nrhs * 2 * c->g.nf * c->g.nxy * (2 * sizeof(cplx<T>) + sizeof(cplx<TR>)));
   return hipGetLastError();
+}
+
+hipError_t launch_bloch_stencil(iobm_ctx c, const BlochPhase& ph, const zd* x, zd* y, int nrhs, const double* E_rhs,
+                                const int* sgn, const int* active) {
+  if (nrhs <= 0) return hipSuccess;
+  const StencilArgs S = stencil_args(c, 16);
+  OpBloch op;
+  op.x = x;
+  op.y = y;
+  op.sgn = sgn;
+  for (int n = 0; n < 4; ++n) {
+    op.f[0][n] = S.wx[n] * ph.x[n];
+    op.f[1][n] = S.wy[n] * ph.y[n];
+  }
+  // read x, write y
+  return launch_stencil<double, OpBloch>(c, op, nrhs, E_rhs, active, 2.0 * sizeof(zd), IOBM_K_BLOCH_STENCIL);
 }
 
 hipError_t launch_face_sigma(iobm_ctx c, const zd* x, zd* y, int nrhs, const int* e_rhs, const int* active) {

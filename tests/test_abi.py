@@ -27,7 +27,8 @@ def test_header_declares_the_boundary():
     for n in ["iobm_create", "iobm_set_potential", "iobm_set_nonlocal", "iobm_channels",
               "iobm_self_energy", "iobm_apply", "iobm_precondition", "iobm_rhs", "iobm_solve",
               "iobm_grad_transmission", "iobm_destroy", "iobm_status_str", "iobm_last_error",
-              "iobm_default_opts", "iobm_get_launch_shape", "iobm_set_launch_shape"]:
+              "iobm_default_opts", "iobm_get_launch_shape", "iobm_set_launch_shape", "iobm_smatrix",
+              "iobm_channels_bloch", "iobm_smatrix_bloch"]:
         assert n in names
 
 

@@ -1,0 +1,158 @@
+"""Scattering at a lateral Bloch vector kappa != 0 (Eqs. (2), (12)-(16) taken
+at G + kappa) on the GPU, through the C ABI: the scattering matrices at kappa
+and -kappa against the oracle's element by element, with every
+preconditioner and on square (register FFT) and rectangular (LDS FFT) cross
+sections; unitarity and reciprocity at a larger size; kappa = 0 against the
+complex-symmetric path; rejections."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import Grid, make
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _solver(w):
+    from paper_1009_5300_amd import iobm
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
+    s.set_potential(w.V)
+    if w.nonlocal_ is not None:
+        s.set_nonlocal(w.nonlocal_)
+    return s
+
+
+def _kappa(g, fx, fy):
+    """kappa as fractions of the zone edge pi / L_mu."""
+    return (fx * np.pi / (g.nx * g.hx), fy * np.pi / (g.ny * g.hy))
+
+
+def _neg(g, m):
+    return ((g.ny - m // g.nx) % g.ny) * g.nx + (g.nx - m % g.nx) % g.nx
+
+
+CASES = [(5, Grid(16, 12, 40, 0.4, 2), [1.2], (0.7, -0.3)),
+         (2, Grid(12, 12, 30, 0.4, 2, hz_=0.55), [2.0], (0.45, 0.8)),
+         (5, Grid(12, 12, 24, 0.4, 1), [1.5], (1.0, 0.0))]
+IDS = ["wells_rect_nf2", "barrier_square_aniso", "wells_nf1_zone_edge"]
+_REF = {}
+
+
+def _oracle_smatrix(k, w, E, kap):
+    key = (k, float(E), float(kap[0]), float(kap[1]))
+    if key not in _REF:
+        _REF[key] = O.Problem(w.grid, w.V, w.nonlocal_, kappa=kap).smatrix(E)
+    return _REF[key]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=IDS)
+@pytest.mark.parametrize("precond", [0, 1, 2, 3], ids=["none", "eq17", "lateral_fft", "jacobi"])
+def test_bloch_smatrix_against_oracle(torch, case, precond):
+    from paper_1009_5300_amd import iobm
+    cfg, grid, Es, f = CASES[case]
+    w = make(cfg, grid)
+    g = w.grid
+    kap = _kappa(g, *f)
+    s = _solver(w)
+    Sp, Sm, stats, status = s.smatrix_bloch(Es, kap, opts=iobm.default_opts(precision=iobm.C128, precond=precond,
+                                                                              max_iter=200000))
+    assert status == 0
+    assert all(st[2] == 0 and st[3] <= 1e-10 for st in stats)
+    for sign, Ss in ((1, Sp), (-1, Sm)):
+        k = (sign * kap[0], sign * kap[1])
+        for E, S in zip(Es, Ss):
+            modes, S_ref = _oracle_smatrix(case, w, E, k)
+            ids, _, _ = s.channels_bloch(E, k)
+            assert list(ids) == list(modes) and len(modes) >= 3
+            assert S.shape == S_ref.shape
+            assert np.abs(S - S_ref).max() <= 1e-7, (sign, np.abs(S - S_ref).max())
+
+
+def test_bloch_unitarity_and_reciprocity(torch):
+    """The wide-wire recipe on a 24 x 24 x 48 grid at a general kappa, two
+    energies, with the default (lateral-Fourier) preconditioner: S(kappa) and
+    S(-kappa) unitary, and time reversal S(kappa)[b nu][a mu] =
+    S(-kappa)[a -mu][b -nu]."""
+    from paper_1009_5300_amd import iobm
+    w = make(4, Grid(24, 24, 48, 0.4, 2))
+    g = w.grid
+    kap = _kappa(g, 0.37, 0.61)
+    Es = [0.45, 0.9]
+    s = _solver(w)
+    Sp, Sm, stats, status = s.smatrix_bloch(Es, kap, opts=iobm.default_opts(precision=iobm.C128))
+    assert status == 0
+    assert all(abs(st[4]) <= 1e-8 for st in stats)
+    for E, A, B in zip(Es, Sp, Sm):
+        n = A.shape[0] // 2
+        assert n >= 5
+        for S in (A, B):
+            assert np.abs(S.conj().T @ S - np.eye(2 * n)).max() <= 1e-8
+        ids_p = list(s.channels_bloch(E, kap)[0])
+        ids_m = list(s.channels_bloch(E, (-kap[0], -kap[1]))[0])
+        neg = [ids_m.index(_neg(g, m)) for m in ids_p]
+        perm = neg + [n + i for i in neg]
+        assert np.abs(A - B[np.ix_(perm, perm)].T).max() <= 1e-8
+    # a kappa that differs from the first: transmissions change
+    Sq, _, _, _ = s.smatrix_bloch(Es[:1], _kappa(g, 0.1, 0.0), opts=iobm.default_opts(precision=iobm.C128))
+    n = Sq[0].shape[0] // 2
+    assert Sq[0].shape != Sp[0].shape or np.abs(Sq[0] - Sp[0]).max() > 1e-3
+
+
+def test_bloch_at_zero_kappa_matches_complex_symmetric_path(torch):
+    """kappa = 0 through the paired solve equals iobm_smatrix (complex
+    symmetric COCG in the real lateral basis), at both signs."""
+    from paper_1009_5300_amd import iobm
+    w = make(5, Grid(16, 12, 40, 0.4, 2))
+    s = _solver(w)
+    Es = [1.2, 1.6]
+    S0, _, st0 = s.smatrix(Es, opts=iobm.default_opts(precision=iobm.C128))
+    assert st0 == 0
+    Sp, Sm, _, status = s.smatrix_bloch(Es, (0.0, 0.0), opts=iobm.default_opts(precision=iobm.C128))
+    assert status == 0
+    for a, b, c in zip(S0, Sp, Sm):
+        assert np.abs(a - b).max() <= 1e-8 and np.abs(a - c).max() <= 1e-8
+
+
+def test_bloch_channels_follow_the_shifted_dispersion(torch):
+    """Open channels at kappa are those of the oracle's lead at G + kappa,
+    with the same propagating wave numbers."""
+    w = make(5, Grid(16, 12, 40, 0.4, 2))
+    g = w.grid
+    s = _solver(w)
+    for f in ((0.3, 0.0), (0.7, -0.3), (1.0, 1.0)):
+        kap = _kappa(g, *f)
+        for E in (0.5, 1.2):
+            ids, kz, v = s.channels_bloch(E, kap)
+            ref = O.open_channels(g, E, kap)
+            assert list(ids) == list(ref)
+            for m, k in zip(ids, kz):
+                lm = O.LeadMode(g, E, int(m), kappa=kap)
+                assert abs(k - np.angle(lm.x_in) / g.hz) <= 1e-9
+
+
+def test_bloch_rejections(torch):
+    from paper_1009_5300_amd import iobm
+    w = make(5, Grid(16, 12, 40, 0.4, 2))
+    s = _solver(w)
+    with pytest.raises(iobm.IobmError) as e:
+        s.smatrix_bloch([1.2], (0.1, 0.0), opts=iobm.default_opts(precision=iobm.C64_REFINED))
+    assert e.value.status == 8
+    with pytest.raises(iobm.IobmError) as e:
+        s.smatrix_bloch([1.2], (0.1, 0.0), opts=iobm.default_opts(precision=iobm.C128, block=1))
+    assert e.value.status == 8
+    with pytest.raises(iobm.IobmError) as e:
+        s.smatrix_bloch([1.2], (float("nan"), 0.0), opts=iobm.default_opts(precision=iobm.C128))
+    assert e.value.status == 1
+    wk = make(3, Grid(12, 12, 40, 0.35, 3))  # carries a nonlocal term
+    sk = _solver(wk)
+    with pytest.raises(iobm.IobmError) as e:
+        sk.smatrix_bloch([1.3], (0.1, 0.0), opts=iobm.default_opts(precision=iobm.C128))
+    assert e.value.status == 8
