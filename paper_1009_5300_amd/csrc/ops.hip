@@ -897,8 +897,51 @@ __global__ void __launch_bounds__(256) k_fft_planes(FFTPlan2D plan, int nz, cons
 // transform of the preconditioner comes with the update.
 enum { FFT_PLAIN = 0, FFT_DOT = 1, FFT_UPDATE = 2 };
 
+// Threads per row of the register FFT: complex128 rows of 24 points and more
+// take two threads, each holding half a row (a whole 48-point complex128 row
+// and the transform's scratch exceed the register file and went to scratch
+// memory); each transforms half the samples (even or odd) and the pair
+// combines by one radix-2 step, exchanging values between adjacent lanes.
+template <typename T, int N>
+constexpr int fft_split() { return (sizeof(T) == 8 && N >= 24) ? 2 : 1; }
+
+// One row (or column) of the plane in LDS, elements at a[i * stride],
+// i < N, transformed in place by the SPLIT threads that own it (half = the
+// thread's index in the pair); tw = exp(-2 pi i k / N), tw2 = exp(-2 pi i k
+// / (N/2)).  The pair are adjacent lanes of one wavefront.
+template <typename T, int N, int SPLIT>
+__device__ __forceinline__ void lds_line_fft(cplx<T>* a, int stride, int half, const cplx<T>* tw,
+                                             const cplx<T>* tw2, int sign, T scale) {
+  if constexpr (SPLIT == 1) {
+    cplx<T> v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = a[i * stride];
+    reg_fft<T, N>(v, tw, sign);
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i * stride] = scale * v[i];
+  } else {
+    constexpr int M = N / 2;
+    cplx<T> v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = a[(2 * m + half) * stride];  // even (half 0) or odd samples
+    reg_fft<T, M>(v, tw2, sign);
+    // X[k] = E[k] + w^k O[k], X[k + M] = E[k] - w^k O[k]; half 0 holds E and
+    // writes X[k], half 1 holds O and writes X[k + M]
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      cplx<T> o;
+      o.re = __shfl_xor(v[k].re, 1);
+      o.im = __shfl_xor(v[k].im, 1);
+      const cplx<T> e = half ? o : v[k];
+      const cplx<T> t = twid(tw, k, sign) * (half ? v[k] : o);
+      a[(k + half * M) * stride] = scale * (half ? e - t : e + t);
+    }
+  }
+}
+
 template <typename T, int N, int PPB, int MODE>
-__global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes, const cplx<T>* in, cplx<T>* out,
+__global__ void __launch_bounds__((fft_split<T, N>() * N * PPB))
+    k_fft_planes_reg(int nz, int nplanes, const cplx<T>* in, cplx<T>* out,
                                                            const cplx<T>* __restrict__ tw, int sign, T scale,
                                                            const int* __restrict__ active,
                                                            const cplx<T>* __restrict__ mvec,
@@ -908,9 +951,13 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
   constexpr int PE = Pair<T>::n;          // elements per vector access
   constexpr int NN = N * N;
   constexpr int NV = PPB * NN / PE;       // vector accesses per block
-  constexpr int BLK = N * PPB;
+  constexpr int SPLIT = fft_split<T, N>();
+  constexpr int BLK = SPLIT * N * PPB;
   constexpr int EPT = (NV + BLK - 1) / BLK;
   __shared__ cplx<T> sm[PPB][N][N + 1];
+  __shared__ cplx<T> tw2[N / 2 + 1];  // exp(-2 pi i k / (N/2)) for the split transform
+  if (SPLIT > 1)
+    for (int k = threadIdx.x; k < N / 2; k += BLK) tw2[k] = tw[2 * k];
   const long long vol = (long long)NN * nz;
   const int g0 = blockIdx.x * PPB;
   long long poff[PPB];
@@ -953,11 +1000,10 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
       const int v = threadIdx.x + e * BLK;
       const int q = v / (NN / PE), w = v - q * (NN / PE);
       if (v < NV) {
-        const cplx<T>* c = reinterpret_cast<const cplx<T>*>(&mb[e]);
 #pragma unroll
         for (int k = 0; k < PE; ++k) {
           const int el = w * PE + k;
-          sm[q][el / N][el % N] = c[k];
+          sm[q][el / N][el % N] = Pair<T>::get(mb[e], k);
         }
       }
     }
@@ -973,17 +1019,17 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
       const int v = threadIdx.x + e * BLK;
       const int q = v / (NN / PE), w = v - q * (NN / PE);
       if (v < NV && pok[q]) {
-        const cplx<T>* c = reinterpret_cast<const cplx<T>*>(&buf[e]);
 #pragma unroll
         for (int k = 0; k < PE; ++k) {
           const int el = w * PE + k;
           const int ky = el / N, kx = el % N;
           const cplx<T> rm = sm[q][(N - ky) % N][(N - kx) % N];
+          const cplx<T> ck = Pair<T>::get(buf[e], k);
 #pragma unroll
           for (int qq = 0; qq < PPB; ++qq)
             if (qq == q) {
-              ds_re[qq] += (double)c[k].re * rm.re - (double)c[k].im * rm.im;
-              ds_im[qq] += (double)c[k].re * rm.im + (double)c[k].im * rm.re;
+              ds_re[qq] += (double)ck.re * rm.re - (double)ck.im * rm.im;
+              ds_im[qq] += (double)ck.re * rm.im + (double)ck.im * rm.re;
             }
         }
       }
@@ -1009,28 +1055,19 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
     const int v = threadIdx.x + e * BLK;
     const int q = v / (NN / PE), w = v - q * (NN / PE);
     if (v < NV) {
-      const cplx<T>* c = reinterpret_cast<const cplx<T>*>(&buf[e]);
 #pragma unroll
       for (int k = 0; k < PE; ++k) {
         const int el = w * PE + k;
-        sm[q][el / N][el % N] = c[k];
+        sm[q][el / N][el % N] = Pair<T>::get(buf[e], k);
       }
     }
   }
   __syncthreads();
-  const int pl = threadIdx.x / N, li = threadIdx.x - pl * N;
-  cplx<T> v[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = sm[pl][li][i];  // row li
-  reg_fft<T, N>(v, tw, sign);
-#pragma unroll
-  for (int i = 0; i < N; ++i) sm[pl][li][i] = v[i];
+  const int pl = threadIdx.x / (SPLIT * N);
+  const int li = (threadIdx.x - pl * SPLIT * N) / SPLIT, half = threadIdx.x % SPLIT;
+  lds_line_fft<T, N, SPLIT>(&sm[pl][li][0], 1, half, tw, tw2, sign, (T)1);        // row li
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = sm[pl][i][li];  // column li
-  reg_fft<T, N>(v, tw, sign);
-#pragma unroll
-  for (int i = 0; i < N; ++i) sm[pl][i][li] = scale * v[i];
+  lds_line_fft<T, N, SPLIT>(&sm[pl][0][li], N + 1, half, tw, tw2, sign, scale);  // column li
   __syncthreads();
   if constexpr (MODE == FFT_UPDATE) {
     // R -= alpha FFT(q), the old R loaded in two batches
@@ -1049,15 +1086,15 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
         const int vv = threadIdx.x + (b0 + e) * BLK;
         const int q = vv / (NN / PE), w = vv - q * (NN / PE);
         if (b0 + e < EPT && vv < NV && pok[q]) {
-          cplx<T>* c = reinterpret_cast<cplx<T>*>(&ro[e]);
 #pragma unroll
           for (int k = 0; k < PE; ++k) {
             const int el = w * PE + k;
 #pragma unroll
             for (int qq = 0; qq < PPB; ++qq)
               if (qq == q) {
-                c[k] = c[k] - al[qq] * sm[q][el / N][el % N];
-                ds_re[qq] += (double)c[k].re * c[k].re + (double)c[k].im * c[k].im;
+                const cplx<T> ck = Pair<T>::get(ro[e], k) - al[qq] * sm[q][el / N][el % N];
+                Pair<T>::set(ro[e], k, ck);
+                ds_re[qq] += (double)ck.re * ck.re + (double)ck.im * ck.im;
               }
           }
           reinterpret_cast<VT*>(out + poff[q])[w] = ro[e];
@@ -1071,11 +1108,10 @@ __global__ void __launch_bounds__(N * PPB) k_fft_planes_reg(int nz, int nplanes,
       const int q = vv / (NN / PE), w = vv - q * (NN / PE);
       if (vv < NV && pok[q]) {
         VT o;
-        cplx<T>* c = reinterpret_cast<cplx<T>*>(&o);
 #pragma unroll
         for (int k = 0; k < PE; ++k) {
           const int el = w * PE + k;
-          c[k] = sm[q][el / N][el % N];
+          Pair<T>::set(o, k, sm[q][el / N][el % N]);
         }
         reinterpret_cast<VT*>(out + poff[q])[w] = o;
       }
@@ -1933,7 +1969,7 @@ template <typename T, int N, int PPB>
 static void launch_fft_reg(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                            const int* active, const cplx<T>* mvec, Partial* dpart, const FftUpd<T>* upd) {
   const int nplanes = nrhs * c->g.nz;
-  const dim3 grid((nplanes + PPB - 1) / PPB), blk(N * PPB);
+  const dim3 grid((nplanes + PPB - 1) / PPB), blk(fft_split<T, N>() * N * PPB);
   const FftUpd<T> U = upd ? *upd : FftUpd<T>();
   if (upd)
     hipLaunchKernelGGL((k_fft_planes_reg<T, N, PPB, FFT_UPDATE>), grid, blk, 0, c->stream, c->g.nz, nplanes, in, out,

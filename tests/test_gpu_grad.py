@@ -80,6 +80,14 @@ def test_autograd_function(torch):
     T2, g2 = s2.grad_transmission([0.35])
     assert abs(T.item() - T2) < 1e-9
     assert torch.allclose(V.grad, 2.0 * g2, rtol=0, atol=1e-8 * float(g2.abs().max()))
+    # a fresh context with the first one's launch shapes pinned runs the same
+    # kernels in the same order: bit-identical T and gradient
+    s3 = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
+    s3.set_potential(w.V)
+    for prec in (iobm.C128, iobm.C64_REFINED):
+        s3.set_launch_shape(prec, s.get_launch_shape(prec))
+    T3, g3 = s3.grad_transmission([0.35])
+    assert T3 == T1 and torch.equal(g3, g1)
 
 
 def _wire_voxels(w, n, seed, radius=3.0):

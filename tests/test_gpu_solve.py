@@ -442,6 +442,32 @@ def test_block_cocg_every_preconditioner(torch, precond):
                 k += 1
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pinned_shapes_are_bit_identical_across_contexts(torch, precision):
+    """The same input solved in two contexts: the second pins the launch
+    shapes the first one's autotuner chose, so both run the same kernels in
+    the same order and every FP64 partial sum is taken in the same order.
+    T, R, psi and the iteration counts agree bit for bit; the same context
+    solving twice agrees too.  Wide-wire recipe on a 48 x 48 x 24 grid
+    (the benchmark's kernels), two energies."""
+    from paper_1009_5300_amd import iobm
+    w = make(4, Grid(48, 48, 24, 0.4, 2))
+    Es = [float(w.energies[0]), float(w.energies[-1])]
+    o = iobm.default_opts(precision=precision)
+    s1 = _solver(w)
+    a = s1.solve(Es, opts=o, want_psi=True)
+    b = s1.solve(Es, opts=o, want_psi=True)
+    s2 = _solver(w)
+    for prec in (iobm.C128, iobm.C64_REFINED):
+        s2.set_launch_shape(prec, s1.get_launch_shape(prec))
+    c = s2.solve(Es, opts=o, want_psi=True)
+    for out in (b, c):
+        assert out["status"] == 0 and a["status"] == 0
+        assert np.array_equal(out["T"], a["T"]) and np.array_equal(out["R"], a["R"])
+        assert torch.equal(out["psi"], a["psi"])
+        assert [st[0] for st in out["stats"]] == [st[0] for st in a["stats"]]
+
+
 def test_block_cocg_needs_complex128(torch):
     from paper_1009_5300_amd import iobm
     w = make(2)
