@@ -155,8 +155,11 @@ typedef struct {
 void iobm_default_opts(iobm_solve_opts* opts);
 
 /* Create a context on the current HIP device.  hip_stream: hipStream_t or NULL.
- * The grid is copied.  Errors: INVALID_ARG (sizes, nf), UNSUPPORTED
- * (nx*ny > 4096, nz > 256, or a lateral size with a prime factor > 31),
+ * The grid is copied.  Sizes: nf in 1..3, nx, ny >= max(2, nf), nz >= 2 nf,
+ * finite h > 0.  Errors: INVALID_ARG (sizes, nf), UNSUPPORTED
+ * (nx*ny > 4096, nz > 256, a lateral size with a prime factor > 31, or
+ * (nf + 1) * nx*ny * 16 bytes beyond the device's LDS per workgroup: on
+ * MI355X (160 KiB) nx*ny <= 4096, 3413 and 2560 for nf = 1, 2, 3),
  * DEVICE, OOM. */
 iobm_status iobm_create(const iobm_grid* grid, void* hip_stream, iobm_ctx* out);
 

@@ -1364,7 +1364,10 @@ const char* iobm_last_error(iobm_ctx ctx) { return ctx ? ctx->err.c_str() : "no 
 iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
   if (!g || !out) return IOBM_E_INVALID_ARG;
   *out = nullptr;
-  if (g->nf < 1 || g->nf > 3 || g->nx < 2 || g->ny < 2 || g->nz < 2 * g->nf || !(g->hx > 0) ||
+  // a lateral period of at least nf points: a neighbour at distance n <= nf
+  // wraps across the cell at most once
+  if (g->nf < 1 || g->nf > 3 || g->nx < std::max(2, g->nf) || g->ny < std::max(2, g->nf) || g->nz < 2 * g->nf ||
+      !(g->hx > 0) ||
       !(g->hy > 0) || !(g->hz > 0) || !isfinite(g->hx) || !isfinite(g->hy) || !isfinite(g->hz))
     return IOBM_E_INVALID_ARG;
   if ((long long)g->nx * g->ny > 4096 || g->nz > 256) return IOBM_E_UNSUPPORTED;
@@ -1389,6 +1392,14 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
   try {
     HIPCHK(hipGetDevice(&ctx->device));
     HIPCHK(hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    // the LDS kernels (readout, electrode term and plane FFT on non-square
+    // planes) hold nf + 1 complex128 planes in one workgroup's LDS (gfx950:
+    // 160 KiB per workgroup)
+    const size_t max_lds = 160 * 1024;
+    if ((size_t)(g->nf + 1) * ctx->g.nxy * sizeof(zd) > max_lds) {
+      ctx->err = "nx*ny too large for the workgroup LDS at this FD order";
+      throw Fail{IOBM_E_UNSUPPORTED};
+    }
     {
       std::lock_guard<std::mutex> lock(static_ws_mu);
       if (ctx->device < 0 || ctx->device >= kMaxDevices) {

@@ -341,8 +341,9 @@ __global__ void __launch_bounds__(256) k_apply(StencilArgs S, Op op, const T* __
 // element is read from memory once per chunk (plus 2 NF halo planes), each
 // result written once.
 
-// Largest block of each points-per-thread variant (any nxy <= 4096 has an
-// admissible variant); the bound sets the compiler's register budget.
+// Largest block of each points-per-thread variant (planes up to 2304 points
+// at any order, up to 4096 at nf = 1; larger planes take the cache-based
+// kernel); the bound sets the compiler's register budget.
 template <int MAXP>
 struct A25 {
   static constexpr int max_threads = MAXP == 3 ? 768 : (MAXP == 4 ? 640 : 1024);
@@ -1934,6 +1935,7 @@ template hipError_t launch_refresh<double>(iobm_ctx, const zd*, const zd*, zd*, 
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z, int nrhs,
                                     const int* active, Partial* dpart) {
+  if (nrhs <= 0) return hipSuccess;
   StencilArgs S = stencil_args(c, 16);
   const int rec = prof_start(c, IOBM_K_PRECOND_LAP);
   hipLaunchKernelGGL(k_precond_lap<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S,
@@ -1945,6 +1947,7 @@ hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, 
 template <typename T>
 hipError_t launch_precond_jacobi(iobm_ctx c, const cplx<T>* r, cplx<T>* z, int nrhs, const int* e_rhs,
                                  const double* E_rhs, const int* active, Partial* dpart) {
+  if (nrhs <= 0) return hipSuccess;
   const int nblk = dot_blocks(c);
   const StencilArgs S = stencil_args(c, 16);
   const int rec = prof_start(c, IOBM_K_PRECOND_JACOBI);
@@ -2020,6 +2023,7 @@ template <typename T>
 hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int sign, double scale, int nrhs,
                              const int* active, const cplx<T>* dvec = nullptr, const cplx<T>* mvec = nullptr,
                              Partial* dpart = nullptr, const FftUpd<T>* upd = nullptr) {
+  if (nrhs <= 0) return hipSuccess;
   if (upd && !fft_reg_available<T>(c)) return hipErrorInvalidValue;
   const int rec = prof_start(c, upd ? IOBM_K_FFT_PLANES_UPD : (dpart ? IOBM_K_FFT_PLANES_DOT : IOBM_K_FFT_PLANES));
   if (!fft_reg_dispatch<T>(c, in, out, sign, scale, nrhs, active, mvec, dpart, upd)) {
@@ -2079,6 +2083,7 @@ template <typename T>
 hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>* scratch, int nrhs,
                               const int* e_rhs, const ModeData* modes, const int* active, Partial* dpart,
                               const FftUpd<T>* upd) {
+  if (nrhs <= 0) return hipSuccess;
   const int L = zfilter_chunk<T>(c);
   if ((c->g.nz + L - 1) / L > 8) return hipErrorInvalidValue;
   const int rec = prof_start(c, IOBM_K_PRECOND_FFT);
@@ -2227,6 +2232,7 @@ static dim3 vol_grid(long long vol, int nrhs) {
 
 hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs,
                       int side, const ModeData* modes, zd* b, bool faces_only) {
+  if (nrhs <= 0) return hipSuccess;
   const bool fo = faces_only && c->g.nz >= 2 * c->g.nf;
   const long long n = fo ? 2LL * c->g.nf * c->g.nxy : c->g.npts;
   hipLaunchKernelGGL(k_rhs, vol_grid(n, nrhs), dim3(256), 0, c->stream, c->g.nx, c->g.ny, c->g.nz, c->g.nf,
@@ -2256,6 +2262,7 @@ __global__ void __launch_bounds__(256) k_face_norm2(const zd* __restrict__ b, lo
 }
 
 hipError_t launch_face_norm2(iobm_ctx c, const zd* b, int nact, const int* active, Partial* part) {
+  if (nact <= 0) return hipSuccess;
   if (c->g.nz < 2 * c->g.nf) return hipErrorInvalidValue;
   const int rec = prof_start(c, IOBM_K_DOT);
   hipLaunchKernelGGL(k_face_norm2, dim3(nact), dim3(256), 0, c->stream, b, c->g.npts, c->g.nxy, c->g.nz, c->g.nf,
@@ -2281,6 +2288,7 @@ __global__ void __launch_bounds__(256) k_init_r(const zd* __restrict__ b, cplx<T
 
 template <typename T>
 hipError_t launch_init_r(iobm_ctx c, const zd* b, cplx<T>* r, int nact, const int* active) {
+  if (nact <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_init_r<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, b, r, c->g.npts, c->g.nxy,
                      c->g.nz, c->g.nf, active);
   return hipGetLastError();
@@ -2299,6 +2307,7 @@ int dot_blocks(iobm_ctx c) {
 template <typename T>
 hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, const int* active,
                       void* part) {
+  if (nact <= 0) return hipSuccess;
   int nblk = dot_blocks(c);
   const int rec = prof_start(c, IOBM_K_DOT);
   hipLaunchKernelGGL(k_dot<T>, dim3(nact * nblk), dim3(256), 0, c->stream, a, b, c->g.npts, nblk,
@@ -2310,6 +2319,7 @@ hipError_t launch_dot(iobm_ctx c, const cplx<T>* a, const cplx<T>* b, int nact, 
 template <typename T>
 hipError_t launch_update_r(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* alpha, int nact, const int* active,
                            void* part) {
+  if (nact <= 0) return hipSuccess;
   int nblk = dot_blocks(c);
   const int rec = prof_start(c, IOBM_K_UPDATE);
   hipLaunchKernelGGL(k_update_r<T>, dim3(nact * nblk), dim3(256), 0, c->stream, r, q, alpha, c->g.npts, nblk,
@@ -2331,6 +2341,7 @@ hipError_t launch_finish2(iobm_ctx c, zd* rho, zd* alpha, zd* beta, double* rn2,
 
 template <typename T>
 hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const int* active) {
+  if (nact <= 0) return hipSuccess;
   const long long lo = (long long)c->g.nf * c->g.nxy, hi = (long long)(c->g.nz - c->g.nf) * c->g.nxy;
   hipLaunchKernelGGL(k_residual<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, b, y, c->g.npts, lo, hi,
                      active);
@@ -2339,6 +2350,7 @@ hipError_t launch_residual(iobm_ctx c, const zd* b, cplx<T>* y, int nact, const 
 
 template <typename TD, typename TS>
 hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int nact, const int* active) {
+  if (nact <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_convert<TD, TS>), vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, src, dst,
                      c->g.npts, active);
   return hipGetLastError();
@@ -2347,6 +2359,7 @@ hipError_t launch_convert(iobm_ctx c, const cplx<TS>* src, cplx<TD>* dst, int na
 template <typename T>
 hipError_t launch_accumulate(iobm_ctx c, zd* x, const cplx<T>* d, const cplx<T>* p, const zd* alpha,
                              const int* xset, const int* dlive, int nact, const int* active, int nfirst, int ndead) {
+  if (nact <= 0) return hipSuccess;
   const int rec = prof_start(c, IOBM_K_ACCUMULATE);
   hipLaunchKernelGGL(k_accumulate<T>, vol_grid(c->g.npts, nact), dim3(256), 0, c->stream, x, d, p, alpha, xset,
                      dlive, c->g.npts, active);
@@ -2359,6 +2372,7 @@ hipError_t launch_accumulate(iobm_ctx c, zd* x, const cplx<T>* d, const cplx<T>*
 
 hipError_t launch_readout(iobm_ctx c, int nrhs, int side, const zd* x, const ModeData* modes,
                           const int* e_rhs, zd* amp_near, zd* amp_far) {
+  if (nrhs <= 0) return hipSuccess;
   size_t sh = (size_t)(c->g.nf + 1) * c->g.nxy * sizeof(zd);
   hipLaunchKernelGGL(k_readout, dim3(2 * nrhs), dim3(fft_threads(c->g.nxy)), sh, c->stream, c->plan, c->g.nz,
                      c->g.nf, side, x, modes, e_rhs, c->twx_d, c->twy_d, amp_near, amp_far);
@@ -2368,6 +2382,7 @@ hipError_t launch_readout(iobm_ctx c, int nrhs, int side, const zd* x, const Mod
 hipError_t launch_combine(iobm_ctx c, int nreq, const int* req_e, const int* req_mode, const int* req_c,
                           const int* req_s, const int* req_sgn, const ModeData* modes, const zd* amp_near,
                           const zd* amp_far, zd* t_out, zd* r_out, double* T, double* R) {
+  if (nreq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine, dim3(nreq), dim3(256), 0, c->stream, c->g.nxy, req_e, req_mode, req_c, req_s,
                      req_sgn, modes, amp_near, amp_far, t_out, r_out, T, R);
   return hipGetLastError();
@@ -2376,6 +2391,7 @@ hipError_t launch_combine(iobm_ctx c, int nreq, const int* req_e, const int* req
 template <typename TO>
 hipError_t launch_combine_psi(iobm_ctx c, int nreq, const zd* x, cplx<TO>* psi, const int* req_c,
                               const int* req_s, const int* req_sgn) {
+  if (nreq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine_psi<TO>, vol_grid(c->g.npts, nreq), dim3(256), 0, c->stream, x, psi,
                      c->g.npts, req_c, req_s, req_sgn);
   return hipGetLastError();

@@ -53,7 +53,8 @@ def test_status_strings_and_default_opts(lib):
 
 
 @pytest.mark.parametrize("bad", [dict(nf=0), dict(nf=4), dict(nx=1), dict(nz=3), dict(hx=0.0),
-                                 dict(hy=-1.0), dict(hz=float("nan"))])
+                                 dict(hy=-1.0), dict(hz=float("nan")), dict(nf=3, nx=2, nz=24),
+                                 dict(nf=3, ny=2, nz=24)])
 def test_create_rejects_bad_grids_before_touching_the_device(lib, bad):
     from paper_1009_5300_amd import iobm
     kw = dict(nx=8, ny=8, nz=24, hx=0.4, hy=0.4, hz=0.4, nf=2)

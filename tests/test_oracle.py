@@ -656,3 +656,22 @@ def test_truncated_laplacian_bloch_phases():
         fp = np.concatenate([f[1:], [0]])
         ref = ((1 + 2 * c1 * (math.cos(tx) + math.cos(ty))) * f + c1 * (fm + fp))[:, None, None] * lat[None]
         assert np.abs(z - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("nf", [2, 3])
+def test_kinetic_on_the_shortest_lateral_period(nf):
+    """nx = ny = nf: lateral neighbours at distance n <= nf wrap across the
+    cell (onto the point itself at n = nx).  Lateral plane waves stay
+    eigenvectors of the lateral couplings, with the lateral energy of Eq. (13)
+    generalised to order 2 nf."""
+    from oracle.fd import fd_coefficients
+    from oracle.system import kinetic
+    g = Grid(nf, nf, 4 * nf, 0.5, nf)
+    H = kinetic(g).toarray()
+    N = g.nx * g.ny
+    c = fd_coefficients(nf)
+    B = H[N:2 * N, N:2 * N] - np.eye(N) * (-0.5 * c[0] / g.hz ** 2)  # one plane, z diagonal removed
+    jj, ii = np.meshgrid(np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    for m in range(N):
+        lat = np.exp(2j * np.pi * ((m % g.nx) * ii / g.nx + (m // g.nx) * jj / g.ny)).ravel()
+        assert np.allclose(B @ lat, O.lateral_energy(g, m) * lat, atol=1e-12)
