@@ -305,9 +305,12 @@ iobm_status iobm_channels_bloch(iobm_ctx ctx, double E, double kx, double ky, in
  *      S_plus[b nu][a mu] = S_minus[a -mu][b -nu].
  *  st: host [2 sum_e n_e] per pair (left incidence first), or NULL;
  *      flux_error is that of the state at kappa.
- *  opts: precision must be IOBM_C128 and block 0 (UNSUPPORTED otherwise);
- *      precond, alpha, tol, max_iter and check_every apply; inner_tol,
- *      keep_direction and graph are ignored.
+ *  opts: block must be 0 (UNSUPPORTED otherwise); precision, precond,
+ *      alpha, tol, max_iter, check_every and inner_tol apply (IOBM_C64_REFINED:
+ *      complex64 pair recurrences on a correction of the FP64 solution, the
+ *      pair restarted from its FP64 true residual each time both recursive
+ *      residuals have fallen by inner_tol); keep_direction and graph are
+ *      ignored.
  * Errors: UNSUPPORTED with a nonlocal term set (iobm_set_nonlocal);
  * AT_THRESHOLD; NOT_CONVERGED / BREAKDOWN if a pair missed tol (the
  * matrices are still written).  Synchronises the stream. */
@@ -397,7 +400,7 @@ enum { IOBM_K_STENCIL = 1,      /* stencil in the iteration precision; with the
        IOBM_K_BLOCK_GRAM = 16,      /* block COCG: s x s Grams of a group (MFMA f64) + their
                                        fixed-order sum; bytes: read both blocks once */
        IOBM_K_BLOCK_UPDATE = 17,    /* block COCG: Y (+/-)= X C or Y = Z + X C */
-       IOBM_K_BLOCH_STENCIL = 18,   /* stencil with lateral bond phases (kappa != 0), complex128 */
+       IOBM_K_BLOCH_STENCIL = 18,   /* stencil with lateral bond phases (kappa != 0) */
        IOBM_K_BLOCH_VECTOR = 19 };  /* kappa != 0: pair inner products, updates, residuals, directions */
 iobm_status iobm_profile_begin(iobm_ctx ctx, int32_t class_mask);
 iobm_status iobm_profile_end(iobm_ctx ctx, int32_t kernel_class, int32_t* launches, double* total_ms,

@@ -88,21 +88,28 @@ hipError_t launch_block_update(iobm_ctx c, cplx<TY>* Y, const cplx<T>* X, const 
                                int mode, Partial* n2part, int ncols);
 
 // bloch.hip
-struct BlochPhase;
-hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const zd* x, zd* y, int nrhs, const double* E_rhs,
-                              const int* e_rhs, const int* sgn, const int* active);
-hipError_t launch_bloch_laplacian(iobm_ctx c, const BlochPhase& ph, double alpha, const zd* r, zd* z, int nrhs,
-                                  const int* sgn, const int* active);
-hipError_t launch_bloch_dot(iobm_ctx c, const zd* u, const zd* v, int npairs, const int* pairs, Partial* part,
-                            int nblk);
+template <typename T>
+hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
+                              const double* E_rhs, const int* e_rhs, const int* sgn, const int* active);
+template <typename T>
+hipError_t launch_bloch_laplacian(iobm_ctx c, const BlochPhase& ph, double alpha, const cplx<T>* r, cplx<T>* z,
+                                  int nrhs, const int* sgn, const int* active);
+template <typename T>
+hipError_t launch_bloch_dot(iobm_ctx c, const cplx<T>* u, const cplx<T>* v, int npairs, const int* pairs,
+                            Partial* part, int nblk);
 hipError_t launch_bloch_scalars(iobm_ctx c, int mode, int npairs, const int* pairs, const Partial* pd, const Partial* pn,
                                 int nblk, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag);
-hipError_t launch_bloch_update(iobm_ctx c, zd* x, zd* r, const zd* p, const zd* q, const zd* alpha, int nslots,
-                               const int* active, Partial* pn, int nblk);
-hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, zd* r, const zd* y, int nslots, const int* active, Partial* pn,
-                              int nblk);
-hipError_t launch_bloch_direction(iobm_ctx c, zd* p, const zd* z, const zd* beta, int nslots, const int* active,
-                                  int nblk);
+template <typename T>
+hipError_t launch_bloch_update(iobm_ctx c, cplx<T>* d, cplx<T>* r, const cplx<T>* p, const cplx<T>* q,
+                               const zd* alpha, int nslots, const int* active, Partial* pn, int nblk);
+template <typename T>
+hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, cplx<T>* r, const zd* y, int nslots, const int* active,
+                              Partial* pn, int nblk);
+template <typename T>
+hipError_t launch_bloch_fold(iobm_ctx c, zd* x, cplx<T>* d, int nslots, const int* active, int nblk);
+template <typename T>
+hipError_t launch_bloch_direction(iobm_ctx c, cplx<T>* p, const cplx<T>* z, const zd* beta, int nslots,
+                                  const int* active, int nblk);
 
 namespace {
 
@@ -1128,20 +1135,25 @@ struct PairBatch {
 
 enum { BL_ALPHA = 0, BL_BETA = 1, BL_RESTART = 2 };
 
-// Preconditioned biconjugate gradients with the bilinear form, complex128,
-// on pairs (the primary solves A(kappa) x = b, the shadow A(kappa)^T y = c
-// with A(kappa)^T = A(-kappa) and the preconditioner P(kappa)^T = P(-kappa)):
+// Preconditioned biconjugate gradients with the bilinear form on pairs
+// (the primary solves A(kappa) x = b, the shadow A(kappa)^T y = c with
+// A(kappa)^T = A(-kappa) and the preconditioner P(kappa)^T = P(-kappa)):
 //   q = A p, q~ = A^T p~;  alpha = rho / (p~^T q);
-//   x += alpha p, y += alpha p~;  r -= alpha q, r~ -= alpha q~;
+//   d += alpha p, d~ += alpha p~;  r -= alpha q, r~ -= alpha q~;
 //   z = P r, z~ = P^T r~;  rho' = r~^T z;  beta = rho' / rho;
-//   p = z + beta p, p~ = z~ + beta p~.
-// Every inner product is summed in FP64 in a fixed order.  A pair whose
-// recursive residuals both reach tol ||b||, or that broke down (vanishing
-// rho or p~^T q) or diverged, is restarted from its true residual
-// r = b - A x (p = z); it is done when both true residuals are below
-// tol ||b||.  The operators run in the gauge u = exp(-i kappa.r) psi.
+//   p = z + beta p, p~ = z~ + beta p~,
+// in the iteration precision T on the correction d of the FP64 solution x
+// (complex128: d is x itself), every inner product summed in FP64 in a
+// fixed order.  A pair is restarted from its true residual (x += d, d = 0,
+// r = b - A x with the complex128 operator, p = z) when its recursive
+// residuals both reach tol ||b||, or (complex64) have both fallen by
+// opts.inner_tol since its last restart, or when it broke down (vanishing
+// rho or p~^T q) or diverged.  It is done when both true residuals are
+// below tol ||b||.  The operators run in the gauge u = exp(-i kappa.r) psi.
+template <typename T>
 void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& ph, const PairBatch& B, const zd* b,
                       zd* x, SolveOut& out) {
+  constexpr bool lowp = sizeof(T) == sizeof(float);
   const int ns = B.n, np = ns / 2;
   const long long vol = ctx->g.npts;
   out.iters.assign(ns, 0);
@@ -1149,15 +1161,18 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   out.status.assign(ns, IOBM_OK);
   out.rel.assign(ns, 0.0);
   if (np == 0) return;
-  const size_t vb = (size_t)ns * vol * sizeof(zd);
+  const size_t vb = (size_t)ns * vol * sizeof(cplx<T>);
   int* e_d = upload(ctx, S_IDX, B.e, 0);
   double* E_d = upload(ctx, S_IDX, B.E, 16 * 1024);
   int* sg_d = upload(ctx, S_IDX, B.sgn, 32 * 1024);
-  zd* r = (zd*)workspace(ctx, S_R, vb);
-  zd* p = (zd*)workspace(ctx, S_P, vb);
-  zd* q = (zd*)workspace(ctx, S_Q, vb);
-  zd* z = o.precond == IOBM_PC_NONE ? r : (zd*)workspace(ctx, S_Z, vb);
-  zd* pf = o.precond == IOBM_PC_LATERAL_FFT ? (zd*)workspace(ctx, S_PF, vb) : nullptr;
+  cplx<T>* r = (cplx<T>*)workspace(ctx, S_R, vb);
+  cplx<T>* p = (cplx<T>*)workspace(ctx, S_P, vb);
+  cplx<T>* q = (cplx<T>*)workspace(ctx, S_Q, vb);
+  cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)workspace(ctx, S_Z, vb);
+  cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)workspace(ctx, S_PF, vb) : nullptr;
+  // the correction and the FP64 operator image of x (complex128: x and q)
+  cplx<T>* d = lowp ? (cplx<T>*)workspace(ctx, S_D, vb) : (cplx<T>*)x;
+  zd* yx = lowp ? (zd*)workspace(ctx, S_RHI, (size_t)ns * vol * sizeof(zd)) : (zd*)q;
   const int nblk = dot_blocks(ctx);
   Partial* pd = (Partial*)workspace(ctx, S_PART, (size_t)np * nblk * sizeof(Partial));
   Partial* pn = (Partial*)workspace(ctx, S_PARTR, (size_t)ns * nblk * sizeof(Partial));
@@ -1173,8 +1188,10 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   const double* rn2_h = (const double*)rbh;
   const int* flag_h = (const int*)(rbh + (size_t)ns * sizeof(double));
   const double tol2 = o.tol * o.tol;
+  const double delta2 = lowp ? o.inner_tol * o.inner_tol : 0.0;
   const int check = std::max(1, o.check_every);
-  HIPCHK(hipMemsetAsync(x, 0, vb, ctx->stream));
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)ns * vol * sizeof(zd), ctx->stream));
+  if (lowp) HIPCHK(hipMemsetAsync(d, 0, vb, ctx->stream));
 
   // device lists of the pairs in `pairs_h` (pair ids): their slots (2k,
   // 2k+1 in pair order) and their primary slots
@@ -1191,30 +1208,32 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   };
   auto precond = [&](int nsl) {
     if (o.precond == IOBM_PC_TRUNCATED_LAPLACIAN)
-      HIPCHK(launch_bloch_laplacian(ctx, ph, o.alpha, r, z, nsl, sg_d, sl_d));
+      HIPCHK(launch_bloch_laplacian<T>(ctx, ph, o.alpha, r, z, nsl, sg_d, sl_d));
     else if (o.precond == IOBM_PC_LATERAL_FFT)
-      HIPCHK(launch_precond_fft<double>(ctx, r, z, pf, nsl, e_d, ctx->modes_d, sl_d, nullptr));
+      HIPCHK(launch_precond_fft<T>(ctx, r, z, pf, nsl, e_d, ctx->modes_d, sl_d, nullptr));
     else if (o.precond == IOBM_PC_JACOBI)
-      HIPCHK(launch_precond_jacobi<double>(ctx, r, z, nsl, e_d, E_d, sl_d, nullptr));
+      HIPCHK(launch_precond_jacobi<T>(ctx, r, z, nsl, e_d, E_d, sl_d, nullptr));
   };
-  // r = b - A x, z = P r, rho = r~^T z, p = z for the listed pairs
+  // x += d, r = b - A x (complex128 operator), z = P r, rho = r~^T z, p = z
+  // for the listed pairs
   auto restart = [&](int npr) {
-    HIPCHK(launch_bloch_apply(ctx, ph, x, q, 2 * npr, E_d, e_d, sg_d, sl_d));
-    HIPCHK(launch_bloch_resid(ctx, b, r, q, 2 * npr, sl_d, pn, nblk));
+    if (lowp) HIPCHK(launch_bloch_fold<T>(ctx, x, d, 2 * npr, sl_d, nblk));
+    HIPCHK(launch_bloch_apply<double>(ctx, ph, x, yx, 2 * npr, E_d, e_d, sg_d, sl_d));
+    HIPCHK(launch_bloch_resid<T>(ctx, b, r, yx, 2 * npr, sl_d, pn, nblk));
     precond(2 * npr);
-    HIPCHK(launch_bloch_dot(ctx, r, z, npr, pl_d, pd, nblk));
+    HIPCHK(launch_bloch_dot<T>(ctx, r, z, npr, pl_d, pd, nblk));
     HIPCHK(launch_bloch_scalars(ctx, BL_RESTART, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
-    HIPCHK(launch_bloch_direction(ctx, p, z, beta, 2 * npr, sl_d, nblk));
+    HIPCHK(launch_bloch_direction<T>(ctx, p, z, beta, 2 * npr, sl_d, nblk));
   };
   auto iterate = [&](int npr) {
-    HIPCHK(launch_bloch_apply(ctx, ph, p, q, 2 * npr, E_d, e_d, sg_d, sl_d));
-    HIPCHK(launch_bloch_dot(ctx, p, q, npr, pl_d, pd, nblk));
+    HIPCHK(launch_bloch_apply<T>(ctx, ph, p, q, 2 * npr, E_d, e_d, sg_d, sl_d));
+    HIPCHK(launch_bloch_dot<T>(ctx, p, q, npr, pl_d, pd, nblk));
     HIPCHK(launch_bloch_scalars(ctx, BL_ALPHA, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
-    HIPCHK(launch_bloch_update(ctx, x, r, p, q, alpha, 2 * npr, sl_d, pn, nblk));
+    HIPCHK(launch_bloch_update<T>(ctx, d, r, p, q, alpha, 2 * npr, sl_d, pn, nblk));
     precond(2 * npr);
-    HIPCHK(launch_bloch_dot(ctx, r, z, npr, pl_d, pd, nblk));
+    HIPCHK(launch_bloch_dot<T>(ctx, r, z, npr, pl_d, pd, nblk));
     HIPCHK(launch_bloch_scalars(ctx, BL_BETA, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
-    HIPCHK(launch_bloch_direction(ctx, p, z, beta, 2 * npr, sl_d, nblk));
+    HIPCHK(launch_bloch_direction<T>(ctx, p, z, beta, 2 * npr, sl_d, nblk));
   };
   auto read_back = [&]() {
     HIPCHK(hipMemcpyAsync(rbh, rn2, (size_t)ns * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -1228,7 +1247,7 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   set_lists(act);
   restart(np);  // x = 0: r = b
   read_back();
-  std::vector<double> bn2(rn2_h, rn2_h + ns);
+  std::vector<double> bn2(rn2_h, rn2_h + ns), last(bn2);
   std::vector<int> it(np, 0), rs(np, 0);
   auto finish = [&](int k, int status) {
     for (int s2 = 0; s2 < 2; ++s2) {
@@ -1241,6 +1260,15 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   };
   auto pair_conv = [&](int k) {
     return rn2_h[2 * k] <= tol2 * bn2[2 * k] && rn2_h[2 * k + 1] <= tol2 * bn2[2 * k + 1];
+  };
+  // both slots at the target or fallen by the replacement factor since the
+  // last restart (complex64)
+  auto pair_replace = [&](int k) {
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int sl = 2 * k + s2;
+      if (!(rn2_h[sl] <= std::max(tol2 * bn2[sl], delta2 * last[sl]))) return false;
+    }
+    return true;
   };
   {  // right-hand sides that vanish, or a first rho that vanishes
     std::vector<int> keep;
@@ -1265,7 +1293,7 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
       const double a = rn2_h[2 * k], c3 = rn2_h[2 * k + 1];
       const bool bad = flag_h[k] || !std::isfinite(a) || !std::isfinite(c3) || a > 1e20 * bn2[2 * k] ||
                        c3 > 1e20 * bn2[2 * k + 1];
-      if (bad || pair_conv(k)) redo.push_back(k);
+      if (bad || pair_conv(k) || pair_replace(k)) redo.push_back(k);
       else if (it[k] >= o.max_iter) finish(k, IOBM_E_NOT_CONVERGED);
       else keep.push_back(k);
     }
@@ -1275,6 +1303,8 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
       read_back();
       for (int k : redo) {
         ++rs[k];
+        last[2 * k] = rn2_h[2 * k];
+        last[2 * k + 1] = rn2_h[2 * k + 1];
         if (pair_conv(k)) finish(k, IOBM_OK);
         else if (flag_h[k] || rs[k] >= max_restarts) finish(k, IOBM_E_BREAKDOWN);
         else if (it[k] >= o.max_iter) finish(k, IOBM_E_NOT_CONVERGED);
@@ -1286,6 +1316,14 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
       act = keep;
       if (!act.empty()) set_lists(act);
     }
+  }
+  // complex64: fold what the pairs that stopped between restarts (iteration
+  // limit) still hold in d; the others hold d = 0 after their last restart
+  if (lowp) {
+    std::vector<int> all(np);
+    for (int k = 0; k < np; ++k) all[k] = k;
+    set_lists(all);
+    HIPCHK(launch_bloch_fold<T>(ctx, x, d, ns, sl_d, nblk));
   }
 }
 
@@ -1986,8 +2024,7 @@ iobm_status iobm_smatrix_bloch(iobm_ctx ctx, const iobm_solve_opts* opts, double
     validate_opts(ctx, opts);
     if (nE < 0 || (nE > 0 && (!E || !S_plus || !S_minus)) || !isfinite(kx) || !isfinite(ky))
       return fail(ctx, IOBM_E_INVALID_ARG, "bad arguments");
-    if (opts->precision != IOBM_C128 || opts->block != 0)
-      return fail(ctx, IOBM_E_UNSUPPORTED, "the lateral-Bloch-vector solve runs in complex128 without block COCG");
+    if (opts->block != 0) return fail(ctx, IOBM_E_UNSUPPORTED, "the lateral-Bloch-vector solve has no block COCG");
     if (ctx->kb.ncen > 0)
       return fail(ctx, IOBM_E_UNSUPPORTED, "the lateral-Bloch-vector solve does not take a nonlocal term");
     if (!ctx->have_V) return fail(ctx, IOBM_E_BAD_STATE, "iobm_set_potential has not been called");
@@ -2050,7 +2087,8 @@ iobm_status iobm_smatrix_bloch(iobm_ctx ctx, const iobm_solve_opts* opts, double
         HIPCHK(launch_rhs(ctx, B.n, e_d, m_d, k_d, side, ctx->modes_d, b, false));
       }
       SolveOut so;
-      solve_pair_batch(ctx, *opts, ph, B, b, x, so);
+      if (opts->precision == IOBM_C64_REFINED) solve_pair_batch<float>(ctx, *opts, ph, B, b, x, so);
+      else solve_pair_batch<double>(ctx, *opts, ph, B, b, x, so);
       zd* amp = (zd*)workspace(ctx, S_AMP, (size_t)2 * B.n * nxy * sizeof(zd));
       int* e_d = upload(ctx, S_IDX, B.e, 0);
       HIPCHK(launch_readout(ctx, B.n, side, x, ctx->modes_d, e_d, amp, amp + (size_t)B.n * nxy));

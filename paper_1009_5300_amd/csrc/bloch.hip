@@ -1,5 +1,7 @@
 // Kernels of the solve at a lateral Bloch vector kappa != 0 (Eqs. (2),
-// (12)-(13) and (16) at G + kappa), complex128.
+// (12)-(13) and (16) at G + kappa), in complex128 or in complex64 with FP64
+// residual replacement (the pair recurrences run on a correction d of the
+// FP64 solution x; every inner product is summed in FP64).
 //
 // Gauge.  The solve runs on u = exp(-i kappa.r) psi (r the lateral lattice
 // position in the cell).  In this gauge the lateral Fourier transform of
@@ -47,22 +49,24 @@ __device__ __forceinline__ void bl_reduce3(double& a, double& b, double& c) {
 // Eq. (17) in the gauge u: z = r + c1 (sum of the six face neighbours), the
 // lateral ones with the bond phase of distance 1, z neighbours outside the
 // region zero.
-__global__ void __launch_bounds__(256) k_bl_laplacian(StencilArgs S, BlochPhase ph, double c1,
-                                                      const zd* __restrict__ r, zd* __restrict__ z,
+template <typename T>
+__global__ void __launch_bounds__(256) k_bl_laplacian(StencilArgs S, BlochPhase ph, double c1d,
+                                                      const cplx<T>* __restrict__ r, cplx<T>* __restrict__ z,
                                                       const int* __restrict__ sgn, const int* __restrict__ active) {
   const int slot = blockIdx.x / S.nchunks;
   const int chunk = blockIdx.x - slot * S.nchunks;
   const int rhs = bl_rhs(active, slot);
   const long long vol = (long long)S.nxy * S.nz;
-  const zd* rr = r + rhs * vol;
-  zd* zr = z + rhs * vol;
+  const cplx<T>* rr = r + rhs * vol;
+  cplx<T>* zr = z + rhs * vol;
   const bool neg = sgn[rhs] < 0;
-  const zd px = neg ? conj(ph.x[1]) : ph.x[1];
-  const zd py = neg ? conj(ph.y[1]) : ph.y[1];
+  const cplx<T> px = cvt<T>(neg ? conj(ph.x[1]) : ph.x[1]);
+  const cplx<T> py = cvt<T>(neg ? conj(ph.y[1]) : ph.y[1]);
+  const T c1 = (T)c1d;
   const int z0 = chunk * S.zchunk;
   const int z1 = min(S.nz, z0 + S.zchunk);
   for (int k = z0; k < z1; ++k) {
-    const zd* rp = rr + (long long)k * S.nxy;
+    const cplx<T>* rp = rr + (long long)k * S.nxy;
     for (int p = threadIdx.x; p < S.nxy; p += blockDim.x) {
       const int j = p / S.nx;
       const int i = p - j * S.nx;
@@ -70,7 +74,7 @@ __global__ void __launch_bounds__(256) k_bl_laplacian(StencilArgs S, BlochPhase 
       int im = i - 1; if (im < 0) im += S.nx;
       int jp = j + 1; if (jp >= S.ny) jp -= S.ny;
       int jm = j - 1; if (jm < 0) jm += S.ny;
-      zd s = px * rp[j * S.nx + ip];
+      cplx<T> s = px * rp[j * S.nx + ip];
       s = cfma(conj(px), rp[j * S.nx + im], s);
       s = cfma(py, rp[jp * S.nx + i], s);
       s = cfma(conj(py), rp[jm * S.nx + i], s);
@@ -82,21 +86,23 @@ __global__ void __launch_bounds__(256) k_bl_laplacian(StencilArgs S, BlochPhase 
 }
 
 // Per pair, partials of the bilinear form u(shadow)^T v(primary) over one
-// contiguous chunk of the volume: part[pair][blk], pair = primary / 2.
-__global__ void __launch_bounds__(256) k_bl_dot(const zd* __restrict__ u, const zd* __restrict__ v, long long vol,
-                                                int nblk, const int* __restrict__ pairs, Partial* __restrict__ part) {
+// contiguous chunk of the volume (FP64): part[pair][blk], pair = primary / 2.
+template <typename T>
+__global__ void __launch_bounds__(256) k_bl_dot(const cplx<T>* __restrict__ u, const cplx<T>* __restrict__ v,
+                                                long long vol, int nblk, const int* __restrict__ pairs,
+                                                Partial* __restrict__ part) {
   const int k = blockIdx.x / nblk;
   const int blk = blockIdx.x - k * nblk;
   const int prim = pairs[k];
   const long long per = (vol + nblk - 1) / nblk;
   const long long i0 = blk * per, i1 = min(vol, i0 + per);
-  const zd* us = u + (long long)(prim + 1) * vol;
-  const zd* vp = v + (long long)prim * vol;
+  const cplx<T>* us = u + (long long)(prim + 1) * vol;
+  const cplx<T>* vp = v + (long long)prim * vol;
   double re = 0, im = 0, d = 0;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const zd a = us[i], b = vp[i];
-    re += a.re * b.re - a.im * b.im;
-    im += a.re * b.im + a.im * b.re;
+    const cplx<T> a = us[i], b = vp[i];
+    re += (double)a.re * b.re - (double)a.im * b.im;
+    im += (double)a.re * b.im + (double)a.im * b.re;
   }
   bl_reduce3(re, im, d);
   if (threadIdx.x == 0) {
@@ -160,25 +166,26 @@ __global__ void __launch_bounds__(64) k_bl_scalars(int mode, int npairs, const i
   }
 }
 
-// x += alpha p, r -= alpha q (alpha of the slot's pair), with the partials
+// d += alpha p, r -= alpha q (alpha of the slot's pair), with the partials
 // of |r|^2 in pn[slot][blk].
-__global__ void __launch_bounds__(256) k_bl_update(zd* __restrict__ x, zd* __restrict__ r, const zd* __restrict__ p,
-                                                   const zd* __restrict__ q, const zd* __restrict__ alpha,
-                                                   long long vol, int nblk, const int* __restrict__ active,
-                                                   Partial* __restrict__ pn) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_bl_update(cplx<T>* __restrict__ d, cplx<T>* __restrict__ r,
+                                                   const cplx<T>* __restrict__ p, const cplx<T>* __restrict__ q,
+                                                   const zd* __restrict__ alpha, long long vol, int nblk,
+                                                   const int* __restrict__ active, Partial* __restrict__ pn) {
   const int slot = blockIdx.x / nblk;
   const int blk = blockIdx.x - slot * nblk;
   const int rhs = bl_rhs(active, slot);
-  const zd a = alpha[rhs >> 1];
+  const cplx<T> a = cvt<T>(alpha[rhs >> 1]);
   const long long per = (vol + nblk - 1) / nblk;
   const long long i0 = blk * per, i1 = min(vol, i0 + per);
   const long long o = (long long)rhs * vol;
   double n2 = 0, d0 = 0, d1 = 0;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    x[o + i] = cfma(a, p[o + i], x[o + i]);
-    const zd v = r[o + i] - a * q[o + i];
+    d[o + i] = cfma(a, p[o + i], d[o + i]);
+    const cplx<T> v = r[o + i] - a * q[o + i];
     r[o + i] = v;
-    n2 += v.re * v.re + v.im * v.im;
+    n2 += (double)v.re * v.re + (double)v.im * v.im;
   }
   bl_reduce3(n2, d0, d1);
   if (threadIdx.x == 0) {
@@ -188,8 +195,10 @@ __global__ void __launch_bounds__(256) k_bl_update(zd* __restrict__ x, zd* __res
   }
 }
 
-// r = b - y (y = A x), with the partials of |r|^2 in pn[slot][blk].
-__global__ void __launch_bounds__(256) k_bl_resid(const zd* __restrict__ b, zd* __restrict__ r,
+// The true residual r = b - y (y = A x in FP64), stored in the iteration
+// precision, with the FP64 partials of |b - y|^2 in pn[slot][blk].
+template <typename T>
+__global__ void __launch_bounds__(256) k_bl_resid(const zd* __restrict__ b, cplx<T>* __restrict__ r,
                                                   const zd* __restrict__ y, long long vol, int nblk,
                                                   const int* __restrict__ active, Partial* __restrict__ pn) {
   const int slot = blockIdx.x / nblk;
@@ -201,7 +210,7 @@ __global__ void __launch_bounds__(256) k_bl_resid(const zd* __restrict__ b, zd* 
   double n2 = 0, d0 = 0, d1 = 0;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const zd v = b[o + i] - y[o + i];
-    r[o + i] = v;
+    r[o + i] = cvt<T>(v);
     n2 += v.re * v.re + v.im * v.im;
   }
   bl_reduce3(n2, d0, d1);
@@ -212,16 +221,35 @@ __global__ void __launch_bounds__(256) k_bl_resid(const zd* __restrict__ b, zd* 
   }
 }
 
+// x += d, d = 0 (the correction folded into the FP64 solution).
+template <typename T>
+__global__ void __launch_bounds__(256) k_bl_fold(zd* __restrict__ x, cplx<T>* __restrict__ d, long long vol, int nblk,
+                                                 const int* __restrict__ active) {
+  const int slot = blockIdx.x / nblk;
+  const int blk = blockIdx.x - slot * nblk;
+  const int rhs = bl_rhs(active, slot);
+  const long long per = (vol + nblk - 1) / nblk;
+  const long long i0 = blk * per, i1 = min(vol, i0 + per);
+  const long long o = (long long)rhs * vol;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const cplx<T> v = d[o + i];
+    x[o + i] = x[o + i] + mk((double)v.re, (double)v.im);
+    d[o + i] = mk<T>(0, 0);
+  }
+}
+
 // p = z + beta p (beta of the slot's pair); p = z where beta = 0 (p is then
 // not read: it may hold anything after a restart).
-__global__ void __launch_bounds__(256) k_bl_direction(zd* __restrict__ p, const zd* __restrict__ z,
+template <typename T>
+__global__ void __launch_bounds__(256) k_bl_direction(cplx<T>* __restrict__ p, const cplx<T>* __restrict__ z,
                                                       const zd* __restrict__ beta, long long vol, int nblk,
                                                       const int* __restrict__ active) {
   const int slot = blockIdx.x / nblk;
   const int blk = blockIdx.x - slot * nblk;
   const int rhs = bl_rhs(active, slot);
-  const zd bt = beta[rhs >> 1];
-  const bool fresh = bt.re == 0.0 && bt.im == 0.0;
+  const zd btd = beta[rhs >> 1];
+  const bool fresh = btd.re == 0.0 && btd.im == 0.0;
+  const cplx<T> bt = cvt<T>(btd);
   const long long per = (vol + nblk - 1) / nblk;
   const long long i0 = blk * per, i1 = min(vol, i0 + per);
   const long long o = (long long)rhs * vol;
@@ -232,31 +260,34 @@ __global__ void __launch_bounds__(256) k_bl_direction(zd* __restrict__ p, const 
 }  // namespace
 
 // =================================================================== host ===
-hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const zd* x, zd* y, int nrhs, const double* E_rhs,
-                              const int* e_rhs, const int* sgn, const int* active) {
+template <typename T>
+hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
+                              const double* E_rhs, const int* e_rhs, const int* sgn, const int* active) {
   if (nrhs <= 0) return hipSuccess;
-  hipError_t err = launch_bloch_stencil(c, ph, x, y, nrhs, E_rhs, sgn, active);
+  hipError_t err = launch_bloch_stencil<T>(c, ph, x, y, nrhs, E_rhs, sgn, active);
   if (err != hipSuccess) return err;
-  return launch_face_sigma(c, x, y, nrhs, e_rhs, active);
+  return launch_face_sigma<T>(c, x, y, nrhs, e_rhs, active);
 }
 
-hipError_t launch_bloch_laplacian(iobm_ctx c, const BlochPhase& ph, double alpha, const zd* r, zd* z, int nrhs,
-                                  const int* sgn, const int* active) {
+template <typename T>
+hipError_t launch_bloch_laplacian(iobm_ctx c, const BlochPhase& ph, double alpha, const cplx<T>* r, cplx<T>* z,
+                                  int nrhs, const int* sgn, const int* active) {
   if (nrhs <= 0) return hipSuccess;
   const StencilArgs S = stencil_args(c, 16);
   const int rec = prof_start(c, IOBM_K_PRECOND_LAP);
-  hipLaunchKernelGGL(k_bl_laplacian, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, ph, exp(-alpha), r, z,
+  hipLaunchKernelGGL(k_bl_laplacian<T>, dim3(nrhs * S.nchunks), dim3(256), 0, c->stream, S, ph, exp(-alpha), r, z,
                      sgn, active);
-  prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(zd));
+  prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
-hipError_t launch_bloch_dot(iobm_ctx c, const zd* u, const zd* v, int npairs, const int* pairs, Partial* part,
-                            int nblk) {
+template <typename T>
+hipError_t launch_bloch_dot(iobm_ctx c, const cplx<T>* u, const cplx<T>* v, int npairs, const int* pairs,
+                            Partial* part, int nblk) {
   if (npairs <= 0) return hipSuccess;
   const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
-  hipLaunchKernelGGL(k_bl_dot, dim3(npairs * nblk), dim3(256), 0, c->stream, u, v, c->g.npts, nblk, pairs, part);
-  prof_stop(c, rec, 2.0 * npairs * c->g.npts * sizeof(zd));
+  hipLaunchKernelGGL(k_bl_dot<T>, dim3(npairs * nblk), dim3(256), 0, c->stream, u, v, c->g.npts, nblk, pairs, part);
+  prof_stop(c, rec, 2.0 * npairs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -268,32 +299,63 @@ hipError_t launch_bloch_scalars(iobm_ctx c, int mode, int npairs, const int* pai
   return hipGetLastError();
 }
 
-hipError_t launch_bloch_update(iobm_ctx c, zd* x, zd* r, const zd* p, const zd* q, const zd* alpha, int nslots,
-                               const int* active, Partial* pn, int nblk) {
+template <typename T>
+hipError_t launch_bloch_update(iobm_ctx c, cplx<T>* d, cplx<T>* r, const cplx<T>* p, const cplx<T>* q,
+                               const zd* alpha, int nslots, const int* active, Partial* pn, int nblk) {
   if (nslots <= 0) return hipSuccess;
   const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
-  hipLaunchKernelGGL(k_bl_update, dim3(nslots * nblk), dim3(256), 0, c->stream, x, r, p, q, alpha, c->g.npts, nblk,
-                     active, pn);
-  // read x, r, p, q; write x, r
-  prof_stop(c, rec, 6.0 * nslots * c->g.npts * sizeof(zd));
+  hipLaunchKernelGGL(k_bl_update<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, d, r, p, q, alpha, c->g.npts,
+                     nblk, active, pn);
+  // read d, r, p, q; write d, r
+  prof_stop(c, rec, 6.0 * nslots * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
-hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, zd* r, const zd* y, int nslots, const int* active, Partial* pn,
-                              int nblk) {
+template <typename T>
+hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, cplx<T>* r, const zd* y, int nslots, const int* active,
+                              Partial* pn, int nblk) {
   if (nslots <= 0) return hipSuccess;
   const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
-  hipLaunchKernelGGL(k_bl_resid, dim3(nslots * nblk), dim3(256), 0, c->stream, b, r, y, c->g.npts, nblk, active, pn);
-  prof_stop(c, rec, 3.0 * nslots * c->g.npts * sizeof(zd));
+  hipLaunchKernelGGL(k_bl_resid<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, b, r, y, c->g.npts, nblk, active,
+                     pn);
+  prof_stop(c, rec, nslots * c->g.npts * (2.0 * sizeof(zd) + sizeof(cplx<T>)));
   return hipGetLastError();
 }
 
-hipError_t launch_bloch_direction(iobm_ctx c, zd* p, const zd* z, const zd* beta, int nslots, const int* active,
-                                  int nblk) {
+template <typename T>
+hipError_t launch_bloch_fold(iobm_ctx c, zd* x, cplx<T>* d, int nslots, const int* active, int nblk) {
   if (nslots <= 0) return hipSuccess;
   const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
-  hipLaunchKernelGGL(k_bl_direction, dim3(nslots * nblk), dim3(256), 0, c->stream, p, z, beta, c->g.npts, nblk,
+  hipLaunchKernelGGL(k_bl_fold<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, x, d, c->g.npts, nblk, active);
+  prof_stop(c, rec, nslots * c->g.npts * (2.0 * sizeof(zd) + 2.0 * sizeof(cplx<T>)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bloch_direction(iobm_ctx c, cplx<T>* p, const cplx<T>* z, const zd* beta, int nslots,
+                                  const int* active, int nblk) {
+  if (nslots <= 0) return hipSuccess;
+  const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
+  hipLaunchKernelGGL(k_bl_direction<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, p, z, beta, c->g.npts, nblk,
                      active);
-  prof_stop(c, rec, 3.0 * nslots * c->g.npts * sizeof(zd));
+  prof_stop(c, rec, 3.0 * nslots * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
+
+#define IOBM_BLOCH_INST(T)                                                                                      \
+  template hipError_t launch_bloch_apply<T>(iobm_ctx, const BlochPhase&, const cplx<T>*, cplx<T>*, int,          \
+                                            const double*, const int*, const int*, const int*);                \
+  template hipError_t launch_bloch_laplacian<T>(iobm_ctx, const BlochPhase&, double, const cplx<T>*, cplx<T>*,   \
+                                                int, const int*, const int*);                                   \
+  template hipError_t launch_bloch_dot<T>(iobm_ctx, const cplx<T>*, const cplx<T>*, int, const int*, Partial*,   \
+                                          int);                                                                 \
+  template hipError_t launch_bloch_update<T>(iobm_ctx, cplx<T>*, cplx<T>*, const cplx<T>*, const cplx<T>*,       \
+                                             const zd*, int, const int*, Partial*, int);                        \
+  template hipError_t launch_bloch_resid<T>(iobm_ctx, const zd*, cplx<T>*, const zd*, int, const int*, Partial*, \
+                                            int);                                                               \
+  template hipError_t launch_bloch_fold<T>(iobm_ctx, zd*, cplx<T>*, int, const int*, int);                       \
+  template hipError_t launch_bloch_direction<T>(iobm_ctx, cplx<T>*, const cplx<T>*, const zd*, int, const int*, \
+                                                int);
+IOBM_BLOCH_INST(float)
+IOBM_BLOCH_INST(double)
+#undef IOBM_BLOCH_INST

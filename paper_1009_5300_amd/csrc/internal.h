@@ -208,13 +208,15 @@ template <typename T>
 hipError_t launch_precond_jacobi(iobm_ctx c, const cplx<T>* r, cplx<T>* z, int nrhs, const int* e_rhs,
                                  const double* E_rhs, const int* active, Partial* dpart = nullptr);
 hipError_t launch_sigma_diag(iobm_ctx c, int nE);  // sdiag_d from sig_d for the current table
-// y = A_st x with lateral bond phases (the gauge of a lateral Bloch vector,
-// complex128): the 2.5D stencil at the context's complex128 shape, else the
+// y = A_st x with lateral bond phases (the gauge of a lateral Bloch vector):
+// the 2.5D stencil at the context's shape for the precision, else the
 // cache-based one; sgn[rhs] < 0 selects -kappa
-hipError_t launch_bloch_stencil(iobm_ctx c, const BlochPhase& ph, const zd* x, zd* y, int nrhs, const double* E_rhs,
-                                const int* sgn, const int* active);
-// y -= Sigma x on the 2 nf face planes (complex128), for the listed rhs
-hipError_t launch_face_sigma(iobm_ctx c, const zd* x, zd* y, int nrhs, const int* e_rhs, const int* active);
+template <typename T>
+hipError_t launch_bloch_stencil(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
+                                const double* E_rhs, const int* sgn, const int* active);
+// y -= Sigma x on the 2 nf face planes, for the listed rhs
+template <typename T>
+hipError_t launch_face_sigma(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const int* e_rhs, const int* active);
 hipError_t launch_rhs(iobm_ctx c, int nrhs, const int* e_rhs, const int* mode_rhs, const int* kind_rhs, int side,
                       const ModeData* modes, zd* b, bool faces_only);
 hipError_t launch_readout(iobm_ctx c, int nrhs, int side, const zd* x, const ModeData* modes, const int* e_rhs,

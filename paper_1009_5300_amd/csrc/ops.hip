@@ -105,19 +105,20 @@ struct OpPlain {  // y = A_st x
   __device__ __forceinline__ void finish(int, int, int) {}
 };
 
-// y = A_st x in the gauge u = exp(-i kappa.r) psi of a lateral Bloch vector
-// (complex128): the lateral neighbour at +n along a direction enters with
-// the weight times exp(i n kappa h), the one at -n with its conjugate;
-// f[dir][n] holds weight x phase for the rhs at +kappa, and the rhs at
-// -kappa (sgn < 0) take the conjugates.
+// y = A_st x in the gauge u = exp(-i kappa.r) psi of a lateral Bloch vector:
+// the lateral neighbour at +n along a direction enters with the weight
+// times exp(i n kappa h), the one at -n with its conjugate; f[dir][n] holds
+// weight x phase for the rhs at +kappa, and the rhs at -kappa (sgn < 0)
+// take the conjugates.
+template <typename T>
 struct OpBloch {
-  typedef zd Raw;
+  typedef cplx<T> Raw;
   static constexpr int lookahead = 2;
   static constexpr bool bloch = true;
-  const zd* x;
-  zd* y;
+  const cplx<T>* x;
+  cplx<T>* y;
   const int* sgn;
-  zd f[2][4];
+  cplx<T> f[2][4];
   __device__ __forceinline__ void bind(int rhs, long long vol) {
     x += rhs * vol;
     y += rhs * vol;
@@ -127,16 +128,16 @@ struct OpBloch {
 #pragma unroll
         for (int n = 1; n < 4; ++n) f[d][n] = conj(f[d][n]);
   }
-  __device__ __forceinline__ zd load(long long o) const { return x[o]; }
+  __device__ __forceinline__ cplx<T> load(long long o) const { return x[o]; }
   __device__ __forceinline__ Raw load_raw(long long o, bool) const { return x[o]; }
-  __device__ __forceinline__ zd combine(Raw r, bool ok) const { return ok ? r : mk(0.0, 0.0); }
+  __device__ __forceinline__ cplx<T> combine(Raw r, bool ok) const { return ok ? r : mk<T>(0, 0); }
   __device__ __forceinline__ void side(const Raw&, long long, bool) {}
-  __device__ __forceinline__ void center(long long, zd) {}
-  __device__ __forceinline__ void center_at(long long, zd) {}
-  __device__ __forceinline__ void store(int, long long o, zd, zd acc) { y[o] = acc; }
+  __device__ __forceinline__ void center(long long, cplx<T>) {}
+  __device__ __forceinline__ void center_at(long long, cplx<T>) {}
+  __device__ __forceinline__ void store(int, long long o, cplx<T>, cplx<T> acc) { y[o] = acc; }
   __device__ __forceinline__ void finish(int, int, int) {}
   // coupling to the neighbours at +n and -n along direction dir (0 x, 1 y)
-  __device__ __forceinline__ zd lat(int dir, int n, zd ap, zd am) const {
+  __device__ __forceinline__ cplx<T> lat(int dir, int n, cplx<T> ap, cplx<T> am) const {
     return cfma(conj(f[dir][n]), am, f[dir][n] * ap);
   }
 };
@@ -1861,26 +1862,35 @@ static hipError_t launch_boundary(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx
   return hipGetLastError();
 }
 
-hipError_t launch_bloch_stencil(iobm_ctx c, const BlochPhase& ph, const zd* x, zd* y, int nrhs, const double* E_rhs,
-                                const int* sgn, const int* active) {
+template <typename T>
+hipError_t launch_bloch_stencil(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
+                                const double* E_rhs, const int* sgn, const int* active) {
   if (nrhs <= 0) return hipSuccess;
   const StencilArgs S = stencil_args(c, 16);
-  OpBloch op;
+  OpBloch<T> op;
   op.x = x;
   op.y = y;
   op.sgn = sgn;
   for (int n = 0; n < 4; ++n) {
-    op.f[0][n] = S.wx[n] * ph.x[n];
-    op.f[1][n] = S.wy[n] * ph.y[n];
+    op.f[0][n] = cvt<T>(S.wx[n] * ph.x[n]);
+    op.f[1][n] = cvt<T>(S.wy[n] * ph.y[n]);
   }
   // read x, write y
-  return launch_stencil<double, OpBloch>(c, op, nrhs, E_rhs, active, 2.0 * sizeof(zd), IOBM_K_BLOCH_STENCIL);
+  return launch_stencil<T, OpBloch<T>>(c, op, nrhs, E_rhs, active, 2.0 * sizeof(cplx<T>), IOBM_K_BLOCH_STENCIL);
 }
+template hipError_t launch_bloch_stencil<float>(iobm_ctx, const BlochPhase&, const zf*, zf*, int, const double*,
+                                                const int*, const int*);
+template hipError_t launch_bloch_stencil<double>(iobm_ctx, const BlochPhase&, const zd*, zd*, int, const double*,
+                                                 const int*, const int*);
 
-hipError_t launch_face_sigma(iobm_ctx c, const zd* x, zd* y, int nrhs, const int* e_rhs, const int* active) {
+template <typename T>
+hipError_t launch_face_sigma(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const int* e_rhs,
+                             const int* active) {
   if (nrhs <= 0) return hipSuccess;
-  return launch_boundary<double, double>(c, x, y, nullptr, nrhs, e_rhs, c->modes_d, active, nullptr);
+  return launch_boundary<T, T>(c, x, y, nullptr, nrhs, e_rhs, c->modes_d, active, nullptr);
 }
+template hipError_t launch_face_sigma<float>(iobm_ctx, const zf*, zf*, int, const int*, const int*);
+template hipError_t launch_face_sigma<double>(iobm_ctx, const zd*, zd*, int, const int*, const int*);
 
 template <typename T>
 hipError_t launch_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const double* E_rhs,
