@@ -107,9 +107,9 @@ def _cpu_info():
 def cpu_baseline():
     """The oracle on a bounded sample of the workload: the same recipe
     (48 x 48 cross-section, h = 0.4, 4th-order FD, V statistics, first
-    energy, all 45 open channels) on a z-shortened 48 x 48 x 4 grid (the two
-    electrode plane groups, nz = 2 nf, the fewest planes it takes), solved
-    with the oracle's dense path (its sparse LU does not finish on a 48 x 48
+    energy, all 45 open channels) on a z-shortened 48 x 48 x 6 grid (the two
+    electrode plane groups and two interior planes; about 10-30 s of CPU
+    work), solved with the oracle's dense path (its sparse LU does not finish on a 48 x 48
     cross-section: the dense 4608 x 4608 self-energy blocks defeat the
     ordering).  Times the assembly (self-energies by explicit sums), the
     solve of every channel and the current readout.  The full 128-plane grid
@@ -121,7 +121,7 @@ def cpu_baseline():
     import oracle as O
     from workloads import Grid, make
 
-    g = Grid(48, 48, 4, 0.4, 2)
+    g = Grid(48, 48, 6, 0.4, 2)
     w = make(4, g)
     E = float(w.energies[0])
     t0 = time.perf_counter()
@@ -135,7 +135,7 @@ def cpu_baseline():
     assert np.all(np.isfinite(T))
     return {"value": len(modes) / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "host_cpus": ncpu, "cpu_model": model,
-            "sample": f"48x48x4 grid (the workload recipe on a z-shortened copy of its cross-section), "
+            "sample": f"48x48x6 grid (the workload recipe on a z-shortened copy of its cross-section), "
                       f"E={E} Ha, {len(modes)} channels, dense LU (LAPACK, {threads} BLAS threads) + "
                       f"solves + current readout in {dt:.1f} s"}
 
@@ -394,6 +394,50 @@ def block_sweep(only=None):
                       "rows": rows}), flush=True)
 
 
+def smatrix_workload(args):
+    """The headline wire (48 x 48 x 128, 16 energies) solved from both
+    electrodes for the full flux-normalised scattering matrix of every
+    energy (1,536 scattering states), default options: states per second,
+    the unitarity error, and the eigenchannel transmissions (eigenvalues of
+    t^dagger t, from the transmission block) of the first energy."""
+    import numpy as np
+    import torch
+
+    from paper_1009_5300_amd import iobm
+    from workloads import make
+
+    torch.cuda.set_device(0)
+    w = make(4)
+    g = w.grid
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
+    s.set_potential(w.V)
+    opts = iobm.default_opts()
+    for _ in range(max(1, args.warmup)):
+        S, stats, status = s.smatrix(w.energies, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S, stats, status = s.smatrix(w.energies, opts=opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert status == 0
+    nst = sum(x.shape[0] for x in S)
+    unit = max(float(np.abs(x.conj().T @ x - np.eye(x.shape[0])).max()) for x in S)
+    n0 = S[0].shape[0] // 2
+    t = S[0][n0:, :n0]  # transmission block, left incidence
+    eig = np.sort(np.linalg.eigvalsh(t.conj().T @ t))[::-1]
+    print(json.dumps({
+        "metric": "scattering-matrix states/sec (both electrodes, every open channel)",
+        "value": round(args.steps * nst / (t1 - t0), 2), "unit": "states/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * (t1 - t0) / args.steps, 3), "higher_is_better": True,
+        "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": "wide 48x48x128 h=0.4 4th-order FD, 16 energies, S-matrix of both leads",
+                   "states": int(nst)},
+        "max_unitarity_error": unit, "total_transmission_E0": float(eig.sum()),
+        "eigenchannels_E0_top5": [float(x) for x in eig[:5]],
+    }), flush=True)
+
+
 def bloch_workload(args):
     """The wide wire (48 x 48 x 128, 4th-order FD) at a general lateral Bloch
     vector kappa = (0.37 pi / L_x, 0.61 pi / L_y), the first 4 energies of
@@ -476,7 +520,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip plain-CG and Eq. (17) samples")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for the HBM counter calibration)")
-    ap.add_argument("--workload", default="4", choices=["3", "4", "5", "na", "precision", "block", "bloch"],
+    ap.add_argument("--workload", default="4", choices=["3", "4", "5", "na", "precision", "block", "bloch",
+                                                         "smatrix"],
                     help="4: the headline wide-wire batch (default); 3: the atomic chain with the nonlocal "
                          "term on MFMA (secondary measurement); 5: the adjoint gradient dT/dV; na: iteration "
                          "counts of the paper's preconditioner experiment on synthetic Na-like wires")
@@ -503,6 +548,9 @@ def main():
         return
     if args.gpus == 1 and args.workload == "bloch":
         bloch_workload(args)
+        return
+    if args.gpus == 1 and args.workload == "smatrix":
+        smatrix_workload(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU (use --gpus 1): the scattering states of different energies are "
