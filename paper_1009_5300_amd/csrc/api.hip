@@ -1550,7 +1550,8 @@ iobm_status iobm_destroy(iobm_ctx ctx) {
     if (e.first) (void)hipFree(e.first);
   void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->V_d, ctx->V_f, ctx->modes_d, ctx->sig_d,
                   ctx->sig_f, ctx->mode_flags_d, ctx->sdiag_d,
-                  ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.hD, ctx->kb.diag_d, ctx->arena_d};
+                  ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.Btd, ctx->kb.Btf, ctx->kb.ctile, ctx->kb.prange,
+                  ctx->kb.hD, ctx->kb.diag_d, ctx->arena_d};
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->arena_h) (void)hipHostFree(ctx->arena_h);
   if (ctx->rb_h) (void)hipHostFree(ctx->rb_h);
@@ -1673,6 +1674,26 @@ iobm_status iobm_set_nonlocal(iobm_ctx ctx, int32_t ncen, int32_t rank, const in
       for (int q = 0; q < rank; ++q)
         hD[(size_t)(a * rank + p) * nproj + a * rank + q] = h3 * D[(a * rank + p) * rank + q];
   std::vector<float> Bf(Bm.begin(), Bm.end());
+  std::vector<double> Bt((size_t)nu * nproj);
+  for (int u = 0; u < nu; ++u)
+    for (int p = 0; p < nproj; ++p) Bt[(size_t)p * nu + u] = Bm[(size_t)u * npad + p];
+  std::vector<float> Btf(Bt.begin(), Bt.end());
+  // where the projectors vanish: nonzero tiles per 64-voxel chunk of the
+  // projection, nonzero projector range per 256-voxel block of the
+  // back-projection
+  std::vector<int> ctile((nu + 63) / 64, 0), prange(2 * (size_t)((nu + 255) / 256));
+  for (size_t b = 0; b < prange.size() / 2; ++b) {
+    prange[2 * b] = nproj;
+    prange[2 * b + 1] = 0;
+  }
+  for (int u = 0; u < nu; ++u)
+    for (int p = 0; p < nproj; ++p)
+      if (Bm[(size_t)u * npad + p] != 0.0) {
+        ctile[u / 64] |= 1 << (p / 16);
+        int* r = &prange[2 * (size_t)(u / 256)];
+        r[0] = std::min(r[0], p);
+        r[1] = std::max(r[1], p + 1);
+      }
   // diagonal of B h^3 D B^T per voxel (zero off the supports)
   std::vector<double> kdiag(nu > 0 ? (size_t)ctx->g.npts : 0, 0.0);
   for (int u = 0; u < nu; ++u) {
@@ -1683,7 +1704,7 @@ iobm_status iobm_set_nonlocal(iobm_ctx ctx, int32_t ncen, int32_t rank, const in
   }
   try {
     stream_sync(ctx);
-    void* old[] = {kb.uvox, kb.Bd, kb.Bf, kb.hD, kb.diag_d};
+    void* old[] = {kb.uvox, kb.Bd, kb.Bf, kb.Btd, kb.Btf, kb.ctile, kb.prange, kb.hD, kb.diag_d};
     for (void* p : old)
       if (p) (void)hipFree(p);
     kb = KBData();
@@ -1691,10 +1712,18 @@ iobm_status iobm_set_nonlocal(iobm_ctx ctx, int32_t ncen, int32_t rank, const in
     HIPCHK(hipMalloc(&kb.uvox, nu * sizeof(int)));
     HIPCHK(hipMalloc(&kb.Bd, Bm.size() * sizeof(double)));
     HIPCHK(hipMalloc(&kb.Bf, Bf.size() * sizeof(float)));
+    HIPCHK(hipMalloc(&kb.Btd, Bt.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&kb.Btf, Btf.size() * sizeof(float)));
+    HIPCHK(hipMalloc(&kb.ctile, ctile.size() * sizeof(int)));
+    HIPCHK(hipMalloc(&kb.prange, prange.size() * sizeof(int)));
     HIPCHK(hipMalloc(&kb.hD, hD.size() * sizeof(double)));
     HIPCHK(hipMemcpy(kb.uvox, uvox.data(), nu * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(kb.Bd, Bm.data(), Bm.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(kb.Bf, Bf.data(), Bf.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(kb.Btd, Bt.data(), Bt.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(kb.Btf, Btf.data(), Btf.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(kb.ctile, ctile.data(), ctile.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(kb.prange, prange.data(), prange.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(kb.hD, hD.data(), hD.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMalloc(&kb.diag_d, kdiag.size() * sizeof(double)));
     HIPCHK(hipMemcpy(kb.diag_d, kdiag.data(), kdiag.size() * sizeof(double), hipMemcpyHostToDevice));

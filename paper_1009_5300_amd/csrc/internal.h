@@ -47,6 +47,10 @@ struct KBData {
   int* uvox = nullptr;    // [nu] flat voxel ids (device)
   double* Bd = nullptr;   // [nu][nproj_pad] projector values, zero where off-support
   float* Bf = nullptr;
+  double* Btd = nullptr;  // [nproj][nu] the same values transposed (back-projection)
+  float* Btf = nullptr;
+  int* ctile = nullptr;   // [chunks of 64 union voxels] bit t: projector tile t has a nonzero value there
+  int* prange = nullptr;  // [blocks of 256 union voxels][2] projectors [lo, hi) with nonzero values there
   double* hD = nullptr;   // [nproj][nproj] block-diagonal h^3 D (device)
   double* diag_d = nullptr;  // [npts] diagonal of B h^3 D B^T (device; Jacobi preconditioner)
   int nproj_pad = 0;      // nproj rounded up to the MFMA tile (multiple of 16)

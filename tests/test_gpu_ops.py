@@ -113,6 +113,54 @@ def test_apply_matches_oracle(torch, g, kb):
     assert np.abs(y32 - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
+def _random_projectors(g, ncen, rank, seed):
+    """ncen centres of rank-`rank` projectors with random values on the
+    sphere supports of the synthetic generator (overlapping, some wrapping
+    the periodic edge) and random symmetric D."""
+    from workloads.synth import Nonlocal, _kb_projectors
+    rng = np.random.default_rng(seed)
+    L = np.array([g.nx * g.hx, g.ny * g.hy, g.nz * g.hz])
+    centres = [rng.uniform(0, 1, 3) * L for _ in range(ncen)]
+    base = _kb_projectors(g, centres, 1.0, 1, rng)
+    beta, D = [], []
+    for idx in base.support:
+        b = rng.standard_normal((rank, len(idx)))
+        beta.append(b / np.sqrt(g.hx * g.hy * g.hz * np.sum(b * b, axis=1))[:, None])
+        M = rng.uniform(-1.0, 1.0, (rank, rank))
+        D.append(M + M.T)
+    return Nonlocal(base.support, beta, D)
+
+
+@pytest.mark.parametrize("ncen,rank,nrhs", [(1, 1, 5), (10, 4, 37), (16, 8, 70)],
+                         ids=["1proj_5rhs", "40proj_37rhs", "128proj_70rhs"])
+def test_nonlocal_apply_projector_tiles_and_rhs_groups(torch, ncen, rank, nrhs):
+    """The nonlocal term with 1 to 128 projectors (one to eight 16-wide MFMA
+    projector tiles) and right-hand-side counts that leave the last 32-wide
+    projection group and the last 16-wide back-projection group partly
+    filled, on a grid whose support union spans many 64-voxel chunks and
+    voxel splits: complex128 to 1e-12 and complex64 to 2e-5 of the oracle's
+    operator, and the nonlocal contribution alone (with the term minus
+    without it, 0.3 to 1.5 percent of the operator here) to 1e-10 of its size."""
+    from paper_1009_5300_amd import iobm
+    g = Grid(24, 24, 32, 0.4, 2)
+    nl = _random_projectors(g, ncen, rank, 60 + ncen)
+    V = _V(g, 12)
+    s = _solver(g, V, nl)
+    P = O.Problem(g, V, nl)
+    E = 0.9
+    x = random_field((nrhs,) + g.shape, 22)
+    ref = P.apply(E, x.reshape(nrhs, -1)).reshape(x.shape)
+    xt = torch.as_tensor(x, device="cuda")
+    y = s.apply(E, xt, iobm.C128).cpu().numpy()
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    y32 = s.apply(E, xt.to(torch.complex64), iobm.C64_REFINED).cpu().numpy()
+    assert np.abs(y32 - ref).max() <= 2e-5 * np.abs(ref).max()
+    # the nonlocal contribution alone: with the term minus without it
+    ref_nl = ref - O.Problem(g, V).apply(E, x.reshape(nrhs, -1)).reshape(x.shape)
+    y_nl = y - _solver(g, V).apply(E, xt, iobm.C128).cpu().numpy()
+    assert np.abs(y_nl - ref_nl).max() <= 1e-10 * np.abs(ref_nl).max()
+
+
 @pytest.mark.parametrize("g", GRIDS, ids=gid)
 def test_truncated_laplacian_preconditioner(torch, g):
     from paper_1009_5300_amd import iobm
