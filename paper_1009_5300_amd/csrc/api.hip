@@ -92,6 +92,9 @@ template <typename T>
 hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
                               const double* E_rhs, const int* e_rhs, const int* sgn, const int* active);
 template <typename T>
+hipError_t launch_bloch_apply_fused(iobm_ctx c, const BlochPhase& ph, const BlochFuse<T>& F, cplx<T>* y, int nrhs,
+                                    const double* E_rhs, const int* e_rhs, const int* sgn, const int* active);
+template <typename T>
 hipError_t launch_bloch_laplacian(iobm_ctx c, const BlochPhase& ph, double alpha, const cplx<T>* r, cplx<T>* z,
                                   int nrhs, const int* sgn, const int* active);
 template <typename T>
@@ -100,16 +103,14 @@ hipError_t launch_bloch_dot(iobm_ctx c, const cplx<T>* u, const cplx<T>* v, int 
 hipError_t launch_bloch_scalars(iobm_ctx c, int mode, int npairs, const int* pairs, const Partial* pd, const Partial* pn,
                                 int nblk, zd* rho, zd* alpha, zd* beta, double* rn2, int* flag);
 template <typename T>
-hipError_t launch_bloch_update(iobm_ctx c, cplx<T>* d, cplx<T>* r, const cplx<T>* p, const cplx<T>* q,
-                               const zd* alpha, int nslots, const int* active, Partial* pn, int nblk);
+hipError_t launch_bloch_update(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* alpha, int nslots,
+                               const int* active, Partial* pn, int nblk);
 template <typename T>
 hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, cplx<T>* r, const zd* y, int nslots, const int* active,
                               Partial* pn, int nblk);
 template <typename T>
-hipError_t launch_bloch_fold(iobm_ctx c, zd* x, cplx<T>* d, int nslots, const int* active, int nblk);
-template <typename T>
-hipError_t launch_bloch_direction(iobm_ctx c, cplx<T>* p, const cplx<T>* z, const zd* beta, int nslots,
-                                  const int* active, int nblk);
+hipError_t launch_bloch_settle(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, int nslots,
+                               const int* active, int nblk);
 
 namespace {
 
@@ -1144,12 +1145,16 @@ enum { BL_ALPHA = 0, BL_BETA = 1, BL_RESTART = 2 };
 //   p = z + beta p, p~ = z~ + beta p~,
 // in the iteration precision T on the correction d of the FP64 solution x
 // (complex128: d is x itself), every inner product summed in FP64 in a
-// fixed order.  A pair is restarted from its true residual (x += d, d = 0,
-// r = b - A x with the complex128 operator, p = z) when its recursive
-// residuals both reach tol ||b||, or (complex64) have both fallen by
-// opts.inner_tol since its last restart, or when it broke down (vanishing
-// rho or p~^T q) or diverged.  It is done when both true residuals are
-// below tol ||b||.  The operators run in the gauge u = exp(-i kappa.r) psi.
+// fixed order.  One operator pass forms the direction (p = z + beta p into
+// the other of two buffers), applies A to it and adds the previous step's
+// alpha p to d, so a step's d update stays pending until the next pass, or
+// until a restart or a stop folds it in (x += d + alpha p).  A pair is
+// restarted from its true residual (that fold, d = 0, r = b - A x with the
+// complex128 operator, then p = z) when its recursive residuals both reach
+// tol ||b||, or (complex64) have both fallen by opts.inner_tol since its
+// last restart, or when it broke down (vanishing rho or p~^T q) or
+// diverged.  It is done when both true residuals are below tol ||b||.  The
+// operators run in the gauge u = exp(-i kappa.r) psi.
 template <typename T>
 void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& ph, const PairBatch& B, const zd* b,
                       zd* x, SolveOut& out) {
@@ -1166,7 +1171,8 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   double* E_d = upload(ctx, S_IDX, B.E, 16 * 1024);
   int* sg_d = upload(ctx, S_IDX, B.sgn, 32 * 1024);
   cplx<T>* r = (cplx<T>*)workspace(ctx, S_R, vb);
-  cplx<T>* p = (cplx<T>*)workspace(ctx, S_P, vb);
+  cplx<T>* pc = (cplx<T>*)workspace(ctx, S_P, vb);   // the last step's direction (its alpha p pending)
+  cplx<T>* po = (cplx<T>*)workspace(ctx, S_P2, vb);  // the next step's
   cplx<T>* q = (cplx<T>*)workspace(ctx, S_Q, vb);
   cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)workspace(ctx, S_Z, vb);
   cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)workspace(ctx, S_PF, vb) : nullptr;
@@ -1192,6 +1198,10 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   const int check = std::max(1, o.check_every);
   HIPCHK(hipMemsetAsync(x, 0, (size_t)ns * vol * sizeof(zd), ctx->stream));
   if (lowp) HIPCHK(hipMemsetAsync(d, 0, vb, ctx->stream));
+  // rho, alpha, beta: nothing pending before the first restart
+  HIPCHK(hipMemsetAsync(rho, 0, (size_t)np * 3 * sizeof(zd), ctx->stream));
+  cplx<T>* dfold = lowp ? d : nullptr;  // complex128: the recurrence updates x itself
+  int nfresh = 0;                       // slots restarted since their last step
 
   // device lists of the pairs in `pairs_h` (pair ids): their slots (2k,
   // 2k+1 in pair order) and their primary slots
@@ -1214,26 +1224,28 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
     else if (o.precond == IOBM_PC_JACOBI)
       HIPCHK(launch_precond_jacobi<T>(ctx, r, z, nsl, e_d, E_d, sl_d, nullptr));
   };
-  // x += d, r = b - A x (complex128 operator), z = P r, rho = r~^T z, p = z
-  // for the listed pairs
+  // x += d + alpha p, r = b - A x (complex128 operator), z = P r,
+  // rho = r~^T z, alpha = beta = 0 (the next pass takes p = z) for the listed
+  // pairs
   auto restart = [&](int npr) {
-    if (lowp) HIPCHK(launch_bloch_fold<T>(ctx, x, d, 2 * npr, sl_d, nblk));
+    HIPCHK(launch_bloch_settle<T>(ctx, x, dfold, pc, alpha, 2 * npr, sl_d, nblk));
     HIPCHK(launch_bloch_apply<double>(ctx, ph, x, yx, 2 * npr, E_d, e_d, sg_d, sl_d));
     HIPCHK(launch_bloch_resid<T>(ctx, b, r, yx, 2 * npr, sl_d, pn, nblk));
     precond(2 * npr);
     HIPCHK(launch_bloch_dot<T>(ctx, r, z, npr, pl_d, pd, nblk));
     HIPCHK(launch_bloch_scalars(ctx, BL_RESTART, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
-    HIPCHK(launch_bloch_direction<T>(ctx, p, z, beta, 2 * npr, sl_d, nblk));
   };
   auto iterate = [&](int npr) {
-    HIPCHK(launch_bloch_apply<T>(ctx, ph, p, q, 2 * npr, E_d, e_d, sg_d, sl_d));
-    HIPCHK(launch_bloch_dot<T>(ctx, p, q, npr, pl_d, pd, nblk));
+    const BlochFuse<T> F{z, pc, po, d, beta, alpha, nfresh};
+    HIPCHK(launch_bloch_apply_fused<T>(ctx, ph, F, q, 2 * npr, E_d, e_d, sg_d, sl_d));
+    std::swap(pc, po);
+    nfresh = 0;
+    HIPCHK(launch_bloch_dot<T>(ctx, pc, q, npr, pl_d, pd, nblk));
     HIPCHK(launch_bloch_scalars(ctx, BL_ALPHA, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
-    HIPCHK(launch_bloch_update<T>(ctx, d, r, p, q, alpha, 2 * npr, sl_d, pn, nblk));
+    HIPCHK(launch_bloch_update<T>(ctx, r, q, alpha, 2 * npr, sl_d, pn, nblk));
     precond(2 * npr);
     HIPCHK(launch_bloch_dot<T>(ctx, r, z, npr, pl_d, pd, nblk));
     HIPCHK(launch_bloch_scalars(ctx, BL_BETA, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
-    HIPCHK(launch_bloch_direction<T>(ctx, p, z, beta, 2 * npr, sl_d, nblk));
   };
   auto read_back = [&]() {
     HIPCHK(hipMemcpyAsync(rbh, rn2, (size_t)ns * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -1246,6 +1258,7 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   for (int k = 0; k < np; ++k) act[k] = k;
   set_lists(act);
   restart(np);  // x = 0: r = b
+  nfresh = ns;
   read_back();
   std::vector<double> bn2(rn2_h, rn2_h + ns), last(bn2);
   std::vector<int> it(np, 0), rs(np, 0);
@@ -1288,14 +1301,20 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
     for (int c2 = 0; c2 < check; ++c2) iterate(npr);
     for (int k : act) it[k] += check;
     read_back();
-    std::vector<int> keep, redo;
+    std::vector<int> keep, redo, stop;
     for (int k : act) {
       const double a = rn2_h[2 * k], c3 = rn2_h[2 * k + 1];
       const bool bad = flag_h[k] || !std::isfinite(a) || !std::isfinite(c3) || a > 1e20 * bn2[2 * k] ||
                        c3 > 1e20 * bn2[2 * k + 1];
       if (bad || pair_conv(k) || pair_replace(k)) redo.push_back(k);
-      else if (it[k] >= o.max_iter) finish(k, IOBM_E_NOT_CONVERGED);
-      else keep.push_back(k);
+      else if (it[k] >= o.max_iter) {
+        finish(k, IOBM_E_NOT_CONVERGED);
+        stop.push_back(k);
+      } else keep.push_back(k);
+    }
+    if (!stop.empty()) {  // fold in the pending correction of the pairs that stop here
+      set_lists(stop);
+      HIPCHK(launch_bloch_settle<T>(ctx, x, dfold, pc, alpha, 2 * (int)stop.size(), sl_d, nblk));
     }
     if (!redo.empty()) {
       set_lists(redo);
@@ -1308,7 +1327,10 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
         if (pair_conv(k)) finish(k, IOBM_OK);
         else if (flag_h[k] || rs[k] >= max_restarts) finish(k, IOBM_E_BREAKDOWN);
         else if (it[k] >= o.max_iter) finish(k, IOBM_E_NOT_CONVERGED);
-        else keep.push_back(k);
+        else {
+          keep.push_back(k);
+          nfresh += 2;
+        }
       }
     }
     std::sort(keep.begin(), keep.end());
@@ -1317,14 +1339,8 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
       if (!act.empty()) set_lists(act);
     }
   }
-  // complex64: fold what the pairs that stopped between restarts (iteration
-  // limit) still hold in d; the others hold d = 0 after their last restart
-  if (lowp) {
-    std::vector<int> all(np);
-    for (int k = 0; k < np; ++k) all[k] = k;
-    set_lists(all);
-    HIPCHK(launch_bloch_fold<T>(ctx, x, d, ns, sl_d, nblk));
-  }
+  // every pair ended right after a restart or a stop, each of which folded
+  // in its pending correction: x holds the solution
 }
 
 }  // namespace

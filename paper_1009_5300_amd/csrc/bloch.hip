@@ -11,9 +11,10 @@
 // condition psi(r + L) = exp(i kappa L) psi(r) turns into a periodic u whose
 // lateral couplings carry a bond phase: the neighbour at +n along x enters
 // with exp(i n kappa_x h_x), the one at -n with its conjugate.  Only the
-// stencil (the 2.5D kernel with the OpBloch policy, ops.hip) and Eq. (17)
-// (this file) change; the diagonal (and so the Jacobi preconditioner) does
-// not.
+// stencil (the 2.5D kernel with the OpBloch policy, and OpBlochFuse, which
+// also forms the direction and the pending correction of the pair iteration;
+// ops.hip) and Eq. (17) (this file) change; the diagonal (and so the Jacobi
+// preconditioner) does not.
 //
 // Transpose.  A(kappa)^T = A(-kappa): the operator is not complex symmetric
 // for one kappa, so each state at +kappa is solved together with a partner
@@ -166,11 +167,11 @@ __global__ void __launch_bounds__(64) k_bl_scalars(int mode, int npairs, const i
   }
 }
 
-// d += alpha p, r -= alpha q (alpha of the slot's pair), with the partials
-// of |r|^2 in pn[slot][blk].
+// r -= alpha q (alpha of the slot's pair), with the partials of |r|^2 in
+// pn[slot][blk]; the matching d += alpha p is left to the next fused
+// operator pass (or the settle of a restart).
 template <typename T>
-__global__ void __launch_bounds__(256) k_bl_update(cplx<T>* __restrict__ d, cplx<T>* __restrict__ r,
-                                                   const cplx<T>* __restrict__ p, const cplx<T>* __restrict__ q,
+__global__ void __launch_bounds__(256) k_bl_update(cplx<T>* __restrict__ r, const cplx<T>* __restrict__ q,
                                                    const zd* __restrict__ alpha, long long vol, int nblk,
                                                    const int* __restrict__ active, Partial* __restrict__ pn) {
   const int slot = blockIdx.x / nblk;
@@ -182,7 +183,6 @@ __global__ void __launch_bounds__(256) k_bl_update(cplx<T>* __restrict__ d, cplx
   const long long o = (long long)rhs * vol;
   double n2 = 0, d0 = 0, d1 = 0;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    d[o + i] = cfma(a, p[o + i], d[o + i]);
     const cplx<T> v = r[o + i] - a * q[o + i];
     r[o + i] = v;
     n2 += (double)v.re * v.re + (double)v.im * v.im;
@@ -221,40 +221,32 @@ __global__ void __launch_bounds__(256) k_bl_resid(const zd* __restrict__ b, cplx
   }
 }
 
-// x += d, d = 0 (the correction folded into the FP64 solution).
+// The pending correction folded into the FP64 solution: x += d + alpha p,
+// d = 0 (complex64; alpha of the slot's pair), or x += alpha p (complex128,
+// d == nullptr: the recurrence updates x itself).  p is not read where
+// alpha = 0 (it may hold anything after a restart).
 template <typename T>
-__global__ void __launch_bounds__(256) k_bl_fold(zd* __restrict__ x, cplx<T>* __restrict__ d, long long vol, int nblk,
-                                                 const int* __restrict__ active) {
+__global__ void __launch_bounds__(256) k_bl_settle(zd* __restrict__ x, cplx<T>* __restrict__ d,
+                                                   const cplx<T>* __restrict__ p, const zd* __restrict__ alpha,
+                                                   long long vol, int nblk, const int* __restrict__ active) {
   const int slot = blockIdx.x / nblk;
   const int blk = blockIdx.x - slot * nblk;
   const int rhs = bl_rhs(active, slot);
+  const zd a = alpha[rhs >> 1];
+  const bool pend = a.re != 0.0 || a.im != 0.0;
+  if (!d && !pend) return;
   const long long per = (vol + nblk - 1) / nblk;
   const long long i0 = blk * per, i1 = min(vol, i0 + per);
   const long long o = (long long)rhs * vol;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const cplx<T> v = d[o + i];
-    x[o + i] = x[o + i] + mk((double)v.re, (double)v.im);
-    d[o + i] = mk<T>(0, 0);
+    zd v = x[o + i];
+    if (d) {
+      v = v + cvt<double>(d[o + i]);
+      d[o + i] = mk<T>(0, 0);
+    }
+    if (pend) v = cfma(a, cvt<double>(p[o + i]), v);
+    x[o + i] = v;
   }
-}
-
-// p = z + beta p (beta of the slot's pair); p = z where beta = 0 (p is then
-// not read: it may hold anything after a restart).
-template <typename T>
-__global__ void __launch_bounds__(256) k_bl_direction(cplx<T>* __restrict__ p, const cplx<T>* __restrict__ z,
-                                                      const zd* __restrict__ beta, long long vol, int nblk,
-                                                      const int* __restrict__ active) {
-  const int slot = blockIdx.x / nblk;
-  const int blk = blockIdx.x - slot * nblk;
-  const int rhs = bl_rhs(active, slot);
-  const zd btd = beta[rhs >> 1];
-  const bool fresh = btd.re == 0.0 && btd.im == 0.0;
-  const cplx<T> bt = cvt<T>(btd);
-  const long long per = (vol + nblk - 1) / nblk;
-  const long long i0 = blk * per, i1 = min(vol, i0 + per);
-  const long long o = (long long)rhs * vol;
-  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x)
-    p[o + i] = fresh ? z[o + i] : cfma(bt, p[o + i], z[o + i]);
 }
 
 }  // namespace
@@ -267,6 +259,15 @@ hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x
   hipError_t err = launch_bloch_stencil<T>(c, ph, x, y, nrhs, E_rhs, sgn, active);
   if (err != hipSuccess) return err;
   return launch_face_sigma<T>(c, x, y, nrhs, e_rhs, active);
+}
+
+template <typename T>
+hipError_t launch_bloch_apply_fused(iobm_ctx c, const BlochPhase& ph, const BlochFuse<T>& F, cplx<T>* y, int nrhs,
+                                    const double* E_rhs, const int* e_rhs, const int* sgn, const int* active) {
+  if (nrhs <= 0) return hipSuccess;
+  hipError_t err = launch_bloch_stencil_fused<T>(c, ph, F, y, nrhs, E_rhs, sgn, active);
+  if (err != hipSuccess) return err;
+  return launch_face_sigma<T>(c, F.pnew, y, nrhs, e_rhs, active);
 }
 
 template <typename T>
@@ -300,14 +301,14 @@ hipError_t launch_bloch_scalars(iobm_ctx c, int mode, int npairs, const int* pai
 }
 
 template <typename T>
-hipError_t launch_bloch_update(iobm_ctx c, cplx<T>* d, cplx<T>* r, const cplx<T>* p, const cplx<T>* q,
-                               const zd* alpha, int nslots, const int* active, Partial* pn, int nblk) {
+hipError_t launch_bloch_update(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* alpha, int nslots,
+                               const int* active, Partial* pn, int nblk) {
   if (nslots <= 0) return hipSuccess;
   const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
-  hipLaunchKernelGGL(k_bl_update<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, d, r, p, q, alpha, c->g.npts,
-                     nblk, active, pn);
-  // read d, r, p, q; write d, r
-  prof_stop(c, rec, 6.0 * nslots * c->g.npts * sizeof(cplx<T>));
+  hipLaunchKernelGGL(k_bl_update<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, r, q, alpha, c->g.npts, nblk,
+                     active, pn);
+  // read r, q; write r
+  prof_stop(c, rec, 3.0 * nslots * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
 }
 
@@ -323,39 +324,32 @@ hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, cplx<T>* r, const zd* y, 
 }
 
 template <typename T>
-hipError_t launch_bloch_fold(iobm_ctx c, zd* x, cplx<T>* d, int nslots, const int* active, int nblk) {
+hipError_t launch_bloch_settle(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, int nslots,
+                               const int* active, int nblk) {
   if (nslots <= 0) return hipSuccess;
   const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
-  hipLaunchKernelGGL(k_bl_fold<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, x, d, c->g.npts, nblk, active);
-  prof_stop(c, rec, nslots * c->g.npts * (2.0 * sizeof(zd) + 2.0 * sizeof(cplx<T>)));
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_bloch_direction(iobm_ctx c, cplx<T>* p, const cplx<T>* z, const zd* beta, int nslots,
-                                  const int* active, int nblk) {
-  if (nslots <= 0) return hipSuccess;
-  const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
-  hipLaunchKernelGGL(k_bl_direction<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, p, z, beta, c->g.npts, nblk,
+  hipLaunchKernelGGL(k_bl_settle<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, x, d, p, alpha, c->g.npts, nblk,
                      active);
-  prof_stop(c, rec, 3.0 * nslots * c->g.npts * sizeof(cplx<T>));
+  // read and write x; read p; read and write d (complex64)
+  prof_stop(c, rec, nslots * c->g.npts * (2.0 * sizeof(zd) + (d ? 3.0 : 1.0) * sizeof(cplx<T>)));
   return hipGetLastError();
 }
 
 #define IOBM_BLOCH_INST(T)                                                                                      \
   template hipError_t launch_bloch_apply<T>(iobm_ctx, const BlochPhase&, const cplx<T>*, cplx<T>*, int,          \
                                             const double*, const int*, const int*, const int*);                \
+  template hipError_t launch_bloch_apply_fused<T>(iobm_ctx, const BlochPhase&, const BlochFuse<T>&, cplx<T>*, int, \
+                                                  const double*, const int*, const int*, const int*);          \
   template hipError_t launch_bloch_laplacian<T>(iobm_ctx, const BlochPhase&, double, const cplx<T>*, cplx<T>*,   \
                                                 int, const int*, const int*);                                   \
   template hipError_t launch_bloch_dot<T>(iobm_ctx, const cplx<T>*, const cplx<T>*, int, const int*, Partial*,   \
                                           int);                                                                 \
-  template hipError_t launch_bloch_update<T>(iobm_ctx, cplx<T>*, cplx<T>*, const cplx<T>*, const cplx<T>*,       \
-                                             const zd*, int, const int*, Partial*, int);                        \
+  template hipError_t launch_bloch_update<T>(iobm_ctx, cplx<T>*, const cplx<T>*, const zd*, int, const int*,     \
+                                             Partial*, int);                                                    \
   template hipError_t launch_bloch_resid<T>(iobm_ctx, const zd*, cplx<T>*, const zd*, int, const int*, Partial*, \
                                             int);                                                               \
-  template hipError_t launch_bloch_fold<T>(iobm_ctx, zd*, cplx<T>*, int, const int*, int);                       \
-  template hipError_t launch_bloch_direction<T>(iobm_ctx, cplx<T>*, const cplx<T>*, const zd*, int, const int*, \
-                                                int);
+  template hipError_t launch_bloch_settle<T>(iobm_ctx, zd*, cplx<T>*, const cplx<T>*, const zd*, int,          \
+                                             const int*, int);
 IOBM_BLOCH_INST(float)
 IOBM_BLOCH_INST(double)
 #undef IOBM_BLOCH_INST

@@ -218,6 +218,23 @@ hipError_t launch_sigma_diag(iobm_ctx c, int nE);  // sdiag_d from sig_d for the
 template <typename T>
 hipError_t launch_bloch_stencil(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
                                 const double* E_rhs, const int* sgn, const int* active);
+// The same with the pair iteration's direction update fused: y = A_st p_new
+// with p_new = z + beta p_old written to pnew, and the pending correction
+// d += alpha p_old (beta, alpha per pair; both zero after a restart, when
+// p_old and d are not read; d is the FP64 solution itself in complex128)
+template <typename T>
+struct BlochFuse {
+  const cplx<T>* z;
+  const cplx<T>* pold;
+  cplx<T>* pnew;
+  cplx<T>* d;
+  const zd* beta;
+  const zd* alpha;
+  int nfresh;  // slots restarted since their last step (byte count of the timing hook only)
+};
+template <typename T>
+hipError_t launch_bloch_stencil_fused(iobm_ctx c, const BlochPhase& ph, const BlochFuse<T>& F, cplx<T>* y, int nrhs,
+                                      const double* E_rhs, const int* sgn, const int* active);
 // y -= Sigma x on the 2 nf face planes, for the listed rhs
 template <typename T>
 hipError_t launch_face_sigma(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const int* e_rhs, const int* active);

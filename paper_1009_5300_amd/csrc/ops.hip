@@ -237,6 +237,77 @@ struct OpFuseP {
   }
 };
 
+// The phased stencil of the pair iteration at a lateral Bloch vector with the
+// direction update fused, as OpFuseP does for the complex-symmetric
+// iteration: the operand is p_new = z + beta p_old (p_old not read where
+// beta = 0 and no update is pending), written to pnew for the block's own
+// points, and the previous step's correction d += alpha p_old is applied to
+// the own points from the same p_old loads (d is the FP64 solution itself
+// in complex128).  beta and alpha are per pair (slot / 2); the lateral bond
+// phases are those of OpBloch.
+template <typename T>
+struct OpBlochFuse {
+  struct Raw {
+    cplx<T> z, p, d;
+  };
+  static constexpr int lookahead = sizeof(T) == 4 ? 2 : 1;
+  static constexpr bool bloch = true;
+  const cplx<T>* z;
+  const cplx<T>* pold;
+  cplx<T>* pnew;
+  cplx<T>* y;
+  cplx<T>* d;
+  const zd* beta;
+  const zd* alpha;
+  const int* sgn;
+  cplx<T> f[2][4];
+  const cplx<T>* psrc;
+  cplx<T> bt, at;
+  bool use_b, use_d;
+  __device__ __forceinline__ void bind(int rhs, long long vol) {
+    z += rhs * vol; pold += rhs * vol; pnew += rhs * vol; y += rhs * vol; d += rhs * vol;
+    const zd b = beta[rhs >> 1], a = alpha[rhs >> 1];
+    bt = cvt<T>(b);
+    at = cvt<T>(a);
+    use_b = b.re != 0 || b.im != 0;
+    use_d = a.re != 0 || a.im != 0;
+    psrc = (use_b || use_d) ? pold : z;
+    if (sgn[rhs] < 0)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int n = 1; n < 4; ++n) f[e][n] = conj(f[e][n]);
+  }
+  __device__ __forceinline__ cplx<T> load(long long o) const {
+    cplx<T> v = z[o];
+    if (use_b) v = v + bt * pold[o];
+    return v;
+  }
+  __device__ __forceinline__ Raw load_raw(long long o, bool own) const {
+    Raw r;
+    r.z = z[o];
+    r.p = psrc[o];
+    r.d = (own && use_d ? d : z)[o];
+    return r;
+  }
+  __device__ __forceinline__ cplx<T> combine(const Raw& r, bool ok) const {
+    return ok ? (use_b ? r.z + bt * r.p : r.z) : mk<T>(0, 0);
+  }
+  __device__ __forceinline__ void side(const Raw& r, long long o, bool own) {
+    if (use_d && own) d[o] = r.d + at * r.p;
+  }
+  __device__ __forceinline__ void center(long long o, cplx<T> v) { pnew[o] = v; }
+  __device__ __forceinline__ void center_at(long long o, cplx<T> v) {
+    pnew[o] = v;
+    if (use_d) d[o] = d[o] + at * pold[o];
+  }
+  __device__ __forceinline__ void store(int, long long o, cplx<T>, cplx<T> acc) { y[o] = acc; }
+  __device__ __forceinline__ void finish(int, int, int) {}
+  __device__ __forceinline__ cplx<T> lat(int dir, int n, cplx<T> ap, cplx<T> am) const {
+    return cfma(conj(f[dir][n]), am, f[dir][n] * ap);
+  }
+};
+
 // FP64 residual of the refinement, r = b - A x, with b supported on the
 // 2 nf electrode-face planes only (true of every right-hand side the solver
 // builds).  Interior planes: r = -A_st x, stored in the iteration precision
@@ -1882,6 +1953,36 @@ template hipError_t launch_bloch_stencil<float>(iobm_ctx, const BlochPhase&, con
                                                 const int*, const int*);
 template hipError_t launch_bloch_stencil<double>(iobm_ctx, const BlochPhase&, const zd*, zd*, int, const double*,
                                                  const int*, const int*);
+
+template <typename T>
+hipError_t launch_bloch_stencil_fused(iobm_ctx c, const BlochPhase& ph, const BlochFuse<T>& F, cplx<T>* y, int nrhs,
+                                      const double* E_rhs, const int* sgn, const int* active) {
+  if (nrhs <= 0) return hipSuccess;
+  const StencilArgs S = stencil_args(c, 16);
+  OpBlochFuse<T> op;
+  op.z = F.z;
+  op.pold = F.pold;
+  op.pnew = F.pnew;
+  op.y = y;
+  op.d = F.d;
+  op.beta = F.beta;
+  op.alpha = F.alpha;
+  op.sgn = sgn;
+  for (int n = 0; n < 4; ++n) {
+    op.f[0][n] = cvt<T>(S.wx[n] * ph.x[n]);
+    op.f[1][n] = cvt<T>(S.wy[n] * ph.y[n]);
+  }
+  // streams: read z, p_old, d; write p_new, y, d; the nfresh slots right
+  // after a restart read z and write p_new and y only
+  const int nf = std::min(std::max(F.nfresh, 0), nrhs);
+  const double streams = 6.0 * (nrhs - nf) + 3.0 * nf;
+  return launch_stencil<T, OpBlochFuse<T>>(c, op, nrhs, E_rhs, active, streams / nrhs * sizeof(cplx<T>),
+                                            IOBM_K_BLOCH_STENCIL);
+}
+template hipError_t launch_bloch_stencil_fused<float>(iobm_ctx, const BlochPhase&, const BlochFuse<float>&, zf*, int,
+                                                      const double*, const int*, const int*);
+template hipError_t launch_bloch_stencil_fused<double>(iobm_ctx, const BlochPhase&, const BlochFuse<double>&, zd*,
+                                                       int, const double*, const int*, const int*);
 
 template <typename T>
 hipError_t launch_face_sigma(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const int* e_rhs,
