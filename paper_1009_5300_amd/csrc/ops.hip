@@ -247,6 +247,9 @@ struct OpFuseP {
 // phases are those of OpBloch.
 template <typename T>
 struct OpBlochFuse {
+  // complex64 prefetches d with z and p; complex128 reads it when the plane
+  // enters the window (its register queue would otherwise spill)
+  static constexpr bool pre_d = sizeof(T) == sizeof(float);
   struct Raw {
     cplx<T> z, p, d;
   };
@@ -287,14 +290,14 @@ struct OpBlochFuse {
     Raw r;
     r.z = z[o];
     r.p = psrc[o];
-    r.d = (own && use_d ? d : z)[o];
+    if constexpr (pre_d) r.d = (own && use_d ? d : z)[o];
     return r;
   }
   __device__ __forceinline__ cplx<T> combine(const Raw& r, bool ok) const {
     return ok ? (use_b ? r.z + bt * r.p : r.z) : mk<T>(0, 0);
   }
   __device__ __forceinline__ void side(const Raw& r, long long o, bool own) {
-    if (use_d && own) d[o] = r.d + at * r.p;
+    if (use_d && own) d[o] = (pre_d ? r.d : d[o]) + at * r.p;
   }
   __device__ __forceinline__ void center(long long o, cplx<T> v) { pnew[o] = v; }
   __device__ __forceinline__ void center_at(long long o, cplx<T> v) {

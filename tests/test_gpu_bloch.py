@@ -160,3 +160,25 @@ def test_bloch_rejections(torch):
     with pytest.raises(iobm.IobmError) as e:
         sk.smatrix_bloch([1.3], (0.1, 0.0), opts=iobm.default_opts(precision=iobm.C128))
     assert e.value.status == 8
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["c128", "c64"])
+def test_bloch_iteration_limit(torch, precision):
+    """Pairs that stop at the iteration limit (their last step's correction
+    folded into the solution as they stop): every state reports
+    NOT_CONVERGED, the matrices are finite, and a longer limit lands closer
+    to the converged matrices than a shorter one."""
+    from paper_1009_5300_amd import iobm
+    w = make(5, Grid(16, 12, 40, 0.4, 2))
+    kap = _kappa(w.grid, 0.7, -0.3)
+    s = _solver(w)
+    Sp, _, _, status = s.smatrix_bloch([1.2], kap, opts=iobm.default_opts(precision=iobm.C128))
+    assert status == 0
+    err = []
+    for m in (2, 30):
+        o = iobm.default_opts(precision=precision, precond=iobm.PC_NONE, max_iter=m, check_every=1)
+        Sl, Sml, stats, status = s.smatrix_bloch([1.2], kap, opts=o)
+        assert status == 5 and all(st[2] == 5 for st in stats)
+        assert np.all(np.isfinite(Sl[0])) and np.all(np.isfinite(Sml[0]))
+        err.append(np.abs(Sl[0] - Sp[0]).max())
+    assert err[1] < err[0]
