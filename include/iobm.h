@@ -320,8 +320,10 @@ iobm_status iobm_smatrix_bloch(iobm_ctx ctx, const iobm_solve_opts* opts, double
 /* Total transmission T_tot = sum over energies and every open incident
  * channel of T_mu, and its gradient with respect to the local potential,
  * dT_tot/dV(r), by one adjoint solve per channel with the same (complex
- * symmetric) operator.  T_total: host scalar; dT_dV: device float64
- * [nz][ny][nx] (overwritten).  Synchronises the stream. */
+ * symmetric) operator.  The forward and adjoint states are solved as one
+ * batch, so the context's workspaces hold twice the states that
+ * iobm_solve would on the same energies.  T_total: host scalar; dT_dV:
+ * device float64 [nz][ny][nx] (overwritten).  Synchronises the stream. */
 iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, int32_t nE,
                                    const double* E, double* T_total, void* dT_dV);
 

@@ -141,7 +141,7 @@ iobm_status fail(iobm_ctx ctx, iobm_status s, const std::string& msg) {
 enum Slot {
   S_B, S_XHI, S_RHI, S_Y, S_R, S_Z, S_P, S_P2, S_Q, S_D, S_PF, S_PART, S_PARTA, S_PARTZ, S_PARTR, S_PARTN, S_SCAL,
   S_IDX, S_AMP,
-  S_TR, S_KB, S_GRAD_U, S_GRAD_D, S_BLK_PART, S_BLK_G, S_BLK_N2, NSLOT
+  S_TR, S_KB, S_GRAD_D, S_BLK_PART, S_BLK_G, S_BLK_N2, NSLOT
 };
 
 void* workspace(iobm_ctx ctx, int slot, size_t bytes) {
@@ -2238,18 +2238,28 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
       stream_sync(ctx);
       return IOBM_OK;
     }
-    zd* b = (zd*)workspace(ctx, S_B, (size_t)nb * vol * sizeof(zd));
-    zd* u = (zd*)workspace(ctx, S_XHI, (size_t)nb * vol * sizeof(zd));
-    zd* w = (zd*)workspace(ctx, S_GRAD_U, (size_t)nb * vol * sizeof(zd));
-    // forward solves
+    // the forward solves A u_b = rhs_b (slots 0 .. nb-1) and the adjoint
+    // solves A w_b = l_b in the same real lateral basis (slots nb .. 2nb-1):
+    // the adjoint right-hand sides do not depend on u, so both run in one
+    // batch and share every iteration
+    zd* b = (zd*)workspace(ctx, S_B, (size_t)2 * nb * vol * sizeof(zd));
+    zd* u = (zd*)workspace(ctx, S_XHI, (size_t)2 * nb * vol * sizeof(zd));
+    zd* w = u + (size_t)nb * vol;
     {
       int* e_d = upload(ctx, S_IDX, B.e, 0);
       int* m_d = upload(ctx, S_IDX, B.mode, 16 * 1024);
       int* k_d = upload(ctx, S_IDX, B.kind, 32 * 1024);
       HIPCHK(launch_rhs(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b, true));
+      HIPCHK(launch_rhs_adjoint(ctx, nb, e_d, m_d, k_d, o.side, ctx->modes_d, b + (size_t)nb * vol));
     }
-    SolveOut so;
-    solve_batch(ctx, o, B, b, u, so);
+    Batch B2 = B;
+    B2.n = 2 * nb;
+    B2.e.insert(B2.e.end(), B.e.begin(), B.e.end());
+    B2.E.insert(B2.E.end(), B.E.begin(), B.E.end());
+    B2.mode.insert(B2.mode.end(), B.mode.begin(), B.mode.end());
+    B2.kind.insert(B2.kind.end(), B.kind.begin(), B.kind.end());
+    SolveOut s2;
+    solve_batch(ctx, o, B2, b, u, s2);
     zd* amp = (zd*)workspace(ctx, S_AMP, (size_t)(2 * nb + 2 * nreq) * nxy * sizeof(zd));
     zd* amp_near = amp;
     zd* amp_far = amp + (size_t)nb * nxy;
@@ -2270,15 +2280,6 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
     stream_sync(ctx);
     double Ttot = 0;
     for (int c = 0; c < nreq; ++c) Ttot += TRh[c];
-    // adjoint solves: A w_b = l_b in the same real lateral basis
-    {
-      int* e2 = upload(ctx, S_IDX, B.e, 0);
-      int* m2 = upload(ctx, S_IDX, B.mode, 8 * 1024);
-      int* k2 = upload(ctx, S_IDX, B.kind, 56 * 1024);
-      HIPCHK(launch_rhs_adjoint(ctx, nb, e2, m2, k2, o.side, ctx->modes_d, b));
-    }
-    SolveOut sa;
-    solve_batch(ctx, o, B, b, w, sa);
     // D blocks per energy and the gradient contraction
     std::vector<int> base(nE + 1, 0);
     for (int k = 0; k < nb; ++k) base[B.e[k] + 1]++;
@@ -2319,10 +2320,10 @@ extern "C" iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opt
     HIPCHK(launch_grad(ctx, nE, base_d, dbase_d, Dd, u, w, (double*)dT_dV));
     stream_sync(ctx);
     *T_total = Ttot;
-    for (int k = 0; k < nb; ++k)
-      if (so.status[k] != IOBM_OK || sa.status[k] != IOBM_OK) {
-        ctx->err = "forward or adjoint solve did not converge";
-        return (iobm_status)(so.status[k] != IOBM_OK ? so.status[k] : sa.status[k]);
+    for (int k = 0; k < 2 * nb; ++k)
+      if (s2.status[k] != IOBM_OK) {
+        ctx->err = k < nb ? "forward solve did not converge" : "adjoint solve did not converge";
+        return (iobm_status)s2.status[k];
       }
   } catch (Fail& f) {
     return f.s;
