@@ -76,7 +76,7 @@ typedef enum {
                                converged ones are valid, per-RHS status in the stats */
   IOBM_E_BREAKDOWN = 6,     /* Krylov breakdown that restarts could not cure */
   IOBM_E_AT_THRESHOLD = 7,  /* energy within 1e-9 (relative) of a lateral channel threshold */
-  IOBM_E_UNSUPPORTED = 8    /* valid request this build does not implement */
+  IOBM_E_UNSUPPORTED = 8    /* valid request the library does not implement */
 } iobm_status;
 
 /* Grid: nx, ny >= 2 (lateral, periodic), nz >= 2*nf (planes of the transition
