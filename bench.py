@@ -478,7 +478,8 @@ def bloch_workload(args):
         s.smatrix_bloch(Es, kap, opts=opts)
         kern = {}
         for kname, cls in (("stencil_bloch", iobm.K_BLOCH_STENCIL), ("vector_bloch", iobm.K_BLOCH_VECTOR),
-                           ("precond_fft", iobm.K_PRECOND_FFT), ("boundary", iobm.K_BOUNDARY)):
+                           ("precond_fft", iobm.K_PRECOND_FFT), ("boundary", iobm.K_BOUNDARY),
+                           ("restart_residual", iobm.K_STENCIL_C128)):
             n, ms, b = s.profile_end(cls)
             if n:
                 kern[kname] = {"launches": n, "avg_ms": round(ms / n, 4), "total_ms": round(ms, 3),

@@ -89,9 +89,6 @@ hipError_t launch_block_update(iobm_ctx c, cplx<TY>* Y, const cplx<T>* X, const 
 
 // bloch.hip
 template <typename T>
-hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
-                              const double* E_rhs, const int* e_rhs, const int* sgn, const int* active);
-template <typename T>
 hipError_t launch_bloch_apply_fused(iobm_ctx c, const BlochPhase& ph, const BlochFuse<T>& F, cplx<T>* y, int nrhs,
                                     const double* E_rhs, const int* e_rhs, const int* sgn, const int* active);
 template <typename T>
@@ -105,9 +102,6 @@ hipError_t launch_bloch_scalars(iobm_ctx c, int mode, int npairs, const int* pai
 template <typename T>
 hipError_t launch_bloch_update(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const zd* alpha, int nslots,
                                const int* active, Partial* pn, int nblk);
-template <typename T>
-hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, cplx<T>* r, const zd* y, int nslots, const int* active,
-                              Partial* pn, int nblk);
 template <typename T>
 hipError_t launch_bloch_settle(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, int nslots,
                                const int* active, int nblk);
@@ -1176,12 +1170,14 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   cplx<T>* q = (cplx<T>*)workspace(ctx, S_Q, vb);
   cplx<T>* z = o.precond == IOBM_PC_NONE ? r : (cplx<T>*)workspace(ctx, S_Z, vb);
   cplx<T>* pf = o.precond == IOBM_PC_LATERAL_FFT ? (cplx<T>*)workspace(ctx, S_PF, vb) : nullptr;
-  // the correction and the FP64 operator image of x (complex128: x and q)
+  // the correction (complex128: x itself), and the FP64 face planes of a
+  // restart's residual (complex128: in q, which the next pass overwrites)
   cplx<T>* d = lowp ? (cplx<T>*)workspace(ctx, S_D, vb) : (cplx<T>*)x;
-  zd* yx = lowp ? (zd*)workspace(ctx, S_RHI, (size_t)ns * vol * sizeof(zd)) : (zd*)q;
+  zd* rface = lowp ? (zd*)workspace(ctx, S_RHI, (size_t)ns * vol * sizeof(zd)) : (zd*)q;
   const int nblk = dot_blocks(ctx);
   Partial* pd = (Partial*)workspace(ctx, S_PART, (size_t)np * nblk * sizeof(Partial));
   Partial* pn = (Partial*)workspace(ctx, S_PARTR, (size_t)ns * nblk * sizeof(Partial));
+  Partial* pq = (Partial*)workspace(ctx, S_PARTN, (size_t)ns * PQ_SLOTS * sizeof(Partial));
   char* sc = (char*)workspace(ctx, S_SCAL, (size_t)np * 3 * sizeof(zd) + (size_t)ns * sizeof(double) +
                                                   (size_t)np * sizeof(int) + 64);
   zd* rho = (zd*)sc;
@@ -1224,16 +1220,15 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
     else if (o.precond == IOBM_PC_JACOBI)
       HIPCHK(launch_precond_jacobi<T>(ctx, r, z, nsl, e_d, E_d, sl_d, nullptr));
   };
-  // x += d + alpha p, r = b - A x (complex128 operator), z = P r,
-  // rho = r~^T z, alpha = beta = 0 (the next pass takes p = z) for the listed
-  // pairs
+  // x += d + alpha p, r = b - A x (one complex128 operator pass that writes
+  // r in the iteration precision), z = P r, rho = r~^T z, alpha = beta = 0
+  // (the next pass takes p = z) for the listed pairs
   auto restart = [&](int npr) {
     HIPCHK(launch_bloch_settle<T>(ctx, x, dfold, pc, alpha, 2 * npr, sl_d, nblk));
-    HIPCHK(launch_bloch_apply<double>(ctx, ph, x, yx, 2 * npr, E_d, e_d, sg_d, sl_d));
-    HIPCHK(launch_bloch_resid<T>(ctx, b, r, yx, 2 * npr, sl_d, pn, nblk));
+    HIPCHK(launch_bloch_refresh<T>(ctx, ph, x, b, rface, r, 2 * npr, E_d, e_d, sg_d, sl_d, pq));
     precond(2 * npr);
     HIPCHK(launch_bloch_dot<T>(ctx, r, z, npr, pl_d, pd, nblk));
-    HIPCHK(launch_bloch_scalars(ctx, BL_RESTART, npr, pl_d, pd, pn, nblk, rho, alpha, beta, rn2, flag));
+    HIPCHK(launch_bloch_scalars(ctx, BL_RESTART, npr, pl_d, pd, pq, nblk, rho, alpha, beta, rn2, flag));
   };
   auto iterate = [&](int npr) {
     const BlochFuse<T> F{z, pc, po, d, beta, alpha, nfresh};

@@ -11,10 +11,10 @@
 // condition psi(r + L) = exp(i kappa L) psi(r) turns into a periodic u whose
 // lateral couplings carry a bond phase: the neighbour at +n along x enters
 // with exp(i n kappa_x h_x), the one at -n with its conjugate.  Only the
-// stencil (the 2.5D kernel with the OpBloch policy, and OpBlochFuse, which
-// also forms the direction and the pending correction of the pair iteration;
-// ops.hip) and Eq. (17) (this file) change; the diagonal (and so the Jacobi
-// preconditioner) does not.
+// stencil (the 2.5D kernel with the OpBlochFuse policy, which also forms
+// the direction and the pending correction of the pair iteration, and with
+// OpBlochRefresh for a restart's residual; ops.hip) and Eq. (17) (this file)
+// change; the diagonal (and so the Jacobi preconditioner) does not.
 //
 // Transpose.  A(kappa)^T = A(-kappa): the operator is not complex symmetric
 // for one kappa, so each state at +kappa is solved together with a partner
@@ -119,7 +119,9 @@ enum { BL_ALPHA = 0, BL_BETA = 1, BL_RESTART = 2 };
 // pair):
 //   BL_ALPHA:   mu = p~^T A p, alpha = rho / mu;
 //   BL_BETA:    rho' = r~^T z, beta = rho' / rho, rho = rho', |r|^2 of both slots;
-//   BL_RESTART: rho = r~^T z of a fresh residual, alpha = beta = 0, |r|^2.
+//   BL_RESTART: rho = r~^T z of a fresh residual, alpha = beta = 0, |r|^2
+//               (from the residual operator's partials, PQ_SLOTS per slot:
+//               the stencil chunks, then the two faces).
 // A vanishing or non-finite denominator sets flag[pair] (the host restarts
 // the pair from its true residual) and zeroes the step.
 __global__ void __launch_bounds__(64) k_bl_scalars(int mode, int npairs, const int* __restrict__ pairs,
@@ -146,7 +148,13 @@ __global__ void __launch_bounds__(64) k_bl_scalars(int mode, int npairs, const i
   }
   for (int sl = 0; sl < 2; ++sl) {
     double n = 0;
-    for (int b = 0; b < nblk; ++b) n += pn[(long long)(prim + sl) * nblk + b].n2;
+    if (mode == BL_RESTART) {
+      const Partial* q = pn + (long long)(prim + sl) * PQ_SLOTS;
+      for (int c = 0; c < PQ_STENCIL_MAX; ++c) n += q[c].n2;
+      n += q[PQ_BOUNDARY].n2 + q[PQ_BOUNDARY + 1].n2;
+    } else {
+      for (int b = 0; b < nblk; ++b) n += pn[(long long)(prim + sl) * nblk + b].n2;
+    }
     rn2[prim + sl] = n;
   }
   if (mode == BL_RESTART) {
@@ -195,32 +203,6 @@ __global__ void __launch_bounds__(256) k_bl_update(cplx<T>* __restrict__ r, cons
   }
 }
 
-// The true residual r = b - y (y = A x in FP64), stored in the iteration
-// precision, with the FP64 partials of |b - y|^2 in pn[slot][blk].
-template <typename T>
-__global__ void __launch_bounds__(256) k_bl_resid(const zd* __restrict__ b, cplx<T>* __restrict__ r,
-                                                  const zd* __restrict__ y, long long vol, int nblk,
-                                                  const int* __restrict__ active, Partial* __restrict__ pn) {
-  const int slot = blockIdx.x / nblk;
-  const int blk = blockIdx.x - slot * nblk;
-  const int rhs = bl_rhs(active, slot);
-  const long long per = (vol + nblk - 1) / nblk;
-  const long long i0 = blk * per, i1 = min(vol, i0 + per);
-  const long long o = (long long)rhs * vol;
-  double n2 = 0, d0 = 0, d1 = 0;
-  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const zd v = b[o + i] - y[o + i];
-    r[o + i] = cvt<T>(v);
-    n2 += v.re * v.re + v.im * v.im;
-  }
-  bl_reduce3(n2, d0, d1);
-  if (threadIdx.x == 0) {
-    Partial P;
-    P.re = 0; P.im = 0; P.n2 = n2; P.pad = 0;
-    pn[(long long)rhs * nblk + blk] = P;
-  }
-}
-
 // The pending correction folded into the FP64 solution: x += d + alpha p,
 // d = 0 (complex64; alpha of the slot's pair), or x += alpha p (complex128,
 // d == nullptr: the recurrence updates x itself).  p is not read where
@@ -252,15 +234,6 @@ __global__ void __launch_bounds__(256) k_bl_settle(zd* __restrict__ x, cplx<T>* 
 }  // namespace
 
 // =================================================================== host ===
-template <typename T>
-hipError_t launch_bloch_apply(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
-                              const double* E_rhs, const int* e_rhs, const int* sgn, const int* active) {
-  if (nrhs <= 0) return hipSuccess;
-  hipError_t err = launch_bloch_stencil<T>(c, ph, x, y, nrhs, E_rhs, sgn, active);
-  if (err != hipSuccess) return err;
-  return launch_face_sigma<T>(c, x, y, nrhs, e_rhs, active);
-}
-
 template <typename T>
 hipError_t launch_bloch_apply_fused(iobm_ctx c, const BlochPhase& ph, const BlochFuse<T>& F, cplx<T>* y, int nrhs,
                                     const double* E_rhs, const int* e_rhs, const int* sgn, const int* active) {
@@ -313,17 +286,6 @@ hipError_t launch_bloch_update(iobm_ctx c, cplx<T>* r, const cplx<T>* q, const z
 }
 
 template <typename T>
-hipError_t launch_bloch_resid(iobm_ctx c, const zd* b, cplx<T>* r, const zd* y, int nslots, const int* active,
-                              Partial* pn, int nblk) {
-  if (nslots <= 0) return hipSuccess;
-  const int rec = prof_start(c, IOBM_K_BLOCH_VECTOR);
-  hipLaunchKernelGGL(k_bl_resid<T>, dim3(nslots * nblk), dim3(256), 0, c->stream, b, r, y, c->g.npts, nblk, active,
-                     pn);
-  prof_stop(c, rec, nslots * c->g.npts * (2.0 * sizeof(zd) + sizeof(cplx<T>)));
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_bloch_settle(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, const zd* alpha, int nslots,
                                const int* active, int nblk) {
   if (nslots <= 0) return hipSuccess;
@@ -336,8 +298,6 @@ hipError_t launch_bloch_settle(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, 
 }
 
 #define IOBM_BLOCH_INST(T)                                                                                      \
-  template hipError_t launch_bloch_apply<T>(iobm_ctx, const BlochPhase&, const cplx<T>*, cplx<T>*, int,          \
-                                            const double*, const int*, const int*, const int*);                \
   template hipError_t launch_bloch_apply_fused<T>(iobm_ctx, const BlochPhase&, const BlochFuse<T>&, cplx<T>*, int, \
                                                   const double*, const int*, const int*, const int*);          \
   template hipError_t launch_bloch_laplacian<T>(iobm_ctx, const BlochPhase&, double, const cplx<T>*, cplx<T>*,   \
@@ -346,8 +306,6 @@ hipError_t launch_bloch_settle(iobm_ctx c, zd* x, cplx<T>* d, const cplx<T>* p, 
                                           int);                                                                 \
   template hipError_t launch_bloch_update<T>(iobm_ctx, cplx<T>*, const cplx<T>*, const zd*, int, const int*,     \
                                              Partial*, int);                                                    \
-  template hipError_t launch_bloch_resid<T>(iobm_ctx, const zd*, cplx<T>*, const zd*, int, const int*, Partial*, \
-                                            int);                                                               \
   template hipError_t launch_bloch_settle<T>(iobm_ctx, zd*, cplx<T>*, const cplx<T>*, const zd*, int,          \
                                              const int*, int);
 IOBM_BLOCH_INST(float)

@@ -212,16 +212,12 @@ template <typename T>
 hipError_t launch_precond_jacobi(iobm_ctx c, const cplx<T>* r, cplx<T>* z, int nrhs, const int* e_rhs,
                                  const double* E_rhs, const int* active, Partial* dpart = nullptr);
 hipError_t launch_sigma_diag(iobm_ctx c, int nE);  // sdiag_d from sig_d for the current table
-// y = A_st x with lateral bond phases (the gauge of a lateral Bloch vector):
-// the 2.5D stencil at the context's shape for the precision, else the
-// cache-based one; sgn[rhs] < 0 selects -kappa
-template <typename T>
-hipError_t launch_bloch_stencil(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
-                                const double* E_rhs, const int* sgn, const int* active);
-// The same with the pair iteration's direction update fused: y = A_st p_new
-// with p_new = z + beta p_old written to pnew, and the pending correction
-// d += alpha p_old (beta, alpha per pair; both zero after a restart, when
-// p_old and d are not read; d is the FP64 solution itself in complex128)
+// y = A_st p_new with lateral bond phases (the gauge of a lateral Bloch
+// vector; sgn[rhs] < 0 selects -kappa), with the pair iteration's direction
+// update fused: p_new = z + beta p_old written to pnew, and the pending
+// correction d += alpha p_old (beta, alpha per pair; both zero after a
+// restart, when p_old and d are not read; d is the FP64 solution itself in
+// complex128)
 template <typename T>
 struct BlochFuse {
   const cplx<T>* z;
@@ -235,6 +231,15 @@ struct BlochFuse {
 template <typename T>
 hipError_t launch_bloch_stencil_fused(iobm_ctx c, const BlochPhase& ph, const BlochFuse<T>& F, cplx<T>* y, int nrhs,
                                       const double* E_rhs, const int* sgn, const int* active);
+// The pair restart's true residual at a lateral Bloch vector: r = b - A x
+// from the FP64 solution with the phased stencil and the electrode term,
+// stored in the iteration precision TR (b supported on the 2 nf face planes;
+// rface holds the faces in FP64 on the way); |r|^2 partials per rhs in the
+// operator layout (stencil chunk slots and the two faces of PQ_SLOTS)
+template <typename TR>
+hipError_t launch_bloch_refresh(iobm_ctx c, const BlochPhase& ph, const zd* x, const zd* b, zd* rface, cplx<TR>* r,
+                                int nrhs, const double* E_rhs, const int* e_rhs, const int* sgn, const int* active,
+                                Partial* part);
 // y -= Sigma x on the 2 nf face planes, for the listed rhs
 template <typename T>
 hipError_t launch_face_sigma(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, const int* e_rhs, const int* active);

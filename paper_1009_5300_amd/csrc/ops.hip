@@ -105,43 +105,6 @@ struct OpPlain {  // y = A_st x
   __device__ __forceinline__ void finish(int, int, int) {}
 };
 
-// y = A_st x in the gauge u = exp(-i kappa.r) psi of a lateral Bloch vector:
-// the lateral neighbour at +n along a direction enters with the weight
-// times exp(i n kappa h), the one at -n with its conjugate; f[dir][n] holds
-// weight x phase for the rhs at +kappa, and the rhs at -kappa (sgn < 0)
-// take the conjugates.
-template <typename T>
-struct OpBloch {
-  typedef cplx<T> Raw;
-  static constexpr int lookahead = 2;
-  static constexpr bool bloch = true;
-  const cplx<T>* x;
-  cplx<T>* y;
-  const int* sgn;
-  cplx<T> f[2][4];
-  __device__ __forceinline__ void bind(int rhs, long long vol) {
-    x += rhs * vol;
-    y += rhs * vol;
-    if (sgn[rhs] < 0)
-#pragma unroll
-      for (int d = 0; d < 2; ++d)
-#pragma unroll
-        for (int n = 1; n < 4; ++n) f[d][n] = conj(f[d][n]);
-  }
-  __device__ __forceinline__ cplx<T> load(long long o) const { return x[o]; }
-  __device__ __forceinline__ Raw load_raw(long long o, bool) const { return x[o]; }
-  __device__ __forceinline__ cplx<T> combine(Raw r, bool ok) const { return ok ? r : mk<T>(0, 0); }
-  __device__ __forceinline__ void side(const Raw&, long long, bool) {}
-  __device__ __forceinline__ void center(long long, cplx<T>) {}
-  __device__ __forceinline__ void center_at(long long, cplx<T>) {}
-  __device__ __forceinline__ void store(int, long long o, cplx<T>, cplx<T> acc) { y[o] = acc; }
-  __device__ __forceinline__ void finish(int, int, int) {}
-  // coupling to the neighbours at +n and -n along direction dir (0 x, 1 y)
-  __device__ __forceinline__ cplx<T> lat(int dir, int n, cplx<T> ap, cplx<T> am) const {
-    return cfma(conj(f[dir][n]), am, f[dir][n] * ap);
-  }
-};
-
 // The number of z chunks of a launch depends on the batch size, so the
 // chunk-0 block of each rhs zeroes the stencil slots past the last chunk.
 __device__ __forceinline__ void clear_unused_slots(Partial* part, int rhs, int chunk, int nchunks) {
@@ -243,8 +206,11 @@ struct OpFuseP {
 // beta = 0 and no update is pending), written to pnew for the block's own
 // points, and the previous step's correction d += alpha p_old is applied to
 // the own points from the same p_old loads (d is the FP64 solution itself
-// in complex128).  beta and alpha are per pair (slot / 2); the lateral bond
-// phases are those of OpBloch.
+// in complex128).  beta and alpha are per pair (slot / 2).  Lateral
+// couplings in the gauge u = exp(-i kappa.r) psi: the neighbour at +n
+// along a direction enters with the weight times exp(i n kappa h), the one
+// at -n with its conjugate; f[dir][n] holds weight x phase for the rhs at
+// +kappa, and the rhs at -kappa (sgn < 0) take the conjugates.
 template <typename T>
 struct OpBlochFuse {
   // complex64 prefetches d with z and p; complex128 reads it when the plane
@@ -356,6 +322,27 @@ struct OpRefresh {
       part[(long long)rhs * PQ_SLOTS + chunk] = P;
     }
     clear_unused_slots(part, rhs, chunk, nchunks);
+  }
+};
+
+// The same residual at a lateral Bloch vector: the stencil in the gauge u
+// with the lateral bond phases of OpBlochFuse (weights times phases in f,
+// the rhs at -kappa, sgn < 0, taking the conjugates).
+template <typename TR>
+struct OpBlochRefresh : OpRefresh<TR> {
+  static constexpr bool bloch = true;
+  const int* sgn;
+  zd f[2][4];
+  __device__ __forceinline__ void bind(int rhs, long long vol) {
+    OpRefresh<TR>::bind(rhs, vol);
+    if (sgn[rhs] < 0)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int n = 1; n < 4; ++n) f[e][n] = conj(f[e][n]);
+  }
+  __device__ __forceinline__ zd lat(int dir, int n, zd ap, zd am) const {
+    return cfma(conj(f[dir][n]), am, f[dir][n] * ap);
   }
 };
 
@@ -1937,27 +1924,6 @@ static hipError_t launch_boundary(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx
 }
 
 template <typename T>
-hipError_t launch_bloch_stencil(iobm_ctx c, const BlochPhase& ph, const cplx<T>* x, cplx<T>* y, int nrhs,
-                                const double* E_rhs, const int* sgn, const int* active) {
-  if (nrhs <= 0) return hipSuccess;
-  const StencilArgs S = stencil_args(c, 16);
-  OpBloch<T> op;
-  op.x = x;
-  op.y = y;
-  op.sgn = sgn;
-  for (int n = 0; n < 4; ++n) {
-    op.f[0][n] = cvt<T>(S.wx[n] * ph.x[n]);
-    op.f[1][n] = cvt<T>(S.wy[n] * ph.y[n]);
-  }
-  // read x, write y
-  return launch_stencil<T, OpBloch<T>>(c, op, nrhs, E_rhs, active, 2.0 * sizeof(cplx<T>), IOBM_K_BLOCH_STENCIL);
-}
-template hipError_t launch_bloch_stencil<float>(iobm_ctx, const BlochPhase&, const zf*, zf*, int, const double*,
-                                                const int*, const int*);
-template hipError_t launch_bloch_stencil<double>(iobm_ctx, const BlochPhase&, const zd*, zd*, int, const double*,
-                                                 const int*, const int*);
-
-template <typename T>
 hipError_t launch_bloch_stencil_fused(iobm_ctx c, const BlochPhase& ph, const BlochFuse<T>& F, cplx<T>* y, int nrhs,
                                       const double* E_rhs, const int* sgn, const int* active) {
   if (nrhs <= 0) return hipSuccess;
@@ -2045,6 +2011,35 @@ template hipError_t launch_refresh<float>(iobm_ctx, const zd*, const zd*, zd*, z
                                           const ModeData*, const int*, Partial*);
 template hipError_t launch_refresh<double>(iobm_ctx, const zd*, const zd*, zd*, zd*, int, const double*, const int*,
                                            const ModeData*, const int*, Partial*);
+
+template <typename TR>
+hipError_t launch_bloch_refresh(iobm_ctx c, const BlochPhase& ph, const zd* x, const zd* b, zd* rface, cplx<TR>* r,
+                                int nrhs, const double* E_rhs, const int* e_rhs, const int* sgn, const int* active,
+                                Partial* part) {
+  if (nrhs <= 0) return hipSuccess;
+  const StencilArgs S = stencil_args(c, 16);
+  OpBlochRefresh<TR> op;
+  op.x = x;
+  op.b = b;
+  op.rface = rface;
+  op.r = r;
+  op.part = part;
+  op.nz = c->g.nz;
+  op.nf = c->g.nf;
+  op.nxy = c->g.nxy;
+  op.sgn = sgn;
+  for (int n = 0; n < 4; ++n) {
+    op.f[0][n] = S.wx[n] * ph.x[n];
+    op.f[1][n] = S.wy[n] * ph.y[n];
+  }
+  hipError_t err = launch_stencil<double>(c, op, nrhs, E_rhs, active, (double)sizeof(zd) + sizeof(cplx<TR>));
+  if (err != hipSuccess) return err;
+  return launch_boundary<double, TR>(c, x, rface, r, nrhs, e_rhs, c->modes_d, active, part);
+}
+template hipError_t launch_bloch_refresh<float>(iobm_ctx, const BlochPhase&, const zd*, const zd*, zd*, zf*, int,
+                                                const double*, const int*, const int*, const int*, Partial*);
+template hipError_t launch_bloch_refresh<double>(iobm_ctx, const BlochPhase&, const zd*, const zd*, zd*, zd*, int,
+                                                 const double*, const int*, const int*, const int*, Partial*);
 
 template <typename T>
 hipError_t launch_precond_laplacian(iobm_ctx c, double alpha, const cplx<T>* r, cplx<T>* z, int nrhs,
