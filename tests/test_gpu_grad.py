@@ -59,6 +59,23 @@ def test_gradient_matches_oracle_adjoint_and_fd(torch, precision):
     s.set_potential(w.V)
 
 
+def test_gradient_with_block_cocg(torch):
+    """Block COCG per energy in the gradient: the forward and the adjoint
+    states of one energy form two groups of the combined batch; against the
+    oracle's LU adjoint."""
+    from paper_1009_5300_amd import iobm
+    w = make(5, Grid(12, 12, 32, 0.4, 2))
+    g = w.grid
+    Es = [0.2, 0.55]
+    s = iobm.Solver(g.nx, g.ny, g.nz, g.spacings, g.nf)
+    s.set_potential(w.V)
+    T, dT = s.grad_transmission(Es, iobm.default_opts(precision=iobm.C128, block=1, tol=1e-11))
+    dT = dT.cpu().numpy()
+    T_ref, g_ref = O.total_transmission_and_gradient(O.Problem(g, w.V), Es)
+    assert abs(T - T_ref) <= 1e-6
+    assert np.abs(dT - g_ref).max() <= 1e-4 * np.abs(g_ref).max()
+
+
 def test_autograd_function(torch):
     from paper_1009_5300_amd import iobm
     from paper_1009_5300_amd.autograd import transmission
