@@ -31,10 +31,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # HBM traffic of the dominant kernel, measured with rocprofv3 counters
 # (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy kernel), kept with
-# the git blob ids of the sources it was measured on
+# the git blob ids of the sources it was measured on: the kernels, and the
+# solver driver, whose iteration schedule sets the sizes of the launches
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
 KERNEL_SOURCES = ["paper_1009_5300_amd/csrc/ops.hip", "paper_1009_5300_amd/csrc/common.h",
-                  "paper_1009_5300_amd/csrc/internal.h"]
+                  "paper_1009_5300_amd/csrc/internal.h", "paper_1009_5300_amd/csrc/api.hip"]
 
 
 def _blob_id(path):
@@ -43,9 +44,12 @@ def _blob_id(path):
     return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
 
 
-def _measured_traffic(kernel):
+def _measured_traffic(kernel, launches_per_solve=None):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None if there is none or the kernel sources changed since."""
+    or None if there is none or the kernel sources changed since.  A record
+    taken per solve is divided by `launches_per_solve`: the residual-driven
+    check schedule may split one solve's iterations into a different number
+    of launches from run to run, while the bytes per solve stay put."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = {}
@@ -60,6 +64,10 @@ def _measured_traffic(kernel):
         if rec.get("blob " + src) != _blob_id(src):
             return None
     try:
+        if "hbm_bytes_per_solve" in rec:
+            if not launches_per_solve:
+                return None
+            return float(rec["hbm_bytes_per_solve"]) / launches_per_solve
         return float(rec["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -614,7 +622,7 @@ def main():
     dom = kern[dom_name]
     roofline = {"bound": "hbm", "achieved": round(dom["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(dom["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                "traffic": _measured_traffic(dom_name), "kernel": dom_name,
+                "traffic": _measured_traffic(dom_name, dom["launches"] / args.steps), "kernel": dom_name,
                 "avg_launch_ms": round(dom["avg_ms"], 4),
                 "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
     st = kern["stencil"]

@@ -112,7 +112,13 @@ typedef struct {
                           this factor; default 1e-3 */
   int32_t max_iter;    /* total COCG iterations per RHS; default 50000 */
   int32_t side;        /* 0: incidence from the left electrode, 1: from the right */
-  int32_t check_every; /* iterations between host convergence checks; default 2 */
+  int32_t check_every; /* iterations between host convergence checks; default 0:
+                          scheduled, 1 to 4 iterations ahead, from the decay of
+                          each active residual towards its replacement or
+                          stopping threshold, weighing the iterations that
+                          states would run past it against the cost of a check
+                          (2 under graph capture and in block COCG, 1 in
+                          iobm_smatrix_bloch) */
   int32_t keep_direction; /* at a residual replacement: 0 = restart the search
                           direction (p = z; default), 1 = keep it (the
                           recurrence continues from the replaced residual; it

@@ -426,7 +426,15 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   const bool lowp = sizeof(T) == sizeof(float);
   const double tol2 = o.tol * o.tol;
   const double delta2 = lowp ? o.inner_tol * o.inner_tol : 0.0;
-  const int check = std::max(1, o.check_every);
+  // iterations per host check: fixed, or (check_every = 0, launched path)
+  // scheduled from the observed decay of each active residual, between 1
+  // and kMaxCheck (below)
+  const bool graphs = o.graph != 0 && ctx->prof_mask == 0;
+  const bool adapt = o.check_every == 0 && !graphs;
+  constexpr int kMaxCheck = 4;
+  constexpr double kCheckSeconds = 1e-4;          // a host check's round trip (measured: 50-120 us)
+  constexpr double kStreamBytesPerSecond = 5e12;  // what the iteration's kernels stream (measured: 4.6-5.7 TB/s)
+  int check = o.check_every > 0 ? o.check_every : (adapt ? 1 : 2);
   // keeping the direction across replacements diverged with the
   // lateral-Fourier preconditioner (measured): it always restarts there
   const bool keep_dir = o.keep_direction != 0 && o.precond != IOBM_PC_LATERAL_FFT;
@@ -500,6 +508,11 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   std::vector<int> stall(nb, 0);
   for (int i = 0; i < nb; ++i) maxr2[i] = best[i] = last[i] = bn2[i];
   tn2_h = bn2;
+  // check schedule: |r|^2 at the last observation (a check, or the true
+  // residual of a refresh), the iterations since, and the per-iteration
+  // decay log(|r|^2) of the last observed stretch (0: none yet)
+  std::vector<double> obs_r2(bn2), decay(nb, 0.0);
+  std::vector<int> obs_it(nb, 0);
   if (act.empty()) return;
   int nact = (int)act.size();
   int* act_d = upload(ctx, S_IDX, act, 64 * 1024);
@@ -525,7 +538,6 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
   //   precond:   z = P r, partials of r^T z
   // with the scalar steps (alpha; beta, rho, |r|^2) in between.
   // one check's iterations, launched one by one or captured into a graph
-  const bool graphs = o.graph != 0 && ctx->prof_mask == 0;
   CheckGraph cg;
   auto enqueue_check = [&]() {
     for (int k = 0; k < check; ++k) {
@@ -603,51 +615,84 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     for (int i : act) {
       out.iters[i] += check;
       const double r2 = rn2_h[i];
+      obs_it[i] += check;
+      if (r2 > 0 && obs_r2[i] > 0 && r2 == r2) decay[i] = log(r2 / obs_r2[i]) / obs_it[i];
+      obs_r2[i] = r2;
+      obs_it[i] = 0;
       const bool bad = flag_h[i] || !(r2 == r2) || r2 > 1e4 * maxr2[i];  // breakdown or divergence
       badv[i] = bad;
       if (bad || r2 <= 0.25 * tol2 * bn2[i] || r2 <= delta2 * maxr2[i] || out.iters[i] >= o.max_iter)
         upd.push_back(i);
       else maxr2[i] = std::max(maxr2[i], r2);
     }
-    if (upd.empty()) continue;
-    refresh(upd, 7);
-    std::vector<int> rst, keep;  // updated rhs that go on iterating: from a restart / with the old direction
-    for (int i : upd) {
-      out.refin[i] += 1;
-      const double t2 = tn2_h[i];
-      if (t2 <= tol2 * bn2[i]) continue;  // converged
-      if (out.iters[i] >= o.max_iter) { out.status[i] = IOBM_E_NOT_CONVERGED; continue; }
-      const bool improved = t2 < best[i];
-      if (t2 < 0.25 * best[i]) { best[i] = t2; stall[i] = 0; }
-      else if (++stall[i] >= 6) {
-        out.status[i] = flag_h[i] ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
-        continue;
+    if (!upd.empty()) {
+      refresh(upd, 7);
+      std::vector<int> rst, keep;  // updated rhs that go on iterating: from a restart / with the old direction
+      for (int i : upd) {
+        out.refin[i] += 1;
+        const double t2 = tn2_h[i];
+        if (t2 <= tol2 * bn2[i]) continue;  // converged
+        if (out.iters[i] >= o.max_iter) { out.status[i] = IOBM_E_NOT_CONVERGED; continue; }
+        const bool improved = t2 < best[i];
+        if (t2 < 0.25 * best[i]) { best[i] = t2; stall[i] = 0; }
+        else if (++stall[i] >= 6) {
+          out.status[i] = flag_h[i] ? IOBM_E_BREAKDOWN : IOBM_E_NOT_CONVERGED;
+          continue;
+        }
+        (keep_dir && !badv[i] && improved && since[i] > 0 ? keep : rst).push_back(i);
+        maxr2[i] = t2;
       }
-      (keep_dir && !badv[i] && improved && since[i] > 0 ? keep : rst).push_back(i);
-      maxr2[i] = t2;
+      std::vector<char> gone(nb, 0);
+      for (int i : upd) gone[i] = 1;
+      for (int i : rst) gone[i] = 0;
+      for (int i : keep) gone[i] = 0;
+      std::vector<int> lists(rst);  // one upload: [restarted rhs | kept rhs | new active list]
+      lists.insert(lists.end(), keep.begin(), keep.end());
+      for (int i : act)
+        if (!gone[i]) lists.push_back(i);
+      const int nr = (int)rst.size(), nk = (int)keep.size(), nc = nr + nk;
+      int* ld = upload(ctx, S_IDX, lists, 64 * 1024);
+      if (nc > 0) {
+        // z = P r of the replaced residual, rho = r^T z; a restart sets beta = 0
+        // (p_new = z next), a kept direction beta = rho' / rho (p_new = z + beta p)
+        precond(nc, ld);
+        if (nr) HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nr, ld));
+        if (nk) HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_KEEP, nk, ld + nr));
+      }
+      act.assign(lists.begin() + nc, lists.end());
+      nact = (int)act.size();
+      act_d = ld + nc;  // the old list's region was rewritten
+      for (int i : rst) { since[i] = 0; kept[i] = 0; }
+      for (int i : keep) { since[i] = 0; kept[i] = 1; }
+      for (int i : upd) obs_r2[i] = tn2_h[i];  // the true residual restarts the observation
     }
-    std::vector<char> gone(nb, 0);
-    for (int i : upd) gone[i] = 1;
-    for (int i : rst) gone[i] = 0;
-    for (int i : keep) gone[i] = 0;
-    std::vector<int> lists(rst);  // one upload: [restarted rhs | kept rhs | new active list]
-    lists.insert(lists.end(), keep.begin(), keep.end());
-    for (int i : act)
-      if (!gone[i]) lists.push_back(i);
-    const int nr = (int)rst.size(), nk = (int)keep.size(), nc = nr + nk;
-    int* ld = upload(ctx, S_IDX, lists, 64 * 1024);
-    if (nc > 0) {
-      // z = P r of the replaced residual, rho = r^T z; a restart sets beta = 0
-      // (p_new = z next), a kept direction beta = rho' / rho (p_new = z + beta p)
-      precond(nc, ld);
-      if (nr) HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_RESTART, nr, ld));
-      if (nk) HIPCHK(launch_finish2(ctx, rho, alpha, beta, rn2, flag, part_rz, nz_slots, nullptr, 0, FIN_KEEP, nk, ld + nr));
+    if (adapt && nact > 0) {
+      // Each active residual is predicted to reach its replacement or
+      // stopping threshold after n_i more iterations (1 while it has no
+      // observed decay yet, never while it grows).  A check after c
+      // iterations costs a host round trip, s iterations' worth of the
+      // batch's streaming; a rhs that passes its threshold before the check
+      // runs c - n_i iterations that only its own share of the batch pays.
+      // c in 1..kMaxCheck maximises the useful iterations per unit time,
+      // (c - W(c)) / (c + s) with W(c) = mean over rhs of max(0, c - n_i).
+      std::vector<int> hist(kMaxCheck + 1, 0);  // rhs with n_i = 1 .. kMaxCheck (and beyond)
+      for (int i : act) {
+        const double target = std::max(0.25 * tol2 * bn2[i], delta2 * maxr2[i]);
+        int n = kMaxCheck;
+        if (decay[i] == 0.0 || (decay[i] < 0.0 && obs_r2[i] <= target)) n = 1;
+        else if (decay[i] < 0.0) n = (int)std::min<double>(kMaxCheck, ceil(log(target / obs_r2[i]) / decay[i]));
+        hist[std::max(1, std::min(kMaxCheck, n))]++;
+      }
+      const double it_bytes = (lowp ? 112.0 : 224.0) * nact * (double)vol;  // one iteration's vector streams
+      const double s_rel = kCheckSeconds / (it_bytes / kStreamBytesPerSecond);
+      double best_rate = -1;
+      for (int c = 1; c <= kMaxCheck; ++c) {
+        double waste = 0;
+        for (int n = 1; n < c; ++n) waste += (double)hist[n] * (c - n);
+        const double rate = (c - waste / nact) / (c + s_rel);
+        if (rate > best_rate) { best_rate = rate; check = c; }
+      }
     }
-    act.assign(lists.begin() + nc, lists.end());
-    nact = (int)act.size();
-    act_d = ld + nc;  // the old list's region was rewritten
-    for (int i : rst) { since[i] = 0; kept[i] = 0; }
-    for (int i : keep) { since[i] = 0; kept[i] = 1; }
   }
   for (int i = 0; i < nb; ++i) {
     out.rel[i] = bn2[i] > 0 ? sqrt(tn2_h[i] / bn2[i]) : 0.0;
@@ -761,7 +806,7 @@ void solve_block_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, c
   const bool lowp = sizeof(T) == sizeof(float);
   const double tol2 = o.tol * o.tol;
   const double delta2 = lowp ? o.inner_tol * o.inner_tol : 0.0;
-  const int check = std::max(1, o.check_every);
+  const int check = o.check_every > 0 ? o.check_every : 2;  // 0 (scheduled checks): every 2 iterations here
 
   auto precond = [&](int n, const int* ld) {
     if (o.precond == IOBM_PC_TRUNCATED_LAPLACIAN) HIPCHK(launch_precond_laplacian<T>(ctx, o.alpha, r, z, n, ld));
@@ -983,10 +1028,10 @@ void validate_opts(iobm_ctx ctx, const iobm_solve_opts* o) {
     ctx->err = "unknown preconditioner"; throw Fail{IOBM_E_INVALID_ARG};
   }
   if (!(o->tol > 0 && o->tol < 1) || !(o->inner_tol > 0 && o->inner_tol < 1) || o->max_iter < 1 ||
-      o->check_every < 1 || (o->keep_direction != 0 && o->keep_direction != 1) || (o->graph != 0 && o->graph != 1) || (o->block != 0 && o->block != 1) ||
+      o->check_every < 0 || (o->keep_direction != 0 && o->keep_direction != 1) || (o->graph != 0 && o->graph != 1) || (o->block != 0 && o->block != 1) ||
       (o->side != 0 && o->side != 1) || !(o->alpha > 0) || !isfinite(o->alpha)) {
-    ctx->err = "invalid solver option (tol, inner_tol in (0,1), max_iter >= 1, side 0/1, keep_direction 0/1, graph 0/1, "
-               "block 0/1, alpha > 0)";
+    ctx->err = "invalid solver option (tol, inner_tol in (0,1), max_iter >= 1, check_every >= 0, side 0/1, "
+               "keep_direction 0/1, graph 0/1, block 0/1, alpha > 0)";
     throw Fail{IOBM_E_INVALID_ARG};
   }
 }
@@ -1191,7 +1236,7 @@ void solve_pair_batch(iobm_ctx ctx, const iobm_solve_opts& o, const BlochPhase& 
   const int* flag_h = (const int*)(rbh + (size_t)ns * sizeof(double));
   const double tol2 = o.tol * o.tol;
   const double delta2 = lowp ? o.inner_tol * o.inner_tol : 0.0;
-  const int check = std::max(1, o.check_every);
+  const int check = o.check_every > 0 ? o.check_every : 1;  // 0 (scheduled checks): every iteration here
   HIPCHK(hipMemsetAsync(x, 0, (size_t)ns * vol * sizeof(zd), ctx->stream));
   if (lowp) HIPCHK(hipMemsetAsync(d, 0, vb, ctx->stream));
   // rho, alpha, beta: nothing pending before the first restart
@@ -1386,7 +1431,7 @@ void iobm_default_opts(iobm_solve_opts* o) {
   o->inner_tol = 1e-3;
   o->max_iter = 50000;
   o->side = 0;
-  o->check_every = 2;
+  o->check_every = 0;
   o->keep_direction = 0;
   o->graph = 0;
   o->block = 0;

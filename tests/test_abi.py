@@ -49,7 +49,7 @@ def test_status_strings_and_default_opts(lib):
     o = iobm.default_opts()
     assert o.precision == iobm.C64_REFINED and o.precond == iobm.PC_LATERAL_FFT
     assert o.tol == 1e-10 and abs(o.alpha - 1.8) < 1e-15 and o.max_iter == 50000
-    assert o.inner_tol == 1e-3 and o.check_every == 2 and o.keep_direction == 0 and o.graph == 0 and o.block == 0
+    assert o.inner_tol == 1e-3 and o.check_every == 0 and o.keep_direction == 0 and o.graph == 0 and o.block == 0
 
 
 @pytest.mark.parametrize("bad", [dict(nf=0), dict(nf=4), dict(nx=1), dict(nz=3), dict(hx=0.0),

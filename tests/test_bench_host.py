@@ -38,3 +38,6 @@ def test_traffic_record_is_dropped_when_sources_change(tmp_path, monkeypatch):
     assert bench._measured_traffic("stencil") is None  # another kernel
     rec.write_text(f"kernel_class = fft_planes\nhbm_bytes_per_launch = 123\nblob {src} = {'0' * 40}\n")
     assert bench._measured_traffic("fft_planes") is None  # stale record
+    rec.write_text(f"kernel_class = fft_planes\nhbm_bytes_per_solve = 300\nblob {src} = {good}\n")
+    assert bench._measured_traffic("fft_planes", 15) == 20.0  # per-solve record, per launch
+    assert bench._measured_traffic("fft_planes") is None  # no launch count to divide by
