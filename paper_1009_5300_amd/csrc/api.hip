@@ -524,7 +524,8 @@ void solve_rhs_batch(iobm_ctx ctx, const iobm_solve_opts& o, const Batch& B, con
     HIPCHK(hipMemsetAsync(beta, 0x3F, nb * sizeof(zd), ctx->stream));
     HIPCHK(hipMemsetAsync(alpha, 0x3F, nb * sizeof(zd), ctx->stream));  // d += alpha * 0 leaves d = 0
     ApplyFuse<T> TF{r, pa, beta, pb, part_pq, alpha, d, dlive};
-    autotune<T>(ctx, r, q, pf, nact, E_d, e_d, modes, act_d, &TF);
+    autotune<T>(ctx, r, q, pf, nact, E_d, e_d, modes, act_d, &TF,
+                o.precond == IOBM_PC_LATERAL_FFT ? part_rz : nullptr);
     HIPCHK(hipMemsetAsync(part_pq, 0, (size_t)nb * PQ_SLOTS * sizeof(Partial), ctx->stream));
   }
   precond(nact, act_d);
@@ -1527,6 +1528,32 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
     HIPCHK(hipMemcpy(ctx->twy_d, ty.data(), g->ny * sizeof(zd), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->twx_f, fx.data(), g->nx * sizeof(zf), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->twy_f, fy.data(), g->ny * sizeof(zf), hipMemcpyHostToDevice));
+    {
+      // z-filter lane map: every lateral mode k = (ix, iy) of the natural
+      // FFT order beside its partner -k = ((nx - ix) mod nx, (ny - iy) mod ny),
+      // 32 pairs per block; self-paired modes (k = -k) two to a pair, flagged
+      const int nx = g->nx, ny = g->ny, nxy = nx * ny;
+      std::vector<std::pair<int, int>> pairs;
+      std::vector<int> selfp;
+      for (int m = 0; m < nxy; ++m) {
+        const int ix = m % nx, iy = m / nx;
+        const int pm = ((ny - iy) % ny) * nx + (nx - ix) % nx;
+        if (pm == m) selfp.push_back(m);
+        else if (m < pm) pairs.push_back({m, pm});
+      }
+      constexpr int kSelf = 1 << 30;
+      for (size_t i = 0; i < selfp.size(); i += 2)
+        pairs.push_back({selfp[i] | kSelf, i + 1 < selfp.size() ? (selfp[i + 1] | kSelf) : -1});
+      const int nmb = (int)((pairs.size() + 31) / 32);
+      std::vector<int> map((size_t)nmb * 64, -1);
+      for (size_t j = 0; j < pairs.size(); ++j) {
+        map[(j / 32) * 64 + j % 32] = pairs[j].first;
+        map[(j / 32) * 64 + 32 + j % 32] = pairs[j].second;
+      }
+      HIPCHK(hipMalloc(&ctx->zpair_d, map.size() * sizeof(int)));
+      HIPCHK(hipMemcpy(ctx->zpair_d, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice));
+      ctx->zpair_nmb = nmb;
+    }
     HIPCHK(hipMalloc(&ctx->arena_d, kRegion * kRegions));
     HIPCHK(hipHostMalloc(&ctx->arena_h, kRegion * kRegions, hipHostMallocDefault));
     HIPCHK(hipMalloc(&ctx->V_d, ctx->g.npts * sizeof(double)));
@@ -1583,6 +1610,7 @@ iobm_status iobm_set_launch_shape(iobm_ctx ctx, int32_t precision, const iobm_la
   if (!shape) {  // unpin: the next solve in this precision tunes again
     ctx->shape[p] = iobm_launch_shape{};
     ctx->tuned[p] = ctx->pinned[p] = false;
+    ctx->zdot[p] = 0;
     return IOBM_OK;
   }
   std::string why;
@@ -1592,6 +1620,7 @@ iobm_status iobm_set_launch_shape(iobm_ctx ctx, int32_t precision, const iobm_la
   if (!launch_shape_valid(ctx, p, *shape, why)) return fail(ctx, IOBM_E_UNSUPPORTED, why);
   ctx->shape[p] = *shape;
   ctx->tuned[p] = ctx->pinned[p] = true;
+  ctx->zdot[p] = 0;
   return IOBM_OK;
 }
 
@@ -1604,7 +1633,7 @@ iobm_status iobm_destroy(iobm_ctx ctx) {
   else (void)hipDeviceSynchronize();
   for (auto& e : ctx->pool)
     if (e.first) (void)hipFree(e.first);
-  void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->V_d, ctx->V_f, ctx->modes_d, ctx->sig_d,
+  void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->zpair_d, ctx->V_d, ctx->V_f, ctx->modes_d, ctx->sig_d,
                   ctx->sig_f, ctx->mode_flags_d, ctx->sdiag_d,
                   ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.Btd, ctx->kb.Btf, ctx->kb.ctile, ctx->kb.prange,
                   ctx->kb.hD, ctx->kb.diag_d, ctx->arena_d};

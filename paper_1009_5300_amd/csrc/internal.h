@@ -73,6 +73,11 @@ struct iobm_ctx_s {
   zd* twy_d = nullptr;
   zf* twx_f = nullptr;
   zf* twy_f = nullptr;
+  // lane map of the z filter's paired layout (block b: 32 lateral modes in
+  // lanes 0..31, their partners -k in lanes 32..63; -1 = no mode; bit 30 =
+  // the mode is its own partner), zpair_nmb blocks per rhs
+  int* zpair_d = nullptr;
+  int zpair_nmb = 0;
   double* V_d = nullptr;
   float* V_f = nullptr;
   bool have_V = false;
@@ -104,6 +109,10 @@ struct iobm_ctx_s {
   iobm_launch_shape shape[2] = {};
   bool tuned[2] = {false, false};
   bool pinned[2] = {false, false};
+  // where the lateral-Fourier preconditioner takes r^T z on square planes:
+  // 0 in the z filter (paired layout; the default), 1 in the inverse
+  // transform (the autotuner's choice where that composition timed faster)
+  int zdot[2] = {0, 0};
   // kernel timing hook
   int prof_mask = 0;
   std::vector<hipEvent_t> prof_ev;  // start/stop pairs
@@ -274,7 +283,8 @@ hipError_t launch_kb_apply(iobm_ctx c, const cplx<T>* x, cplx<T>* y, int nrhs, P
 // context and precision, unless a shape is pinned.
 template <typename T>
 void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
-              const int* e_rhs, const ModeData* modes, const int* active, const ApplyFuse<T>* fuse = nullptr);
+              const int* e_rhs, const ModeData* modes, const int* active, const ApplyFuse<T>* fuse = nullptr,
+              Partial* rz_part = nullptr);
 size_t kb_proj_bytes(iobm_ctx c, int nrhs);
 // Launch-shape rules (ops.hip): whether a pinned shape is admissible for
 // this grid, and the shape in effect (pinned, tuned or the default rule).

@@ -1267,17 +1267,36 @@ __device__ void state_power(const cplx<T>* al, int nf, int n, cplx<T>* P) {
   for (int i = 0; i < 9; ++i) P[i] = R[i];
 }
 
-template <typename T, int L, int NF>
-__global__ void __launch_bounds__(512) k_zfilter(int nz, int nf_unused, int nxy, const cplx<T>* __restrict__ in,
+//
+// With DOT (the preconditioner inside COCG), block b takes its 64 modes from
+// the lane map zmap: 32 modes k in lanes 0..31 and their partners -k in
+// lanes 32..63, so that one wavefront holds both factors of the bilinear
+// form in mode space (Parseval, with R = in and Z = out in natural FFT order)
+//   sum_x r(x) z(x) = dscale * sum_k sum_z R(-k, z) Z(k, z),   dscale = 1 / Nxy,
+// the partner's output coming from lane t ^ 32 (a mode that is its own
+// partner uses its own).  The block's partial goes to dpart[rhs][b], and
+// block 0 clears slots [nmb, nz) of its rhs, so that the nz slots per rhs
+// read by the scalar step sum to the form.  This spares the inverse
+// transform a read of R.
+template <typename T, int L, int NF, bool DOT>
+__global__ void __launch_bounds__(512) k_zfilter(int nz, int nmb, int nxy, const cplx<T>* __restrict__ in,
                                                   cplx<T>* __restrict__ out, const ModeData* __restrict__ modes,
-                                                  const int* __restrict__ e_rhs, const int* __restrict__ active) {
+                                                  const int* __restrict__ e_rhs, const int* __restrict__ active,
+                                                  const int* __restrict__ zmap, Partial* __restrict__ dpart,
+                                                  double dscale) {
   extern __shared__ char smem_raw[];
   const int C = blockDim.y;
   cplx<T>* sc = reinterpret_cast<cplx<T>*>(smem_raw);  // [C][64][3] causal end states
   cplx<T>* sb = sc + (size_t)C * 64 * 3;                // [C][64][3] anti-causal begin states
-  const int nmb = (nxy + 63) / 64;
   const int slot = blockIdx.x / nmb;
-  const int m = (blockIdx.x - slot * nmb) * 64 + threadIdx.x;
+  const int mb = blockIdx.x - slot * nmb;
+  int m = mb * 64 + threadIdx.x;
+  bool self = false;
+  if constexpr (DOT) {
+    const int e = zmap[mb * 64 + threadIdx.x];
+    m = e < 0 ? nxy : (e & ~(1 << 30));
+    self = e >= 0 && (e & (1 << 30)) != 0;
+  }
   // one wavefront per chunk: the chunk index (and every plane offset below)
   // is wave-uniform, which keeps the load addresses in scalar registers
   const int c = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -1363,7 +1382,9 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nf_unused, int nxy,
     }
   }
   __syncthreads();
-  if (!live) return;
+  // (with DOT every lane stays for the exchange and the reduction below; a
+  // lane without a mode carries zero coefficients and stores nothing)
+  if (!DOT && !live) return;
   // homogeneous responses to the true incoming states
   if (c > 0) {
     const cplx<T>* S = sc + ((c - 1) * 64 + threadIdx.x) * 3;
@@ -1396,6 +1417,48 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nf_unused, int nxy,
       h0 = B;
       y[i] = y[i] + B;
     }
+  }
+  if constexpr (DOT) {
+    double a = 0, b = 0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      cplx<T> zp;
+      zp.re = __shfl_xor(y[i].re, 32);
+      zp.im = __shfl_xor(y[i].im, 32);
+      if (self) zp = y[i];
+      const cplx<T> rv = rr[i + 2];  // R(k, z0 + i); zero past nz and on lanes without a mode
+      a += (double)rv.re * zp.re - (double)rv.im * zp.im;
+      b += (double)rv.re * zp.im + (double)rv.im * zp.re;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o);
+      b += __shfl_xor(b, o);
+    }
+    double* red = reinterpret_cast<double*>(sb + (size_t)C * 64 * 3);  // [C][2]
+    if (threadIdx.x == 0) {
+      red[2 * c] = a;
+      red[2 * c + 1] = b;
+    }
+    __syncthreads();
+    if (c == 0) {
+      if (threadIdx.x == 0) {
+        double sa = 0, sb2 = 0;
+        for (int cc = 0; cc < C; ++cc) {
+          sa += red[2 * cc];
+          sb2 += red[2 * cc + 1];
+        }
+        Partial P;
+        P.re = dscale * sa; P.im = dscale * sb2; P.n2 = 0; P.pad = 0;
+        dpart[(long long)rhs * nz + mb] = P;
+      }
+      if (mb == 0) {
+        Partial Z;
+        Z.re = Z.im = Z.n2 = Z.pad = 0;
+        for (int k = nmb + threadIdx.x; k < nz; k += 64) dpart[(long long)rhs * nz + k] = Z;
+      }
+    }
+    if (!live) return;
   }
 #pragma unroll
   for (int i = 0; i < L; ++i)
@@ -2147,17 +2210,24 @@ hipError_t launch_fft_planes(iobm_ctx c, const cplx<T>* in, cplx<T>* out, int si
 }
 
 // chunk length of the z filter (tuned per context and precision)
+// With dpart (requires zfilter_dot_ok), the paired layout and the partials of
+// the bilinear form r^T z, dpart[rhs][0..nz).
 template <typename T>
 static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* out, int nrhs, const int* e_rhs,
-                                 const ModeData* modes, const int* active) {
+                                 const ModeData* modes, const int* active, Partial* dpart = nullptr) {
   const int nxy = c->g.nxy, nz = c->g.nz;
-  const int nmb = (nxy + 63) / 64;
+  const bool dot = dpart != nullptr;
+  const int nmb = dot ? c->zpair_nmb : (nxy + 63) / 64;
   const int C = (nz + L - 1) / L;
-  size_t sh = 2 * (size_t)C * 64 * 3 * sizeof(cplx<T>);
+  size_t sh = 2 * (size_t)C * 64 * 3 * sizeof(cplx<T>) + (dot ? 2 * (size_t)C * sizeof(double) : 0);
+  const double dscale = 1.0 / nxy;
   const int rec = prof_start(c, IOBM_K_ZFILTER);
-#define IOBM_ZF2(LL, NFF)                                                                                  \
-  hipLaunchKernelGGL((k_zfilter<T, LL, NFF>), dim3(nrhs * nmb), dim3(64, C), sh, c->stream, nz, c->g.nf, nxy, in, \
-                     out, modes, e_rhs, active)
+#define IOBM_ZF3(LL, NFF, DD)                                                                                     \
+  hipLaunchKernelGGL((k_zfilter<T, LL, NFF, DD>), dim3(nrhs * nmb), dim3(64, C), sh, c->stream, nz, nmb, nxy, in, \
+                     out, modes, e_rhs, active, c->zpair_d, dpart, dscale)
+#define IOBM_ZF2(LL, NFF)        \
+  if (dot) IOBM_ZF3(LL, NFF, true); \
+  else IOBM_ZF3(LL, NFF, false)
 #define IOBM_ZF(LL)                                   \
   switch (c->g.nf) {                                  \
     case 1: IOBM_ZF2(LL, 1); break;                   \
@@ -2171,8 +2241,19 @@ static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* 
   }
 #undef IOBM_ZF
 #undef IOBM_ZF2
+#undef IOBM_ZF3
   prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
   return hipGetLastError();
+}
+
+// The z filter takes the r^T z partials when the plane transforms are the
+// register ones (natural mode order, R in the scratch that feeds the filter),
+// its pair blocks fit the nz partial slots of a rhs, and the autotuner did
+// not find the inverse transform's dot faster.
+template <typename T>
+static bool zfilter_dot_ok(iobm_ctx c) {
+  return c->zpair_d != nullptr && c->zpair_nmb <= c->g.nz && fft_reg_available<T>(c) &&
+         c->zdot[prec_index<T>()] == 0;
 }
 
 static int default_zfilter_chunk(iobm_ctx c) {
@@ -2199,8 +2280,11 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
   // with upd, scratch holds the residual in mode space and is updated from q
   hipError_t err = launch_fft_planes<T>(c, upd ? upd->q : r, scratch, -1, 1.0, nrhs, active, nullptr, nullptr,
                                         upd ? upd->n2part : nullptr, upd);
-  if (err == hipSuccess) err = launch_zfilter<T>(c, L, scratch, z, nrhs, e_rhs, modes, active);
-  if (err == hipSuccess) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active, r, scratch, dpart);
+  const bool zdot = dpart != nullptr && zfilter_dot_ok<T>(c);
+  if (err == hipSuccess) err = launch_zfilter<T>(c, L, scratch, z, nrhs, e_rhs, modes, active, zdot ? dpart : nullptr);
+  if (err == hipSuccess && zdot) err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active);
+  else if (err == hipSuccess)
+    err = launch_fft_planes<T>(c, z, z, +1, 1.0 / c->g.nxy, nrhs, active, r, scratch, dpart);
   prof_stop(c, rec, 2.0 * nrhs * c->g.npts * sizeof(cplx<T>));
   return err;
 }
@@ -2208,9 +2292,12 @@ hipError_t launch_precond_fft(iobm_ctx c, const cplx<T>* r, cplx<T>* z, cplx<T>*
 // Autotuner: time every admissible (points per thread, planes per block)
 // shape of the 2.5D stencil and every z-filter chunk length once on the
 // caller's own batch (x -> y, y is scratch), keep the fastest per precision.
+// With rz_part (nrhs x nz partials), the z filter is timed as the
+// preconditioner will run it: with the r^T z partials where it takes them.
 template <typename T>
 void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nrhs, const double* E_rhs,
-              const int* e_rhs, const ModeData* modes, const int* active, const ApplyFuse<T>* fuse) {
+              const int* e_rhs, const ModeData* modes, const int* active, const ApplyFuse<T>* fuse,
+              Partial* rz_part) {
   bool& done = c->tuned[prec_index<T>()];
   if (done || nrhs <= 0) return;
   done = true;
@@ -2250,23 +2337,36 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
     if (bp > 0) { sh.stencil = 1; sh.points_per_thread = bp; sh.planes_per_block = bz; }
   }
   if (scratch) {
+    // the z filter's chunk length and, where the z filter can take the r^T z
+    // partials, which pass takes them: each composition is timed with the
+    // inverse transform that follows the filter (plain after the filter's
+    // dot, with the dot from R otherwise)
+    const bool try_dot = rz_part != nullptr && zfilter_dot_ok<T>(c);
     float best = 1e30f;
-    int bl = 0;
-    for (int L : {8, 16, 32}) {
-      if ((c->g.nz + L - 1) / L > 8) continue;
-      float t = timed([&] { (void)launch_zfilter<T>(c, L, scratch, y, nrhs, e_rhs, modes, active); });
-      if (t < best) { best = t; bl = L; }
-    }
+    int bl = 0, bd = 0;
+    for (int dot = 0; dot <= (try_dot ? 1 : 0); ++dot)
+      for (int L : {8, 16, 32}) {
+        if ((c->g.nz + L - 1) / L > 8) continue;
+        float t = timed([&] {
+          (void)launch_zfilter<T>(c, L, scratch, y, nrhs, e_rhs, modes, active, dot ? rz_part : nullptr);
+          if (try_dot && dot)
+            (void)launch_fft_planes<T>(c, y, y, +1, 1.0 / c->g.nxy, nrhs, active);
+          else if (try_dot)
+            (void)launch_fft_planes<T>(c, y, y, +1, 1.0 / c->g.nxy, nrhs, active, nullptr, scratch, rz_part);
+        });
+        if (t < best) { best = t; bl = L; bd = dot; }
+      }
     if (bl > 0) sh.zfilter_chunk = bl;
+    if (try_dot && bl > 0) c->zdot[prec_index<T>()] = bd ? 0 : 1;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
 }
 
 template void autotune<float>(iobm_ctx, const zf*, zf*, zf*, int, const double*, const int*, const ModeData*,
-                              const int*, const ApplyFuse<float>*);
+                              const int*, const ApplyFuse<float>*, Partial*);
 template void autotune<double>(iobm_ctx, const zd*, zd*, zd*, int, const double*, const int*, const ModeData*,
-                               const int*, const ApplyFuse<double>*);
+                               const int*, const ApplyFuse<double>*, Partial*);
 
 template hipError_t launch_apply<double>(iobm_ctx, const zd*, zd*, int, const double*, const int*,
                                          const ModeData*, const int*, const ApplyFuse<double>*);
