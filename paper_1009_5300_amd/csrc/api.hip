@@ -1529,30 +1529,27 @@ iobm_status iobm_create(const iobm_grid* g, void* stream, iobm_ctx* out) {
     HIPCHK(hipMemcpy(ctx->twx_f, fx.data(), g->nx * sizeof(zf), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->twy_f, fy.data(), g->ny * sizeof(zf), hipMemcpyHostToDevice));
     {
-      // z-filter lane map: every lateral mode k = (ix, iy) of the natural
-      // FFT order beside its partner -k = ((nx - ix) mod nx, (ny - iy) mod ny),
-      // 32 pairs per block; self-paired modes (k = -k) two to a pair, flagged
+      // the z filter's paired layout (zpair_mode): count the pairs and check
+      // that they cover every lateral mode once, each non-self pair being
+      // (k, -k); the layout stays off otherwise
       const int nx = g->nx, ny = g->ny, nxy = nx * ny;
-      std::vector<std::pair<int, int>> pairs;
-      std::vector<int> selfp;
-      for (int m = 0; m < nxy; ++m) {
-        const int ix = m % nx, iy = m / nx;
-        const int pm = ((ny - iy) % ny) * nx + (nx - ix) % nx;
-        if (pm == m) selfp.push_back(m);
-        else if (m < pm) pairs.push_back({m, pm});
+      std::vector<char> seen(nxy, 0);
+      int npair = 0, covered = 0;
+      bool ok = true;
+      for (;; ++npair) {
+        bool s0 = false, s1 = false;
+        const int a = zpair_mode(npair, 0, ny, nx, s0), b = zpair_mode(npair, 1, ny, nx, s1);
+        if (a >= nxy) break;
+        const int pa = ((ny - a / nx) % ny) * nx + (nx - a % nx) % nx;
+        if (s0 ? pa != a : (b >= nxy || pa != b)) ok = false;
+        for (int m : {a, b})
+          if (m < nxy) {
+            if (seen[m]) ok = false;
+            seen[m] = 1;
+            ++covered;
+          }
       }
-      constexpr int kSelf = 1 << 30;
-      for (size_t i = 0; i < selfp.size(); i += 2)
-        pairs.push_back({selfp[i] | kSelf, i + 1 < selfp.size() ? (selfp[i + 1] | kSelf) : -1});
-      const int nmb = (int)((pairs.size() + 31) / 32);
-      std::vector<int> map((size_t)nmb * 64, -1);
-      for (size_t j = 0; j < pairs.size(); ++j) {
-        map[(j / 32) * 64 + j % 32] = pairs[j].first;
-        map[(j / 32) * 64 + 32 + j % 32] = pairs[j].second;
-      }
-      HIPCHK(hipMalloc(&ctx->zpair_d, map.size() * sizeof(int)));
-      HIPCHK(hipMemcpy(ctx->zpair_d, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice));
-      ctx->zpair_nmb = nmb;
+      ctx->zpair_nmb = ok && covered == nxy ? (npair + 31) / 32 : 0;
     }
     HIPCHK(hipMalloc(&ctx->arena_d, kRegion * kRegions));
     HIPCHK(hipHostMalloc(&ctx->arena_h, kRegion * kRegions, hipHostMallocDefault));
@@ -1633,7 +1630,7 @@ iobm_status iobm_destroy(iobm_ctx ctx) {
   else (void)hipDeviceSynchronize();
   for (auto& e : ctx->pool)
     if (e.first) (void)hipFree(e.first);
-  void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->zpair_d, ctx->V_d, ctx->V_f, ctx->modes_d, ctx->sig_d,
+  void* ptrs[] = {ctx->twx_d, ctx->twy_d, ctx->twx_f, ctx->twy_f, ctx->V_d, ctx->V_f, ctx->modes_d, ctx->sig_d,
                   ctx->sig_f, ctx->mode_flags_d, ctx->sdiag_d,
                   ctx->kb.uvox, ctx->kb.Bd, ctx->kb.Bf, ctx->kb.Btd, ctx->kb.Btf, ctx->kb.ctile, ctx->kb.prange,
                   ctx->kb.hD, ctx->kb.diag_d, ctx->arena_d};

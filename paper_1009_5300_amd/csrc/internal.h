@@ -73,10 +73,7 @@ struct iobm_ctx_s {
   zd* twy_d = nullptr;
   zf* twx_f = nullptr;
   zf* twy_f = nullptr;
-  // lane map of the z filter's paired layout (block b: 32 lateral modes in
-  // lanes 0..31, their partners -k in lanes 32..63; -1 = no mode; bit 30 =
-  // the mode is its own partner), zpair_nmb blocks per rhs
-  int* zpair_d = nullptr;
+  // blocks per rhs of the z filter's paired layout (zpair_mode; 0: off)
   int zpair_nmb = 0;
   double* V_d = nullptr;
   float* V_f = nullptr;
@@ -131,6 +128,34 @@ struct iobm_ctx_s {
   void* static_ws = nullptr;
   std::string err;
 };
+
+// Pair j of the z filter's paired layout, member h (0: the mode k, 1: its
+// partner -k), as a mode index of the natural FFT order m = iy nx + ix, or
+// nxy past the last pair.  The pairs are, in order: row 0 with 1 <= ix <=
+// (nx-1)/2; rows 1 .. (ny-1)/2, every ix; row ny/2 (even ny) with 1 <= ix <=
+// (nx-1)/2; then the self-paired modes (k = -k: ix in {0, nx/2}, iy in
+// {0, ny/2}), two to a pair, flagged in self.  Every other mode is the
+// partner of one of these.
+__host__ __device__ inline int zpair_mode(int j, int h, int ny, int nx, bool& self) {
+  const int nxy = nx * ny, r0 = (nx - 1) / 2, nb = ((ny - 1) / 2) * nx;
+  const int nc = (ny % 2 == 0) ? r0 : 0;
+  const int npair = r0 + nb + nc;
+  self = false;
+  if (j < npair) {
+    int ix, iy;
+    if (j < r0) { ix = j + 1; iy = 0; }
+    else if (j < r0 + nb) { iy = 1 + (j - r0) / nx; ix = (j - r0) % nx; }
+    else { ix = j - r0 - nb + 1; iy = ny / 2; }
+    if (h) { ix = (nx - ix) % nx; iy = (ny - iy) % ny; }
+    return iy * nx + ix;
+  }
+  // self-paired modes: (0,0), (nx/2,0) for even nx, (0,ny/2) for even ny, (nx/2,ny/2) for both
+  const int sx = (nx % 2 == 0) ? 2 : 1, sy = (ny % 2 == 0) ? 2 : 1;
+  const int si = 2 * (j - npair) + h;
+  if (si >= sx * sy) return nxy;
+  self = true;
+  return (si / sx) * (ny / 2) * nx + (si % sx) * (nx / 2);
+}
 
 template <typename T> constexpr int prec_index() { return sizeof(T) == sizeof(float) ? 1 : 0; }
 

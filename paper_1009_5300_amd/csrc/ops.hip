@@ -1268,10 +1268,10 @@ __device__ void state_power(const cplx<T>* al, int nf, int n, cplx<T>* P) {
 }
 
 //
-// With DOT (the preconditioner inside COCG), block b takes its 64 modes from
-// the lane map zmap: 32 modes k in lanes 0..31 and their partners -k in
-// lanes 32..63, so that one wavefront holds both factors of the bilinear
-// form in mode space (Parseval, with R = in and Z = out in natural FFT order)
+// With DOT (the preconditioner inside COCG), block b takes 32 modes k in
+// lanes 0..31 and their partners -k in lanes 32..63 (zpair_mode), so that
+// one wavefront holds both factors of the bilinear form in mode space
+// (Parseval, with R = in and Z = out in natural FFT order)
 //   sum_x r(x) z(x) = dscale * sum_k sum_z R(-k, z) Z(k, z),   dscale = 1 / Nxy,
 // the partner's output coming from lane t ^ 32 (a mode that is its own
 // partner uses its own).  The block's partial goes to dpart[rhs][b], and
@@ -1282,8 +1282,7 @@ template <typename T, int L, int NF, bool DOT>
 __global__ void __launch_bounds__(512) k_zfilter(int nz, int nmb, int nxy, const cplx<T>* __restrict__ in,
                                                   cplx<T>* __restrict__ out, const ModeData* __restrict__ modes,
                                                   const int* __restrict__ e_rhs, const int* __restrict__ active,
-                                                  const int* __restrict__ zmap, Partial* __restrict__ dpart,
-                                                  double dscale) {
+                                                  int nx, Partial* __restrict__ dpart, double dscale) {
   extern __shared__ char smem_raw[];
   const int C = blockDim.y;
   cplx<T>* sc = reinterpret_cast<cplx<T>*>(smem_raw);  // [C][64][3] causal end states
@@ -1292,11 +1291,7 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nmb, int nxy, const
   const int mb = blockIdx.x - slot * nmb;
   int m = mb * 64 + threadIdx.x;
   bool self = false;
-  if constexpr (DOT) {
-    const int e = zmap[mb * 64 + threadIdx.x];
-    m = e < 0 ? nxy : (e & ~(1 << 30));
-    self = e >= 0 && (e & (1 << 30)) != 0;
-  }
+  if constexpr (DOT) m = zpair_mode(mb * 32 + (threadIdx.x & 31), threadIdx.x >> 5, nxy / nx, nx, self);
   // one wavefront per chunk: the chunk index (and every plane offset below)
   // is wave-uniform, which keeps the load addresses in scalar registers
   const int c = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -1419,6 +1414,13 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nmb, int nxy, const
     }
   }
   if constexpr (DOT) {
+    // the outputs are stored first, so that they drain while the partner
+    // exchange and the block reduction run
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+        if (z0 + i < nz) out[base + (long long)(z0 + i) * nxy + m] = y[i];
+    }
     double a = 0, b = 0;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -1458,7 +1460,7 @@ __global__ void __launch_bounds__(512) k_zfilter(int nz, int nmb, int nxy, const
         for (int k = nmb + threadIdx.x; k < nz; k += 64) dpart[(long long)rhs * nz + k] = Z;
       }
     }
-    if (!live) return;
+    return;
   }
 #pragma unroll
   for (int i = 0; i < L; ++i)
@@ -2224,7 +2226,7 @@ static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* 
   const int rec = prof_start(c, IOBM_K_ZFILTER);
 #define IOBM_ZF3(LL, NFF, DD)                                                                                     \
   hipLaunchKernelGGL((k_zfilter<T, LL, NFF, DD>), dim3(nrhs * nmb), dim3(64, C), sh, c->stream, nz, nmb, nxy, in, \
-                     out, modes, e_rhs, active, c->zpair_d, dpart, dscale)
+                     out, modes, e_rhs, active, c->g.nx, dpart, dscale)
 #define IOBM_ZF2(LL, NFF)        \
   if (dot) IOBM_ZF3(LL, NFF, true); \
   else IOBM_ZF3(LL, NFF, false)
@@ -2252,7 +2254,7 @@ static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* 
 // not find the inverse transform's dot faster.
 template <typename T>
 static bool zfilter_dot_ok(iobm_ctx c) {
-  return c->zpair_d != nullptr && c->zpair_nmb <= c->g.nz && fft_reg_available<T>(c) &&
+  return c->zpair_nmb > 0 && c->zpair_nmb <= c->g.nz && fft_reg_available<T>(c) &&
          c->zdot[prec_index<T>()] == 0;
 }
 
