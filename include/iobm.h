@@ -353,6 +353,11 @@ iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, in
  *                      chunk of the z recursion (at most 8 chunks)
  *   plane_fft:         1 = in-register plane FFT (square planes of 8, 12, 16,
  *                      24, 32 or 48 points), 2 = LDS Stockham plane FFT
+ * With the in-register plane FFT the autotuner also times which pass of the
+ * lateral-Fourier preconditioner forms the r^T z partials (the z filter, with
+ * each mode and its negative in one wavefront, or the inverse plane FFT) and
+ * keeps the faster; a pinned shape uses the z filter's wherever its pair
+ * blocks fit the nz partial slots of a state.
  * Shapes are kept per kernel arithmetic: IOBM_C64_REFINED selects the
  * complex64 kernels of the inner iteration, IOBM_C128 the complex128 ones
  * (including the FP64 residual refresh of a IOBM_C64_REFINED solve).
