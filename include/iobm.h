@@ -353,11 +353,12 @@ iobm_status iobm_grad_transmission(iobm_ctx ctx, const iobm_solve_opts* opts, in
  *                      chunk of the z recursion (at most 8 chunks)
  *   plane_fft:         1 = in-register plane FFT (square planes of 8, 12, 16,
  *                      24, 32 or 48 points), 2 = LDS Stockham plane FFT
- * With the in-register plane FFT the autotuner also times which pass of the
- * lateral-Fourier preconditioner forms the r^T z partials (the z filter, with
- * each mode and its negative in one wavefront, or the inverse plane FFT) and
- * keeps the faster; a pinned shape uses the z filter's wherever its pair
- * blocks fit the nz partial slots of a state.
+ *   rz_pass:           lateral-Fourier preconditioner with the in-register
+ *                      plane FFT: the pass that forms the r^T z partials,
+ *                      1 = the z filter (each mode beside its negative in one
+ *                      wavefront; used where its pair blocks fit the nz
+ *                      partial slots of a state), 2 = the inverse plane FFT
+ *                      (the autotuner times both and keeps the faster)
  * Shapes are kept per kernel arithmetic: IOBM_C64_REFINED selects the
  * complex64 kernels of the inner iteration, IOBM_C128 the complex128 ones
  * (including the FP64 residual refresh of a IOBM_C64_REFINED solve).
@@ -373,6 +374,7 @@ typedef struct {
   int32_t planes_per_block;
   int32_t zfilter_chunk;
   int32_t plane_fft;
+  int32_t rz_pass;
 } iobm_launch_shape;
 iobm_status iobm_get_launch_shape(iobm_ctx ctx, int32_t precision, iobm_launch_shape* shape);
 iobm_status iobm_set_launch_shape(iobm_ctx ctx, int32_t precision, const iobm_launch_shape* shape);

@@ -1607,17 +1607,16 @@ iobm_status iobm_set_launch_shape(iobm_ctx ctx, int32_t precision, const iobm_la
   if (!shape) {  // unpin: the next solve in this precision tunes again
     ctx->shape[p] = iobm_launch_shape{};
     ctx->tuned[p] = ctx->pinned[p] = false;
-    ctx->zdot[p] = 0;
     return IOBM_OK;
   }
   std::string why;
   if (shape->stencil < 0 || shape->stencil > 2 || shape->plane_fft < 0 || shape->plane_fft > 2 ||
-      shape->points_per_thread < 0 || shape->planes_per_block < 0 || shape->zfilter_chunk < 0)
+      shape->points_per_thread < 0 || shape->planes_per_block < 0 || shape->zfilter_chunk < 0 ||
+      shape->rz_pass < 0 || shape->rz_pass > 2)
     return fail(ctx, IOBM_E_INVALID_ARG, "launch shape field out of range");
   if (!launch_shape_valid(ctx, p, *shape, why)) return fail(ctx, IOBM_E_UNSUPPORTED, why);
   ctx->shape[p] = *shape;
   ctx->tuned[p] = ctx->pinned[p] = true;
-  ctx->zdot[p] = 0;
   return IOBM_OK;
 }
 

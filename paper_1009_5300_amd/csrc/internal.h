@@ -106,10 +106,6 @@ struct iobm_ctx_s {
   iobm_launch_shape shape[2] = {};
   bool tuned[2] = {false, false};
   bool pinned[2] = {false, false};
-  // where the lateral-Fourier preconditioner takes r^T z on square planes:
-  // 0 in the z filter (paired layout; the default), 1 in the inverse
-  // transform (the autotuner's choice where that composition timed faster)
-  int zdot[2] = {0, 0};
   // kernel timing hook
   int prof_mask = 0;
   std::vector<hipEvent_t> prof_ev;  // start/stop pairs

@@ -2250,12 +2250,12 @@ static hipError_t launch_zfilter(iobm_ctx c, int L, const cplx<T>* in, cplx<T>* 
 
 // The z filter takes the r^T z partials when the plane transforms are the
 // register ones (natural mode order, R in the scratch that feeds the filter),
-// its pair blocks fit the nz partial slots of a rhs, and the autotuner did
-// not find the inverse transform's dot faster.
+// its pair blocks fit the nz partial slots of a rhs, and the launch shape
+// does not name the inverse transform (rz_pass 2).
+static bool zfilter_dot_fits(iobm_ctx c) { return c->zpair_nmb > 0 && c->zpair_nmb <= c->g.nz; }
 template <typename T>
 static bool zfilter_dot_ok(iobm_ctx c) {
-  return c->zpair_nmb > 0 && c->zpair_nmb <= c->g.nz && fft_reg_available<T>(c) &&
-         c->zdot[prec_index<T>()] == 0;
+  return zfilter_dot_fits(c) && fft_reg_available<T>(c) && c->shape[prec_index<T>()].rz_pass != 2;
 }
 
 static int default_zfilter_chunk(iobm_ctx c) {
@@ -2359,7 +2359,7 @@ void autotune(iobm_ctx c, const cplx<T>* x, cplx<T>* y, cplx<T>* scratch, int nr
         if (t < best) { best = t; bl = L; bd = dot; }
       }
     if (bl > 0) sh.zfilter_chunk = bl;
-    if (try_dot && bl > 0) c->zdot[prec_index<T>()] = bd ? 0 : 1;
+    if (try_dot && bl > 0) sh.rz_pass = bd ? 1 : 2;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -2421,6 +2421,7 @@ iobm_launch_shape launch_shape_in_effect(iobm_ctx c, int prec) {
   r.planes_per_block = r.stencil == 1 ? (s.planes_per_block > 0 ? s.planes_per_block : 32) : 16;
   r.zfilter_chunk = s.zfilter_chunk > 0 ? s.zfilter_chunk : default_zfilter_chunk(c);
   r.plane_fft = (square_reg_size(c) && s.plane_fft != 2) ? 1 : 2;
+  r.rz_pass = (r.plane_fft == 1 && zfilter_dot_fits(c) && s.rz_pass != 2) ? 1 : 2;
   return r;
 }
 

@@ -51,7 +51,7 @@ class SolveStat(C.Structure):
 
 class LaunchShape(C.Structure):
     _fields_ = [("stencil", C.c_int32), ("points_per_thread", C.c_int32), ("planes_per_block", C.c_int32),
-                ("zfilter_chunk", C.c_int32), ("plane_fft", C.c_int32)]
+                ("zfilter_chunk", C.c_int32), ("plane_fft", C.c_int32), ("rz_pass", C.c_int32)]
 
 
 SHAPE_FIELDS = [f for f, _ in LaunchShape._fields_]

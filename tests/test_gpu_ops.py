@@ -343,7 +343,7 @@ def test_launch_shape_rejections(torch):
     for bad, status in ((dict(stencil=1, points_per_thread=1), 8),   # 2304 threads per block
                         (dict(stencil=1, points_per_thread=4), 8),   # 4 points per thread only for nf = 1
                         (dict(planes_per_block=12), 8), (dict(zfilter_chunk=4), 8),
-                        (dict(stencil=3), 1), (dict(planes_per_block=-1), 1)):
+                        (dict(stencil=3), 1), (dict(planes_per_block=-1), 1), (dict(rz_pass=3), 1)):
         with pytest.raises(iobm.IobmError) as e:
             s.set_launch_shape(iobm.C64_REFINED, bad)
         assert e.value.status == status, bad
